@@ -1,0 +1,225 @@
+"""Problem descriptions and seeded synthetic inputs.
+
+This module holds no arithmetic of the lattice Boltzmann method: it only
+states problems in the form of the paper's Eq. 1 (polynomial coefficients of
+B(phi), D(phi), K(phi) = K0 k(phi), R(phi), lattice, walls, rates) and draws
+seeded initial fields.  The GPU binding and the CPU oracle each read these
+plain dicts and derive every method quantity (C of Eq. 7, A of Eq. 26, the
+equilibria, ...) on their own.
+
+Lattice units throughout: node i of a periodic axis sits at x = i; node k of
+an axis with anti-bounce-back walls sits at z = k + 1/2, walls at 0 and n.
+"""
+import numpy as np
+
+__all__ = [
+    "spec_linear_gaussian", "spec_nonlinear_2d", "spec_d3q19_aniso",
+    "gaussian_hill", "noise_field", "gaussians_3d", "random_spd3",
+    "C1", "C2", "C3", "C5", "C5B", "batch_specs",
+]
+
+
+def _rates(q, diag=1.0, **over):
+    s = [float(diag)] * q
+    s[0] = 0.0
+    for k, v in over.items():
+        s[int(k[1:])] = float(v)
+    return s
+
+
+# ----------------------------------------------------------------------------
+# problem specs
+# ----------------------------------------------------------------------------
+
+def spec_linear_gaussian(n=64, u=(0.05, 0.02), kappa=0.01, s12=1.2, precision="f64"):
+    """Linear isotropic CDE with constant velocity (Eq. 58/61 with K = kappa I):
+    B = phi u, D = phi I, K = kappa I, R = 0.  Rates: s1 = s2 = s12, the other
+    non-flux rates 1.0; the flux block follows from K."""
+    return dict(
+        lattice=9, shape=(n, n), bc=["periodic"] * 3, scheme="A", d=1.0,
+        s=_rates(9, 1.0, s1=s12, s2=s12),
+        b=[[0.0, u[0]], [0.0, u[1]]], dpoly=[0.0, 1.0], dten=np.eye(3).tolist(),
+        k0=(kappa * np.eye(3)).tolist(), kpoly=[1.0], rpoly=[],
+        precision=precision, phi_ref=0.0,
+    )
+
+
+# Grid spacing and time step of the nonlinear 2-D workloads, in the length and
+# time units their coefficients are stated in.  Read with dx = dt = 1 the
+# stated problem is linearly unstable on any grid (grid Peclet number
+# |B'| dx / K_min of about 150); with dx = 1/32 and lattice speed
+# c = dx / dt = 10 it is stable with flux relaxation rates between 1.0 and 1.7.
+NONLINEAR_DX = 1.0 / 32.0
+NONLINEAR_DT = NONLINEAR_DX / 10.0
+
+
+def lattice_units(b, k0, rpoly, dx, dt):
+    """Rewrite Eq. 1 with x' = x / dx, t' = t / dt: B' = B dt/dx, K' = K dt/dx^2,
+    R' = R dt; D is unchanged.  Polynomials in phi keep their phi dependence."""
+    cl = dt / dx
+    b2 = [[v * cl for v in row] for row in b]
+    k2 = (np.asarray(k0, dtype=np.float64) * dt / (dx * dx)).tolist()
+    r2 = [v * dt for v in rpoly]
+    return b2, k2, r2
+
+
+def spec_nonlinear_2d(nx=1024, ny=None, bcoef=0.5, k0=((0.02, 0.008), (0.008, 0.01)),
+                      source=True, precision="f64", phi_ref=0.5,
+                      dx=NONLINEAR_DX, dt=NONLINEAR_DT):
+    """Nonlinear anisotropic CDE with source: B = bcoef phi^2 (1, 1),
+    K = K0 (1 + phi^2), D = phi I, R = 0.1 phi (1 - phi) (or 0), Scheme A,
+    on a periodic nx x ny grid of spacing dx, time step dt (coefficients
+    returned in lattice units)."""
+    ny = nx if ny is None else ny
+    k = np.zeros((3, 3))
+    k[:2, :2] = np.asarray(k0, dtype=np.float64)
+    b, kl, r = lattice_units([[0.0, 0.0, bcoef], [0.0, 0.0, bcoef]], k,
+                             [0.0, 0.1, -0.1] if source else [], dx, dt)
+    return dict(
+        lattice=9, shape=(nx, ny), bc=["periodic"] * 3, scheme="A", d=1.0,
+        s=_rates(9, 1.0),
+        b=b, dpoly=[0.0, 1.0], dten=np.eye(3).tolist(),
+        k0=kl, kpoly=[1.0, 0.0, 1.0], rpoly=r,
+        precision=precision, phi_ref=phi_ref,
+    )
+
+
+def spec_d3q19_aniso(n=(256, 256, 256), K=None, u=(0.03, 0.0, 0.01), phi_wall=0.0,
+                     precision="f64", phi_ref=0.0, s_other=1.0):
+    """Linear anisotropic CDE on D3Q19: B = phi u, D = phi I, constant full K,
+    periodic in x and y, anti-bounce-back Dirichlet walls at both z ends."""
+    if K is None:
+        K = random_spd3(3)
+    return dict(
+        lattice=19, shape=tuple(n), bc=["periodic", "periodic", "abb"],
+        phi_wall=[[0.0, 0.0], [0.0, 0.0], [phi_wall, phi_wall]], scheme="A", d=1.0,
+        s=_rates(19, s_other),
+        b=[[0.0, u[0]], [0.0, u[1]], [0.0, u[2]]], dpoly=[0.0, 1.0], dten=np.eye(3).tolist(),
+        k0=np.asarray(K).tolist(), kpoly=[1.0], rpoly=[],
+        precision=precision, phi_ref=phi_ref,
+    )
+
+
+# ----------------------------------------------------------------------------
+# seeded fields
+# ----------------------------------------------------------------------------
+
+def gaussian_hill(n=64, sigma0=6.0, centre=None, amp=1.0, images=2):
+    """Gaussian hill of amplitude ``amp`` and width sigma0 on an n x n periodic
+    grid, summed over periodic images |i|,|j| <= images.  Returns [ny, nx]."""
+    centre = (n / 2.0, n / 2.0) if centre is None else centre
+    x = np.arange(n, dtype=np.float64)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    out = np.zeros((n, n))
+    for i in range(-images, images + 1):
+        for j in range(-images, images + 1):
+            dx = X - centre[0] - i * n
+            dy = Y - centre[1] - j * n
+            out += np.exp(-(dx * dx + dy * dy) / (2.0 * sigma0 * sigma0))
+    return amp * out
+
+
+def noise_field(shape, seed, mean=0.5, amp=0.1):
+    """mean + amp * U[-1, 1) from numpy's PCG64 generator, C order."""
+    rng = np.random.default_rng(seed)
+    return mean + amp * rng.uniform(-1.0, 1.0, size=shape)
+
+
+def random_spd3(seed, lo=0.005, hi=0.05):
+    """Symmetric 3x3 tensor Q diag(lam) Q^T, Q from the QR of a seeded normal
+    matrix (signs fixed so that diag(R) > 0), lam ~ U[lo, hi]."""
+    rng = np.random.default_rng(seed)
+    Q, R = np.linalg.qr(rng.standard_normal((3, 3)))
+    Q = Q * np.sign(np.diag(R))[None, :]
+    lam = rng.uniform(lo, hi, size=3)
+    K = Q @ np.diag(lam) @ Q.T
+    return 0.5 * (K + K.T)
+
+
+def gaussians_3d(n=(256, 256, 256), seed=3, count=8):
+    """Sum of ``count`` Gaussians: amplitude U[0.5, 1], width U[8, 24] cells
+    (scaled with the grid), centres uniform in x, y and in the middle 69% of z;
+    periodic images in x and y.  Node k of z sits at k + 1/2.  Returns [nz, ny, nx]."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    scale = min(nx, ny, nz) / 256.0
+    amp = rng.uniform(0.5, 1.0, size=count)
+    sig = rng.uniform(8.0, 24.0, size=count) * scale
+    cx = rng.uniform(0, nx, size=count)
+    cy = rng.uniform(0, ny, size=count)
+    cz = rng.uniform(40.0 / 256.0 * nz, 216.0 / 256.0 * nz, size=count)
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+    z = np.arange(nz, dtype=np.float64) + 0.5
+    out = np.zeros((nz, ny, nx))
+    for g in range(count):
+        gz = np.exp(-((z - cz[g]) ** 2) / (2 * sig[g] ** 2))
+        gy = np.zeros(ny)
+        gx = np.zeros(nx)
+        for i in (-1, 0, 1):
+            gy += np.exp(-((y - cy[g] - i * ny) ** 2) / (2 * sig[g] ** 2))
+            gx += np.exp(-((x - cx[g] - i * nx) ** 2) / (2 * sig[g] ** 2))
+        out += amp[g] * gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+    return out
+
+
+# ----------------------------------------------------------------------------
+# the five workloads (plus the non-degenerate gradient variant)
+# ----------------------------------------------------------------------------
+
+def C1():
+    """D2Q9, linear isotropic CDE, periodic 64 x 64, u = (0.05, 0.02),
+    kappa = 0.01, Gaussian hill (amplitude 1, sigma 6, centred), R = 0,
+    s1 = s2 = 1.2, 1000 steps."""
+    spec = spec_linear_gaussian(64)
+    return spec, gaussian_hill(64, 6.0), 1000
+
+
+def C2(n=1024, precision="f64"):
+    """D2Q9 nonlinear anisotropic CDE, periodic n x n, phi0 = 0.5 + 0.1 U[-1, 1)
+    (seed 2), Scheme A source, 5000 steps."""
+    spec = spec_nonlinear_2d(n, precision=precision)
+    return spec, noise_field((n, n), 2), 5000
+
+
+def C3(n=(256, 256, 256), precision="f64"):
+    """D3Q19 anisotropic CDE, periodic x/y, phi_w = 0 walls on z, K from seed 3,
+    u = (0.03, 0, 0.01), sum of 8 Gaussians (seed 3), 2000 steps."""
+    spec = spec_d3q19_aniso(n, K=random_spd3(3), precision=precision, phi_ref=0.0)
+    return spec, gaussians_3d(n, 3), 2000
+
+
+def C5(n=512, precision="f64"):
+    """Adjoint workload: C2 physics on n x n (seed 5), target phi* from seed 6,
+    2000 steps, sqrt(T) = 45-step checkpoints."""
+    spec = spec_nonlinear_2d(n, precision=precision)
+    return spec, noise_field((n, n), 5), noise_field((n, n), 6), 2000
+
+
+def C5B(n=512, precision="f64", nsteps=2000):
+    """Non-degenerate gradient variant of C5: R = 0, so the sensitivities do
+    not vanish; the target is a forward run of the same model from seed 6."""
+    spec = spec_nonlinear_2d(n, precision=precision, source=False)
+    return spec, noise_field((n, n), 5), noise_field((n, n), 6), nsteps
+
+
+def batch_specs(count=512, seed=4, lo=32, hi=512, precision="f32"):
+    """Batched workload: ``count`` independent D2Q9 instances, sides uniform in
+    [lo, hi] (square with probability 1/2), per-instance K0 = Rot diag(lam)
+    Rot^T with lam ~ U[0.005, 0.05], B = c phi^2 (1, 1) with c ~ U[0, 1],
+    K = K0 (1 + phi^2), R = 0, phi0 = 0.15 + 0.05 U[-1, 1)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        nx = int(rng.integers(lo, hi + 1))
+        ny = nx if rng.uniform() < 0.5 else int(rng.integers(lo, hi + 1))
+        th = rng.uniform(0.0, np.pi)
+        lam = rng.uniform(0.005, 0.05, size=2)
+        Rm = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        K0 = Rm @ np.diag(lam) @ Rm.T
+        c = rng.uniform(0.0, 1.0)
+        spec = spec_nonlinear_2d(nx, ny, bcoef=c, k0=0.5 * (K0 + K0.T), source=False,
+                                 precision=precision, phi_ref=0.15)
+        phi0 = noise_field((ny, nx), seed * 100003 + i, mean=0.15, amp=0.05)
+        out.append((spec, phi0))
+    return out

@@ -1,0 +1,595 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test names the passage it checks.  None of them re-types the oracle's own
+formula: they use identities the paper prints separately (Eq. 10, 16, 26, 30,
+50, 72), textbook special cases (BGK, an Adams-Bashforth ODE step), exact
+solutions (Gaussian hill Eq. 60, sine wave Eq. 45, channel Eq. 70-72),
+invariants (conservation, uniform fixed points, basis independence) and
+finite differences for the adjoint.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1603_09577_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+
+def base_spec(q=9, shape=(8, 8), **kw):
+    s = [0.0] + [1.0] * (q - 1)
+    spec = dict(lattice=q, shape=shape, bc=["periodic"] * 3, scheme="A", d=1.0, s=s,
+                b=[[0.0, 0.05], [0.0, 0.02], [0.0, 0.01]], dpoly=[0.0, 1.0],
+                dten=np.eye(3).tolist(), k0=(0.02 * np.eye(3)).tolist(), kpoly=[1.0], rpoly=[])
+    spec.update(kw)
+    return spec
+
+
+def nonlinear_spec(q=9, shape=(8, 8), **kw):
+    """Nonlinear B, C, D, K and R, full anisotropic K0 and d != 1."""
+    k0 = np.array([[0.03, 0.007, 0.004], [0.007, 0.02, -0.003], [0.004, -0.003, 0.025]])
+    spec = base_spec(q, shape, b=[[0.0, 0.02, 0.05, -0.01], [0.0, -0.03, 0.04], [0.0, 0.01, 0.0, 0.02]],
+                     dpoly=[0.1, 0.8, 0.2], dten=[[1.0, 0.1, 0.0], [0.1, 1.2, 0.05], [0.0, 0.05, 0.9]],
+                     k0=k0.tolist(), kpoly=[1.0, 0.3, 0.5], rpoly=[0.0, 0.01, -0.02], d=0.8)
+    spec["s"] = [0.0] + [1.1 + 0.05 * i for i in range(q - 1)]
+    spec.update(kw)
+    return spec
+
+
+def dim_of(p):
+    return 2 if p.q == 9 else 3
+
+
+# ---------------------------------------------------------------------------
+# lattices and transforms (Eq. 5, 6, 15; D3Q19 basis)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_lattice_isotropy(q):
+    """Eq. 5/6 weights: sum w = 1, sum w c = 0, sum w c c = cs^2 I, 4th-order
+    isotropy sum w c_a c_b c_c c_d = cs^4 (d_ab d_cd + d_ac d_bd + d_ad d_bc)."""
+    p = orc.params_from_spec(base_spec(q, (4, 4, 4) if q == 19 else (4, 4)))
+    c, w, M, Minv = orc.tables(p)
+    dim = dim_of(p)
+    c = c[:, :dim].astype(float)
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.abs(w @ c).max() < 1e-15
+    assert np.abs(np.einsum("k,ka,kb->ab", w, c, c) - np.eye(dim) / 3).max() < 1e-15
+    I = np.eye(dim)
+    iso = (np.einsum("ab,cd->abcd", I, I) + np.einsum("ac,bd->abcd", I, I) + np.einsum("ad,bc->abcd", I, I)) / 9
+    assert np.abs(np.einsum("k,ka,kb,kc,kd->abcd", w, c, c, c, c) - iso).max() < 1e-15
+
+
+def test_d2q9_transform_matches_eq15_norms():
+    """Eq. 15: rows of M0 mutually orthogonal with the printed norms; inverse exact."""
+    p = orc.params_from_spec(base_spec())
+    c, w, M, Minv = orc.tables(p)
+    G = M @ M.T
+    want = json.load(open(GOLDEN))["d2q9_moment_norms"]["value"]
+    assert np.abs(G - np.diag(want)).max() == 0.0
+    assert np.abs(Minv @ M - np.eye(9)).max() < 1e-15
+    # flux rows are c_x and c_y (Eq. 15 rows 4 and 6)
+    assert np.array_equal(M[3], c[:, 0]) and np.array_equal(M[5], c[:, 1])
+
+
+@pytest.mark.parametrize("basis", [0, 1])
+def test_d3q19_basis_orthogonal(basis):
+    """Both D3Q19 bases: orthogonal rows, density row 1, flux rows c_x, c_y, c_z."""
+    p = orc.params_from_spec(base_spec(19, (4, 4, 4)), basis=basis)
+    c, w, M, Minv = orc.tables(p)
+    G = M @ M.T
+    assert np.abs(G - np.diag(np.diag(G))).max() < 1e-12
+    assert np.abs(Minv @ M - np.eye(19)).max() < 1e-13
+    assert np.allclose(M[0], 1) and np.array_equal(M[3], c[:, 0]) and np.array_equal(M[5], c[:, 1]) \
+        and np.array_equal(M[7], c[:, 2])
+    if basis == 0:
+        assert np.allclose(np.diag(G), [19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8])
+
+
+# ---------------------------------------------------------------------------
+# equilibrium (Eq. 3) against Eq. 10 and Eq. 16; C against Eq. 7 / Eq. 50
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("phi", [0.0, 0.37, 1.3])
+def test_equilibrium_moments_eq10(q, phi):
+    """Eq. 10: sum feq = phi, sum c feq = B, sum c c feq = C + d cs^2 D."""
+    spec = nonlinear_spec(q, (4, 4, 4) if q == 19 else (4, 4))
+    p = orc.params_from_spec(spec)
+    c, w, M, Minv = orc.tables(p)
+    dim = dim_of(p)
+    c = c[:, :dim].astype(float)
+    fe = orc.feq(p, phi)
+    B = np.array([np.polyval(spec["b"][a][::-1], phi) for a in range(dim)])
+    C = orc.ctensor(p, phi)[:dim, :dim]
+    D = np.polyval(spec["dpoly"][::-1], phi) * np.asarray(spec["dten"])[:dim, :dim]
+    assert abs(fe.sum() - phi) < 1e-14
+    assert np.abs(c.T @ fe - B).max() < 1e-14
+    assert np.abs(np.einsum("k,ka,kb->ab", fe, c, c) - (C + spec["d"] / 3.0 * D)).max() < 1e-14
+
+
+def test_equilibrium_moments_eq16():
+    """Eq. 16: M0 feq equals the printed closed form of the equilibrium moments."""
+    spec = nonlinear_spec(9, (4, 4))
+    p = orc.params_from_spec(spec)
+    c, w, M, Minv = orc.tables(p)
+    for phi in (0.2, 0.8, 1.7):
+        fe = orc.feq(p, phi)
+        B = [np.polyval(spec["b"][a][::-1], phi) for a in range(2)]
+        Cbar = orc.ctensor(p, phi)[:2, :2] + spec["d"] / 3.0 * np.polyval(spec["dpoly"][::-1], phi) \
+            * np.asarray(spec["dten"])[:2, :2]
+        C2 = Cbar[0, 0] + Cbar[1, 1]
+        meq = np.array([phi, -4 * phi + 3 * C2, 3 * phi - 3 * C2, B[0], -B[0], B[1], -B[1],
+                        Cbar[0, 0] - Cbar[1, 1], Cbar[0, 1]])
+        assert np.abs(M @ fe - meq).max() < 1e-14
+
+
+def test_ctensor_eq50():
+    """Eq. 49-50 (Burgers-Fisher): B = phi^(delta+1) (a/(delta+1), 0) gives
+    C_xx = a^2 phi^(2 delta + 1) / (2 delta + 1), other entries 0 (delta = 1, 2)."""
+    a = 4.0
+    for delta in (1, 2):
+        bx = [0.0] * (delta + 2)
+        bx[delta + 1] = a / (delta + 1)
+        p = orc.params_from_spec(base_spec(b=[bx, [0.0]]))
+        for phi in (0.3, 0.9):
+            C = orc.ctensor(p, phi)
+            assert abs(C[0, 0] - a * a * phi ** (2 * delta + 1) / (2 * delta + 1)) < 1e-14
+            assert abs(C[0, 1]) + abs(C[1, 1]) == 0.0
+
+
+def test_ctensor_derivative_eq7():
+    """Eq. 7: C' = B' B'^T and C(0) = 0, by central differences."""
+    spec = nonlinear_spec(19, (4, 4, 4))
+    p = orc.params_from_spec(spec)
+    assert np.abs(orc.ctensor(p, 0.0)).max() == 0.0
+    h = 1e-5
+    for phi in (0.3, 1.1):
+        dC = (orc.ctensor(p, phi + h) - orc.ctensor(p, phi - h)) / (2 * h)
+        bp = np.array([np.polyval(np.polyder(np.asarray(spec["b"][a][::-1])), phi) for a in range(3)])
+        assert np.abs(dC - np.outer(bp, bp)).max() < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# relaxation block A (Eq. 26, 30) and the source (Eq. 9, 10, 28, 30)
+# ---------------------------------------------------------------------------
+
+def test_ablock_eq26_full_tensor():
+    """Eq. 26: K = d cs^2 (A^-1 - I/2) dt, recovered from the oracle's A."""
+    for q in (9, 19):
+        spec = nonlinear_spec(q, (4, 4, 4) if q == 19 else (4, 4))
+        p = orc.params_from_spec(spec)
+        dim = dim_of(p)
+        for phi in (0.0, 0.6):
+            A = orc.ablock(p, phi)
+            K = np.asarray(spec["k0"])[:dim, :dim] * np.polyval(spec["kpoly"][::-1], phi)
+            assert np.abs(spec["d"] / 3.0 * (np.linalg.inv(A) - 0.5 * np.eye(dim)) - K).max() < 1e-15
+
+
+def test_ablock_eq30_diagonal():
+    """Eq. 30b: diagonal K gives diagonal A with kappa_xx = d cs^2 (1/s3 - 1/2)."""
+    p = orc.params_from_spec(base_spec(k0=np.diag([0.01, 0.04, 0.0]).tolist()))
+    A = orc.ablock(p, 0.5)
+    assert A[0, 1] == 0.0 and A[1, 0] == 0.0
+    assert abs((1 / A[0, 0] - 0.5) / 3 - 0.01) < 1e-16
+    assert abs((1 / A[1, 1] - 0.5) / 3 - 0.04) < 1e-16
+
+
+def _source_vector(p, phi):
+    """R_k at a node in equilibrium with pprev = phi (Scheme A): the collision
+    then returns feq + R_k, since 3/2 R_k - 1/2 R_k = R_k."""
+    fe = orc.feq(p, phi)
+    out, _ = orc.collide(p, fe, phi)
+    return out - fe
+
+
+@pytest.mark.parametrize("scheme", ["A", "B"])
+def test_source_moments_eq10_eq30(scheme):
+    """Eq. 10: sum R_k = R and sum c R_k = Btilde R with Btilde from Eq. 30a
+    (diagonal K): lambda_i = (s_i - 2)/(gamma s_i - 2)."""
+    k = [0.01, 0.04]
+    spec = base_spec(k0=np.diag(k + [0.0]).tolist(), b=[[0.0, 0.1, 0.3], [0.0, -0.2, 0.1]],
+                     rpoly=[0.02, 0.05], scheme=scheme)
+    if scheme == "B":
+        spec["rpoly"] = [0.02]
+    p = orc.params_from_spec(spec)
+    c, w, M, Minv = orc.tables(p)
+    phi = 0.7
+    gamma = 0.0 if scheme == "A" else 1.0
+    if scheme == "A":
+        Rk = _source_vector(p, phi)
+    else:
+        # Scheme B (Eq. 34): with f = feq - R/2 the update adds M^-1 (I - S/2) M R
+        # and removes S applied to the shift; check Eq. 10 moments of R via the
+        # Eq. 35 identity sum fbar + R/2 = phi on the initial state instead.
+        f, pp = orc.init(p, np.full(orc.field_shape(p), phi))
+        fe = orc.feq(p, phi)
+        Rk = 2.0 * (fe - f.reshape(9, -1)[:, 0])
+    R = np.polyval(spec["rpoly"][::-1], phi)
+    Bp = np.array([np.polyval(np.polyder(np.asarray(spec["b"][a][::-1])), phi) for a in range(2)])
+    s3, s5 = (1.0 / (3 * k[0] + 0.5), 1.0 / (3 * k[1] + 0.5))
+    lam = np.array([(s3 - 2) / (gamma * s3 - 2), (s5 - 2) / (gamma * s5 - 2)])
+    assert abs(Rk.sum() - R) < 1e-15
+    assert np.abs(c[:, :2].T @ Rk - lam * Bp * R).max() < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# collision special cases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_mrt_equal_rates_is_bgk(q):
+    """All rates equal (A = s I): MRT reduces to BGK, f* = f - s (f - feq) + R_k."""
+    s = 1.37
+    kap = (1.0 / s - 0.5) / 3.0
+    spec = base_spec(q, (4, 4, 4) if q == 19 else (4, 4), k0=(kap * np.eye(3)).tolist(),
+                     b=[[0.0, 0.1, 0.2], [0.0, -0.05], [0.0, 0.03, 0.1]], rpoly=[0.01, 0.02])
+    spec["s"] = [s] * q
+    p = orc.params_from_spec(spec)
+    rng = np.random.default_rng(0)
+    f = orc.feq(p, 0.6) + 0.01 * rng.standard_normal(q)
+    phi = f.sum()
+    Rk = _source_vector(p, phi)
+    out, _ = orc.collide(p, f, phi)
+    assert np.abs(out - (f - s * (f - orc.feq(p, phi)) + Rk)).max() < 1e-15
+
+
+def test_s0_irrelevant_in_scheme_a():
+    """Eq. 41 sets s0 = 0; in Scheme A m0 = m0eq, so any s0 gives the same step."""
+    spec = nonlinear_spec(9, (8, 8))
+    rng = np.random.default_rng(1)
+    phi0 = 0.5 + 0.05 * rng.standard_normal((8, 8))
+    outs = []
+    for s0 in (0.0, 0.7, 1.9):
+        spec["s"][0] = s0
+        p = orc.params_from_spec(spec)
+        outs.append(orc.run(p, phi0, 20)[0])
+    assert np.abs(outs[1] - outs[0]).max() < 1e-14 and np.abs(outs[2] - outs[0]).max() < 1e-14
+
+
+def test_scheme_a_uniform_field_is_ab2():
+    """Remark II, Scheme A: on a uniform field the method reduces to the
+    two-step Adams-Bashforth rule phi' = phi + 3/2 R(phi) - 1/2 R(phi_prev)
+    for dphi/dt = R(phi), started with R(t = -1) = R(t = 0)."""
+    spec = nonlinear_spec(9, (3, 3))
+    spec["rpoly"] = [0.0, 0.05, -0.05]
+    p = orc.params_from_spec(spec)
+    R = lambda x: 0.05 * x - 0.05 * x * x
+    phi, prev = 0.2, 0.2
+    f, pp = orc.init(p, np.full((3, 3), 0.2))
+    for _ in range(60):
+        orc.step(p, f, pp)
+        phi, prev = phi + 1.5 * R(phi) - 0.5 * R(prev), phi
+        got = orc.phi(p, f)
+        assert np.abs(got - phi).max() < 1e-14
+
+
+def test_uniform_fixed_point():
+    """A uniform field with R = 0 stays uniform and unchanged (nonlinear B, K, D)."""
+    spec = nonlinear_spec(19, (4, 4, 4), rpoly=[])
+    p = orc.params_from_spec(spec)
+    phi, _ = orc.run(p, np.full((4, 4, 4), 0.73), 10)
+    assert np.abs(phi - 0.73).max() < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# conservation and basis independence
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_conservation_periodic(q):
+    """Periodic, R = 0: sum phi is invariant (Eq. 10a plus streaming is a
+    permutation), for nonlinear B, K, D and a full K0."""
+    shape = (6, 5, 4) if q == 19 else (12, 10)
+    spec = nonlinear_spec(q, shape, rpoly=[])
+    p = orc.params_from_spec(spec)
+    rng = np.random.default_rng(2)
+    phi0 = 0.5 + 0.1 * rng.uniform(-1, 1, orc.field_shape(p))
+    phiT, _ = orc.run(p, phi0, 40)
+    assert abs(phiT.sum() - phi0.sum()) / phi0.sum() < 1e-13
+    assert np.abs(phiT - phi0).max() > 1e-3
+
+
+def test_conservation_with_source_scheme_a():
+    """Scheme A with R(phi): sum phi(t+1) = sum phi(t) + sum[3/2 R(t) - 1/2 R(t-1)]."""
+    spec = nonlinear_spec(9, (10, 8))
+    p = orc.params_from_spec(spec)
+    rng = np.random.default_rng(3)
+    phi0 = 0.5 + 0.1 * rng.uniform(-1, 1, (8, 10))
+    f, pp = orc.init(p, phi0)
+    R = lambda x: np.polyval(spec["rpoly"][::-1], x)
+    cur = phi0.copy()
+    prev = phi0.copy()
+    for _ in range(15):
+        orc.step(p, f, pp)
+        nxt = orc.phi(p, f)
+        want = cur.sum() + (1.5 * R(cur) - 0.5 * R(prev)).sum()
+        assert abs(nxt.sum() - want) < 1e-13 * abs(want)
+        prev, cur = cur, nxt
+
+
+def test_d3q19_basis_independence():
+    """With equal non-flux rates the D3Q19 result does not depend on the
+    choice of orthogonal basis (density and flux rows fixed)."""
+    spec = nonlinear_spec(19, (5, 4, 6), bc=["periodic", "periodic", "abb"],
+                          phi_wall=[[0, 0], [0, 0], [0.2, 0.7]])
+    spec["s"] = [0.0] + [1.3] * 18
+    rng = np.random.default_rng(4)
+    phi0 = 0.5 + 0.1 * rng.uniform(-1, 1, (6, 4, 5))
+    a = orc.run(orc.params_from_spec(spec, basis=0), phi0, 12)[0]
+    b = orc.run(orc.params_from_spec(spec, basis=1), phi0, 12)[0]
+    assert np.abs(a - b).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# exact solutions
+# ---------------------------------------------------------------------------
+
+def _channel(N, s1, s3, ux, phi0=0.0, phiL=1.0, bgk=False):
+    kap = (1 / s3 - 0.5) / 3
+    dphi = phiL - phi0
+    s = [s1] * 9
+    s[0] = 0.0
+    spec = dict(lattice=9, shape=(3, N), bc=["periodic", "abb", "periodic"],
+                phi_wall=[[0, 0], [phi0, phiL], [0, 0]], scheme="B", d=1.0, s=s,
+                b=[[0, ux], [0, 0]], dpoly=[0, 1], dten=np.eye(3).tolist(),
+                k0=(kap * np.eye(3)).tolist(), kpoly=[1.0], rpoly=[2 * kap * dphi / N ** 2])
+    p = orc.params_from_spec(spec)
+    f, pp = orc.init(p, np.full((N, 3), 0.5 * (phi0 + phiL)))
+    for _ in range(int(30 * N * N / kap) + 1000):
+        orc.step(p, f, pp, nthreads=1)
+    return orc.phi(p, f)[:, 0]
+
+
+@pytest.mark.parametrize("N,s1,s3,ux", [(4, 1.0, 0.6, 0.1), (4, 0.7, 1.9, 0.0), (8, 1.3, 0.9, 0.1)])
+def test_channel_abb_exact_discrete_solution(N, s1, s3, ux):
+    """Sec. 3.6: with anti-bounce-back walls the steady MRT channel solution is
+    phi_j = phi0 + dphi yb_j (2 - yb_j) + phi_s (Eq. 71, with the sign of the
+    quadratic term as in Eq. 70) and phi_s from Eq. 72b, to round-off."""
+    ph = _channel(N, s1, s3, ux)
+    yb = (np.arange(1, N + 1) - 0.5) / N
+    phis = 1.0 / (12 * N ** 2 * s1 * s3) * (s1 * s3 - 8 * (s1 + s3) + 16)
+    assert np.abs(ph - (yb * (2 - yb) + phis)).max() < 1e-12
+
+
+def test_channel_zero_slip_rates():
+    """Sec. 3.6: the BGK slip vanishes at s = 4(2 - sqrt 3) (the printed value),
+    and the MRT slip vanishes on s1 = 8(2 - s3)/(8 - s3) (Eq. 73 solved from
+    Eq. 72b; the printed Eq. 73 has the sign of (s3 - 2) flipped)."""
+    spec = json.load(open(GOLDEN))["bgk_zero_slip_rate"]
+    s = eval(spec["value"], {"sqrt": math.sqrt})
+    N = 4
+    yb = (np.arange(1, N + 1) - 0.5) / N
+    ph = _channel(N, s, s, 0.0)
+    assert np.abs(ph - yb * (2 - yb)).max() < 1e-12
+    s3 = 1.4
+    ph = _channel(N, 8 * (2 - s3) / (8 - s3), s3, 0.1)
+    assert np.abs(ph - yb * (2 - yb)).max() < 1e-12
+
+
+def _gaussian_closed_form(shape, centre, u, K, sigma0, t, images=2):
+    """Eq. 60 summed over periodic images: sigma = sigma0^2 I + 2 K t."""
+    dim = len(shape)
+    sig = sigma0 ** 2 * np.eye(dim) + 2 * np.asarray(K)[:dim, :dim] * t
+    si = np.linalg.inv(sig)
+    grids = np.meshgrid(*[np.arange(n, dtype=float) for n in shape], indexing="ij")
+    out = np.zeros(shape)
+    rng = range(-images, images + 1)
+    for img in np.array(np.meshgrid(*[list(rng)] * dim, indexing="ij")).reshape(dim, -1).T:
+        r = [grids[a] - centre[a] - u[a] * t - img[a] * shape[a] for a in range(dim)]
+        quad = sum(si[a, b] * r[a] * r[b] for a in range(dim) for b in range(dim))
+        out += np.exp(-0.5 * quad)
+    return out * sigma0 ** dim / math.sqrt(np.linalg.det(sig))
+
+
+def _gre(num, ana):
+    """Eq. 39."""
+    return np.abs(ana - num).sum() / np.abs(ana).sum()
+
+
+def _hill_run(n, K, u, sigma0, T, q=9, rates=1.0):
+    dim = 2 if q == 9 else 3
+    shape = (n,) * dim
+    k0 = np.zeros((3, 3))
+    k0[:dim, :dim] = K
+    bl = [[0.0, u[a]] for a in range(dim)]
+    s = [0.0] + [rates] * (q - 1)
+    spec = dict(lattice=q, shape=shape, bc=["periodic"] * 3, scheme="A", d=1.0, s=s, b=bl,
+                dpoly=[0, 1], dten=np.eye(3).tolist(), k0=k0.tolist(), kpoly=[1.0], rpoly=[])
+    p = orc.params_from_spec(spec)
+    centre = [n / 2.0] * dim
+    # oracle fields are [z][y][x] / [y][x]; closed form built in (x, y, z) index order
+    phi0 = _gaussian_closed_form(shape, centre, u, K, sigma0, 0.0).transpose()
+    phiT, _ = orc.run(p, phi0, T)
+    ana = _gaussian_closed_form(shape, centre, u, K, sigma0, float(T)).transpose()
+    return _gre(phiT, ana)
+
+
+def test_gaussian_hill_c1_accuracy_and_order():
+    """Eq. 58-60 (C1 physics): GRE against the image-summed closed form, and
+    second order under diffusive refinement (sigma0, u, T scaled; kappa fixed,
+    so the rates are fixed): Sec. 3.4 Fig. 11 slope 2."""
+    K = 0.01 * np.eye(2)
+    gres = []
+    for r in (1, 2, 4):
+        gres.append(_hill_run(32 * r, K, (0.05 / r, 0.02 / r), 3.0 * r, 125 * r * r))
+    order = [math.log2(gres[i] / gres[i + 1]) for i in range(2)]
+    assert gres[-1] < 2e-3
+    assert all(1.8 < o < 2.2 for o in order), (gres, order)
+
+
+def test_gaussian_hill_full_anisotropic_order():
+    """Eq. 60 with a full K (Sec. 3.4, third tensor of Eq. 63 scaled): second order."""
+    K = 0.01 * np.array([[1.0, 1.0], [1.0, 2.0]])
+    gres = [_hill_run(32 * r, K, (0.04 / r, -0.03 / r), 3.0 * r, 100 * r * r) for r in (1, 2, 4)]
+    order = [math.log2(gres[i] / gres[i + 1]) for i in range(2)]
+    assert all(1.7 < o < 2.3 for o in order), (gres, order)
+
+
+def test_gaussian_hill_d3q19_full_tensor():
+    """3-D Gaussian hill (Eq. 60 in three dimensions) with a full K on D3Q19:
+    small error and second order between two resolutions."""
+    K = np.array([[0.02, 0.005, -0.004], [0.005, 0.03, 0.006], [-0.004, 0.006, 0.025]])
+    gres = [_hill_run(12 * r, K, (0.03 / r, -0.02 / r, 0.01 / r), 2.0 * r, 30 * r * r, q=19) for r in (1, 2)]
+    order = math.log2(gres[0] / gres[1])
+    assert gres[1] < 1e-2 and 1.6 < order < 2.4, (gres, order)
+
+
+def test_sine_wave_scheme_b_source_order():
+    """Sec. 3.1 (Eq. 42-45), Scheme B with the time-dependent source of Eq. 43,
+    domain [0, 2]^2 periodic, u = (0.1, 0.1), kappa = 0.002: GRE against Eq. 45
+    falls at second order (Fig. 2).  Diffusive refinement: the lattice
+    diffusivity (and so every rate) is the same on every grid."""
+    kap, ux, uy, L = 0.002, 0.1, 0.1, 2.0
+    klat = 1.0 / 24.0
+    gres = []
+    for r in (1, 2, 4):
+        n = 32 * r
+        dx = L / n
+        dt = klat * dx * dx / kap
+        spec = dict(lattice=9, shape=(n, n), bc=["periodic"] * 3, scheme="B", d=1.0,
+                    s=[0.0] + [1.0] * 8, b=[[0.0, ux * dt / dx], [0.0, uy * dt / dx]],
+                    dpoly=[0, 1], dten=np.eye(3).tolist(),
+                    k0=(klat * np.eye(3)).tolist(), kpoly=[1.0], rpoly=[])
+        p = orc.params_from_spec(spec)
+        x = np.arange(n) * dx
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        g = 1 - 2 * math.pi ** 2 * kap
+
+        def src(step):
+            t = step * dt
+            return dt * math.exp(g * t) * (np.sin(math.pi * (X + Y)) + math.pi * (ux + uy) * np.cos(math.pi * (X + Y)))
+
+        nst = 10 * r * r
+        phiT, _ = orc.run(p, np.sin(math.pi * (X + Y)), nst, source=src)
+        gres.append(_gre(phiT, math.exp(g * nst * dt) * np.sin(math.pi * (X + Y))))
+    order = [math.log2(gres[i] / gres[i + 1]) for i in range(2)]
+    assert all(1.7 < o < 2.3 for o in order), (gres, order)
+
+
+def test_variable_diffusion_tensor_order():
+    """Sec. 3.5 (Eq. 64-68): K(x) = kappa diag(2 - sin 2pi x sin 2pi y, 1) per
+    node, source Eq. 66, Scheme B, periodic [0, 1]^2, u = 0.1, kappa = 1e-3
+    (Pe = 100): second-order convergence to Eq. 68 (Fig. 14), diffusive
+    refinement with a fixed lattice diffusivity scale."""
+    kap, u = 1e-3, 0.1
+    klat = 1.0 / 24.0
+    gres = []
+    for r in (1, 2, 4):
+        n = 24 * r
+        dx = 1.0 / n
+        dt = klat * dx * dx / kap
+        x = np.arange(n) * dx
+        X, Y = np.meshgrid(x, x, indexing="xy")
+        sxy = np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+        kf = np.zeros((n, n, 3, 3))
+        kf[..., 0, 0] = klat * (2 - sxy)
+        kf[..., 1, 1] = klat
+        spec = dict(lattice=9, shape=(n, n), bc=["periodic"] * 3, scheme="B", d=1.0,
+                    s=[0.0] + [1.0] * 8, b=[[0.0, u * dt / dx], [0.0, u * dt / dx]],
+                    dpoly=[0, 1], dten=np.eye(3).tolist(), k0=(klat * np.eye(3)).tolist(),
+                    kpoly=[1.0], rpoly=[])
+        p = orc.params_from_spec(spec)
+        g = 1 - 12 * np.pi ** 2 * kap
+        body = (sxy + 4 * kap * np.pi ** 2 * np.cos(4 * np.pi * X) * np.sin(2 * np.pi * Y) ** 2
+                + 2 * np.pi * (u * np.cos(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+                               + u * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)))
+        nst = 12 * r * r
+        phiT, _ = orc.run(p, sxy, nst, source=lambda s: dt * math.exp(g * s * dt) * body, kfield=kf)
+        gres.append(_gre(phiT, math.exp(g * nst * dt) * sxy))
+    order = [math.log2(gres[i] / gres[i + 1]) for i in range(2)]
+    assert all(1.7 < o < 2.3 for o in order), (gres, order)
+
+
+def test_mrt_more_stable_than_bgk():
+    """Sec. 3.6 (Eq. 75-76): Gaussian hill, D = K phi / kappa with
+    K = kappa [[1, 1], [1, 2]], u = (0.1, 0.1) and c = 1; at kappa = 1e-4 the
+    BGK model blows up while MRT with s = 0.6 stays bounded."""
+    n, dx = 64, 2.0 / 400
+    kl = 1e-4 * dx / dx ** 2
+    sj = 1.0 / (3 * kl + 0.5)
+    D = [[1.0, 1.0, 0.0], [1.0, 2.0, 0.0], [0.0, 0.0, 1.0]]
+    res = {}
+    for name, s in (("bgk", sj), ("mrt", 0.6)):
+        spec = dict(lattice=9, shape=(n, n), bc=["periodic"] * 3, scheme="A", d=1.0,
+                    s=[s] * 9, b=[[0.0, 0.1], [0.0, 0.1]], dpoly=[0, 1], dten=D,
+                    k0=(kl * np.eye(3)).tolist(), kpoly=[1.0], rpoly=[])
+        p = orc.params_from_spec(spec)
+        phi0 = W.gaussian_hill(n, 2.0)
+        phiT, _ = orc.run(p, phi0, 400)
+        res[name] = np.nanmax(np.abs(phiT)) if np.isfinite(phiT).all() else np.inf
+    assert res["mrt"] < 1.5
+    assert res["bgk"] > 1e3
+
+
+# ---------------------------------------------------------------------------
+# discrete adjoint (complex step) against finite differences
+# ---------------------------------------------------------------------------
+
+def _adjoint_problem(q=9):
+    spec = nonlinear_spec(q, (6, 5) if q == 9 else (4, 3, 5))
+    if q == 19:
+        spec["bc"] = ["periodic", "periodic", "abb"]
+        spec["phi_wall"] = [[0, 0], [0, 0], [0.1, 0.4]]
+    return spec
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_adjoint_one_step_dot_product(q):
+    """<w, J v> = <J^T w, v> for the full one-step map (f, pprev) -> (f', pprev'),
+    J v by central differences of the stepper, J^T w by the adjoint step."""
+    spec = _adjoint_problem(q)
+    p = orc.params_from_spec(spec)
+    N = orc.nodes(p)
+    rng = np.random.default_rng(5)
+    f0, pp0 = orc.init(p, 0.5 + 0.1 * rng.uniform(-1, 1, orc.field_shape(p)))
+    vf, vp = rng.standard_normal(f0.size), rng.standard_normal(N)
+    wf, wp = rng.standard_normal(f0.size), rng.standard_normal(N)
+    eps = 1e-6
+
+    def F(df, dp):
+        f, pp = f0 + df, pp0 + dp
+        orc.step(p, f, pp)
+        return f, pp
+
+    fp, pp_p = F(eps * vf, eps * vp)
+    fm, pp_m = F(-eps * vf, -eps * vp)
+    jv_f, jv_p = (fp - fm) / (2 * eps), (pp_p - pp_m) / (2 * eps)
+    lam, mu, _ = orc.adjoint_step(p, f0, pp0, wf, wp)
+    lhs = wf @ jv_f + wp @ jv_p
+    rhs = lam @ vf + mu @ vp
+    assert abs(lhs - rhs) < 1e-8 * abs(lhs)
+
+
+def test_adjoint_gradient_vs_finite_differences():
+    """dL/dphi0 and dL/dK0 of L = 1/2 sum (phi(T) - phi*)^2 after T steps,
+    against central differences of the forward oracle."""
+    spec = nonlinear_spec(9, (7, 6))
+    rng = np.random.default_rng(6)
+    phi0 = 0.5 + 0.1 * rng.uniform(-1, 1, (6, 7))
+    target = 0.5 + 0.1 * rng.uniform(-1, 1, (6, 7))
+    T = 12
+    p = orc.params_from_spec(spec)
+    phiT, gphi0, gk = orc.gradient(p, phi0, T, lambda ph: ph - target)
+
+    def loss(ph0, k0):
+        sp = dict(spec)
+        sp["k0"] = k0.tolist()
+        ph, _ = orc.run(orc.params_from_spec(sp), ph0, T)
+        return 0.5 * ((ph - target) ** 2).sum()
+
+    k0 = np.asarray(spec["k0"])
+    v = rng.standard_normal(phi0.shape)
+    h = 1e-6
+    fd = (loss(phi0 + h * v, k0) - loss(phi0 - h * v, k0)) / (2 * h)
+    assert abs(fd - (gphi0 * v).sum()) < 1e-7 * abs(fd)
+    for name, (a, b) in {"xx": (0, 0), "xy": (0, 1), "yy": (1, 1)}.items():
+        dk = np.zeros((3, 3))
+        dk[a, b] = dk[b, a] = 1.0
+        h = 1e-7
+        fd = (loss(phi0, k0 + h * dk) - loss(phi0, k0 - h * dk)) / (2 * h)
+        assert abs(fd - gk[name]) < 1e-6 * max(abs(fd), 1e-12), (name, fd, gk[name])
