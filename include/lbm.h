@@ -1,0 +1,194 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) MRT lattice Boltzmann sweep for the
+ * nonlinear anisotropic convection-diffusion equation with a source term
+ *
+ *     d_t phi + div B(phi) = div[K . (div D(phi))] + R            (Eq. 1)
+ *
+ * following the general multiple-relaxation-time model of Chai, Shi & Guo
+ * (Sec. 2.2, Eq. 2-10, 14-28; Remark II for the source schemes).
+ *
+ * Conventions
+ *  - Lattice units: c = dx = dt = 1, cs^2 = 1/3 (Eq. 5/6 and the text after
+ *    them).  A problem stated with other dx, dt is rewritten by the caller
+ *    (B dt/dx, K dt/dx^2, R dt).
+ *  - Every device pointer is owned by the caller (the library never allocates
+ *    or frees caller buffers); the context owns only its parameter tables and
+ *    a small device scratch area for flags and reduction partials.
+ *  - Calls are asynchronous on the caller's HIP stream (a hipStream_t passed
+ *    as void*, NULL = the default stream) unless stated otherwise.
+ *  - Every call returns LBM_OK (0) or a negative error code; lbm_last_error()
+ *    returns a thread-local message.  No exception crosses the ABI.
+ *  - Field layout seen by the caller (phi0, phi, targets, gradients): FP64,
+ *    C order [nz][ny][nx].  Distribution buffers are opaque (size from
+ *    lbm_state_bytes); internally they are structure-of-arrays planes, one
+ *    plane of nx*ny*nz values per lattice direction, in the storage type.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_E_INVALID -1      /* bad argument or parameter set               */
+#define LBM_E_UNSUPPORTED -2  /* valid for the method, not built on the GPU  */
+#define LBM_E_HIP -3          /* a HIP runtime call failed                   */
+#define LBM_E_DIVERGED -4     /* a non-finite phi was produced               */
+#define LBM_E_STATE -5        /* call out of order (e.g. step before init)   */
+
+/* ---- enumerations ------------------------------------------------------- */
+#define LBM_D2Q9 9            /* Eq. 5 */
+#define LBM_D3Q19 19          /* Eq. 6 */
+
+#define LBM_BC_PERIODIC 0
+#define LBM_BC_ABB 1          /* anti-bounce-back Dirichlet wall half a link
+                                 beyond the first / last node (Sec. 3.6)    */
+
+#define LBM_F64 0             /* distributions stored in FP64, FP64 math     */
+#define LBM_F32 1             /* stored as FP32 offsets f_k - w_k phi_ref,
+                                 FP32 math                                    */
+#define LBM_F16 2             /* stored as FP16 offsets, FP32 math            */
+
+#define LBM_SCHEME_A 0        /* Remark II, gamma = 0: explicit time difference
+                                 of the source, needs phi of the last step   */
+#define LBM_SCHEME_B 1        /* Remark II, gamma = 1 (GPU: only with R = 0,
+                                 where it coincides with Scheme A)           */
+
+#define LBM_FLAG_MOMENT_PATH 1 /* always use the moment-space collision even
+                                  when all non-flux rates are equal          */
+#define LBM_FLAG_NO_XCD_REMAP 2 /* launch blocks in plain order             */
+
+#define LBM_MAXP 9            /* polynomial coefficients per function        */
+
+/* Problem and model description (Eq. 1 coefficients, Eq. 3, Eq. 17).
+ *  B_a(phi)  = sum_p b[a][p] phi^p                       (convection, Eq. 1)
+ *  D(phi)    = (sum_p dpoly[p] phi^p) * dten             (Eq. 1)
+ *  K(phi)    = k0 * (sum_p kpoly[p] phi^p)               (diffusion tensor)
+ *  R(phi)    = sum_p rpoly[p] phi^p                      (source)
+ *  C(phi)    = integral_0^phi B' B'^T                    (Eq. 7, C(0) = 0)
+ *  Flux relaxation block A = (K / (d cs^2) + I/2)^-1      (Eq. 26), per node
+ *  when kpoly is not constant.  s[] holds the remaining diagonal rates in the
+ *  moment order of Eq. 15 (D2Q9: rho, e, eps, jx, qx, jy, qy, pxx, pxy) or of
+ *  the d'Humieres polynomial basis (D3Q19); entries of the flux rows are
+ *  ignored.  Only the upper-left 2x2 of k0/dten is used for D2Q9. */
+typedef struct lbm_desc {
+    int lattice;              /* LBM_D2Q9 or LBM_D3Q19                        */
+    int nx, ny, nz;           /* nodes per axis (nz = 1 for D2Q9)             */
+    int bc[3];                /* per axis; walls only on the last axis
+                                 (y for D2Q9, z for D3Q19)                    */
+    double phi_wall[3][2];    /* Dirichlet phi at the low / high wall          */
+    int precision;            /* LBM_F64 / LBM_F32 / LBM_F16                  */
+    double phi_ref;           /* offset reference of the stored distributions */
+    int scheme;               /* LBM_SCHEME_A / LBM_SCHEME_B                  */
+    double d;                 /* positive parameter of Eq. 3                  */
+    double s[19];             /* diagonal relaxation rates (Eq. 17)           */
+    double b[3][LBM_MAXP];
+    double dpoly[LBM_MAXP];
+    double dten[3][3];
+    double k0[3][3];
+    double kpoly[LBM_MAXP];
+    double rpoly[LBM_MAXP];
+    int flags;                /* LBM_FLAG_*                                    */
+} lbm_desc;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Validate a description and derive the model constants.  Rejects
+ * (LBM_E_INVALID): unknown lattice, sizes < 1 or more than 2^31 nodes,
+ * d <= 0, a used rate outside (0, 2), k0 not symmetric positive definite,
+ * dten not symmetric.  LBM_E_UNSUPPORTED: walls on an axis other than the
+ * last, Scheme B with a source.  Allocates a few KB of device scratch on the
+ * current device.  *out is set only on success. */
+int lbm_create(const lbm_desc *desc, lbm_ctx **out);
+
+/* Bytes of one distribution buffer (f_bytes) and of the phi-history buffer
+ * (p_bytes) that the caller must provide; both multiples of 256. */
+int lbm_state_bytes(const lbm_ctx *ctx, size_t *f_bytes, size_t *p_bytes);
+
+/* Bind two distribution buffers and the phi-history buffer, and initialise
+ * with the equilibrium of phi0 (Eq. 40; the history is set to phi0, the
+ * reading of the first Scheme-A step).  phi0_dev: FP64 [nz][ny][nx] on the
+ * device.  Buffers must be 256-byte aligned and of lbm_state_bytes sizes. */
+int lbm_init(lbm_ctx *ctx, const double *phi0_dev, void *f_a, void *f_b, void *p,
+             void *stream);
+
+/* Advance nsteps time steps (Eq. 2 with the Scheme-A source, anti-bounce-back
+ * walls), one fused stream-collide sweep per step.  Asynchronous unless a
+ * divergence check is due (lbm_set_check), in which case it synchronises the
+ * stream and returns LBM_E_DIVERGED when a non-finite phi appeared. */
+int lbm_step(lbm_ctx *ctx, int nsteps, void *stream);
+
+/* One sweep between explicit buffers: f_out <- sweep(f_in), p updated in
+ * place (Scheme A history).  f_in and f_out must differ.  Does not touch the
+ * bound buffers or the step counter. */
+int lbm_sweep(lbm_ctx *ctx, const void *f_in, void *f_out, void *p, void *stream);
+
+/* phi of the current state (Eq. 10a), FP64 [nz][ny][nx] into phi_dev. */
+int lbm_get_phi(lbm_ctx *ctx, double *phi_dev, void *stream);
+
+/* phi of an explicit distribution buffer (same layout as the bound ones). */
+int lbm_phi_of(lbm_ctx *ctx, const void *f, double *phi_dev, void *stream);
+
+/* The buffers that hold the current state and the number of steps taken. */
+int lbm_current(const lbm_ctx *ctx, void **f, void **p, long long *t);
+
+/* Exchange the roles of the two bound distribution buffers and set the step
+ * counter (used after the caller restored a state into the other buffer). */
+int lbm_set_current(lbm_ctx *ctx, int which, long long t);
+
+/* Divergence check every `every` steps inside lbm_step (0 = off). */
+int lbm_set_check(lbm_ctx *ctx, int every);
+
+/* Replace K0 (keeps every other parameter); same validation as lbm_create. */
+int lbm_set_k0(lbm_ctx *ctx, const double k0[9]);
+
+/* FP64 reductions over a phi field (synchronous).  out[0] = sum phi,
+ * out[1] = sum phi^2, out[2] = sum (phi - ref)^2, out[3] = sum ref^2,
+ * out[4] = min phi, out[5] = max phi, out[6] = number of non-finite values,
+ * out[7] = sum |phi - ref|.  ref_dev may be NULL (then ref = 0). */
+int lbm_reduce(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev, double out[8],
+               void *stream);
+
+/* ---- discrete adjoint (D2Q9, F64 and F32) -------------------------------- *
+ * Sweep s maps the state X_s = (f_s, p_s) to X_{s+1}: it gathers g_s from f_s,
+ * collides with history p_s and stores f_{s+1}; p_{s+1} = sum_k g_s,k.
+ * With L a function of phi(T) = sum_k g_T,k, the adjoint variables are
+ *   psi_s = dL/dg_s  (q values per node, same layout and size as f buffers,
+ *                      stored in the compute type: FP64 or FP32),
+ *   pi_s  = dL/dp_s  (FP64 [nz][ny][nx]).
+ * psi_s equals the gradient with respect to the pre-collision distributions
+ * of step s.  Gradients with respect to K0 accumulate into a per-context FP64
+ * accumulator (lbm_adjoint_grad_k0).  Not defined for FP16 storage. */
+
+/* psi_T from dL/dphi(T) (FP64 field): psi_T,k = gphi for every k, pi_T = 0;
+ * clears the K0 accumulator. */
+int lbm_adjoint_seed(lbm_ctx *ctx, const double *gphi_dev, void *psi, double *pi_out,
+                     void *stream);
+
+/* One reversed sweep: from the forward state (f_s, p_s) and (psi_{s+1},
+ * pi_{s+1}) compute (psi_s, pi_s) and add dL/dK0 of this sweep.  psi_next and
+ * psi_out must differ; pi may be updated in place (pi_out == pi_next). */
+int lbm_adjoint_step(lbm_ctx *ctx, const void *f_s, const void *p_s, const void *psi_next,
+                     const double *pi_next, void *psi_out, double *pi_out, void *stream);
+
+/* Adjoint of the initialisation (Eq. 40): dL/dphi0 = sum_k psi_0,k dfeq_k/dphi
+ * + pi_0, into gphi0_dev (FP64). */
+int lbm_adjoint_init(lbm_ctx *ctx, const double *phi0_dev, const void *psi0, const double *pi0,
+                     double *gphi0_dev, void *stream);
+
+/* Accumulated dL/dK0 (synchronous): out = (xx, xy, yy, xz, yz, zz), the
+ * symmetric entries each treated as one parameter. */
+int lbm_adjoint_grad_k0(lbm_ctx *ctx, double out[6], void *stream);
+
+void lbm_destroy(lbm_ctx *ctx);
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

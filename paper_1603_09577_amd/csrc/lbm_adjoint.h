@@ -1,0 +1,354 @@
+// Reversed (discrete adjoint) sweep of the D2Q9 stream-collide step.
+//
+// Forward sweep s at node x: g = gather(f_s) (offset form h), phi = phi_ref
+// + sum h, then (equal-rate or moment-space relaxation, Eq. 2/17/19) plus the
+// Scheme-A source 3/2 R_k(phi) - 1/2 R_k(p) with R_k = w_k (1 + 3 c.Btilde) R
+// and Btilde = (I - A/2) B' (Eq. 9, 28 with gamma = 0); the result is stored
+// at x and p(x) <- phi - phi_ref.
+//
+// Reverse: lambda_k(x) = dL/df_{s+1,k}(x) is psi_{s+1} read at the node that
+// gathers it, x + c_k (or, across a wall, -psi_{s+1,kbar}(x): the
+// anti-bounce-back read has coefficient -1).  The node map is then
+// differentiated by hand in reverse order: relaxation -> A block -> Btilde,
+// R -> equilibrium -> phi.  A depends on phi through K(phi) = K0 k(phi):
+// A = G^-1 with G = (3/d) K0 k(phi) + I/2, so the adjoint of G is
+// Gbar = -A Abar A, which also gives dL/dK0.
+#pragma once
+
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+template <int Q, typename TC>
+__device__ __forceinline__ void eq_derivative(const Coefs<TC> *__restrict__ cf, TC phi, TC *dfeq) {
+    // d feq_k / d phi = w_k [1 + 3 c.B' + 9/2 (E' : c c - tr E' / 3)],
+    // E' = C-bar'(phi) - I/3
+    using L = Lattice<Q>;
+    constexpr int D = L::dim;
+    TC Bp[3], E[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Bp[a] = (a < D) ? poly<kMaxP>(cf->bp[a], cf->nb, phi) : TC(0);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const bool used = (D == 3) || (i == 0 || i == 1 || i == 3);
+        E[i] = used ? poly<kMaxC>(cf->cbd[i], cf->ncb, phi) : TC(0);
+    }
+    E[0] -= TC(1.0 / 3.0); E[1] -= TC(1.0 / 3.0);
+    if (D == 3) E[2] -= TC(1.0 / 3.0);
+    const TC trE3 = (E[0] + E[1] + E[2]) * TC(1.0 / 3.0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int x = L::cx(k), y = L::cy(k), z = L::cz(k);
+        TC cB = TC(0), ccE = -trE3;
+        if (x) { cB += x * Bp[0]; ccE += E[0]; }
+        if (y) { cB += y * Bp[1]; ccE += E[1]; }
+        if (z) { cB += z * Bp[2]; ccE += E[2]; }
+        if (x && y) ccE += TC(2 * x * y) * E[3];
+        if (y && z) ccE += TC(2 * y * z) * E[4];
+        if (x && z) ccE += TC(2 * x * z) * E[5];
+        dfeq[k] = TC(L::w(k)) * (TC(1) + TC(3) * cB + TC(4.5) * ccE);
+    }
+}
+
+// Adjoint of A = G^-1 for a symmetric Abar (full storage Ab[a][b]):
+// Gbar = -A Abar A (symmetric), returned in symmetric slots.
+template <int DIM, typename TC>
+__device__ __forceinline__ void gbar_of(const TC *A, const TC Ab[3][3], TC *Gb) {
+    TC T[3][3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            TC acc = TC(0);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc += A[sym(a, c)] * TC(0.5) * (Ab[c][b] + Ab[b][c]);
+            T[a][b] = acc;
+        }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) Gb[i] = TC(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = a; b < DIM; ++b) {
+            TC acc = TC(0);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc += T[a][c] * A[sym(c, b)];
+            Gb[sym(a, b)] = -acc;
+        }
+}
+
+// Contribution of Gbar at a phi value to dL/dphi (when k varies) and to the
+// per-node K0 accumulator (symmetric parametrisation: off-diagonal entries
+// count twice).
+template <int DIM, bool KVAR, typename TC>
+__device__ __forceinline__ TC gbar_scatter(const Coefs<TC> *__restrict__ cf, TC phi, const TC *Gb, TC *gk) {
+    const TC kv = KVAR ? poly<kMaxP>(cf->kp, cf->nk, phi) : cf->kp[0];
+    // g0 = 3 K0 / d, so dG/dK0_ab = (3/d) k(phi); g0 / K0 = 3 / d is folded on the host
+#pragma unroll
+    for (int i = 0; i < 6; ++i) gk[i] += Gb[i] * kv * (i < 3 ? TC(1) : TC(2));
+    if (!KVAR) return TC(0);
+    const TC kd = poly<kMaxP>(cf->kdp, cf->nk, phi);
+    TC acc = TC(0);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc += Gb[i] * cf->g0[i] * (i < 3 ? TC(1) : TC(2));
+    return acc * kd;
+}
+
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL>
+__global__ void __launch_bounds__(kBlock)
+k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fs,
+          const typename HistType<TS>::T *__restrict__ ps, const TC *__restrict__ psi_next,
+          const double *pi_next, TC *__restrict__ psi_out, double *pi_out, double *__restrict__ gk_part) {
+    using L = Lattice<Q>;
+    constexpr int D = L::dim;
+    const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
+    TC gk[6] = {TC(0), TC(0), TC(0), TC(0), TC(0), TC(0)};
+    if (n < g.N) {
+        const NodeGeo ng = node_geometry<Q, WALL>(g, n);
+        // ---- forward recomputation ----
+        TC h[Q];
+        gather<Q, WALL>(g, cf, fs, ng, h);
+        TC phio = TC(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) phio += h[k];
+        const TC phi = cf->phi_ref + phio;
+        TC A[6];
+        ablock<D, KVAR>(cf, phi, A);
+        TC feq[Q], dlt[Q];
+        equilibrium<Q>(cf, phi, phio, feq);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) dlt[k] = h[k] - feq[k];
+
+        // ---- lambda = dL/d(out) by transposed streaming ----
+        TC lam[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            int off = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int c = L::c(k, a);
+                off += (c == 1) ? ng.op[a] : ((c == -1) ? ng.om[a] : 0);
+            }
+            const int cl = L::c(k, D - 1);
+            if (WALL && ((cl == 1 && ng.hi) || (cl == -1 && ng.lo)))
+                lam[k] = -psi_next[(uint64_t)L::opp(k) * g.plane + n];
+            else
+                lam[k] = psi_next[(uint64_t)k * g.plane + (uint32_t)((int)n + off)];
+        }
+
+        TC Ab[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Ab[a][b] = TC(0);
+        TC db[Q];   // adjoint of dlt = h - feq
+        if (EQR) {
+            const TC s = cf->srate;
+            TC jd[3], vb[3], jdb[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                TC acc = TC(0), accl = TC(0);
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    const int c = L::c(k, a);
+                    if (c) { acc += TC(c) * dlt[k]; accl += TC(c) * lam[k]; }
+                }
+                jd[a] = acc;
+                vb[a] = -accl;   // out = h - s dlt - c.v
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                TC acc = TC(0);
+#pragma unroll
+                for (int b = 0; b < D; ++b) acc += (A[sym(a, b)] - (a == b ? s : TC(0))) * vb[b];
+                jdb[a] = acc * TC(1.0 / L::jnorm);
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = 0; b < D; ++b) Ab[a][b] += vb[a] * jd[b] * TC(1.0 / L::jnorm);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                TC acc = -s * lam[k];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const int c = L::c(k, a);
+                    if (c) acc += TC(c) * jdb[a];
+                }
+                db[k] = acc;
+            }
+        } else {
+            // out = h - M^T N^-1 S M dlt: u = N^-1 M lambda, rbar = -u,
+            // mbar = S^T rbar, dbar = M^T mbar, Abar_ab += rbar_ja m_jb
+            TC m[Q], u[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                TC acc = TC(0), accl = TC(0);
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    const int mm = L::M(i, k);
+                    if (mm) { acc += TC(mm) * dlt[k]; accl += TC(mm) * lam[k]; }
+                }
+                m[i] = acc;
+                u[i] = accl * TC(1.0 / L::N(i));
+            }
+            TC mb[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) mb[i] = -cf->s[i] * u[i];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                TC acc = TC(0);
+#pragma unroll
+                for (int b = 0; b < D; ++b) acc -= A[sym(b, a)] * u[L::jrow[b]];
+                mb[L::jrow[a]] = acc;
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = 0; b < D; ++b) Ab[a][b] -= u[L::jrow[a]] * m[L::jrow[b]];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                TC acc = TC(0);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const int mm = L::M(i, k);
+                    if (mm) acc += TC(mm) * mb[i];
+                }
+                db[k] = acc;
+            }
+        }
+        // h enters directly (out = h - ...) and through dlt
+        TC hb[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) hb[k] = lam[k] + db[k];
+        // feq enters through dlt with a minus sign; feq depends on phi only
+        TC phib = TC(0);
+        {
+            TC dfe[Q];
+            eq_derivative<Q>(cf, phi, dfe);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) phib -= db[k] * dfe[k];
+        }
+
+        TC pb = TC(0);
+        if (SRC) {
+            TC Bt[3], R, Btp[3], Rp, Ap[6];
+            source_terms<D>(cf, phi, A, Bt, R);
+            const TC pp = cf->phi_ref + (TC)ps[n];
+            ablock<D, KVAR>(cf, pp, Ap);
+            source_terms<D>(cf, pp, Ap, Btp, Rp);
+            TC S1 = TC(0), T1[3] = {TC(0), TC(0), TC(0)};
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const TC wl = TC(L::w(k)) * lam[k];
+                S1 += wl;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const int c = L::c(k, a);
+                    if (c) T1[a] += TC(c) * wl;
+                }
+            }
+            // time level t: + 3/2 R (S1 + 3 T1.Bt);  level t-1: - 1/2 Rp (S1 + 3 T1.Btp)
+            TC tb = TC(0), tbp = TC(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) { tb += T1[a] * Bt[a]; tbp += T1[a] * Btp[a]; }
+            const TC Rb = TC(1.5) * (S1 + TC(3) * tb);
+            const TC Rpb = TC(-0.5) * (S1 + TC(3) * tbp);
+            TC Btb[3], Btpb[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) { Btb[a] = TC(4.5) * R * T1[a]; Btpb[a] = TC(-1.5) * Rp * T1[a]; }
+            // R(phi), R(p)
+            phib += Rb * poly<kMaxP>(cf->rp, cf->nr, phi);
+            pb += Rpb * poly<kMaxP>(cf->rp, cf->nr, pp);
+            // Btilde = B' - A B' / 2
+            TC Bp[3], Bpp[3], Bpq[3], Bppq[3];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                Bp[a] = poly<kMaxP>(cf->bp[a], cf->nb, phi);
+                Bpp[a] = poly<kMaxP>(cf->bpp[a], cf->nb, phi);
+                Bpq[a] = poly<kMaxP>(cf->bp[a], cf->nb, pp);
+                Bppq[a] = poly<kMaxP>(cf->bpp[a], cf->nb, pp);
+            }
+            TC Apb[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Apb[a][b] = TC(0);
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                TC acc = Btb[b], accp = Btpb[b];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    acc -= TC(0.5) * A[sym(a, b)] * Btb[a];
+                    accp -= TC(0.5) * Ap[sym(a, b)] * Btpb[a];
+                }
+                phib += acc * Bpp[b];
+                pb += accp * Bppq[b];
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    Ab[a][b] -= TC(0.5) * Btb[a] * Bp[b];
+                    Apb[a][b] -= TC(0.5) * Btpb[a] * Bpq[b];
+                }
+            TC Gbp[6];
+            gbar_of<D>(Ap, Apb, Gbp);
+            pb += gbar_scatter<D, KVAR>(cf, pp, Gbp, gk);
+        }
+        {
+            TC Gb[6];
+            gbar_of<D>(A, Ab, Gb);
+            phib += gbar_scatter<D, KVAR>(cf, phi, Gb, gk);
+        }
+        const TC pin = (TC)pi_next[n];   // p_{s+1} = phi - phi_ref
+#pragma unroll
+        for (int k = 0; k < Q; ++k) psi_out[(uint64_t)k * g.plane + n] = hb[k] + phib + pin;
+        pi_out[n] = (double)pb;
+    }
+    // K0 partials of this workgroup: (3/d) is applied here, FP64 accumulation
+    __shared__ double sh[6][kBlock / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double v = (double)gk[i] * (double)cf->k0scale;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) sh[i][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) v += sh[threadIdx.x][w];
+        gk_part[(size_t)blockIdx.x * 6 + threadIdx.x] = v;
+    }
+}
+
+// dL/dphi0 = sum_k psi_0,k dfeq_k/dphi(phi0) + pi_0   (adjoint of Eq. 40)
+template <int Q, typename TC>
+__global__ void __launch_bounds__(kBlock)
+k_adjoint_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict__ phi0,
+               const TC *__restrict__ psi0, const double *__restrict__ pi0, double *__restrict__ out) {
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    TC dfe[Q];
+    eq_derivative<Q>(cf, (TC)phi0[n], dfe);
+    double acc = pi0[n];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) acc += (double)(psi0[(uint64_t)k * g.plane + n] * dfe[k]);
+    out[n] = acc;
+}
+
+template <int Q, typename TC>
+__global__ void __launch_bounds__(kBlock)
+k_seed(const Geom g, const double *__restrict__ gphi, TC *__restrict__ psi, double *__restrict__ pi) {
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const TC v = (TC)gphi[n];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) psi[(uint64_t)k * g.plane + n] = v;
+    pi[n] = 0.0;
+}
+
+}  // namespace lbm

@@ -1,0 +1,518 @@
+// Host side of the C ABI declared in include/lbm.h: validation, derivation
+// of the model constants, context state and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+#include "lbm_lattice.h"
+
+namespace lbm {
+hipError_t launch_sweep_q9(const Dims &, const Geom &, const void *, const void *, void *, void *, int *,
+                           hipStream_t);
+hipError_t launch_sweep_q19(const Dims &, const Geom &, const void *, const void *, void *, void *, int *,
+                            hipStream_t);
+hipError_t launch_init_q9(const Dims &, const Geom &, const void *, const double *, void *, void *,
+                          hipStream_t);
+hipError_t launch_init_q19(const Dims &, const Geom &, const void *, const double *, void *, void *,
+                           hipStream_t);
+hipError_t launch_phi_q9(const Dims &, const Geom &, const void *, const void *, double *, hipStream_t);
+hipError_t launch_phi_q19(const Dims &, const Geom &, const void *, const void *, double *, hipStream_t);
+hipError_t launch_adjoint_q9(const Dims &, const Geom &, const void *, const void *, const void *,
+                             const void *, const double *, void *, double *, double *, hipStream_t);
+hipError_t launch_adjoint_init_q9(const Dims &, const Geom &, const void *, const double *, const void *,
+                                  const double *, double *, hipStream_t);
+hipError_t launch_seed_q9(const Dims &, const Geom &, const double *, void *, double *, hipStream_t);
+}  // namespace lbm
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return LBM_E_HIP;
+}
+
+constexpr int kRedParts = 1024;       // partial rows of the phi reductions
+constexpr int kAdjWidth = 6;          // K0 gradient entries per adjoint partial
+constexpr int kMaxAdjParts = 65536;   // workgroups covered by the adjoint partials
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_desc desc;
+    Dims dm;
+    Geom g;
+    size_t coef_bytes;
+    unsigned char host_coefs[sizeof(Coefs<double>)];
+    void *d_coefs = nullptr;
+    // device scratch: [flag int (256 B)] [reduce partials] [reduce out 8] [adj partials] [k0 acc 6]
+    void *d_scratch = nullptr;
+    int *d_flag = nullptr;
+    double *d_red_part = nullptr, *d_red_out = nullptr, *d_adj_part = nullptr, *d_k0acc = nullptr;
+    void *f[2] = {nullptr, nullptr};
+    void *p = nullptr;
+    int cur = 0;
+    long long t = 0;
+    int check_every = 0;
+    bool bound = false;
+};
+
+namespace {
+
+size_t storage_size(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+size_t hist_size(int prec) { return prec == 0 ? 8 : 4; }
+size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int top_count(const double *c, int n) {
+    int m = 0;
+    for (int i = 0; i < n; ++i)
+        if (c[i] != 0.0) m = i + 1;
+    return m;
+}
+
+bool spd(const double K[3][3], int dim) {
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b)
+            if (std::fabs(K[a][b] - K[b][a]) > 1e-14 * (std::fabs(K[a][b]) + std::fabs(K[b][a])) + 0.0)
+                return false;
+    const double m1 = K[0][0];
+    const double m2 = K[0][0] * K[1][1] - K[0][1] * K[1][0];
+    if (!(m1 > 0.0) || !(m2 > 0.0)) return false;
+    if (dim == 3) {
+        const double m3 = K[0][0] * (K[1][1] * K[2][2] - K[1][2] * K[2][1]) -
+                          K[0][1] * (K[1][0] * K[2][2] - K[1][2] * K[2][0]) +
+                          K[0][2] * (K[1][0] * K[2][1] - K[1][1] * K[2][0]);
+        if (!(m3 > 0.0)) return false;
+    }
+    return true;
+}
+
+// symmetric 2x2 / 3x3 inverse in FP64 (storage xx, yy, zz, xy, yz, xz)
+void sym_inv_host(const double *G, double *A, int dim) {
+    if (dim == 2) {
+        const double det = G[0] * G[1] - G[3] * G[3];
+        A[0] = G[1] / det; A[1] = G[0] / det; A[3] = -G[3] / det;
+        A[2] = A[4] = A[5] = 0.0;
+    } else {
+        const double c00 = G[1] * G[2] - G[4] * G[4], c11 = G[0] * G[2] - G[5] * G[5];
+        const double c22 = G[0] * G[1] - G[3] * G[3], c01 = G[5] * G[4] - G[3] * G[2];
+        const double c12 = G[3] * G[5] - G[0] * G[4], c02 = G[3] * G[4] - G[5] * G[1];
+        const double det = G[0] * c00 + G[3] * c01 + G[5] * c02;
+        A[0] = c00 / det; A[1] = c11 / det; A[2] = c22 / det;
+        A[3] = c01 / det; A[4] = c12 / det; A[5] = c02 / det;
+    }
+}
+
+struct HostModel {
+    double b[3][kMaxP], bp[3][kMaxP], bpp[3][kMaxP], cb[6][kMaxC], cbd[6][kMaxC], g0[6], kp[kMaxP],
+        kdp[kMaxP], a[6], r[kMaxP], rp[kMaxP], ew[2][19], s[19], phi_ref, srate, k0scale;
+    int nb, ncb, nk, nr;
+};
+
+double polyval(const double *c, int n, double x) {
+    double acc = 0.0;
+    for (int p = n - 1; p >= 0; --p) acc = acc * x + c[p];
+    return acc;
+}
+
+// All derived constants of a description (FP64).
+void derive(const lbm_desc &d, const Dims &dm, HostModel &m) {
+    std::memset(&m, 0, sizeof(m));
+    const int dim = dm.q == 9 ? 2 : 3;
+    static const int pa[6] = {0, 1, 2, 0, 1, 0}, pb[6] = {0, 1, 2, 1, 2, 2};
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p < kMaxP; ++p) m.b[a][p] = (a < dim) ? d.b[a][p] : 0.0;
+    m.nb = 1;
+    for (int a = 0; a < dim; ++a) m.nb = std::max(m.nb, top_count(d.b[a], kMaxP));
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p + 1 < kMaxP; ++p) m.bp[a][p] = (p + 1) * m.b[a][p + 1];
+    // Eq. 7 integrated term by term from C(0) = 0:
+    //   C_ab = sum_{p,r>=1} p r b_ap b_br / (p + r - 1) phi^(p + r - 1),
+    // plus d cs^2 D_ab(phi) to form C-bar (Eq. 16 notation).
+    for (int i = 0; i < 6; ++i) {
+        const int a = pa[i], b = pb[i];
+        if (a >= dim || b >= dim) continue;
+        for (int p = 1; p < kMaxP; ++p)
+            for (int r = 1; r < kMaxP; ++r) {
+                const double v = m.b[a][p] * m.b[b][r];
+                if (v != 0.0) m.cb[i][p + r - 1] += p * r * v / (p + r - 1);
+            }
+        for (int p = 0; p < kMaxP; ++p) m.cb[i][p] += d.d / 3.0 * d.dten[a][b] * d.dpoly[p];
+    }
+    m.ncb = 1;
+    for (int i = 0; i < 6; ++i) m.ncb = std::max(m.ncb, top_count(m.cb[i], kMaxC));
+    for (int i = 0; i < 6; ++i)
+        for (int p = 0; p + 1 < kMaxC; ++p) m.cbd[i][p] = (p + 1) * m.cb[i][p + 1];
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p + 1 < kMaxP; ++p) m.bpp[a][p] = (p + 1) * m.bp[a][p + 1];
+    m.k0scale = 3.0 / d.d;
+    // Eq. 26 with dt = 1, cs^2 = 1/3:  A^-1 = 3 K / d + I/2
+    for (int i = 0; i < 6; ++i) m.g0[i] = (pa[i] < dim && pb[i] < dim) ? 3.0 * d.k0[pa[i]][pb[i]] / d.d : 0.0;
+    for (int p = 0; p < kMaxP; ++p) m.kp[p] = d.kpoly[p];
+    for (int p = 0; p + 1 < kMaxP; ++p) m.kdp[p] = (p + 1) * d.kpoly[p + 1];
+    m.nk = std::max(1, top_count(d.kpoly, kMaxP));
+    {
+        double G[6];
+        for (int i = 0; i < 6; ++i) G[i] = m.g0[i] * d.kpoly[0] + (i < dim ? 0.5 : 0.0);
+        if (dim == 2) G[2] = 1.0;
+        sym_inv_host(G, m.a, dim);
+        if (dim == 2) m.a[2] = 0.0;
+    }
+    for (int p = 0; p < kMaxP; ++p) m.r[p] = d.rpoly[p];
+    for (int p = 0; p + 1 < kMaxP; ++p) m.rp[p] = (p + 1) * d.rpoly[p + 1];
+    m.nr = std::max(1, top_count(d.rpoly, kMaxP));
+    // anti-bounce-back constants: 2 (e+_k(phi_w) - w_k phi_ref), e+ the even
+    // part of Eq. 3 at the wall value
+    const int la = dim - 1;
+    for (int side = 0; side < 2; ++side) {
+        const double pw = d.phi_wall[la][side];
+        double Cb[6];
+        for (int i = 0; i < 6; ++i) Cb[i] = polyval(m.cb[i], kMaxC, pw);
+        double E[6];
+        for (int i = 0; i < 6; ++i) E[i] = Cb[i] - (i < dim ? pw / 3.0 : 0.0);
+        if (dim == 2) E[2] = 0.0;
+        const double tr3 = (E[0] + E[1] + E[2]) / 3.0;
+        for (int k = 0; k < dm.q; ++k) {
+            int c[3];
+            double w;
+            if (dm.q == 9) { c[0] = Lattice<9>::cx(k); c[1] = Lattice<9>::cy(k); c[2] = 0; w = Lattice<9>::w(k); }
+            else { c[0] = Lattice<19>::cx(k); c[1] = Lattice<19>::cy(k); c[2] = Lattice<19>::cz(k); w = Lattice<19>::w(k); }
+            double cc = -tr3;
+            for (int a = 0; a < 3; ++a) cc += c[a] * c[a] * E[a];
+            cc += 2.0 * (c[0] * c[1] * E[3] + c[1] * c[2] * E[4] + c[0] * c[2] * E[5]);
+            const double ep = w * (pw + 4.5 * cc);
+            m.ew[side][k] = 2.0 * (ep - w * d.phi_ref);
+        }
+    }
+    for (int i = 0; i < 19; ++i) m.s[i] = (i < dm.q) ? d.s[i] : 0.0;
+    m.srate = d.s[1];
+    m.phi_ref = d.phi_ref;
+}
+
+template <typename TC>
+void pack(const HostModel &m, Coefs<TC> &c) {
+    std::memset(&c, 0, sizeof(c));
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p < kMaxP; ++p) {
+            c.b[a][p] = (TC)m.b[a][p]; c.bp[a][p] = (TC)m.bp[a][p]; c.bpp[a][p] = (TC)m.bpp[a][p];
+        }
+    for (int i = 0; i < 6; ++i)
+        for (int p = 0; p < kMaxC; ++p) { c.cb[i][p] = (TC)m.cb[i][p]; c.cbd[i][p] = (TC)m.cbd[i][p]; }
+    for (int i = 0; i < 6; ++i) { c.g0[i] = (TC)m.g0[i]; c.a[i] = (TC)m.a[i]; }
+    for (int p = 0; p < kMaxP; ++p) {
+        c.kp[p] = (TC)m.kp[p]; c.kdp[p] = (TC)m.kdp[p]; c.r[p] = (TC)m.r[p]; c.rp[p] = (TC)m.rp[p];
+    }
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < 19; ++k) c.ew[s][k] = (TC)m.ew[s][k];
+    for (int i = 0; i < 19; ++i) c.s[i] = (TC)m.s[i];
+    c.phi_ref = (TC)m.phi_ref;
+    c.srate = (TC)m.srate;
+    c.k0scale = (TC)m.k0scale;
+    c.nb = m.nb; c.ncb = m.ncb; c.nk = m.nk; c.nr = m.nr;
+}
+
+int validate(const lbm_desc *d, Dims &dm) {
+    if (!d) return fail(LBM_E_INVALID, "null description");
+    if (d->lattice != LBM_D2Q9 && d->lattice != LBM_D3Q19) return fail(LBM_E_INVALID, "lattice must be 9 or 19");
+    const int dim = d->lattice == LBM_D2Q9 ? 2 : 3;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(LBM_E_INVALID, "grid sizes must be >= 1");
+    if (dim == 2 && d->nz != 1) return fail(LBM_E_INVALID, "D2Q9 needs nz = 1");
+    const double nn = (double)d->nx * d->ny * d->nz;
+    if (nn >= 2147483648.0) return fail(LBM_E_INVALID, "more than 2^31 nodes");
+    if (d->precision < LBM_F64 || d->precision > LBM_F16) return fail(LBM_E_INVALID, "unknown precision");
+    if (!(d->d > 0.0) || !std::isfinite(d->d)) return fail(LBM_E_INVALID, "d must be positive");
+    if (d->scheme != LBM_SCHEME_A && d->scheme != LBM_SCHEME_B) return fail(LBM_E_INVALID, "unknown scheme");
+    for (int a = 0; a < 3; ++a)
+        if (d->bc[a] != LBM_BC_PERIODIC && d->bc[a] != LBM_BC_ABB) return fail(LBM_E_INVALID, "unknown boundary");
+    for (int a = 0; a < dim - 1; ++a)
+        if (d->bc[a] != LBM_BC_PERIODIC) return fail(LBM_E_UNSUPPORTED, "walls are supported on the last axis only");
+    const bool wall = d->bc[dim - 1] == LBM_BC_ABB;
+    if (!spd(d->k0, dim)) return fail(LBM_E_INVALID, "k0 must be symmetric positive definite");
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b)
+            if (d->dten[a][b] != d->dten[b][a]) return fail(LBM_E_INVALID, "dten must be symmetric");
+    const int q = d->lattice;
+    const int j0 = 3, j1 = 5, j2 = (q == 19) ? 7 : -1;
+    bool eq = true;
+    double s_common = -1.0;
+    for (int i = 1; i < q; ++i) {
+        if (i == j0 || i == j1 || i == j2) continue;
+        if (!(d->s[i] > 0.0 && d->s[i] < 2.0)) return fail(LBM_E_INVALID, "relaxation rates must lie in (0, 2)");
+        if (s_common < 0.0) s_common = d->s[i];
+        else if (d->s[i] != s_common) eq = false;
+    }
+    if (!(d->s[0] >= 0.0 && d->s[0] < 2.0)) return fail(LBM_E_INVALID, "s0 must lie in [0, 2)");
+    bool src = false, kvar = false;
+    for (int p = 0; p < LBM_MAXP; ++p) {
+        if (!std::isfinite(d->rpoly[p]) || !std::isfinite(d->kpoly[p]) || !std::isfinite(d->dpoly[p]))
+            return fail(LBM_E_INVALID, "non-finite polynomial coefficient");
+        if (d->rpoly[p] != 0.0) src = true;
+        if (p > 0 && d->kpoly[p] != 0.0) kvar = true;
+    }
+    if (!(d->kpoly[0] > 0.0)) return fail(LBM_E_INVALID, "kpoly[0] must be positive (K(0) positive definite)");
+    if (d->scheme == LBM_SCHEME_B && src)
+        return fail(LBM_E_UNSUPPORTED, "Scheme B with a source is not built on the GPU");
+    dm.q = q;
+    dm.prec = d->precision;
+    dm.eqr = eq && !(d->flags & LBM_FLAG_MOMENT_PATH);
+    dm.src = src;
+    dm.kvar = kvar;
+    dm.wall = wall;
+    return LBM_OK;
+}
+
+int upload_coefs(lbm_ctx *c) {
+    HostModel m;
+    derive(c->desc, c->dm, m);
+    if (c->dm.prec == 0) {
+        Coefs<double> cf;
+        pack(m, cf);
+        std::memcpy(c->host_coefs, &cf, sizeof(cf));
+        c->coef_bytes = sizeof(cf);
+    } else {
+        Coefs<float> cf;
+        pack(m, cf);
+        std::memcpy(c->host_coefs, &cf, sizeof(cf));
+        c->coef_bytes = sizeof(cf);
+    }
+    hipError_t e = hipMemcpy(c->d_coefs, c->host_coefs, c->coef_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(coefficients)");
+    return LBM_OK;
+}
+
+hipError_t sweep(lbm_ctx *c, const void *fin, void *fout, void *p, hipStream_t st) {
+    return c->dm.q == 9 ? launch_sweep_q9(c->dm, c->g, c->d_coefs, fin, fout, p, c->d_flag, st)
+                        : launch_sweep_q19(c->dm, c->g, c->d_coefs, fin, fout, p, c->d_flag, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
+    if (!out) return fail(LBM_E_INVALID, "null output pointer");
+    Dims dm;
+    int rc = validate(desc, dm);
+    if (rc != LBM_OK) return rc;
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_E_INVALID, "out of host memory");
+    c->desc = *desc;
+    c->dm = dm;
+    Geom &g = c->g;
+    g.nx = desc->nx; g.ny = desc->ny; g.nz = desc->nz;
+    g.N = (uint32_t)((size_t)desc->nx * desc->ny * desc->nz);
+    g.plane = g.N;
+    g.fx.set(g.nx);
+    g.fxy.set(g.nx * g.ny);
+    g.nblocks = (g.N + kBlock - 1) / kBlock;
+    g.remap = (desc->flags & LBM_FLAG_NO_XCD_REMAP) ? 0 : 1;
+    hipError_t e = hipMalloc(&c->d_coefs, sizeof(Coefs<double>));
+    if (e != hipSuccess) { delete c; return hip_fail(e, "hipMalloc(coefficients)"); }
+    const size_t scratch = 256 + sizeof(double) * (size_t)(kRedParts * 8 + 8 + kMaxAdjParts * kAdjWidth + 8);
+    e = hipMalloc(&c->d_scratch, scratch);
+    if (e != hipSuccess) { (void)hipFree(c->d_coefs); delete c; return hip_fail(e, "hipMalloc(scratch)"); }
+    char *base = (char *)c->d_scratch;
+    c->d_flag = (int *)base;
+    c->d_red_part = (double *)(base + 256);
+    c->d_red_out = c->d_red_part + kRedParts * 8;
+    c->d_adj_part = c->d_red_out + 8;
+    c->d_k0acc = c->d_adj_part + (size_t)kMaxAdjParts * kAdjWidth;
+    e = hipMemset(c->d_scratch, 0, scratch);
+    if (e != hipSuccess) { lbm_destroy(c); return hip_fail(e, "hipMemset(scratch)"); }
+    rc = upload_coefs(c);
+    if (rc != LBM_OK) { lbm_destroy(c); return rc; }
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    if (c->d_coefs) (void)hipFree(c->d_coefs);
+    if (c->d_scratch) (void)hipFree(c->d_scratch);
+    delete c;
+}
+
+int lbm_state_bytes(const lbm_ctx *c, size_t *f_bytes, size_t *p_bytes) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (f_bytes) *f_bytes = round256((size_t)c->dm.q * c->g.plane * storage_size(c->dm.prec));
+    if (p_bytes) *p_bytes = round256((size_t)c->g.N * hist_size(c->dm.prec));
+    return LBM_OK;
+}
+
+int lbm_init(lbm_ctx *c, const double *phi0, void *f_a, void *f_b, void *p, void *stream) {
+    if (!c || !phi0 || !f_a || !f_b || !p) return fail(LBM_E_INVALID, "null argument");
+    if (f_a == f_b) return fail(LBM_E_INVALID, "the two distribution buffers must differ");
+    if (((uintptr_t)f_a | (uintptr_t)f_b | (uintptr_t)p) & 255) return fail(LBM_E_INVALID, "buffers must be 256-byte aligned");
+    c->f[0] = f_a; c->f[1] = f_b; c->p = p;
+    c->cur = 0; c->t = 0; c->bound = true;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = (c->dm.q == 9) ? launch_init_q9(c->dm, c->g, c->d_coefs, phi0, f_a, p, st)
+                                  : launch_init_q19(c->dm, c->g, c->d_coefs, phi0, f_a, p, st);
+    if (e != hipSuccess) return hip_fail(e, "init kernel");
+    e = hipMemsetAsync(c->d_flag, 0, sizeof(int), st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(flag)");
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int nsteps, void *stream) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (!c->bound) return fail(LBM_E_STATE, "lbm_init has not been called");
+    if (nsteps < 0) return fail(LBM_E_INVALID, "negative step count");
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < nsteps; ++i) {
+        hipError_t e = sweep(c, c->f[c->cur], c->f[c->cur ^ 1], c->p, st);
+        if (e != hipSuccess) return hip_fail(e, "sweep kernel");
+        c->cur ^= 1;
+        ++c->t;
+        if (c->check_every > 0 && c->t % c->check_every == 0) {
+            int flag = 0;
+            e = hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "divergence check");
+            if (flag) {
+                char buf[96];
+                std::snprintf(buf, sizeof(buf), "non-finite phi by step %lld", c->t);
+                return fail(LBM_E_DIVERGED, buf);
+            }
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_sweep(lbm_ctx *c, const void *f_in, void *f_out, void *p, void *stream) {
+    if (!c || !f_in || !f_out || !p) return fail(LBM_E_INVALID, "null argument");
+    if (f_in == f_out) return fail(LBM_E_INVALID, "f_in and f_out must differ");
+    hipError_t e = sweep(c, f_in, f_out, p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sweep kernel");
+    return LBM_OK;
+}
+
+int lbm_phi_of(lbm_ctx *c, const void *f, double *phi, void *stream) {
+    if (!c || !f || !phi) return fail(LBM_E_INVALID, "null argument");
+    hipError_t e = (c->dm.q == 9) ? launch_phi_q9(c->dm, c->g, c->d_coefs, f, phi, (hipStream_t)stream)
+                                  : launch_phi_q19(c->dm, c->g, c->d_coefs, f, phi, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "phi kernel");
+    return LBM_OK;
+}
+
+int lbm_get_phi(lbm_ctx *c, double *phi, void *stream) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (!c->bound) return fail(LBM_E_STATE, "lbm_init has not been called");
+    return lbm_phi_of(c, c->f[c->cur], phi, stream);
+}
+
+int lbm_current(const lbm_ctx *c, void **f, void **p, long long *t) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (!c->bound) return fail(LBM_E_STATE, "lbm_init has not been called");
+    if (f) *f = c->f[c->cur];
+    if (p) *p = c->p;
+    if (t) *t = c->t;
+    return LBM_OK;
+}
+
+int lbm_set_current(lbm_ctx *c, int which, long long t) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (!c->bound) return fail(LBM_E_STATE, "lbm_init has not been called");
+    if (which != 0 && which != 1) return fail(LBM_E_INVALID, "which must be 0 or 1");
+    c->cur = which;
+    c->t = t;
+    return LBM_OK;
+}
+
+int lbm_set_check(lbm_ctx *c, int every) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (every < 0) return fail(LBM_E_INVALID, "negative check interval");
+    c->check_every = every;
+    return LBM_OK;
+}
+
+int lbm_set_k0(lbm_ctx *c, const double k0[9]) {
+    if (!c || !k0) return fail(LBM_E_INVALID, "null argument");
+    lbm_desc d = c->desc;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) d.k0[a][b] = k0[a * 3 + b];
+    Dims dm;
+    int rc = validate(&d, dm);
+    if (rc != LBM_OK) return rc;
+    c->desc = d;
+    return upload_coefs(c);
+}
+
+int lbm_reduce(lbm_ctx *c, const double *phi, const double *ref, double out[8], void *stream) {
+    if (!c || !phi || !out) return fail(LBM_E_INVALID, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    int parts = (int)std::min<uint32_t>(kRedParts, (c->g.N + kBlock - 1) / kBlock);
+    if (parts < 1) parts = 1;
+    hipError_t e = launch_reduce(phi, ref, c->g.N, c->d_red_part, parts, c->d_red_out, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, c->d_red_out, 8 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "reduction");
+    return LBM_OK;
+}
+
+int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void *stream) {
+    if (!c || !gphi || !psi || !pi) return fail(LBM_E_INVALID, "null argument");
+    if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
+    if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_seed_q9(c->dm, c->g, gphi, psi, pi, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_k0acc, 0, 8 * sizeof(double), st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint seed");
+    return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *psi_next,
+                     const double *pi_next, void *psi_out, double *pi_out, void *stream) {
+    if (!c || !f_s || !p_s || !psi_next || !pi_next || !psi_out || !pi_out)
+        return fail(LBM_E_INVALID, "null argument");
+    if (psi_next == psi_out) return fail(LBM_E_INVALID, "psi_next and psi_out must differ");
+    if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
+    if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_adjoint_q9(c->dm, c->g, c->d_coefs, f_s, p_s, psi_next, pi_next, psi_out, pi_out,
+                                     c->d_adj_part, st);
+    if (e == hipSuccess) e = launch_sum_partials(c->d_adj_part, (int)c->g.nblocks, kAdjWidth, c->d_k0acc, st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel");
+    return LBM_OK;
+}
+
+int lbm_adjoint_init(lbm_ctx *c, const double *phi0, const void *psi0, const double *pi0, double *gphi0,
+                     void *stream) {
+    if (!c || !phi0 || !psi0 || !pi0 || !gphi0) return fail(LBM_E_INVALID, "null argument");
+    if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
+    if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    hipError_t e = launch_adjoint_init_q9(c->dm, c->g, c->d_coefs, phi0, psi0, pi0, gphi0, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint init kernel");
+    return LBM_OK;
+}
+
+int lbm_adjoint_grad_k0(lbm_ctx *c, double out[6], void *stream) {
+    if (!c || !out) return fail(LBM_E_INVALID, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    double acc[6];
+    hipError_t e = hipMemcpyAsync(acc, c->d_k0acc, 6 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint gradient copy");
+    // kernel order (xx, yy, zz, xy, yz, xz) -> ABI order (xx, xy, yy, xz, yz, zz)
+    out[0] = acc[0]; out[1] = acc[3]; out[2] = acc[1]; out[3] = acc[5]; out[4] = acc[4]; out[5] = acc[2];
+    return LBM_OK;
+}
+
+}  // extern "C"

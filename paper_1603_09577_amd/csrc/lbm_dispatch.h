@@ -1,0 +1,119 @@
+// Template dispatch of the kernels of one lattice; included by exactly one
+// translation unit per lattice (sweep_d2q9.hip, sweep_d3q19.hip) with
+// LBM_Q defined.
+#pragma once
+
+#include "lbm_kernels.h"
+#include "lbm_adjoint.h"
+
+namespace lbm {
+
+template <int Q, typename TS, typename TC>
+hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                       void *p, int *flag, hipStream_t st) {
+    using TP = typename HistType<TS>::T;
+    const auto *cf = (const Coefs<TC> *)coefs;
+    const auto *fi = (const TS *)fin;
+    auto *fo = (TS *)fout;
+    auto *pp = (TP *)p;
+    const dim3 grid(g.nblocks), block(kBlock);
+    const int code = (dm.eqr ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
+#define LBM_SWEEP(E, S, K, W)                                                                          \
+    case (E * 8 + S * 4 + K * 2 + W):                                                                  \
+        hipLaunchKernelGGL((k_sweep<Q, TS, TC, E, S, K, W>), grid, block, 0, st, g, cf, fi, fo, pp, flag); \
+        break;
+    switch (code) {
+        LBM_SWEEP(0, 0, 0, 0) LBM_SWEEP(0, 0, 0, 1) LBM_SWEEP(0, 0, 1, 0) LBM_SWEEP(0, 0, 1, 1)
+        LBM_SWEEP(0, 1, 0, 0) LBM_SWEEP(0, 1, 0, 1) LBM_SWEEP(0, 1, 1, 0) LBM_SWEEP(0, 1, 1, 1)
+        LBM_SWEEP(1, 0, 0, 0) LBM_SWEEP(1, 0, 0, 1) LBM_SWEEP(1, 0, 1, 0) LBM_SWEEP(1, 0, 1, 1)
+        LBM_SWEEP(1, 1, 0, 0) LBM_SWEEP(1, 1, 0, 1) LBM_SWEEP(1, 1, 1, 0) LBM_SWEEP(1, 1, 1, 1)
+        default: return hipErrorInvalidValue;
+    }
+#undef LBM_SWEEP
+    return hipGetLastError();
+}
+
+template <int Q, typename TS, typename TC>
+hipError_t init_typed(const Dims &dm, const Geom &g, const void *coefs, const double *phi0, void *f,
+                      void *p, hipStream_t st) {
+    using TP = typename HistType<TS>::T;
+    const auto *cf = (const Coefs<TC> *)coefs;
+    const dim3 grid(g.nblocks), block(kBlock);
+    if (dm.wall)
+        hipLaunchKernelGGL((k_init<Q, TS, TC, true>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
+    else
+        hipLaunchKernelGGL((k_init<Q, TS, TC, false>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
+    return hipGetLastError();
+}
+
+template <int Q, typename TS, typename TC>
+hipError_t phi_typed(const Dims &dm, const Geom &g, const void *coefs, const void *f, double *phi,
+                     hipStream_t st) {
+    const auto *cf = (const Coefs<TC> *)coefs;
+    const dim3 grid(g.nblocks), block(kBlock);
+    if (dm.wall)
+        hipLaunchKernelGGL((k_phi<Q, TS, TC, true>), grid, block, 0, st, g, cf, (const TS *)f, phi);
+    else
+        hipLaunchKernelGGL((k_phi<Q, TS, TC, false>), grid, block, 0, st, g, cf, (const TS *)f, phi);
+    return hipGetLastError();
+}
+
+template <int Q, typename TS, typename TC>
+hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const void *f, const void *p,
+                         const void *psi_next, const double *pi_next, void *psi_out, double *pi_out,
+                         double *gk_part, hipStream_t st) {
+    using TP = typename HistType<TS>::T;
+    const auto *cf = (const Coefs<TC> *)coefs;
+    const auto *fs = (const TS *)f;
+    const auto *ps = (const TP *)p;
+    const auto *pn = (const TC *)psi_next;
+    auto *po = (TC *)psi_out;
+    const dim3 grid(g.nblocks), block(kBlock);
+    const int code = (dm.eqr ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
+#define LBM_ADJ(E, S, K, W)                                                                           \
+    case (E * 8 + S * 4 + K * 2 + W):                                                                 \
+        hipLaunchKernelGGL((k_adjoint<Q, TS, TC, E, S, K, W>), grid, block, 0, st, g, cf, fs, ps, pn, \
+                           pi_next, po, pi_out, gk_part);                                             \
+        break;
+    switch (code) {
+        LBM_ADJ(0, 0, 0, 0) LBM_ADJ(0, 0, 0, 1) LBM_ADJ(0, 0, 1, 0) LBM_ADJ(0, 0, 1, 1)
+        LBM_ADJ(0, 1, 0, 0) LBM_ADJ(0, 1, 0, 1) LBM_ADJ(0, 1, 1, 0) LBM_ADJ(0, 1, 1, 1)
+        LBM_ADJ(1, 0, 0, 0) LBM_ADJ(1, 0, 0, 1) LBM_ADJ(1, 0, 1, 0) LBM_ADJ(1, 0, 1, 1)
+        LBM_ADJ(1, 1, 0, 0) LBM_ADJ(1, 1, 0, 1) LBM_ADJ(1, 1, 1, 0) LBM_ADJ(1, 1, 1, 1)
+        default: return hipErrorInvalidValue;
+    }
+#undef LBM_ADJ
+    return hipGetLastError();
+}
+
+template <int Q, typename TS, typename TC>
+hipError_t adjoint_init_typed(const Dims &, const Geom &g, const void *coefs, const double *phi0,
+                              const void *psi0, const double *pi0, double *out, hipStream_t st) {
+    hipLaunchKernelGGL((k_adjoint_init<Q, TC>), dim3(g.nblocks), dim3(kBlock), 0, st, g,
+                       (const Coefs<TC> *)coefs, phi0, (const TC *)psi0, pi0, out);
+    return hipGetLastError();
+}
+
+template <int Q, typename TS, typename TC>
+hipError_t seed_typed(const Dims &, const Geom &g, const double *gphi, void *psi, double *pi, hipStream_t st) {
+    hipLaunchKernelGGL((k_seed<Q, TC>), dim3(g.nblocks), dim3(kBlock), 0, st, g, gphi, (TC *)psi, pi);
+    return hipGetLastError();
+}
+
+// FP64 and FP32 storage only (no adjoint for FP16 storage)
+#define LBM_BY_PREC_ADJ(fn, ...)                                                   \
+    switch (dm.prec) {                                                             \
+        case 0: return fn<LBM_Q, double, double>(__VA_ARGS__);                     \
+        case 1: return fn<LBM_Q, float, float>(__VA_ARGS__);                       \
+        default: return hipErrorNotSupported;                                      \
+    }
+
+#define LBM_BY_PREC(fn, ...)                                                       \
+    switch (dm.prec) {                                                             \
+        case 0: return fn<LBM_Q, double, double>(__VA_ARGS__);                     \
+        case 1: return fn<LBM_Q, float, float>(__VA_ARGS__);                        \
+        case 2: return fn<LBM_Q, _Float16, float>(__VA_ARGS__);                     \
+        default: return hipErrorInvalidValue;                                      \
+    }
+
+}  // namespace lbm

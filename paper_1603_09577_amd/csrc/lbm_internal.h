@@ -1,0 +1,94 @@
+// Internal types shared by the host API and the kernel translation units of
+// liblbm.so.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kBlock = 256;     // threads per workgroup (4 wave64)
+constexpr int kMaxP = 9;        // coefficients of B, D, K, R polynomials
+constexpr int kMaxC = 16;       // coefficients of the C-bar polynomials
+constexpr int kNumXcd = 8;      // accelerator complex dies on MI355X
+
+// n / d for n < 2^31 via one high multiply (Granlund-Montgomery).
+struct FastDiv {
+    uint32_t d, m, s;
+    void set(uint32_t div) {
+        d = div;
+        if (div <= 1) { m = 0; s = 0; return; }
+        uint32_t sh = 0;
+        while ((1ull << sh) < div) ++sh;
+        s = sh;
+        m = (uint32_t)(((1ull << (31 + sh)) / div) + 1);
+    }
+    __device__ __forceinline__ uint32_t div(uint32_t n) const {
+        return d == 1 ? n : (__umulhi(n, m) >> (s - 1));
+    }
+};
+
+// Grid geometry of one instance.
+struct Geom {
+    uint32_t nx, ny, nz, N;
+    uint64_t plane;       // elements between consecutive direction planes
+    FastDiv fx, fxy;      // division by nx and by nx*ny
+    uint32_t nblocks;     // workgroups of one sweep
+    int remap;            // XCD-aware block order
+};
+
+// Per-instance model constants in the compute type.  Symmetric tensors use
+// the order (xx, yy, zz, xy, yz, xz).
+template <typename TC>
+struct Coefs {
+    TC b[3][kMaxP];       // B_a(phi)
+    TC bp[3][kMaxP];      // B'_a(phi)
+    TC cb[6][kMaxC];      // C-bar = C + d cs^2 D  (Eq. 16 notation)
+    TC cbd[6][kMaxC];     // C-bar'(phi)
+    TC bpp[3][kMaxP];     // B''(phi)
+    TC g0[6];             // 3 K0 / d : A^-1 = g0 k(phi) + I/2   (Eq. 26)
+    TC kp[kMaxP];         // k(phi)
+    TC kdp[kMaxP];        // k'(phi)
+    TC a[6];              // A when k is constant
+    TC r[kMaxP];          // R(phi)
+    TC rp[kMaxP];         // R'(phi)
+    TC ew[2][19];         // anti-bounce-back wall terms 2 (e+_k(phi_w) - w_k phi_ref)
+    TC s[19];             // diagonal rates in moment order
+    TC phi_ref;
+    TC srate;             // common non-flux rate (equal-rate path)
+    TC k0scale;           // 3 / d = dG / d(K0 k)
+    int nb, ncb, nk, nr;  // used coefficient counts
+};
+
+struct Dims {
+    int q;
+    int prec;             // 0 f64, 1 f32, 2 f16
+    bool eqr;             // equal non-flux rates: velocity-space collision
+    bool src;             // R != 0 (Scheme-A history needed)
+    bool kvar;            // k(phi) not constant: A per node
+    bool wall;            // walls on the last axis
+};
+
+// Kernel launchers (defined per lattice in sweep_d2q9.hip / sweep_d3q19.hip).
+hipError_t launch_init(const Dims &dm, const Geom &g, const void *coefs, const double *phi0,
+                       void *f, void *p, hipStream_t st);
+hipError_t launch_sweep(const Dims &dm, const Geom &g, const void *coefs, const void *fin,
+                        void *fout, void *p, int *flag, hipStream_t st);
+hipError_t launch_phi(const Dims &dm, const Geom &g, const void *coefs, const void *f,
+                      double *phi, hipStream_t st);
+hipError_t launch_adjoint(const Dims &dm, const Geom &g, const void *coefs, const void *f,
+                          const void *p, const void *psi_next, const double *pi_next,
+                          void *psi_out, double *pi_out, double *gk_part, hipStream_t st);
+hipError_t launch_adjoint_init(const Dims &dm, const Geom &g, const void *coefs,
+                               const double *phi0, const void *psi0, const double *pi0,
+                               double *gphi0, hipStream_t st);
+hipError_t launch_seed(const Dims &dm, const Geom &g, const double *gphi, void *psi,
+                       double *pi, hipStream_t st);
+
+// Generic FP64 reductions (lbm_reduce.hip).
+hipError_t launch_reduce(const double *phi, const double *ref, uint32_t n, double *part,
+                         int nparts, double *out, hipStream_t st);
+hipError_t launch_sum_partials(const double *part, int nparts, int width, double *acc,
+                               hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,403 @@
+// Device code of the fused MRT stream-collide sweep (pull form).
+//
+// State convention: a distribution buffer holds, at node x and direction k,
+// the value that node x + c_k gathers at the next sweep (the post-collision
+// population of the previous step).  One sweep gathers g_k(x) = f_k(x - c_k)
+// (Eq. 2 left-hand side read backwards: streaming), computes phi = sum g
+// (Eq. 10a), relaxes in moment space (Eq. 2, 17-19) or, when every non-flux
+// rate is equal, with the equivalent velocity-space form, adds the Scheme-A
+// source (Remark II), and stores the result at x.  Walls on the last axis use
+// anti-bounce-back: a population that would come from beyond the wall is
+// g_k(x) = -f_kbar(x) + 2 e+_k(phi_w), e+ the even part of Eq. 3.
+//
+// Stored values are offsets h_k = f_k - w_k phi_ref (phi_ref = 0 gives plain
+// distributions); the equilibrium and the source are formed directly in
+// offset form, so FP32/FP16 storage keeps the small differences.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.h"
+#include "lbm_lattice.h"
+
+namespace lbm {
+
+template <typename TS>
+struct HistType { using T = float; };
+template <>
+struct HistType<double> { using T = double; };
+
+template <typename TC, typename TS>
+__device__ __forceinline__ TC load_s(const TS *p) { return (TC)(*p); }
+
+template <typename TS, typename TC>
+__device__ __forceinline__ void store_s(TS *p, TC v) { *p = (TS)v; }
+
+// sum_{p < n} c[p] x^p by Horner, unrolled to the maximum count; the uniform
+// count n turns the unused terms into skipped scalar branches.
+template <int MAXN, typename T>
+__device__ __forceinline__ T poly(const T *c, int n, T x) {
+    T acc = T(0);
+#pragma unroll
+    for (int p = MAXN - 1; p >= 0; --p)
+        if (p < n) acc = acc * x + c[p];
+    return acc;
+}
+
+// Workgroup order that gives each XCD one contiguous run of the domain, so
+// the neighbouring rows and planes a workgroup reads sit in its own L2.
+__device__ __forceinline__ uint32_t block_index(uint32_t b, uint32_t nb, int remap) {
+    if (!remap) return b;
+    const uint32_t q = nb / kNumXcd, r = nb % kNumXcd;
+    const uint32_t xcd = b % kNumXcd, i = b / kNumXcd;
+    return xcd * q + (xcd < r ? xcd : r) + i;
+}
+
+// Symmetric inverse of G (2x2 or 3x3), symmetric storage (xx, yy, zz, xy, yz, xz).
+template <int DIM, typename T>
+__device__ __forceinline__ void sym_inverse(const T *G, T *A) {
+    if (DIM == 2) {
+        const T det = G[0] * G[1] - G[3] * G[3];
+        const T id = T(1) / det;
+        A[0] = G[1] * id;
+        A[1] = G[0] * id;
+        A[3] = -G[3] * id;
+        A[2] = T(0); A[4] = T(0); A[5] = T(0);
+    } else {
+        const T c00 = G[1] * G[2] - G[4] * G[4];
+        const T c11 = G[0] * G[2] - G[5] * G[5];
+        const T c22 = G[0] * G[1] - G[3] * G[3];
+        const T c01 = G[5] * G[4] - G[3] * G[2];
+        const T c12 = G[3] * G[5] - G[0] * G[4];
+        const T c02 = G[3] * G[4] - G[5] * G[1];
+        const T det = G[0] * c00 + G[3] * c01 + G[5] * c02;
+        const T id = T(1) / det;
+        A[0] = c00 * id; A[1] = c11 * id; A[2] = c22 * id;
+        A[3] = c01 * id; A[4] = c12 * id; A[5] = c02 * id;
+    }
+}
+
+// Flux block A at phi (Eq. 26): A = (g0 k(phi) + I/2)^-1, or the constant.
+template <int DIM, bool KVAR, typename TC>
+__device__ __forceinline__ void ablock(const Coefs<TC> *__restrict__ cf, TC phi, TC *A) {
+    if (KVAR) {
+        const TC kv = poly<kMaxP>(cf->kp, cf->nk, phi);
+        TC G[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) G[i] = cf->g0[i] * kv + (i < 3 ? TC(0.5) : TC(0));
+        sym_inverse<DIM>(G, A);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) A[i] = cf->a[i];
+    }
+}
+
+// Equilibrium offsets feq_k - w_k phi_ref (Eq. 3 with c = 1, cs^2 = 1/3):
+// w_k [ (phi - phi_ref) + 3 c.B + 9/2 ((Cbar - phi/3 I) : (c c - I/3)) ].
+template <int Q, typename TC>
+__device__ __forceinline__ void equilibrium(const Coefs<TC> *__restrict__ cf, TC phi, TC phio,
+                                            TC *feq) {
+    using L = Lattice<Q>;
+    constexpr int D = L::dim;
+    TC B[3], E[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) B[a] = (a < D) ? poly<kMaxP>(cf->b[a], cf->nb, phi) : TC(0);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const bool used = (D == 3) || (i == 0 || i == 1 || i == 3);
+        E[i] = used ? poly<kMaxC>(cf->cb[i], cf->ncb, phi) : TC(0);
+    }
+    const TC third = phi * TC(1.0 / 3.0);
+    E[0] -= third; E[1] -= third;
+    if (D == 3) E[2] -= third;
+    const TC trE3 = (E[0] + E[1] + E[2]) * TC(1.0 / 3.0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int x = L::cx(k), y = L::cy(k), z = L::cz(k);
+        TC cB = TC(0), ccE = -trE3;
+        if (x) cB += x * B[0];
+        if (y) cB += y * B[1];
+        if (z) cB += z * B[2];
+        if (x) ccE += E[0];
+        if (y) ccE += E[1];
+        if (z) ccE += E[2];
+        if (x && y) ccE += TC(2 * x * y) * E[3];
+        if (y && z) ccE += TC(2 * y * z) * E[4];
+        if (x && z) ccE += TC(2 * x * z) * E[5];
+        feq[k] = TC(L::w(k)) * (phio + TC(3) * cB + TC(4.5) * ccE);
+    }
+}
+
+// Scheme-A source pieces at one time level: R(phi) and Btilde = (I - A/2) B'
+// (Eq. 28 with gamma = 0).
+template <int DIM, typename TC>
+__device__ __forceinline__ void source_terms(const Coefs<TC> *__restrict__ cf, TC phi, const TC *A,
+                                             TC *Bt, TC &R) {
+    TC Bp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Bp[a] = (a < DIM) ? poly<kMaxP>(cf->bp[a], cf->nb, phi) : TC(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        TC acc = Bp[a];
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) acc -= TC(0.5) * A[sym(a, b)] * Bp[b];
+        Bt[a] = (a < DIM) ? acc : TC(0);
+    }
+    R = poly<kMaxP>(cf->r, cf->nr, phi);
+}
+
+struct NodeGeo {
+    uint32_t n;
+    int om[3], op[3];   // index offset of the neighbour at coord - 1 / coord + 1
+    bool lo, hi;        // node next to the low / high wall of the last axis
+};
+
+template <int Q, bool WALL>
+__device__ __forceinline__ NodeGeo node_geometry(const Geom &g, uint32_t n) {
+    constexpr int D = Lattice<Q>::dim;
+    NodeGeo ng;
+    ng.n = n;
+    uint32_t x, y, z = 0;
+    if (D == 2) {
+        y = g.fx.div(n);
+        x = n - y * g.nx;
+    } else {
+        const uint32_t yz = g.fx.div(n);
+        x = n - yz * g.nx;
+        z = g.fxy.div(n);
+        y = yz - z * g.ny;
+    }
+    const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz;
+    const int sy = nx, sz = nx * ny;
+    ng.om[0] = (x == 0) ? (nx - 1) : -1;
+    ng.op[0] = ((int)x == nx - 1) ? -(nx - 1) : 1;
+    ng.om[1] = (y == 0) ? (ny - 1) * sy : -sy;
+    ng.op[1] = ((int)y == ny - 1) ? -(ny - 1) * sy : sy;
+    ng.om[2] = (z == 0) ? (nz - 1) * sz : -sz;
+    ng.op[2] = ((int)z == nz - 1) ? -(nz - 1) * sz : sz;
+    const uint32_t last = (D == 2) ? y : z;
+    const uint32_t nlast = (D == 2) ? g.ny : g.nz;
+    ng.lo = WALL && last == 0;
+    ng.hi = WALL && last == nlast - 1;
+    return ng;
+}
+
+// Gather g_k(x) (offset form) with periodic wrap and anti-bounce-back walls.
+template <int Q, bool WALL, typename TS, typename TC>
+__device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restrict__ cf,
+                                       const TS *__restrict__ fin, const NodeGeo &ng, TC *h) {
+    using L = Lattice<Q>;
+    constexpr int D = L::dim;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        int off = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int c = L::c(k, a);
+            off += (c == 1) ? ng.om[a] : ((c == -1) ? ng.op[a] : 0);
+        }
+        const int cl = L::c(k, D - 1);
+        if (WALL && ((cl == 1 && ng.lo) || (cl == -1 && ng.hi))) {
+            h[k] = -load_s<TC>(fin + (uint64_t)L::opp(k) * g.plane + ng.n) + cf->ew[cl == 1 ? 0 : 1][k];
+        } else {
+            h[k] = load_s<TC>(fin + (uint64_t)k * g.plane + (uint32_t)((int)ng.n + off));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the sweep
+// ---------------------------------------------------------------------------
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL>
+__global__ void __launch_bounds__(kBlock)
+k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin,
+        TS *__restrict__ fout, typename HistType<TS>::T *p, int *flag) {
+    using L = Lattice<Q>;
+    constexpr int D = L::dim;
+    const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const NodeGeo ng = node_geometry<Q, WALL>(g, n);
+
+    TC h[Q];
+    gather<Q, WALL>(g, cf, fin, ng, h);
+
+    TC phio = TC(0);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) phio += h[k];
+    const TC phi = cf->phi_ref + phio;
+
+    TC A[6];
+    ablock<D, KVAR>(cf, phi, A);
+    TC feq[Q];
+    equilibrium<Q>(cf, phi, phio, feq);
+
+    TC out[Q];
+    if (EQR) {
+        // All non-flux rates equal s: (M^-1 S M)(g - feq) = s (g - feq)
+        // + c_k . (A - s I)(j - B) / |c_a|^2, since the rows of M are
+        // orthogonal and the flux rows are c_a (the density row drops out in
+        // Scheme A because sum g = sum feq).
+        const TC s = cf->srate;
+        TC jd[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            TC acc = TC(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const int c = L::c(k, a);
+                if (c) acc += TC(c) * (h[k] - feq[k]);
+            }
+            jd[a] = (a < D) ? acc : TC(0);
+        }
+        TC v[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            TC acc = TC(0);
+#pragma unroll
+            for (int b = 0; b < D; ++b) acc += (A[sym(a, b)] - (a == b ? s : TC(0))) * jd[b];
+            v[a] = acc * TC(1.0 / L::jnorm);
+        }
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            TC cv = TC(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int c = L::c(k, a);
+                if (c) cv += TC(c) * v[a];
+            }
+            out[k] = h[k] - s * (h[k] - feq[k]) - cv;
+        }
+    } else {
+        // m = M (g - feq); relax with S (diagonal rates, block A on the flux
+        // rows, Eq. 17); back with M^-1 = M^T N^-1 (orthogonal rows).
+        TC dlt[Q], m[Q], r[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) dlt[k] = h[k] - feq[k];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            TC acc = TC(0);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const int mm = L::M(i, k);
+                if (mm == 1) acc += dlt[k];
+                else if (mm == -1) acc -= dlt[k];
+                else if (mm) acc += TC(mm) * dlt[k];
+            }
+            m[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) r[i] = cf->s[i] * m[i];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            TC acc = TC(0);
+#pragma unroll
+            for (int b = 0; b < D; ++b) acc += A[sym(a, b)] * m[L::jrow[b]];
+            r[L::jrow[a]] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) r[i] *= TC(1.0 / L::N(i));
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            TC acc = TC(0);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int mm = L::M(i, k);
+                if (mm == 1) acc += r[i];
+                else if (mm == -1) acc -= r[i];
+                else if (mm) acc += TC(mm) * r[i];
+            }
+            out[k] = h[k] - acc;
+        }
+    }
+
+    if (SRC) {
+        // Scheme A: + 3/2 R_k(t) - 1/2 R_k(t - 1), R_k = w_k (1 + 3 c.Btilde) R (Eq. 9)
+        TC Bt[3], R, Btp[3], Rp, Ap[6];
+        source_terms<D>(cf, phi, A, Bt, R);
+        const TC pp = cf->phi_ref + (TC)p[n];
+        ablock<D, KVAR>(cf, pp, Ap);
+        source_terms<D>(cf, pp, Ap, Btp, Rp);
+        const TC r1 = TC(1.5) * R, r0 = TC(0.5) * Rp;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            TC cb1 = TC(0), cb0 = TC(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int c = L::c(k, a);
+                if (c) { cb1 += TC(c) * Bt[a]; cb0 += TC(c) * Btp[a]; }
+            }
+            out[k] += TC(L::w(k)) * (r1 * (TC(1) + TC(3) * cb1) - r0 * (TC(1) + TC(3) * cb0));
+        }
+        p[n] = (typename HistType<TS>::T)phio;
+    }
+
+#pragma unroll
+    for (int k = 0; k < Q; ++k) store_s(fout + (uint64_t)k * g.plane + n, out[k]);
+
+    if (!__builtin_isfinite(phio)) *flag = 1;
+}
+
+// ---------------------------------------------------------------------------
+// initialisation (Eq. 40) in the gather convention
+// ---------------------------------------------------------------------------
+template <int Q, typename TC>
+__device__ __forceinline__ TC feq_one(const Coefs<TC> *__restrict__ cf, TC phi, int kk) {
+    TC feq[Q];
+    equilibrium<Q>(cf, phi, phi - cf->phi_ref, feq);
+    TC v = feq[0];
+#pragma unroll
+    for (int k = 1; k < Q; ++k)
+        if (k == kk) v = feq[k];
+    return v;
+}
+
+template <int Q, typename TS, typename TC, bool WALL>
+__global__ void __launch_bounds__(kBlock)
+k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict__ phi0,
+       TS *__restrict__ f, typename HistType<TS>::T *p) {
+    using L = Lattice<Q>;
+    constexpr int D = L::dim;
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const NodeGeo ng = node_geometry<Q, WALL>(g, n);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        // slot k at x is read by x + c_k, unless that lies beyond a wall;
+        // then it is read back by x itself for the opposite direction.
+        const int cl = L::c(k, D - 1);
+        TC v;
+        if (WALL && ((cl == 1 && ng.hi) || (cl == -1 && ng.lo))) {
+            const TC ph = (TC)phi0[n];
+            v = cf->ew[cl == 1 ? 1 : 0][k] - feq_one<Q>(cf, ph, L::opp(k));
+        } else {
+            int off = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int c = L::c(k, a);
+                off += (c == 1) ? ng.op[a] : ((c == -1) ? ng.om[a] : 0);
+            }
+            const TC ph = (TC)phi0[(uint32_t)((int)n + off)];
+            v = feq_one<Q>(cf, ph, k);
+        }
+        store_s(f + (uint64_t)k * g.plane + n, v);
+    }
+    if (p) p[n] = (typename HistType<TS>::T)((TC)phi0[n] - cf->phi_ref);
+}
+
+// phi = phi_ref + sum_k g_k, accumulated in FP64.
+template <int Q, typename TS, typename TC, bool WALL>
+__global__ void __launch_bounds__(kBlock)
+k_phi(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
+      double *__restrict__ phi) {
+    const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const NodeGeo ng = node_geometry<Q, WALL>(g, n);
+    TC h[Q];
+    gather<Q, WALL>(g, cf, f, ng, h);
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) acc += (double)h[k];
+    phi[n] = (double)cf->phi_ref + acc;
+}
+
+}  // namespace lbm

@@ -1,0 +1,42 @@
+// Kernel instantiations for the D2Q9 lattice.
+#define LBM_Q 9
+#include "lbm_dispatch.h"
+
+namespace lbm {
+
+hipError_t launch_sweep_q9(const Dims &dm, const Geom &g, const void *coefs, const void *fin,
+                            void *fout, void *p, int *flag, hipStream_t st) {
+    LBM_BY_PREC(sweep_typed, dm, g, coefs, fin, fout, p, flag, st)
+}
+
+hipError_t launch_init_q9(const Dims &dm, const Geom &g, const void *coefs, const double *phi0,
+                           void *f, void *p, hipStream_t st) {
+    LBM_BY_PREC(init_typed, dm, g, coefs, phi0, f, p, st)
+}
+
+hipError_t launch_phi_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f,
+                          double *phi, hipStream_t st) {
+    LBM_BY_PREC(phi_typed, dm, g, coefs, f, phi, st)
+}
+
+}  // namespace lbm
+
+namespace lbm {
+
+hipError_t launch_adjoint_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f, const void *p,
+                             const void *psi_next, const double *pi_next, void *psi_out, double *pi_out,
+                             double *gk_part, hipStream_t st) {
+    LBM_BY_PREC_ADJ(adjoint_typed, dm, g, coefs, f, p, psi_next, pi_next, psi_out, pi_out, gk_part, st)
+}
+
+hipError_t launch_adjoint_init_q9(const Dims &dm, const Geom &g, const void *coefs, const double *phi0,
+                                  const void *psi0, const double *pi0, double *out, hipStream_t st) {
+    LBM_BY_PREC_ADJ(adjoint_init_typed, dm, g, coefs, phi0, psi0, pi0, out, st)
+}
+
+hipError_t launch_seed_q9(const Dims &dm, const Geom &g, const double *gphi, void *psi, double *pi,
+                          hipStream_t st) {
+    LBM_BY_PREC_ADJ(seed_typed, dm, g, gphi, psi, pi, st)
+}
+
+}  // namespace lbm

@@ -1,0 +1,22 @@
+// Kernel instantiations for the D3Q19 lattice.
+#define LBM_Q 19
+#include "lbm_dispatch.h"
+
+namespace lbm {
+
+hipError_t launch_sweep_q19(const Dims &dm, const Geom &g, const void *coefs, const void *fin,
+                            void *fout, void *p, int *flag, hipStream_t st) {
+    LBM_BY_PREC(sweep_typed, dm, g, coefs, fin, fout, p, flag, st)
+}
+
+hipError_t launch_init_q19(const Dims &dm, const Geom &g, const void *coefs, const double *phi0,
+                           void *f, void *p, hipStream_t st) {
+    LBM_BY_PREC(init_typed, dm, g, coefs, phi0, f, p, st)
+}
+
+hipError_t launch_phi_q19(const Dims &dm, const Geom &g, const void *coefs, const void *f,
+                          double *phi, hipStream_t st) {
+    LBM_BY_PREC(phi_typed, dm, g, coefs, f, phi, st)
+}
+
+}  // namespace lbm

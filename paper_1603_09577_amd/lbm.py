@@ -1,0 +1,289 @@
+"""Thin ctypes binding of liblbm.so (include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  PyTorch provides device memory and the stream.  Importing
+this module does not load the library; the first call does, and raises
+``LbmLibraryMissing`` if it has not been built (python -m
+paper_1603_09577_amd.build).  There is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+MAXP = 9
+
+LBM_OK, LBM_E_INVALID, LBM_E_UNSUPPORTED, LBM_E_HIP, LBM_E_DIVERGED, LBM_E_STATE = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"f64": 0, "f32": 1, "f16": 2}
+FLAG_MOMENT_PATH = 1
+FLAG_NO_XCD_REMAP = 2
+
+# every symbol include/lbm.h declares
+EXPORTS = [
+    "lbm_create", "lbm_state_bytes", "lbm_init", "lbm_step", "lbm_sweep", "lbm_get_phi",
+    "lbm_phi_of", "lbm_current", "lbm_set_current", "lbm_set_check", "lbm_set_k0",
+    "lbm_reduce", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_init",
+    "lbm_adjoint_grad_k0", "lbm_destroy", "lbm_last_error",
+]
+
+
+class LbmLibraryMissing(RuntimeError):
+    pass
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblbm error {code}: {msg}")
+        self.code = code
+
+
+class LbmDesc(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("bc", ctypes.c_int * 3),
+        ("phi_wall", (ctypes.c_double * 2) * 3),
+        ("precision", ctypes.c_int),
+        ("phi_ref", ctypes.c_double),
+        ("scheme", ctypes.c_int),
+        ("d", ctypes.c_double),
+        ("s", ctypes.c_double * 19),
+        ("b", (ctypes.c_double * MAXP) * 3),
+        ("dpoly", ctypes.c_double * MAXP),
+        ("dten", (ctypes.c_double * 3) * 3),
+        ("k0", (ctypes.c_double * 3) * 3),
+        ("kpoly", ctypes.c_double * MAXP),
+        ("rpoly", ctypes.c_double * MAXP),
+        ("flags", ctypes.c_int),
+    ]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def load():
+    """Load liblbm.so (raises LbmLibraryMissing when it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LbmLibraryMissing(
+            f"{LIB_PATH} not found: build it with `python -m paper_1603_09577_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "lbm_create": ([ctypes.POINTER(LbmDesc), ctypes.POINTER(_VP)], ctypes.c_int),
+        "lbm_state_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_init": ([_VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_step": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
+        "lbm_sweep": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_get_phi": ([_VP, _VP, _VP], ctypes.c_int),
+        "lbm_phi_of": ([_VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_current": ([_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+        "lbm_set_current": ([_VP, ctypes.c_int, ctypes.c_longlong], ctypes.c_int),
+        "lbm_set_check": ([_VP, ctypes.c_int], ctypes.c_int),
+        "lbm_set_k0": ([_VP, _DP], ctypes.c_int),
+        "lbm_reduce": ([_VP, _VP, _VP, _DP, _VP], ctypes.c_int),
+        "lbm_adjoint_seed": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_adjoint_step": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_adjoint_init": ([_VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_adjoint_grad_k0": ([_VP, _DP, _VP], ctypes.c_int),
+        "lbm_destroy": ([_VP], None),
+        "lbm_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != LBM_OK:
+        raise LbmError(rc, load().lbm_last_error().decode())
+
+
+def _pad(coeffs, n=MAXP):
+    out = [0.0] * n
+    for i, c in enumerate(coeffs or []):
+        out[i] = float(c)
+    return out
+
+
+def desc_from_spec(spec, flags=0):
+    """lbm_desc from a problem dict (see paper_1603_09577_amd.workloads)."""
+    d = LbmDesc()
+    d.lattice = int(spec["lattice"])
+    shape = list(spec["shape"]) + [1] * (3 - len(spec["shape"]))
+    d.nx, d.ny, d.nz = (int(v) for v in shape)
+    bc = list(spec.get("bc", ["periodic"] * 3)) + ["periodic"] * 3
+    for a in range(3):
+        d.bc[a] = {"periodic": 0, "abb": 1}[bc[a]]
+    pw = spec.get("phi_wall", [[0.0, 0.0]] * 3)
+    for a in range(3):
+        d.phi_wall[a][0], d.phi_wall[a][1] = float(pw[a][0]), float(pw[a][1])
+    d.precision = PRECISIONS[spec.get("precision", "f64")]
+    d.phi_ref = float(spec.get("phi_ref", 0.0))
+    d.scheme = {"A": 0, "B": 1}[spec.get("scheme", "A")]
+    d.d = float(spec.get("d", 1.0))
+    s = _pad(spec["s"], 19)
+    for i in range(19):
+        d.s[i] = s[i]
+    b = spec["b"]
+    for a in range(3):
+        row = _pad(b[a] if a < len(b) else [])
+        for i in range(MAXP):
+            d.b[a][i] = row[i]
+    for name, default in (("dpoly", [0.0, 1.0]), ("kpoly", [1.0]), ("rpoly", [])):
+        row = _pad(spec.get(name, default))
+        arr = getattr(d, name)
+        for i in range(MAXP):
+            arr[i] = row[i]
+    dten = np.asarray(spec.get("dten", np.eye(3)), dtype=np.float64)
+    k0 = np.asarray(spec["k0"], dtype=np.float64)
+    for a in range(3):
+        for c in range(3):
+            d.dten[a][c] = dten[a, c] if a < dten.shape[0] and c < dten.shape[1] else 0.0
+            d.k0[a][c] = k0[a, c] if a < k0.shape[0] and c < k0.shape[1] else 0.0
+    d.flags = int(flags | spec.get("flags", 0))
+    return d
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Lbm:
+    """One MRT lattice Boltzmann instance on the current GPU.
+
+    Owns two distribution buffers and the phi-history buffer as torch tensors
+    (uint8 storage, sizes from lbm_state_bytes) and the library context.
+    """
+
+    def __init__(self, spec, device="cuda", flags=0):
+        import torch
+        self.spec = spec
+        self.lib = load()
+        self.desc = desc_from_spec(spec, flags)
+        ctx = _VP()
+        _check(self.lib.lbm_create(ctypes.byref(self.desc), ctypes.byref(ctx)))
+        self.ctx = ctx
+        fb, pb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(self.lib.lbm_state_bytes(self.ctx, ctypes.byref(fb), ctypes.byref(pb)))
+        self.f_bytes, self.p_bytes = fb.value, pb.value
+        self.device = torch.device(device)
+        self.shape = (self.desc.nz, self.desc.ny, self.desc.nx) if self.desc.lattice == 19 \
+            else (self.desc.ny, self.desc.nx)
+        self.q = self.desc.lattice
+        self.N = int(np.prod(self.shape))
+        self.f = [torch.empty(self.f_bytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.p = torch.empty(self.p_bytes, dtype=torch.uint8, device=self.device)
+        self.compute_dtype = torch.float64 if self.desc.precision == 0 else torch.float32
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.lbm_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # -- forward -----------------------------------------------------------
+    def init(self, phi0, stream=None):
+        import torch
+        phi0 = torch.as_tensor(phi0, dtype=torch.float64, device=self.device).contiguous()
+        assert phi0.numel() == self.N
+        self._phi0 = phi0
+        _check(self.lib.lbm_init(self.ctx, _ptr(phi0), _ptr(self.f[0]), _ptr(self.f[1]), _ptr(self.p),
+                                 _stream(stream)))
+        return self
+
+    def step(self, n=1, stream=None):
+        _check(self.lib.lbm_step(self.ctx, int(n), _stream(stream)))
+
+    def sweep(self, f_in, f_out, p, stream=None):
+        _check(self.lib.lbm_sweep(self.ctx, _ptr(f_in), _ptr(f_out), _ptr(p), _stream(stream)))
+
+    def phi(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _check(self.lib.lbm_get_phi(self.ctx, _ptr(out), _stream(stream)))
+        return out
+
+    def phi_of(self, f, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _check(self.lib.lbm_phi_of(self.ctx, _ptr(f), _ptr(out), _stream(stream)))
+        return out
+
+    def current(self):
+        fp, pp, t = _VP(), _VP(), ctypes.c_longlong()
+        _check(self.lib.lbm_current(self.ctx, ctypes.byref(fp), ctypes.byref(pp), ctypes.byref(t)))
+        which = 0 if fp.value == self.f[0].data_ptr() else 1
+        return which, t.value
+
+    def set_current(self, which, t):
+        _check(self.lib.lbm_set_current(self.ctx, int(which), int(t)))
+
+    def set_check(self, every):
+        _check(self.lib.lbm_set_check(self.ctx, int(every)))
+
+    def set_k0(self, k0):
+        arr = (ctypes.c_double * 9)(*np.asarray(k0, dtype=np.float64).reshape(-1).tolist())
+        _check(self.lib.lbm_set_k0(self.ctx, arr))
+
+    def reduce(self, phi, ref=None, stream=None):
+        out = (ctypes.c_double * 8)()
+        _check(self.lib.lbm_reduce(self.ctx, _ptr(phi), _ptr(ref), out, _stream(stream)))
+        keys = ("sum", "sumsq", "sum_d2", "sum_ref2", "min", "max", "nonfinite", "sum_absd")
+        return dict(zip(keys, list(out)))
+
+    # -- adjoint -------------------------------------------------------------
+    def adjoint_buffers(self):
+        """(psi, pi) buffers of the adjoint variables."""
+        import torch
+        psi_bytes = self.q * self.N * (8 if self.desc.precision == 0 else 4)
+        psi = torch.empty(((psi_bytes + 255) // 256) * 256, dtype=torch.uint8, device=self.device)
+        pi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        return psi, pi
+
+    def adjoint_seed(self, gphi, psi, pi, stream=None):
+        _check(self.lib.lbm_adjoint_seed(self.ctx, _ptr(gphi), _ptr(psi), _ptr(pi), _stream(stream)))
+
+    def adjoint_step(self, f_s, p_s, psi_next, pi_next, psi_out, pi_out, stream=None):
+        _check(self.lib.lbm_adjoint_step(self.ctx, _ptr(f_s), _ptr(p_s), _ptr(psi_next), _ptr(pi_next),
+                                         _ptr(psi_out), _ptr(pi_out), _stream(stream)))
+
+    def adjoint_init(self, phi0, psi0, pi0, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _check(self.lib.lbm_adjoint_init(self.ctx, _ptr(phi0), _ptr(psi0), _ptr(pi0), _ptr(out),
+                                         _stream(stream)))
+        return out
+
+    def adjoint_grad_k0(self, stream=None):
+        out = (ctypes.c_double * 6)()
+        _check(self.lib.lbm_adjoint_grad_k0(self.ctx, out, _stream(stream)))
+        v = list(out)
+        return {"xx": v[0], "xy": v[1], "yy": v[2], "xz": v[3], "yz": v[4], "zz": v[5]}
+
+    # -- views ---------------------------------------------------------------
+    def storage_view(self, buf):
+        """Typed [q, N] view of a distribution buffer (offsets f - w phi_ref)."""
+        import torch
+        dt = {0: torch.float64, 1: torch.float32, 2: torch.float16}[self.desc.precision]
+        return buf.view(dt)[: self.q * self.N].view(self.q, self.N)

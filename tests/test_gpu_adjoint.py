@@ -1,0 +1,154 @@
+"""GPU discrete adjoint (reversed sweep + checkpointed rollout).
+
+* against the oracle's complex-step adjoint on small grids (FP64 <= 1e-10
+  relative; FP32 storage compared to the FP64 oracle and reported),
+* against central finite differences of the GPU forward run along 16 seeded
+  joint directions (phi0, K0) at the full 512 x 512 adjoint workload,
+  relative error <= 1e-6.
+Loss: L = 1/2 sum (phi(T) - phi*)^2.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1603_09577_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def k0_entries(spec):
+    k = np.asarray(spec["k0"])
+    return np.array([k[0, 0], k[0, 1], k[1, 1]])
+
+
+def gpu_gradient(spec, phi0, target, T, seg=None, flags=0):
+    from paper_1603_09577_amd import lbm
+    from paper_1603_09577_amd.rollout import rollout
+    sim = lbm.Lbm(spec, flags=flags)
+    p0 = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+    k0 = torch.tensor(k0_entries(spec), dtype=torch.float64, requires_grad=True)
+    tgt = torch.tensor(target, dtype=torch.float64, device="cuda")
+    phiT = rollout(sim, p0, k0, T, seg)
+    loss = 0.5 * ((phiT - tgt) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return float(loss), p0.grad.cpu().numpy(), k0.grad.cpu().numpy()
+
+
+def oracle_gradient(spec, phi0, target, T):
+    p = orc.params_from_spec(spec)
+    phiT, g0, gk = orc.gradient(p, phi0, T, lambda ph: ph - target)
+    return 0.5 * ((phiT - target) ** 2).sum(), g0, np.array([gk["xx"], gk["xy"], gk["yy"]])
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_adjoint_matches_oracle_nonlinear(flags):
+    """Nonlinear B, K(phi) and Scheme-A source; equal-rate and moment paths;
+    checkpoint segments that do not divide T."""
+    spec = W.spec_nonlinear_2d(26, 19)
+    rng = np.random.default_rng(21)
+    phi0 = W.noise_field((19, 26), 22)
+    target = 0.5 + 0.1 * rng.uniform(-1, 1, (19, 26))
+    T = 23
+    say(f"[gpu adjoint] nonlinear 26x19 T={T} flags={flags}")
+    lg, gg, kg = gpu_gradient(spec, phi0, target, T, seg=5, flags=flags)
+    lo, go, ko = oracle_gradient(spec, phi0, target, T)
+    say(f"    loss {lg:.15e} / {lo:.15e}  dphi0 {rel(gg, go):.2e}  dK0 {rel(kg, ko):.2e}")
+    assert abs(lg - lo) <= 1e-12 * abs(lo)
+    assert rel(gg, go) <= 1e-10
+    assert rel(kg, ko) <= 1e-10
+
+
+def test_adjoint_matches_oracle_walls_general_rates():
+    spec = W.spec_nonlinear_2d(17, 22)
+    spec["bc"] = ["periodic", "abb", "periodic"]
+    spec["phi_wall"] = [[0, 0], [0.35, 0.7], [0, 0]]
+    spec["s"] = [0.0, 1.3, 1.1, 1.0, 1.4, 1.0, 0.9, 1.2, 1.05]
+    rng = np.random.default_rng(23)
+    phi0 = W.noise_field((22, 17), 24)
+    target = 0.5 + 0.1 * rng.uniform(-1, 1, (22, 17))
+    T = 19
+    say(f"[gpu adjoint] walls general rates T={T}")
+    lg, gg, kg = gpu_gradient(spec, phi0, target, T, seg=4)
+    lo, go, ko = oracle_gradient(spec, phi0, target, T)
+    say(f"    dphi0 {rel(gg, go):.2e}  dK0 {rel(kg, ko):.2e}")
+    assert rel(gg, go) <= 1e-10 and rel(kg, ko) <= 1e-10
+
+
+def test_adjoint_fp32_against_fp64_oracle():
+    spec = W.spec_nonlinear_2d(40, 32, precision="f32")
+    rng = np.random.default_rng(25)
+    phi0 = W.noise_field((32, 40), 26)
+    target = 0.5 + 0.1 * rng.uniform(-1, 1, (32, 40))
+    T = 60
+    say("[gpu adjoint] fp32 vs fp64 oracle")
+    lg, gg, kg = gpu_gradient(spec, phi0, target, T)
+    lo, go, ko = oracle_gradient(dict(spec, precision="f64"), phi0, target, T)
+    e0, ek = rel(gg, go), rel(kg, ko)
+    say(f"    fp32 adjoint: dphi0 rel {e0:.2e}  dK0 rel {ek:.2e}")
+    assert e0 <= 1e-4 and ek <= 1e-3
+
+
+def _fd_check(spec, phi0, target, T, ndir=16, seed=7, eps=1e-3):
+    from paper_1603_09577_amd import lbm
+    lg, gg, kg = gpu_gradient(spec, phi0, target, T)
+    sim = lbm.Lbm(spec)
+    tgt = torch.tensor(target, dtype=torch.float64, device="cuda")
+    k0 = np.asarray(spec["k0"], dtype=np.float64)
+
+    def loss(ph0, kent):
+        km = k0.copy()
+        km[0, 0], km[0, 1], km[1, 0], km[1, 1] = kent[0], kent[1], kent[1], kent[2]
+        sim.set_k0(km)
+        sim.init(ph0)
+        sim.step(T)
+        return float(0.5 * ((sim.phi() - tgt) ** 2).sum())
+
+    rng = np.random.default_rng(seed)
+    p0 = torch.tensor(phi0, dtype=torch.float64, device="cuda")
+    ke = k0_entries(spec)
+    worst = 0.0
+    for i in range(ndir):
+        vp = rng.standard_normal(phi0.shape)
+        vp /= np.linalg.norm(vp)
+        vk = rng.standard_normal(3)
+        vk /= np.linalg.norm(vk)
+        vk *= np.linalg.norm(ke)
+        vpt = torch.tensor(vp, device="cuda")
+        fd = (loss(p0 + eps * vpt, ke + eps * vk) - loss(p0 - eps * vpt, ke - eps * vk)) / (2 * eps)
+        ad = float((gg * vp).sum() + (kg * vk).sum())
+        err = abs(fd - ad) / max(abs(fd), 1e-300)
+        worst = max(worst, err)
+        say(f"    dir {i:2d}: fd {fd:+.12e} adjoint {ad:+.12e} rel {err:.2e}")
+    return worst
+
+
+def test_adjoint_finite_differences_full_c5():
+    """The adjoint workload at full size (512 x 512, 2000 steps, 45-step
+    checkpoints), FP64: adjoint vs central differences on 16 directions."""
+    spec, phi0, target, T = W.C5()
+    say(f"[gpu adjoint] C5 full FD, T={T}")
+    worst = _fd_check(spec, phi0, target, T)
+    assert worst <= 1e-6
+
+
+def test_adjoint_finite_differences_c5b_reduced():
+    """Source-free variant (sensitivities do not decay with the logistic
+    source), 256 x 256, 800 steps."""
+    spec, phi0, target, T = W.C5B(256, nsteps=800)
+    say(f"[gpu adjoint] C5b 256 FD, T={T}")
+    worst = _fd_check(spec, phi0, target, T)
+    assert worst <= 1e-6

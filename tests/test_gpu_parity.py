@@ -1,0 +1,215 @@
+"""GPU forward sweep against the CPU oracle, element by element.
+
+Every case starts both sides from the same seeded phi0 (workloads module) and
+compares phi after a number of steps by relative L2:
+    FP64 storage    <= 1e-12   (the target stated for the FP64 path)
+    FP32 offsets    <= 1e-5    (the target stated for FP32 storage)
+    FP16 offsets    reported, loose sanity bound only.
+Sizes are chosen to span several 256-node workgroups with a ragged tail;
+the full-size cases run a few steps at the benchmark's configuration.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1603_09577_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    from paper_1603_09577_amd import lbm
+    return lbm
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(spec, phi0, snapshots, flags=0):
+    lbm = _lbm()
+    sim = lbm.Lbm(spec, flags=flags).init(phi0)
+    out = {}
+    t = 0
+    for s in sorted(snapshots):
+        sim.step(s - t)
+        t = s
+        out[s] = sim.phi().cpu().numpy()
+    torch.cuda.synchronize()
+    return out
+
+
+def oracle_run(spec, phi0, snapshots):
+    p = orc.params_from_spec(spec)
+    last = max(snapshots)
+    _, snaps = orc.run(p, phi0, last, snapshots=tuple(snapshots))
+    return snaps
+
+
+def compare(spec, phi0, snapshots, tol, flags=0, name=""):
+    say(f"[gpu parity] {name} shape={spec['shape']} prec={spec.get('precision')} flags={flags} steps={snapshots}")
+    g = gpu_run(spec, phi0, snapshots, flags)
+    o = oracle_run(spec, phi0, snapshots)
+    errs = {s: rel_l2(g[s], o[s]) for s in snapshots}
+    say(f"    rel L2 {errs}")
+    for s in snapshots:
+        assert np.isfinite(g[s]).all(), (name, s)
+        assert errs[s] <= tol, (name, s, errs[s])
+    return errs
+
+
+# ---------------------------------------------------------------------------
+# D2Q9
+# ---------------------------------------------------------------------------
+
+def test_c1_full_fp64_moment_path():
+    """Linear Gaussian hill, 64 x 64, 1000 steps, s1 = s2 = 1.2 (moment path)."""
+    spec, phi0, T = W.C1()
+    compare(spec, phi0, (1, 250, 500, T), 1e-12, name="C1")
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_nonlinear_small_fp64(flags):
+    """Nonlinear B, K(phi), Scheme-A source on a ragged 72 x 41 grid; both the
+    equal-rate path (flags = 0) and the forced moment path (flags = 1)."""
+    spec = W.spec_nonlinear_2d(72, 41)
+    phi0 = W.noise_field((41, 72), 12)
+    compare(spec, phi0, (1, 10, 100, 400), 1e-12, flags=flags, name="nonlinear-2d")
+
+
+def test_general_rates_anisotropic_fp64():
+    """Unequal non-flux rates, full K0, nonlinear D and d != 1 (moment path)."""
+    spec = W.spec_nonlinear_2d(50, 37)
+    spec["s"] = [0.0, 1.3, 1.1, 1.0, 1.4, 1.0, 0.9, 1.2, 1.05]
+    spec["d"] = 0.8
+    spec["dpoly"] = [0.05, 0.9, 0.1]
+    phi0 = W.noise_field((37, 50), 13)
+    compare(spec, phi0, (1, 50, 300), 1e-12, name="general-rates")
+
+
+def test_channel_walls_fp64():
+    """D2Q9 anti-bounce-back walls on y with different wall values."""
+    spec = W.spec_nonlinear_2d(40, 33, source=True)
+    spec["bc"] = ["periodic", "abb", "periodic"]
+    spec["phi_wall"] = [[0, 0], [0.3, 0.8], [0, 0]]
+    phi0 = W.noise_field((33, 40), 14)
+    compare(spec, phi0, (1, 20, 200), 1e-12, name="channel")
+    spec["s"] = [0.0, 1.3, 1.1, 1.0, 1.4, 1.0, 0.9, 1.2, 1.05]
+    compare(spec, phi0, (1, 20, 200), 1e-12, name="channel-general-rates")
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 2e-2)])
+def test_nonlinear_reduced_storage(prec, tol):
+    """FP32 / FP16 offset storage against the FP64 oracle."""
+    spec = W.spec_nonlinear_2d(96, 80, precision=prec)
+    phi0 = W.noise_field((80, 96), 15)
+    compare(spec, phi0, (1, 10, 100, 1000), tol, name=f"nonlinear-{prec}")
+
+
+def test_c2_full_size_fp64_and_fp32():
+    """The benchmark configuration (1024 x 1024) for a few steps: FP64 <= 1e-12
+    and FP32 offsets <= 1e-5 against the oracle at full size."""
+    spec, phi0, _ = W.C2(1024)
+    compare(spec, phi0, (1, 4), 1e-12, name="C2-full-f64")
+    spec32, _, _ = W.C2(1024, precision="f32")
+    compare(spec32, phi0, (1, 4), 1e-5, name="C2-full-f32")
+
+
+# ---------------------------------------------------------------------------
+# D3Q19
+# ---------------------------------------------------------------------------
+
+def test_d3q19_walls_fp64():
+    """C3 physics on a ragged 21 x 18 x 26 grid with z walls (equal rates)."""
+    spec, phi0, _ = W.C3((21, 18, 26))
+    compare(spec, phi0, (1, 30, 150), 1e-12, name="d3q19-walls")
+
+
+def test_d3q19_everything_fp64():
+    """D3Q19 with nonlinear B, K(phi), D, source, nonzero wall values and
+    unequal rates (moment path), and the same with forced moment path on
+    equal rates."""
+    spec = W.spec_d3q19_aniso((13, 11, 17), phi_wall=0.4)
+    spec["b"] = [[0.0, 0.02, 0.03], [0.0, -0.01, 0.02], [0.0, 0.01, -0.02]]
+    spec["kpoly"] = [1.0, 0.0, 0.5]
+    spec["rpoly"] = [0.0, 0.002, -0.002]
+    spec["dpoly"] = [0.02, 0.95]
+    spec["phi_wall"] = [[0, 0], [0, 0], [0.2, 0.6]]
+    rng = np.random.default_rng(16)
+    phi0 = 0.4 + 0.1 * rng.uniform(-1, 1, (17, 11, 13))
+    compare(spec, phi0, (1, 40), 1e-12, flags=1, name="d3q19-moment-equal")
+    spec["s"] = [0.0] + [1.0 + 0.04 * i for i in range(18)]
+    compare(spec, phi0, (1, 40), 1e-12, name="d3q19-general")
+
+
+def test_d3q19_fp32():
+    spec, phi0, _ = W.C3((32, 24, 40), precision="f32")
+    compare(spec, phi0, (1, 50, 200), 1e-5, name="d3q19-f32")
+
+
+def test_c3_full_size_two_steps():
+    """The D3Q19 benchmark grid (256^3, walls) for two steps, FP64 and FP32."""
+    spec, phi0, _ = W.C3()
+    compare(spec, phi0, (2,), 1e-12, name="C3-full-f64")
+    spec32, _, _ = W.C3(precision="f32")
+    compare(spec32, phi0, (2,), 1e-5, name="C3-full-f32")
+
+
+# ---------------------------------------------------------------------------
+# properties on the GPU
+# ---------------------------------------------------------------------------
+
+def test_conservation_reduction_fp64():
+    """Periodic, R = 0: the FP64 reduction of sum phi is conserved."""
+    lbm = _lbm()
+    spec = W.spec_nonlinear_2d(200, 130, source=False)
+    phi0 = W.noise_field((130, 200), 17)
+    say("[gpu] conservation 200x130")
+    sim = lbm.Lbm(spec).init(phi0)
+    s0 = sim.reduce(sim.phi())["sum"]
+    sim.step(500)
+    r = sim.reduce(sim.phi())
+    assert r["nonfinite"] == 0
+    assert abs(r["sum"] - s0) <= 1e-13 * abs(s0)
+    assert abs(s0 - phi0.sum()) <= 1e-13 * abs(s0)
+
+
+def test_every_node_written():
+    """Poison the destination with NaN: one sweep must overwrite every value."""
+    lbm = _lbm()
+    for spec, phi0 in ((W.spec_nonlinear_2d(77, 29), W.noise_field((29, 77), 18)),
+                       (W.C3((9, 7, 11))[0], W.C3((9, 7, 11))[1])):
+        say(f"[gpu] poison {spec['shape']}")
+        sim = lbm.Lbm(spec).init(phi0)
+        view = sim.storage_view(sim.f[1])
+        view.fill_(float("nan"))
+        sim.step(1)
+        assert torch.isfinite(view).all().item()
+        assert torch.isfinite(sim.phi()).all().item()
+
+
+def test_divergence_detected():
+    """An unstable BGK setting (Sec. 3.6, kappa = 1e-4) trips the NaN check."""
+    lbm = _lbm()
+    n, dx = 64, 2.0 / 400
+    kl = 1e-4 * dx / dx ** 2
+    sj = 1.0 / (3 * kl + 0.5)
+    spec = dict(lattice=9, shape=(n, n), bc=["periodic"] * 3, scheme="A", d=1.0, s=[sj] * 9,
+                b=[[0.0, 0.1], [0.0, 0.1]], dpoly=[0, 1], dten=[[1, 1, 0], [1, 2, 0], [0, 0, 1]],
+                k0=(kl * np.eye(3)).tolist(), kpoly=[1.0], rpoly=[])
+    say("[gpu] divergence check")
+    sim = lbm.Lbm(spec).init(W.gaussian_hill(n, 2.0))
+    sim.set_check(50)
+    with pytest.raises(lbm.LbmError) as e:
+        sim.step(3000)
+    assert e.value.code == lbm.LBM_E_DIVERGED
