@@ -1,0 +1,301 @@
+"""Throughput of the fused MRT stream-collide sweep on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+
+Headline workload: D2Q9 MRT, nonlinear anisotropic CDE with the Scheme-A
+source on a periodic 1024 x 1024 grid (B = 0.5 phi^2 (1, 1),
+K = K0 (1 + phi^2), R = 0.1 phi (1 - phi), phi0 = 0.5 + 0.1 U[-1, 1) seed 2),
+distributions stored as FP32 offsets.  One step = one fused sweep over the
+grid.  The same run in FP64 storage, the reversed (adjoint) sweep on the
+512 x 512 adjoint workload, the D3Q19 sweep on 256^3 with walls, a plain copy
+kernel (practical HBM ceiling) and the CPU oracle on a bounded sample are
+reported beside it.  Inputs are synthetic and resident in HBM before timing.
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "MRT LBM MLUPS & % of HBM roofline (fwd+adjoint), FP32-store vs FP64 at fixed err"
+
+
+def bytes_per_node(q, prec, src):
+    """Algorithmic bytes of one node update: each population read once and
+    written once, plus the phi history read and write for the Scheme-A source."""
+    s = {"f64": 8, "f32": 4, "f16": 2}[prec]
+    h = 8 if prec == "f64" else 4
+    return 2 * q * s + (2 * h if src else 0)
+
+
+def adjoint_bytes_per_node(q, prec, src):
+    """Reversed sweep: read f_s and psi_{s+1} (q each), write psi_s (q); read
+    pi_{s+1} and write pi_s (FP64); read the phi history (Scheme A)."""
+    s = 8 if prec == "f64" else 4
+    h = 8 if prec == "f64" else 4
+    return 3 * q * s + 2 * 8 + (h if src else 0)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1603_09577_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    v = d.get("workloads", {}).get(kernel_key)
+    return None if v is None else v.get("traffic_bytes_per_launch")
+
+
+def time_steps(torch, sim, steps, warmup):
+    """Average time of one sweep over `steps` sweeps (HIP events on the
+    stream the kernels run on), after `warmup` untimed sweeps."""
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    sim.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3 / steps, wall
+
+
+def run_forward(torch, lbm, spec, phi0, steps, warmup, label):
+    sim = lbm.Lbm(spec).init(phi0)
+    per, wall = time_steps(torch, sim, steps, warmup)
+    N = sim.N
+    prec = spec.get("precision", "f64")
+    src = bool(spec.get("rpoly"))
+    bpn = bytes_per_node(sim.q, prec, src)
+    out = {
+        "label": label, "nodes": N, "steps": steps, "ms_per_step": per * 1e3,
+        "mlups": N / per / 1e6, "bytes_per_node": bpn,
+        "achieved_gbs": bpn * N / per / 1e9, "wall_s": wall,
+    }
+    out["hbm_frac"] = out["achieved_gbs"] / PEAK_HBM_GBS
+    phi = sim.phi()
+    r = sim.reduce(phi)
+    out["nonfinite"] = int(r["nonfinite"])
+    return out, sim, phi
+
+
+def run_adjoint(torch, lbm, spec, phi0, steps, warmup, label):
+    """Time the reversed sweep on a fixed forward state."""
+    sim = lbm.Lbm(spec).init(phi0)
+    sim.step(10)
+    which, _ = sim.current()
+    f_s, p_s = sim.f[which], sim.p
+    psi_a, pi = sim.adjoint_buffers()
+    psi_b, _ = sim.adjoint_buffers()
+    g = torch.full(sim.shape, 1e-3, dtype=torch.float64, device=sim.device)
+    sim.adjoint_seed(g, psi_a, pi)
+    for i in range(warmup):
+        sim.adjoint_step(f_s, p_s, psi_a, pi, psi_b, pi)
+        psi_a, psi_b = psi_b, psi_a
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for i in range(steps):
+        sim.adjoint_step(f_s, p_s, psi_a, pi, psi_b, pi)
+        psi_a, psi_b = psi_b, psi_a
+    e1.record(st)
+    torch.cuda.synchronize()
+    per = e0.elapsed_time(e1) / 1e3 / steps
+    prec = spec.get("precision", "f64")
+    bpn = adjoint_bytes_per_node(sim.q, prec, bool(spec.get("rpoly")))
+    gbs = bpn * sim.N / per / 1e9
+    return {"label": label, "nodes": sim.N, "steps": steps, "ms_per_step": per * 1e3,
+            "mlups": sim.N / per / 1e6, "bytes_per_node": bpn, "achieved_gbs": gbs,
+            "hbm_frac": gbs / PEAK_HBM_GBS}
+
+
+def run_batch(torch, lbm, W, steps):
+    """The batched workload: 512 D2Q9 instances (FP32 offsets), autotuned
+    launch shape, `steps` steps of every instance; aggregate MLUPS."""
+    items = W.batch_specs()
+    b = lbm.Batch([s for s, _ in items]).init([p for _, p in items])
+    rep = b.tune(reps=3)
+    b.step(32)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    per = e0.elapsed_time(e1) / 1e3 / steps
+    N = b.total_nodes
+    bpn = bytes_per_node(9, "f32", False)
+    fin = torch.isfinite(b.phi()).all().item()
+    return {"instances": len(items), "nodes": N, "steps": steps, "ms_per_step": per * 1e3,
+            "mlups": N / per / 1e6, "bytes_per_node": bpn, "achieved_gbs": bpn * N / per / 1e9,
+            "hbm_frac": bpn * N / per / 1e9 / PEAK_HBM_GBS, "shape": b.get_shape(),
+            "tuner": rep.splitlines()[-1], "finite": bool(fin)}
+
+
+def copy_probe(torch, nbytes=1 << 30, reps=20):
+    """Plain device copy of a buffer much larger than the caches: read + write."""
+    n = nbytes // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    per = e0.elapsed_time(e1) / 1e3 / reps
+    return {"bytes_per_copy": 2 * nbytes, "gbs": 2 * nbytes / per / 1e9, "ms": per * 1e3}
+
+
+def cpu_baseline(spec, phi0, target_s=12.0):
+    """The oracle as it stands, on the host cores, on a bounded number of
+    steps of the same workload; MLUPS over the timed steps."""
+    import oracle as orc
+    p = orc.params_from_spec(dict(spec, precision="f64"))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    f, pp = orc.init(p, phi0)
+    t0 = time.perf_counter()
+    orc.step(p, f, pp, nthreads=threads)
+    one = time.perf_counter() - t0
+    n = max(1, min(200, int(target_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    for _ in range(n):
+        orc.step(p, f, pp, nthreads=threads)
+    dt = time.perf_counter() - t0
+    N = orc.nodes(p)
+    return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n + 1} steps of the 1024x1024 D2Q9 headline workload in FP64 "
+                      f"(first step untimed), OpenMP over nodes"}, orc.phi(p, f), n + 1
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--quick", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30,
+                    help="size of the plain copy (practical bandwidth, counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1603_09577_amd import lbm, workloads as W
+
+    torch.cuda.set_device(0)
+    K, Wm = args.steps, args.warmup
+    spec32, phi0, _ = W.C2(1024, precision="f32")
+    spec64, _, _ = W.C2(1024, precision="f64")
+
+    head, sim32, phi32 = run_forward(torch, lbm, spec32, phi0, K, Wm, "C2 f32")
+    print(f"# C2 f32: {head['mlups']:.0f} MLUPS, {head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    f64, sim64, phi64 = run_forward(torch, lbm, spec64, phi0, K, Wm, "C2 f64")
+    print(f"# C2 f64: {f64['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    # both ran warmup + K steps from the same phi0: error of FP32 storage
+    # against the FP64 path after the same number of steps
+    err32 = float(torch.linalg.norm(phi32 - phi64) / torch.linalg.norm(phi64))
+
+    extra = {}
+    if not args.quick:
+        spec5, p5, _, _ = W.C5()
+        extra["adjoint_f64"] = run_adjoint(torch, lbm, spec5, p5, 500, 50, "C5 adjoint f64")
+        spec5f, _, _, _ = W.C5(precision="f32")
+        extra["adjoint_f32"] = run_adjoint(torch, lbm, spec5f, p5, 500, 50, "C5 adjoint f32")
+        print(f"# adjoint f64 {extra['adjoint_f64']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        spec3, p3, _ = W.C3(precision="f32")
+        d3, s3, _ = run_forward(torch, lbm, spec3, p3, 200, 20, "C3 f32")
+        del s3
+        extra["d3q19_f32"] = d3
+        spec3d, _, _ = W.C3(precision="f64")
+        d3d, s3d, _ = run_forward(torch, lbm, spec3d, p3, 100, 10, "C3 f64")
+        del s3d
+        extra["d3q19_f64"] = d3d
+        print(f"# C3 f32 {d3['mlups']:.0f} / f64 {d3d['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extra["batch_f32"] = run_batch(torch, lbm, W, 1000)
+        print(f"# batch {extra['batch_f32']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    extra["copy_probe"] = copy_probe(torch, args.copy_bytes)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu, phi_cpu, ncpu = cpu_baseline(spec64, phi0)
+        # same number of steps on the GPU for an oracle comparison of both paths
+        errs = {}
+        for name, sp in (("f64", spec64), ("f32", spec32)):
+            s = lbm.Lbm(sp).init(phi0)
+            s.step(ncpu)
+            ph = s.phi().cpu().numpy()
+            errs[name] = float(np.linalg.norm(ph - phi_cpu) / np.linalg.norm(phi_cpu))
+        extra["rel_l2_vs_oracle"] = {"steps": ncpu, **errs}
+
+    per = head["ms_per_step"] / 1e3
+    traffic = traffic_from_profiles("C2 f32")
+    line = {
+        "metric": METRIC,
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "D2Q9 MRT nonlinear anisotropic CDE with Scheme-A source, periodic 1024x1024, "
+                        "FP32 offset storage (headline); FP64 storage beside it",
+            "lattice": "D2Q9", "grid": [1024, 1024], "storage": "f32 offsets f - w phi_ref",
+            "scheme": "A", "grid_spacing": W.NONLINEAR_DX, "time_step": W.NONLINEAR_DT,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": head["achieved_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": head["hbm_frac"], "traffic": traffic,
+            "kernel": "k_sweep<9, float, float, EQR, SRC, KVAR, !WALL>",
+            "bytes_per_node": head["bytes_per_node"], "nodes_per_launch": head["nodes"],
+        },
+        "cpu_baseline": cpu,
+        "fp64": {"mlups": f64["mlups"], "ms_per_step": f64["ms_per_step"],
+                 "achieved_gbs": f64["achieved_gbs"], "hbm_frac": f64["hbm_frac"]},
+        "fp32_vs_fp64_mlups": head["mlups"] / f64["mlups"],
+        "fp32_rel_l2_vs_fp64_after_run": err32,
+        "nonfinite": head["nonfinite"] + f64["nonfinite"],
+        **extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

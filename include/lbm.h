@@ -62,6 +62,8 @@ extern "C" {
 #define LBM_FLAG_MOMENT_PATH 1 /* always use the moment-space collision even
                                   when all non-flux rates are equal          */
 #define LBM_FLAG_NO_XCD_REMAP 2 /* launch blocks in plain order             */
+#define LBM_FLAG_NO_GRAPH 4   /* lbm_step launches every sweep directly
+                                 instead of replaying captured graphs       */
 
 #define LBM_MAXP 9            /* polynomial coefficients per function        */
 
@@ -118,9 +120,12 @@ int lbm_init(lbm_ctx *ctx, const double *phi0_dev, void *f_a, void *f_b, void *p
              void *stream);
 
 /* Advance nsteps time steps (Eq. 2 with the Scheme-A source, anti-bounce-back
- * walls), one fused stream-collide sweep per step.  Asynchronous unless a
- * divergence check is due (lbm_set_check), in which case it synchronises the
- * stream and returns LBM_E_DIVERGED when a non-finite phi appeared. */
+ * walls), one fused stream-collide sweep per step.  Runs of 32 sweeps are
+ * replayed from a HIP graph captured on first use (an internal stream; the
+ * graph is launched on the caller's stream) unless LBM_FLAG_NO_GRAPH is set or
+ * a divergence check is enabled.  Asynchronous unless a divergence check is
+ * due (lbm_set_check), in which case it synchronises the stream and returns
+ * LBM_E_DIVERGED when a non-finite phi appeared. */
 int lbm_step(lbm_ctx *ctx, int nsteps, void *stream);
 
 /* One sweep between explicit buffers: f_out <- sweep(f_in), p updated in
@@ -187,6 +192,52 @@ int lbm_adjoint_grad_k0(lbm_ctx *ctx, double out[6], void *stream);
 
 void lbm_destroy(lbm_ctx *ctx);
 const char *lbm_last_error(void);
+
+/* ---- batches of independent D2Q9 instances ------------------------------- *
+ * Many periodic D2Q9 instances of uneven size, each with its own description
+ * (sizes, K0, B, ... ; same precision, equal non-flux rates), advanced by one
+ * launch per time step over a device work list of tiles, replayed from
+ * captured HIP graphs.  The caller owns three arenas: two distribution arenas
+ * and one history arena (sizes from lbm_batch_layout); phi fields of all
+ * instances are concatenated in one FP64 arena, instance i at node offset
+ * lbm_batch_instance(i) in [ny][nx] order. */
+typedef struct lbm_batch lbm_batch;
+
+/* Validate every description (as lbm_create; LBM_E_UNSUPPORTED for walls,
+ * D3Q19 or unequal non-flux rates) and build the work lists.  Allocates the
+ * per-instance tables and work lists on the current device. */
+int lbm_batch_create(const lbm_desc *descs, int count, lbm_batch **out);
+int lbm_batch_layout(const lbm_batch *b, size_t *f_bytes, size_t *p_bytes, long long *total_nodes);
+int lbm_batch_instance(const lbm_batch *b, int i, long long *node_offset, int *nx, int *ny);
+
+/* Bind the arenas and initialise every instance at equilibrium (Eq. 40) from
+ * the concatenated phi0 arena (kept by pointer until the next init: the
+ * autotuner re-initialises from it). */
+int lbm_batch_init(lbm_batch *b, const double *phi0_arena, void *f_a, void *f_b, void *p, void *stream);
+
+/* Advance every instance nsteps steps. */
+int lbm_batch_step(lbm_batch *b, int nsteps, void *stream);
+
+/* phi of every instance into the FP64 arena. */
+int lbm_batch_get_phi(lbm_batch *b, double *phi_arena, void *stream);
+
+/* Autotuner (synchronous): times each candidate launch shape (workgroup size
+ * and nodes per thread, persistent grid size, XCD-aware order) over `reps`
+ * sweeps of the bound batch, keeps the fastest, then re-initialises the
+ * state from the phi0 arena given to lbm_batch_init (step counter back to 0).
+ * With use_cache, a previous decision for the same batch signature is read
+ * from (and new ones appended to) the text file named by $LBM_TUNE_CACHE,
+ * default ~/.cache/lbm_batch_tune.txt.  A report of the timings is written
+ * into `report` (may be NULL). */
+int lbm_batch_tune(lbm_batch *b, int reps, int use_cache, void *stream, char *report, size_t report_len);
+
+/* Force / read the launch shape: shape index 0..3 = (256 threads, 1 node per
+ * thread), (256, 2), (128, 1), (512, 1); grid 0 = one workgroup per tile,
+ * otherwise persistent workgroups over contiguous chunks of the list. */
+int lbm_batch_set_shape(lbm_batch *b, int shape, unsigned grid, int remap);
+int lbm_batch_get_shape(const lbm_batch *b, int *shape, unsigned *grid, int *remap, int *wg, int *npt);
+
+void lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus
 }

@@ -49,6 +49,7 @@ int hip_fail(hipError_t e, const char *where) {
 constexpr int kRedParts = 1024;       // partial rows of the phi reductions
 constexpr int kAdjWidth = 6;          // K0 gradient entries per adjoint partial
 constexpr int kMaxAdjParts = 65536;   // workgroups covered by the adjoint partials
+constexpr int kGraphSteps = 32;       // sweeps per captured graph (even: ends on the start buffer)
 
 }  // namespace
 
@@ -69,6 +70,10 @@ struct lbm_ctx {
     long long t = 0;
     int check_every = 0;
     bool bound = false;
+    // graphs of kGraphSteps sweeps starting from buffer 0 / 1, captured on an
+    // internal stream and launched on the caller's stream
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -299,7 +304,66 @@ hipError_t sweep(lbm_ctx *c, const void *fin, void *fout, void *p, hipStream_t s
                         : launch_sweep_q19(c->dm, c->g, c->d_coefs, fin, fout, p, c->d_flag, st);
 }
 
+void drop_graphs(lbm_ctx *c) {
+    for (int i = 0; i < 2; ++i)
+        if (c->gexec[i]) { (void)hipGraphExecDestroy(c->gexec[i]); c->gexec[i] = nullptr; }
+}
+
+// kGraphSteps sweeps starting from buffer `start`, as one executable graph.
+hipError_t make_graph(lbm_ctx *c, int start) {
+    hipError_t e = hipSuccess;
+    if (!c->cap) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    int cur = start;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < kGraphSteps && le == hipSuccess; ++i) {
+        le = sweep(c, c->f[cur], c->f[cur ^ 1], c->p, c->cap);
+        cur ^= 1;
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(c->cap, &graph);
+    if (le != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return le; }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&c->gexec[start], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return e;
+}
+
 }  // namespace
+
+namespace lbm {
+
+// Validation and packed constants of one description (used by the batch API).
+int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, void *coefs_out,
+                 size_t *coef_bytes) {
+    Dims dm;
+    const int rc = validate(d, dm);
+    if (rc != LBM_OK) return rc;
+    HostModel m;
+    derive(*d, dm, m);
+    if (dm.prec == 0) {
+        Coefs<double> cf;
+        pack(m, cf);
+        std::memcpy(coefs_out, &cf, sizeof(cf));
+        *coef_bytes = sizeof(cf);
+    } else {
+        Coefs<float> cf;
+        pack(m, cf);
+        std::memcpy(coefs_out, &cf, sizeof(cf));
+        *coef_bytes = sizeof(cf);
+    }
+    *prec = dm.prec;
+    *eqr = dm.eqr;
+    *src = dm.src;
+    *kvar = dm.kvar;
+    return LBM_OK;
+}
+
+int api_fail(int code, const char *msg) { return fail(code, msg); }
+
+}  // namespace lbm
 
 extern "C" {
 
@@ -343,6 +407,8 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
 
 void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->d_coefs) (void)hipFree(c->d_coefs);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     delete c;
@@ -359,6 +425,7 @@ int lbm_init(lbm_ctx *c, const double *phi0, void *f_a, void *f_b, void *p, void
     if (!c || !phi0 || !f_a || !f_b || !p) return fail(LBM_E_INVALID, "null argument");
     if (f_a == f_b) return fail(LBM_E_INVALID, "the two distribution buffers must differ");
     if (((uintptr_t)f_a | (uintptr_t)f_b | (uintptr_t)p) & 255) return fail(LBM_E_INVALID, "buffers must be 256-byte aligned");
+    if (c->f[0] != f_a || c->f[1] != f_b || c->p != p) drop_graphs(c);
     c->f[0] = f_a; c->f[1] = f_b; c->p = p;
     c->cur = 0; c->t = 0; c->bound = true;
     hipStream_t st = (hipStream_t)stream;
@@ -375,6 +442,17 @@ int lbm_step(lbm_ctx *c, int nsteps, void *stream) {
     if (!c->bound) return fail(LBM_E_STATE, "lbm_init has not been called");
     if (nsteps < 0) return fail(LBM_E_INVALID, "negative step count");
     hipStream_t st = (hipStream_t)stream;
+    const bool graphs = c->check_every == 0 && !(c->desc.flags & LBM_FLAG_NO_GRAPH);
+    while (graphs && nsteps >= kGraphSteps) {
+        if (!c->gexec[c->cur]) {
+            hipError_t e = make_graph(c, c->cur);
+            if (e != hipSuccess) return hip_fail(e, "graph capture");
+        }
+        hipError_t e = hipGraphLaunch(c->gexec[c->cur], st);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        c->t += kGraphSteps;
+        nsteps -= kGraphSteps;
+    }
     for (int i = 0; i < nsteps; ++i) {
         hipError_t e = sweep(c, c->f[c->cur], c->f[c->cur ^ 1], c->p, st);
         if (e != hipSuccess) return hip_fail(e, "sweep kernel");

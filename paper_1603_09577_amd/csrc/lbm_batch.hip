@@ -1,0 +1,537 @@
+// Many independent D2Q9 instances of uneven size advanced by one launch per
+// time step.
+//
+// All instances' distribution planes live in two arenas (ping-pong) and one
+// phi-history arena owned by the caller.  A device work list holds one entry
+// per tile (instance, first node); a tile is WG * NPT consecutive nodes of
+// one instance.  Workgroups walk contiguous chunks of the list (persistent
+// when the grid is smaller than the tile count); the chunk order is
+// XCD-aware so that each XCD sweeps a contiguous run of instances.  Runs of
+// sweeps are replayed from captured HIP graphs.  An autotuner times the
+// candidate (WG, NPT, grid) shapes on the real batch and keeps the fastest;
+// results are cached in a small text file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+struct BatchInst {
+    Geom g;
+    uint64_t f_off;    // element offset of plane 0 in the distribution arenas
+    uint64_t p_off;    // element offset in the history arena and the phi arena
+};
+
+struct TileShape {
+    int wg, npt;
+};
+
+constexpr TileShape kShapes[] = {{256, 1}, {256, 2}, {128, 1}, {512, 1}};
+constexpr int kNumShapes = 4;
+
+template <typename TS, typename TC, bool SRC, bool KVAR, int WG, int NPT>
+__global__ void __launch_bounds__(WG)
+k_batch_sweep(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ coefs,
+              const uint2 *__restrict__ tiles, uint32_t ntiles, uint32_t chunk, int remap,
+              const TS *__restrict__ fin, TS *__restrict__ fout, typename HistType<TS>::T *p, int *flag) {
+    const uint32_t b = block_index(blockIdx.x, gridDim.x, remap);
+    const uint32_t t0 = b * chunk;
+    const uint32_t t1 = min(t0 + chunk, ntiles);
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint2 e = tiles[t];
+        const BatchInst &I = inst[e.x];
+        const Geom g = I.g;
+        const Coefs<TC> *cf = coefs + e.x;
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const uint32_t n = e.y + j * WG + threadIdx.x;
+            if (n < g.N)
+                sweep_node<9, TS, TC, true, SRC, KVAR, false>(g, cf, fin + I.f_off, fout + I.f_off,
+                                                               p + I.p_off, flag, n);
+        }
+    }
+}
+
+template <typename TS, typename TC>
+__global__ void __launch_bounds__(256)
+k_batch_init(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ coefs,
+             const uint2 *__restrict__ tiles, uint32_t ntiles, int tile_nodes, const double *__restrict__ phi0,
+             TS *__restrict__ f, typename HistType<TS>::T *p) {
+    using L = Lattice<9>;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint2 e = tiles[t];
+        const BatchInst &I = inst[e.x];
+        const Geom g = I.g;
+        const Coefs<TC> *cf = coefs + e.x;
+        for (int j = threadIdx.x; j < tile_nodes; j += 256) {
+            const uint32_t n = e.y + j;
+            if (n >= g.N) continue;
+            const NodeGeo ng = node_geometry<9, false>(g, n);
+            const double *ph0 = phi0 + I.p_off;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                int off = 0;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int c = L::c(k, a);
+                    off += (c == 1) ? ng.op[a] : ((c == -1) ? ng.om[a] : 0);
+                }
+                const TC ph = (TC)ph0[(uint32_t)((int)n + off)];
+                store_s(f + I.f_off + (uint64_t)k * g.plane + n, feq_one<9>(cf, ph, k));
+            }
+            p[I.p_off + n] = (typename HistType<TS>::T)((TC)ph0[n] - cf->phi_ref);
+        }
+    }
+}
+
+template <typename TS, typename TC>
+__global__ void __launch_bounds__(256)
+k_batch_phi(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ coefs,
+            const uint2 *__restrict__ tiles, uint32_t ntiles, int tile_nodes, const TS *__restrict__ f,
+            double *__restrict__ phi) {
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint2 e = tiles[t];
+        const BatchInst &I = inst[e.x];
+        const Geom g = I.g;
+        const Coefs<TC> *cf = coefs + e.x;
+        for (int j = threadIdx.x; j < tile_nodes; j += 256) {
+            const uint32_t n = e.y + j;
+            if (n >= g.N) continue;
+            const NodeGeo ng = node_geometry<9, false>(g, n);
+            TC h[9];
+            gather<9, false>(g, cf, f + I.f_off, ng, h);
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc += (double)h[k];
+            phi[I.p_off + n] = (double)cf->phi_ref + acc;
+        }
+    }
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+namespace lbm {
+// coefficient derivation shared with the single-instance API (lbm_api.hip)
+int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, void *coefs_out,
+                 size_t *coef_bytes);
+const char *api_error_message();
+int api_fail(int code, const char *msg);
+}  // namespace lbm
+
+struct lbm_batch {
+    int count = 0;
+    int prec = 0;
+    bool src = false, kvar = false;
+    size_t coef_stride = 0;
+    std::vector<BatchInst> inst;
+    std::vector<int> nx, ny;
+    uint64_t total_nodes = 0;
+    BatchInst *d_inst = nullptr;
+    void *d_coefs = nullptr;
+    // one tile list per shape (tile size differs)
+    uint2 *d_tiles[kNumShapes] = {nullptr, nullptr, nullptr, nullptr};
+    uint32_t ntiles[kNumShapes] = {0, 0, 0, 0};
+    int *d_flag = nullptr;
+    int shape = 0;          // index into kShapes
+    uint32_t grid = 0;      // workgroups per sweep (0 = one per tile)
+    int remap = 1;
+    void *f[2] = {nullptr, nullptr};
+    void *p = nullptr;
+    const double *phi0 = nullptr;
+    int cur = 0;
+    long long t = 0;
+    bool bound = false;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::string key;
+};
+
+namespace {
+
+constexpr int kBatchGraphSteps = 32;
+
+size_t ssize(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+size_t hsize(int prec) { return prec == 0 ? 8 : 4; }
+size_t r256(size_t v) { return (v + 255) & ~size_t(255); }
+
+hipError_t batch_sweep_launch(lbm_batch *b, const void *fin, void *fout, hipStream_t st) {
+    const TileShape sh = kShapes[b->shape];
+    const uint32_t nt = b->ntiles[b->shape];
+    const uint32_t grid = (b->grid == 0 || b->grid > nt) ? nt : b->grid;
+    const uint32_t chunk = (nt + grid - 1) / grid;
+    const uint32_t nblk = (nt + chunk - 1) / chunk;
+    const uint2 *tl = b->d_tiles[b->shape];
+#define LBM_BL(TS, TC, S, K, WG, NPT)                                                                   \
+    hipLaunchKernelGGL((k_batch_sweep<TS, TC, S, K, WG, NPT>), dim3(nblk), dim3(WG), 0, st,             \
+                       b->d_inst, (const Coefs<TC> *)b->d_coefs, tl, nt, chunk, b->remap,               \
+                       (const TS *)fin, (TS *)fout, (typename HistType<TS>::T *)b->p, b->d_flag)
+#define LBM_BL_SHAPE(TS, TC, S, K)                                                                      \
+    switch (b->shape) {                                                                                 \
+        case 0: LBM_BL(TS, TC, S, K, 256, 1); break;                                                    \
+        case 1: LBM_BL(TS, TC, S, K, 256, 2); break;                                                    \
+        case 2: LBM_BL(TS, TC, S, K, 128, 1); break;                                                    \
+        default: LBM_BL(TS, TC, S, K, 512, 1); break;                                                   \
+    }
+#define LBM_BL_FLAGS(TS, TC)                                                                            \
+    if (b->src && b->kvar) { LBM_BL_SHAPE(TS, TC, true, true) }                                         \
+    else if (b->src) { LBM_BL_SHAPE(TS, TC, true, false) }                                              \
+    else if (b->kvar) { LBM_BL_SHAPE(TS, TC, false, true) }                                             \
+    else { LBM_BL_SHAPE(TS, TC, false, false) }
+    (void)sh;
+    if (b->prec == 0) { LBM_BL_FLAGS(double, double) }
+    else if (b->prec == 1) { LBM_BL_FLAGS(float, float) }
+    else { LBM_BL_FLAGS(_Float16, float) }
+#undef LBM_BL_FLAGS
+#undef LBM_BL_SHAPE
+#undef LBM_BL
+    return hipGetLastError();
+}
+
+void drop_graphs(lbm_batch *b) {
+    for (int i = 0; i < 2; ++i)
+        if (b->gexec[i]) { (void)hipGraphExecDestroy(b->gexec[i]); b->gexec[i] = nullptr; }
+}
+
+hipError_t make_graph(lbm_batch *b, int start) {
+    hipError_t e = hipSuccess;
+    if (!b->cap) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    int cur = start;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < kBatchGraphSteps && le == hipSuccess; ++i) {
+        le = batch_sweep_launch(b, b->f[cur], b->f[cur ^ 1], b->cap);
+        cur ^= 1;
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(b->cap, &graph);
+    if (le != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return le; }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&b->gexec[start], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return e;
+}
+
+hipError_t batch_init_launch(lbm_batch *b, hipStream_t st) {
+    const uint32_t nt = b->ntiles[0];
+    const int tn = kShapes[0].wg * kShapes[0].npt;
+    const uint32_t grid = std::min<uint32_t>(nt, 8192);
+    if (b->prec == 0)
+        hipLaunchKernelGGL((k_batch_init<double, double>), dim3(grid), dim3(256), 0, st, b->d_inst,
+                           (const Coefs<double> *)b->d_coefs, b->d_tiles[0], nt, tn, b->phi0, (double *)b->f[0],
+                           (double *)b->p);
+    else if (b->prec == 1)
+        hipLaunchKernelGGL((k_batch_init<float, float>), dim3(grid), dim3(256), 0, st, b->d_inst,
+                           (const Coefs<float> *)b->d_coefs, b->d_tiles[0], nt, tn, b->phi0, (float *)b->f[0],
+                           (float *)b->p);
+    else
+        hipLaunchKernelGGL((k_batch_init<_Float16, float>), dim3(grid), dim3(256), 0, st, b->d_inst,
+                           (const Coefs<float> *)b->d_coefs, b->d_tiles[0], nt, tn, b->phi0, (_Float16 *)b->f[0],
+                           (float *)b->p);
+    return hipGetLastError();
+}
+
+std::string cache_path() {
+    const char *env = std::getenv("LBM_TUNE_CACHE");
+    if (env && *env) return env;
+    const char *home = std::getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/lbm_batch_tune.txt";
+}
+
+bool cache_lookup(const std::string &key, int &shape, uint32_t &grid, int &remap) {
+    std::ifstream in(cache_path());
+    std::string k;
+    int s, r;
+    unsigned g;
+    while (in >> k >> s >> g >> r)
+        if (k == key && s >= 0 && s < kNumShapes) { shape = s; grid = g; remap = r; return true; }
+    return false;
+}
+
+void cache_store(const std::string &key, int shape, uint32_t grid, int remap) {
+    const std::string path = cache_path();
+    const size_t slash = path.find_last_of('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash);
+        std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
+        if (std::system(cmd.c_str()) != 0) return;
+    }
+    std::ofstream out(path, std::ios::app);
+    if (out) out << key << " " << shape << " " << grid << " " << remap << "\n";
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(const lbm_desc *descs, int count, lbm_batch **out) {
+    if (!descs || !out || count < 1) return api_fail(LBM_E_INVALID, "null descriptions or count < 1");
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return api_fail(LBM_E_INVALID, "out of host memory");
+    b->count = count;
+    std::vector<unsigned char> coefs;
+    std::ostringstream key;
+    uint64_t foff = 0, poff = 0;
+    for (int i = 0; i < count; ++i) {
+        const lbm_desc &d = descs[i];
+        if (d.lattice != LBM_D2Q9) { delete b; return api_fail(LBM_E_UNSUPPORTED, "batches are D2Q9 only"); }
+        if (d.bc[0] != LBM_BC_PERIODIC || d.bc[1] != LBM_BC_PERIODIC) {
+            delete b;
+            return api_fail(LBM_E_UNSUPPORTED, "batched instances must be periodic");
+        }
+        int prec = 0;
+        bool eqr = false, src = false, kvar = false;
+        size_t cb = 0;
+        std::vector<unsigned char> tmp(sizeof(Coefs<double>));
+        const int rc = derive_coefs(&d, &prec, &eqr, &src, &kvar, tmp.data(), &cb);
+        if (rc != LBM_OK) { delete b; return rc; }
+        if (!eqr) { delete b; return api_fail(LBM_E_UNSUPPORTED, "batched instances need equal non-flux rates"); }
+        if (i == 0) { b->prec = prec; b->coef_stride = cb; }
+        else if (prec != b->prec) { delete b; return api_fail(LBM_E_INVALID, "all instances need the same precision"); }
+        b->src = b->src || src;
+        b->kvar = b->kvar || kvar;
+        coefs.insert(coefs.end(), tmp.begin(), tmp.begin() + cb);
+        BatchInst I;
+        std::memset(&I, 0, sizeof(I));
+        I.g.nx = d.nx; I.g.ny = d.ny; I.g.nz = 1;
+        I.g.N = (uint32_t)((size_t)d.nx * d.ny);
+        I.g.plane = I.g.N;
+        I.g.fx.set(I.g.nx);
+        I.g.fxy.set(I.g.N);
+        I.g.nblocks = 0;
+        I.g.remap = 0;
+        I.f_off = foff;
+        I.p_off = poff;
+        foff += 9ull * I.g.N;
+        foff = (foff + 63) & ~63ull;   // keep every instance's planes 256-byte aligned in FP32
+        poff += I.g.N;
+        b->inst.push_back(I);
+        b->nx.push_back(d.nx);
+        b->ny.push_back(d.ny);
+        b->total_nodes += I.g.N;
+        key << d.nx << "x" << d.ny << ",";
+    }
+    if (b->total_nodes >= (1ull << 31) || foff >= (1ull << 40)) {
+        delete b;
+        return api_fail(LBM_E_INVALID, "batch too large");
+    }
+    {
+        // short key: precision, flags, FNV-1a of the size list
+        std::string s = key.str();
+        uint64_t h = 1469598103934665603ull;
+        for (char c : s) { h ^= (unsigned char)c; h *= 1099511628211ull; }
+        char buf[64];
+        std::snprintf(buf, sizeof(buf), "p%d_s%d_k%d_n%d_%016llx", b->prec, (int)b->src, (int)b->kvar, count,
+                      (unsigned long long)h);
+        b->key = buf;
+    }
+    hipError_t e = hipMalloc((void **)&b->d_inst, sizeof(BatchInst) * count);
+    if (e == hipSuccess) e = hipMalloc(&b->d_coefs, coefs.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_flag, 256);
+    if (e == hipSuccess) e = hipMemcpy(b->d_inst, b->inst.data(), sizeof(BatchInst) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_coefs, coefs.data(), coefs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->d_flag, 0, 256);
+    for (int s = 0; s < kNumShapes && e == hipSuccess; ++s) {
+        const uint32_t tn = (uint32_t)(kShapes[s].wg * kShapes[s].npt);
+        std::vector<uint2> tl;
+        for (int i = 0; i < count; ++i)
+            for (uint32_t n = 0; n < b->inst[i].g.N; n += tn) tl.push_back(make_uint2((unsigned)i, n));
+        b->ntiles[s] = (uint32_t)tl.size();
+        e = hipMalloc((void **)&b->d_tiles[s], sizeof(uint2) * tl.size());
+        if (e == hipSuccess) e = hipMemcpy(b->d_tiles[s], tl.data(), sizeof(uint2) * tl.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        lbm_batch_destroy(b);
+        std::string m = std::string("batch setup: ") + hipGetErrorString(e);
+        return api_fail(LBM_E_HIP, m.c_str());
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b) {
+    if (!b) return;
+    drop_graphs(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_coefs) (void)hipFree(b->d_coefs);
+    if (b->d_flag) (void)hipFree(b->d_flag);
+    for (int s = 0; s < kNumShapes; ++s)
+        if (b->d_tiles[s]) (void)hipFree(b->d_tiles[s]);
+    delete b;
+}
+
+int lbm_batch_layout(const lbm_batch *b, size_t *f_bytes, size_t *p_bytes, long long *total_nodes) {
+    if (!b) return api_fail(LBM_E_INVALID, "null batch");
+    const BatchInst &last = b->inst.back();
+    const uint64_t fel = last.f_off + 9ull * last.g.N;
+    if (f_bytes) *f_bytes = r256(fel * ssize(b->prec));
+    if (p_bytes) *p_bytes = r256(b->total_nodes * hsize(b->prec));
+    if (total_nodes) *total_nodes = (long long)b->total_nodes;
+    return LBM_OK;
+}
+
+int lbm_batch_instance(const lbm_batch *b, int i, long long *node_offset, int *nx, int *ny) {
+    if (!b || i < 0 || i >= b->count) return api_fail(LBM_E_INVALID, "bad instance index");
+    if (node_offset) *node_offset = (long long)b->inst[i].p_off;
+    if (nx) *nx = b->nx[i];
+    if (ny) *ny = b->ny[i];
+    return LBM_OK;
+}
+
+int lbm_batch_init(lbm_batch *b, const double *phi0, void *f_a, void *f_b, void *p, void *stream) {
+    if (!b || !phi0 || !f_a || !f_b || !p) return api_fail(LBM_E_INVALID, "null argument");
+    if (f_a == f_b) return api_fail(LBM_E_INVALID, "the two distribution buffers must differ");
+    if (((uintptr_t)f_a | (uintptr_t)f_b | (uintptr_t)p) & 255) return api_fail(LBM_E_INVALID, "buffers must be 256-byte aligned");
+    if (b->f[0] != f_a || b->f[1] != f_b || b->p != p) drop_graphs(b);
+    b->f[0] = f_a; b->f[1] = f_b; b->p = p; b->phi0 = phi0;
+    b->cur = 0; b->t = 0; b->bound = true;
+    hipError_t e = batch_init_launch(b, (hipStream_t)stream);
+    if (e != hipSuccess) return api_fail(LBM_E_HIP, hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_batch_set_shape(lbm_batch *b, int shape, unsigned grid, int remap) {
+    if (!b || shape < 0 || shape >= kNumShapes) return api_fail(LBM_E_INVALID, "bad shape index");
+    b->shape = shape;
+    b->grid = grid;
+    b->remap = remap ? 1 : 0;
+    drop_graphs(b);
+    return LBM_OK;
+}
+
+int lbm_batch_get_shape(const lbm_batch *b, int *shape, unsigned *grid, int *remap, int *wg, int *npt) {
+    if (!b) return api_fail(LBM_E_INVALID, "null batch");
+    if (shape) *shape = b->shape;
+    if (grid) *grid = b->grid;
+    if (remap) *remap = b->remap;
+    if (wg) *wg = kShapes[b->shape].wg;
+    if (npt) *npt = kShapes[b->shape].npt;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int nsteps, void *stream) {
+    if (!b) return api_fail(LBM_E_INVALID, "null batch");
+    if (!b->bound) return api_fail(LBM_E_STATE, "lbm_batch_init has not been called");
+    if (nsteps < 0) return api_fail(LBM_E_INVALID, "negative step count");
+    hipStream_t st = (hipStream_t)stream;
+    while (nsteps >= kBatchGraphSteps) {
+        if (!b->gexec[b->cur]) {
+            hipError_t e = make_graph(b, b->cur);
+            if (e != hipSuccess) return api_fail(LBM_E_HIP, hipGetErrorString(e));
+        }
+        hipError_t e = hipGraphLaunch(b->gexec[b->cur], st);
+        if (e != hipSuccess) return api_fail(LBM_E_HIP, hipGetErrorString(e));
+        b->t += kBatchGraphSteps;
+        nsteps -= kBatchGraphSteps;
+    }
+    for (int i = 0; i < nsteps; ++i) {
+        hipError_t e = batch_sweep_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st);
+        if (e != hipSuccess) return api_fail(LBM_E_HIP, hipGetErrorString(e));
+        b->cur ^= 1;
+        ++b->t;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_get_phi(lbm_batch *b, double *phi, void *stream) {
+    if (!b || !phi) return api_fail(LBM_E_INVALID, "null argument");
+    if (!b->bound) return api_fail(LBM_E_STATE, "lbm_batch_init has not been called");
+    const uint32_t nt = b->ntiles[0];
+    const int tn = kShapes[0].wg * kShapes[0].npt;
+    const uint32_t grid = std::min<uint32_t>(nt, 8192);
+    hipStream_t st = (hipStream_t)stream;
+    if (b->prec == 0)
+        hipLaunchKernelGGL((k_batch_phi<double, double>), dim3(grid), dim3(256), 0, st, b->d_inst,
+                           (const Coefs<double> *)b->d_coefs, b->d_tiles[0], nt, tn, (const double *)b->f[b->cur], phi);
+    else if (b->prec == 1)
+        hipLaunchKernelGGL((k_batch_phi<float, float>), dim3(grid), dim3(256), 0, st, b->d_inst,
+                           (const Coefs<float> *)b->d_coefs, b->d_tiles[0], nt, tn, (const float *)b->f[b->cur], phi);
+    else
+        hipLaunchKernelGGL((k_batch_phi<_Float16, float>), dim3(grid), dim3(256), 0, st, b->d_inst,
+                           (const Coefs<float> *)b->d_coefs, b->d_tiles[0], nt, tn, (const _Float16 *)b->f[b->cur], phi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return api_fail(LBM_E_HIP, hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_batch_tune(lbm_batch *b, int reps, int use_cache, void *stream, char *report, size_t report_len) {
+    if (!b) return api_fail(LBM_E_INVALID, "null batch");
+    if (!b->bound) return api_fail(LBM_E_STATE, "lbm_batch_init has not been called");
+    if (reps < 1) reps = 1;
+    hipStream_t st = (hipStream_t)stream;
+    std::ostringstream rep;
+    int shape = 0, remap = 1;
+    uint32_t grid = 0;
+    if (use_cache && cache_lookup(b->key, shape, grid, remap)) {
+        lbm_batch_set_shape(b, shape, grid, remap);
+        rep << "cached " << b->key << " shape " << shape << " grid " << grid << " remap " << remap;
+    } else {
+        int cus = 256;
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t pr;
+            if (hipGetDeviceProperties(&pr, dev) == hipSuccess) cus = pr.multiProcessorCount;
+        }
+        const uint32_t grids[] = {0u, (uint32_t)cus * 4, (uint32_t)cus * 8, (uint32_t)cus * 16};
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return api_fail(LBM_E_HIP, "hipEventCreate");
+        float best = 1e30f;
+        for (int s = 0; s < kNumShapes; ++s)
+            for (uint32_t gr : grids)
+                for (int rm = 0; rm < 2; ++rm) {
+                    b->shape = s; b->grid = gr; b->remap = rm;
+                    // sweeps read the current state and write the other buffer only
+                    hipError_t e = batch_sweep_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st);
+                    if (e == hipSuccess) e = hipEventRecord(e0, st);
+                    for (int r = 0; r < reps && e == hipSuccess; ++r)
+                        e = batch_sweep_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st);
+                    if (e == hipSuccess) e = hipEventRecord(e1, st);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e != hipSuccess) {
+                        (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+                        return api_fail(LBM_E_HIP, hipGetErrorString(e));
+                    }
+                    ms /= reps;
+                    rep << "wg " << kShapes[s].wg << " npt " << kShapes[s].npt << " grid " << gr << " remap " << rm
+                        << ": " << ms << " ms\n";
+                    if (ms < best) { best = ms; shape = s; grid = gr; remap = rm; }
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        lbm_batch_set_shape(b, shape, grid, remap);
+        if (use_cache) cache_store(b->key, shape, grid, remap);
+        rep << "chosen shape " << shape << " grid " << grid << " remap " << remap << " (" << best << " ms)";
+        // the history buffer was overwritten by the trial sweeps: restore the state
+        hipError_t e = batch_init_launch(b, st);
+        if (e != hipSuccess) return api_fail(LBM_E_HIP, hipGetErrorString(e));
+        b->t = 0;
+        b->cur = 0;
+    }
+    if (report && report_len) {
+        std::string s = rep.str();
+        std::snprintf(report, report_len, "%s", s.c_str());
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -208,14 +208,13 @@ __device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restric
 // ---------------------------------------------------------------------------
 // the sweep
 // ---------------------------------------------------------------------------
+// One node of the sweep (shared by the single-instance and batched kernels).
 template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL>
-__global__ void __launch_bounds__(kBlock)
-k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin,
-        TS *__restrict__ fout, typename HistType<TS>::T *p, int *flag) {
+__device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__restrict__ cf,
+                                           const TS *__restrict__ fin, TS *__restrict__ fout,
+                                           typename HistType<TS>::T *p, int *flag, uint32_t n) {
     using L = Lattice<Q>;
     constexpr int D = L::dim;
-    const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
-    if (n >= g.N) return;
     const NodeGeo ng = node_geometry<Q, WALL>(g, n);
 
     TC h[Q];
@@ -335,6 +334,15 @@ k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f
     for (int k = 0; k < Q; ++k) store_s(fout + (uint64_t)k * g.plane + n, out[k]);
 
     if (!__builtin_isfinite(phio)) *flag = 1;
+}
+
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL>
+__global__ void __launch_bounds__(kBlock)
+k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin,
+        TS *__restrict__ fout, typename HistType<TS>::T *p, int *flag) {
+    const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    sweep_node<Q, TS, TC, EQR, SRC, KVAR, WALL>(g, cf, fin, fout, p, flag, n);
 }
 
 // ---------------------------------------------------------------------------

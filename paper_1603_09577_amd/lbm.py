@@ -19,6 +19,7 @@ LBM_OK, LBM_E_INVALID, LBM_E_UNSUPPORTED, LBM_E_HIP, LBM_E_DIVERGED, LBM_E_STATE
 PRECISIONS = {"f64": 0, "f32": 1, "f16": 2}
 FLAG_MOMENT_PATH = 1
 FLAG_NO_XCD_REMAP = 2
+FLAG_NO_GRAPH = 4
 
 # every symbol include/lbm.h declares
 EXPORTS = [
@@ -26,6 +27,9 @@ EXPORTS = [
     "lbm_phi_of", "lbm_current", "lbm_set_current", "lbm_set_check", "lbm_set_k0",
     "lbm_reduce", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_init",
     "lbm_adjoint_grad_k0", "lbm_destroy", "lbm_last_error",
+    "lbm_batch_create", "lbm_batch_layout", "lbm_batch_instance", "lbm_batch_init",
+    "lbm_batch_step", "lbm_batch_get_phi", "lbm_batch_tune", "lbm_batch_set_shape",
+    "lbm_batch_get_shape", "lbm_batch_destroy",
 ]
 
 
@@ -93,6 +97,20 @@ def load():
         "lbm_adjoint_grad_k0": ([_VP, _DP, _VP], ctypes.c_int),
         "lbm_destroy": ([_VP], None),
         "lbm_last_error": ([], ctypes.c_char_p),
+        "lbm_batch_create": ([ctypes.POINTER(LbmDesc), ctypes.c_int, ctypes.POINTER(_VP)], ctypes.c_int),
+        "lbm_batch_layout": ([_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                              ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+        "lbm_batch_instance": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "lbm_batch_init": ([_VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_batch_step": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
+        "lbm_batch_get_phi": ([_VP, _VP, _VP], ctypes.c_int),
+        "lbm_batch_tune": ([_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+        "lbm_batch_set_shape": ([_VP, ctypes.c_int, ctypes.c_uint, ctypes.c_int], ctypes.c_int),
+        "lbm_batch_get_shape": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "lbm_batch_destroy": ([_VP], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -287,3 +305,77 @@ class Lbm:
         import torch
         dt = {0: torch.float64, 1: torch.float32, 2: torch.float16}[self.desc.precision]
         return buf.view(dt)[: self.q * self.N].view(self.q, self.N)
+
+
+class Batch:
+    """Many independent D2Q9 instances advanced together (lbm_batch_*)."""
+
+    def __init__(self, specs, device="cuda"):
+        import torch
+        self.lib = load()
+        self.specs = list(specs)
+        arr = (LbmDesc * len(self.specs))(*[desc_from_spec(sp) for sp in self.specs])
+        b = _VP()
+        _check(self.lib.lbm_batch_create(arr, len(self.specs), ctypes.byref(b)))
+        self.b = b
+        fb, pb, tn = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_longlong()
+        _check(self.lib.lbm_batch_layout(self.b, ctypes.byref(fb), ctypes.byref(pb), ctypes.byref(tn)))
+        self.total_nodes = tn.value
+        self.device = torch.device(device)
+        self.f = [torch.empty(fb.value, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.p = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+        self.offsets, self.shapes = [], []
+        for i in range(len(self.specs)):
+            off, nx, ny = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int()
+            _check(self.lib.lbm_batch_instance(self.b, i, ctypes.byref(off), ctypes.byref(nx), ctypes.byref(ny)))
+            self.offsets.append(off.value)
+            self.shapes.append((ny.value, nx.value))
+
+    def __del__(self):
+        try:
+            if getattr(self, "b", None):
+                self.lib.lbm_batch_destroy(self.b)
+                self.b = None
+        except Exception:
+            pass
+
+    def pack(self, fields):
+        """Concatenate per-instance [ny][nx] fields into one FP64 device arena."""
+        import torch
+        arena = torch.empty(self.total_nodes, dtype=torch.float64, device=self.device)
+        for off, shp, fld in zip(self.offsets, self.shapes, fields):
+            n = shp[0] * shp[1]
+            arena[off:off + n] = torch.as_tensor(np.ascontiguousarray(fld).reshape(-1), dtype=torch.float64)
+        return arena
+
+    def unpack(self, arena):
+        return [arena[off:off + s[0] * s[1]].view(s) for off, s in zip(self.offsets, self.shapes)]
+
+    def init(self, phi0_fields, stream=None):
+        self._phi0 = self.pack(phi0_fields)
+        _check(self.lib.lbm_batch_init(self.b, _ptr(self._phi0), _ptr(self.f[0]), _ptr(self.f[1]), _ptr(self.p),
+                                       _stream(stream)))
+        return self
+
+    def step(self, n=1, stream=None):
+        _check(self.lib.lbm_batch_step(self.b, int(n), _stream(stream)))
+
+    def phi(self, stream=None):
+        import torch
+        out = torch.empty(self.total_nodes, dtype=torch.float64, device=self.device)
+        _check(self.lib.lbm_batch_get_phi(self.b, _ptr(out), _stream(stream)))
+        return out
+
+    def tune(self, reps=5, use_cache=False, stream=None):
+        buf = ctypes.create_string_buffer(8192)
+        _check(self.lib.lbm_batch_tune(self.b, int(reps), int(use_cache), _stream(stream), buf, len(buf)))
+        return buf.value.decode()
+
+    def set_shape(self, shape, grid=0, remap=1):
+        _check(self.lib.lbm_batch_set_shape(self.b, int(shape), int(grid), int(remap)))
+
+    def get_shape(self):
+        s, g, r, wg, npt = (ctypes.c_int(), ctypes.c_uint(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int())
+        _check(self.lib.lbm_batch_get_shape(self.b, ctypes.byref(s), ctypes.byref(g), ctypes.byref(r),
+                                            ctypes.byref(wg), ctypes.byref(npt)))
+        return {"shape": s.value, "grid": g.value, "remap": r.value, "wg": wg.value, "npt": npt.value}

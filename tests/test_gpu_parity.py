@@ -213,3 +213,20 @@ def test_divergence_detected():
     with pytest.raises(lbm.LbmError) as e:
         sim.step(3000)
     assert e.value.code == lbm.LBM_E_DIVERGED
+
+
+def test_graph_replay_identical_to_direct_launches():
+    """lbm_step replays captured 32-sweep graphs; the result is bit-identical
+    to launching every sweep directly."""
+    lbm = _lbm()
+    spec = W.spec_nonlinear_2d(96, 70, precision="f32")
+    phi0 = W.noise_field((70, 96), 19)
+    say("[gpu] graph replay vs direct")
+    a = lbm.Lbm(spec).init(phi0)
+    a.step(100)
+    b = lbm.Lbm(spec, flags=lbm.FLAG_NO_GRAPH).init(phi0)
+    b.step(100)
+    assert torch.equal(a.phi(), b.phi())
+    c = lbm.Lbm(spec, flags=lbm.FLAG_NO_XCD_REMAP).init(phi0)
+    c.step(100)
+    assert torch.equal(a.phi(), c.phi())
