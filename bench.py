@@ -83,8 +83,9 @@ def time_steps(torch, sim, steps, warmup):
     return e0.elapsed_time(e1) / 1e3 / steps, wall
 
 
-def run_forward(torch, lbm, spec, phi0, steps, warmup, label):
+def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True):
     sim = lbm.Lbm(spec).init(phi0)
+    rep = sim.tune(reps=20).splitlines()[-1] if tune else "untuned"
     per, wall = time_steps(torch, sim, steps, warmup)
     N = sim.N
     prec = spec.get("precision", "f64")
@@ -93,7 +94,7 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label):
     out = {
         "label": label, "nodes": N, "steps": steps, "ms_per_step": per * 1e3,
         "mlups": N / per / 1e6, "bytes_per_node": bpn,
-        "achieved_gbs": bpn * N / per / 1e9, "wall_s": wall,
+        "achieved_gbs": bpn * N / per / 1e9, "wall_s": wall, "tuner": rep,
     }
     out["hbm_frac"] = out["achieved_gbs"] / PEAK_HBM_GBS
     phi = sim.phi()
@@ -103,7 +104,9 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label):
 
 
 def run_adjoint(torch, lbm, spec, phi0, steps, warmup, label):
-    """Time the reversed sweep on a fixed forward state."""
+    """Time the reversed sweep on a fixed forward state: `steps` sweeps
+    captured in a HIP graph (through torch's graph capture, which records the
+    library's launches on the capture stream) and replayed."""
     sim = lbm.Lbm(spec).init(phi0)
     sim.step(10)
     which, _ = sim.current()
@@ -116,15 +119,23 @@ def run_adjoint(torch, lbm, spec, phi0, steps, warmup, label):
         sim.adjoint_step(f_s, p_s, psi_a, pi, psi_b, pi)
         psi_a, psi_b = psi_b, psi_a
     torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for i in range(steps):
-        sim.adjoint_step(f_s, p_s, psi_a, pi, psi_b, pi)
-        psi_a, psi_b = psi_b, psi_a
-    e1.record(st)
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    with torch.cuda.graph(graph, stream=cap):
+        a, b = psi_a, psi_b
+        for i in range(steps):
+            sim.adjoint_step(f_s, p_s, a, pi, b, pi)
+            a, b = b, a
+    graph.replay()
     torch.cuda.synchronize()
-    per = e0.elapsed_time(e1) / 1e3 / steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    per = e0.elapsed_time(e1) / 1e3 / (steps * reps)
     prec = spec.get("precision", "f64")
     bpn = adjoint_bytes_per_node(sim.q, prec, bool(spec.get("rpoly")))
     gbs = bpn * sim.N / per / 1e9
@@ -156,22 +167,27 @@ def run_batch(torch, lbm, W, steps):
             "tuner": rep.splitlines()[-1], "finite": bool(fin)}
 
 
-def copy_probe(torch, nbytes=1 << 30, reps=20):
-    """Plain device copy of a buffer much larger than the caches: read + write."""
+def copy_probe(torch, lbm, nbytes=1 << 30, reps=20):
+    """Plain device copy (the library's 16-byte-per-lane copy kernel) of a
+    buffer much larger than the caches: read + write bytes per second."""
     n = nbytes // 4
     a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    per = e0.elapsed_time(e1) / 1e3 / reps
-    return {"bytes_per_copy": 2 * nbytes, "gbs": 2 * nbytes / per / 1e9, "ms": per * 1e3}
+    out = {"bytes_per_copy": 2 * nbytes}
+    for grid in (0, 256 * 64):
+        for _ in range(3):
+            lbm.probe_copy(a, b, grid)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            lbm.probe_copy(a, b, grid)
+        e1.record()
+        torch.cuda.synchronize()
+        per = e0.elapsed_time(e1) / 1e3 / reps
+        out[f"gbs_grid{grid or 4096}"] = 2 * nbytes / per / 1e9
+    out["gbs"] = max(v for k, v in out.items() if k.startswith("gbs_"))
+    return out
 
 
 def cpu_baseline(spec, phi0, target_s=12.0):
@@ -201,6 +217,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--quick", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--only", default="",
+                    help="comma list of secondary workloads to run: adjoint,d3q19,batch (default: all)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain copy (practical bandwidth, counter calibration)")
@@ -226,12 +244,16 @@ def main():
     err32 = float(torch.linalg.norm(phi32 - phi64) / torch.linalg.norm(phi64))
 
     extra = {}
-    if not args.quick:
+    only = set(w for w in args.only.split(",") if w) or {"adjoint", "d3q19", "batch"}
+    if args.quick:
+        only = set()
+    if "adjoint" in only:
         spec5, p5, _, _ = W.C5()
-        extra["adjoint_f64"] = run_adjoint(torch, lbm, spec5, p5, 500, 50, "C5 adjoint f64")
+        extra["adjoint_f64"] = run_adjoint(torch, lbm, spec5, p5, 200, 20, "C5 adjoint f64")
         spec5f, _, _, _ = W.C5(precision="f32")
-        extra["adjoint_f32"] = run_adjoint(torch, lbm, spec5f, p5, 500, 50, "C5 adjoint f32")
+        extra["adjoint_f32"] = run_adjoint(torch, lbm, spec5f, p5, 200, 20, "C5 adjoint f32")
         print(f"# adjoint f64 {extra['adjoint_f64']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    if "d3q19" in only:
         spec3, p3, _ = W.C3(precision="f32")
         d3, s3, _ = run_forward(torch, lbm, spec3, p3, 200, 20, "C3 f32")
         del s3
@@ -242,10 +264,11 @@ def main():
         extra["d3q19_f64"] = d3d
         print(f"# C3 f32 {d3['mlups']:.0f} / f64 {d3d['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
-        extra["batch_f32"] = run_batch(torch, lbm, W, 1000)
+    if "batch" in only:
+        extra["batch_f32"] = run_batch(torch, lbm, W, 1000 if args.steps >= 1000 else args.steps)
         print(f"# batch {extra['batch_f32']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
-    extra["copy_probe"] = copy_probe(torch, args.copy_bytes)
+    extra["copy_probe"] = copy_probe(torch, lbm, args.copy_bytes)
 
     cpu = None
     if not args.no_cpu:

@@ -21,7 +21,8 @@
  *  - Field layout seen by the caller (phi0, phi, targets, gradients): FP64,
  *    C order [nz][ny][nx].  Distribution buffers are opaque (size from
  *    lbm_state_bytes); internally they are structure-of-arrays planes, one
- *    plane of nx*ny*nz values per lattice direction, in the storage type.
+ *    plane of nx*ny*nz values per lattice direction, in the storage type,
+ *    consecutive planes padded apart (plane_pad).
  *  - A context is not thread-safe; distinct contexts are independent.
  */
 #ifndef LBM_H
@@ -96,6 +97,10 @@ typedef struct lbm_desc {
     double kpoly[LBM_MAXP];
     double rpoly[LBM_MAXP];
     int flags;                /* LBM_FLAG_*                                    */
+    int plane_pad;            /* elements added after each direction plane:
+                                 0 = library choice (spreads the planes over
+                                 the L2 sets and memory channels), > 0 exact,
+                                 < 0 none                                      */
 } lbm_desc;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -111,6 +116,10 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out);
 /* Bytes of one distribution buffer (f_bytes) and of the phi-history buffer
  * (p_bytes) that the caller must provide; both multiples of 256. */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *f_bytes, size_t *p_bytes);
+
+/* Bytes of one adjoint-variable buffer psi (same plane layout as the
+ * distribution buffers, in the compute type: FP64 or FP32). */
+int lbm_adjoint_bytes(const lbm_ctx *ctx, size_t *psi_bytes);
 
 /* Bind two distribution buffers and the phi-history buffer, and initialise
  * with the equilibrium of phi0 (Eq. 40; the history is set to phi0, the
@@ -146,6 +155,22 @@ int lbm_current(const lbm_ctx *ctx, void **f, void **p, long long *t);
  * counter (used after the caller restored a state into the other buffer). */
 int lbm_set_current(lbm_ctx *ctx, int which, long long t);
 
+/* Launch shape: each workgroup sweeps `chunk` consecutive 256-node blocks
+ * (1 = one block per workgroup, the default). */
+int lbm_set_chunk(lbm_ctx *ctx, int chunk);
+
+/* Non-temporal (streaming) loads and stores of the distributions in the
+ * equal-rate sweep (default: on when the state exceeds 256 MB, the size of
+ * the Infinity Cache, where they raise HBM throughput; off otherwise, where
+ * they would keep a cache-resident state out of the cache). */
+int lbm_set_nontemporal(lbm_ctx *ctx, int on);
+
+/* Autotuner (synchronous): times the sweep for chunk = 1, 2, 4, 8, 16, with
+ * and without non-temporal accesses, on the bound buffers, keeps the fastest, writes the timings into `report` (may be
+ * NULL) and re-initialises the state from the phi0 given to lbm_init (step
+ * counter back to 0; phi0 must still be valid). */
+int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_len);
+
 /* Divergence check every `every` steps inside lbm_step (0 = off). */
 int lbm_set_check(lbm_ctx *ctx, int every);
 
@@ -171,7 +196,8 @@ int lbm_reduce(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev, doubl
  * accumulator (lbm_adjoint_grad_k0).  Not defined for FP16 storage. */
 
 /* psi_T from dL/dphi(T) (FP64 field): psi_T,k = gphi for every k, pi_T = 0;
- * clears the K0 accumulator. */
+ * clears the K0 accumulator.  Seed, step and init launch kernels only (no
+ * memset or allocation), so a caller may capture them in a HIP graph. */
 int lbm_adjoint_seed(lbm_ctx *ctx, const double *gphi_dev, void *psi, double *pi_out,
                      void *stream);
 
@@ -192,6 +218,12 @@ int lbm_adjoint_grad_k0(lbm_ctx *ctx, double out[6], void *stream);
 
 void lbm_destroy(lbm_ctx *ctx);
 const char *lbm_last_error(void);
+
+/* Measurement aid: plain device copy of `bytes` (multiple of 16, 16-byte
+ * aligned pointers) with `grid` workgroups of 256 lanes (<= 0: 4096), 16
+ * bytes per lane per iteration.  Gives the practical bandwidth of a
+ * read-once / write-once stream and calibrates the traffic counters. */
+int lbm_probe_copy(const void *src, void *dst, size_t bytes, int grid, void *stream);
 
 /* ---- batches of independent D2Q9 instances ------------------------------- *
  * Many periodic D2Q9 instances of uneven size, each with its own description

@@ -23,36 +23,34 @@ FLAGS = [
 ]
 
 
-def sources():
-    return sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
-
-
-def _compile(src):
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(args):
+    src, csrc, build_dir = args
+    obj = os.path.join(build_dir, src.replace(".hip", ".o"))
+    cmd = [HIPCC, *FLAGS, "-c", os.path.join(csrc, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj, r.stderr
 
 
-def build(verbose=False, jobs=None):
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
+def build(verbose=False, jobs=None, csrc=CSRC, build_dir=BUILD, lib=LIB):
+    """Compile every .hip file of `csrc` and link them into `lib`."""
+    os.makedirs(build_dir, exist_ok=True)
+    srcs = sorted(f for f in os.listdir(csrc) if f.endswith(".hip"))
     jobs = jobs or min(len(srcs), os.cpu_count() or 4)
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        for obj, err in ex.map(_compile, srcs):
+        for obj, err in ex.map(_compile, [(f, csrc, build_dir) for f in srcs]):
             objs.append(obj)
             if verbose and err.strip():
                 print(err, file=sys.stderr)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -19,7 +19,7 @@
 
 namespace lbm {
 
-template <int Q, typename TC>
+template <int Q, int NP, typename TC>
 __device__ __forceinline__ void eq_derivative(const Coefs<TC> *__restrict__ cf, TC phi, TC *dfeq) {
     // d feq_k / d phi = w_k [1 + 3 c.B' + 9/2 (E' : c c - tr E' / 3)],
     // E' = C-bar'(phi) - I/3
@@ -27,11 +27,11 @@ __device__ __forceinline__ void eq_derivative(const Coefs<TC> *__restrict__ cf, 
     constexpr int D = L::dim;
     TC Bp[3], E[6];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Bp[a] = (a < D) ? poly<kMaxP>(cf->bp[a], cf->nb, phi) : TC(0);
+    for (int a = 0; a < 3; ++a) Bp[a] = (a < D) ? poly<NP>(cf->bp[a], phi) : TC(0);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         const bool used = (D == 3) || (i == 0 || i == 1 || i == 3);
-        E[i] = used ? poly<kMaxC>(cf->cbd[i], cf->ncb, phi) : TC(0);
+        E[i] = used ? poly<PolyLen<NP>::NC>(cf->cbd[i], phi) : TC(0);
     }
     E[0] -= TC(1.0 / 3.0); E[1] -= TC(1.0 / 3.0);
     if (D == 3) E[2] -= TC(1.0 / 3.0);
@@ -80,22 +80,24 @@ __device__ __forceinline__ void gbar_of(const TC *A, const TC Ab[3][3], TC *Gb) 
 // Contribution of Gbar at a phi value to dL/dphi (when k varies) and to the
 // per-node K0 accumulator (symmetric parametrisation: off-diagonal entries
 // count twice).
-template <int DIM, bool KVAR, typename TC>
+template <int DIM, bool KVAR, int NP, typename TC>
 __device__ __forceinline__ TC gbar_scatter(const Coefs<TC> *__restrict__ cf, TC phi, const TC *Gb, TC *gk) {
-    const TC kv = KVAR ? poly<kMaxP>(cf->kp, cf->nk, phi) : cf->kp[0];
+    const TC kv = KVAR ? poly<NP>(cf->kp, phi) : cf->kp[0];
     // g0 = 3 K0 / d, so dG/dK0_ab = (3/d) k(phi); g0 / K0 = 3 / d is folded on the host
 #pragma unroll
     for (int i = 0; i < 6; ++i) gk[i] += Gb[i] * kv * (i < 3 ? TC(1) : TC(2));
     if (!KVAR) return TC(0);
-    const TC kd = poly<kMaxP>(cf->kdp, cf->nk, phi);
+    const TC kd = poly<NP>(cf->kdp, phi);
     TC acc = TC(0);
 #pragma unroll
     for (int i = 0; i < 6; ++i) acc += Gb[i] * cf->g0[i] * (i < 3 ? TC(1) : TC(2));
     return acc * kd;
 }
 
-template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL>
-__global__ void __launch_bounds__(kBlock)
+// FP64: 4 waves per SIMD at the cost of a few spilled registers measured
+// faster than 3 waves without spills
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fs,
           const typename HistType<TS>::T *__restrict__ ps, const TC *__restrict__ psi_next,
           const double *pi_next, TC *__restrict__ psi_out, double *pi_out, double *__restrict__ gk_part) {
@@ -108,14 +110,16 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
         // ---- forward recomputation ----
         TC h[Q];
         gather<Q, WALL>(g, cf, fs, ng, h);
+        const TC pp_off = SRC ? (TC)ps[n] : TC(0);
+        const TC pin = (TC)pi_next[n];   // p_{s+1} = phi - phi_ref
         TC phio = TC(0);
 #pragma unroll
         for (int k = 0; k < Q; ++k) phio += h[k];
         const TC phi = cf->phi_ref + phio;
         TC A[6];
-        ablock<D, KVAR>(cf, phi, A);
+        ablock<D, KVAR, NP>(cf, phi, A);
         TC feq[Q], dlt[Q];
-        equilibrium<Q>(cf, phi, phio, feq);
+        equilibrium<Q, NP>(cf, phi, phio, feq);
 #pragma unroll
         for (int k = 0; k < Q; ++k) dlt[k] = h[k] - feq[k];
 
@@ -225,7 +229,7 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
         TC phib = TC(0);
         {
             TC dfe[Q];
-            eq_derivative<Q>(cf, phi, dfe);
+            eq_derivative<Q, NP>(cf, phi, dfe);
 #pragma unroll
             for (int k = 0; k < Q; ++k) phib -= db[k] * dfe[k];
         }
@@ -233,10 +237,10 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
         TC pb = TC(0);
         if (SRC) {
             TC Bt[3], R, Btp[3], Rp, Ap[6];
-            source_terms<D>(cf, phi, A, Bt, R);
-            const TC pp = cf->phi_ref + (TC)ps[n];
-            ablock<D, KVAR>(cf, pp, Ap);
-            source_terms<D>(cf, pp, Ap, Btp, Rp);
+            source_terms<D, NP>(cf, phi, A, Bt, R);
+            const TC pp = cf->phi_ref + pp_off;
+            ablock<D, KVAR, NP>(cf, pp, Ap);
+            source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
             TC S1 = TC(0), T1[3] = {TC(0), TC(0), TC(0)};
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
@@ -258,16 +262,16 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
 #pragma unroll
             for (int a = 0; a < D; ++a) { Btb[a] = TC(4.5) * R * T1[a]; Btpb[a] = TC(-1.5) * Rp * T1[a]; }
             // R(phi), R(p)
-            phib += Rb * poly<kMaxP>(cf->rp, cf->nr, phi);
-            pb += Rpb * poly<kMaxP>(cf->rp, cf->nr, pp);
+            phib += Rb * poly<NP>(cf->rp, phi);
+            pb += Rpb * poly<NP>(cf->rp, pp);
             // Btilde = B' - A B' / 2
             TC Bp[3], Bpp[3], Bpq[3], Bppq[3];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                Bp[a] = poly<kMaxP>(cf->bp[a], cf->nb, phi);
-                Bpp[a] = poly<kMaxP>(cf->bpp[a], cf->nb, phi);
-                Bpq[a] = poly<kMaxP>(cf->bp[a], cf->nb, pp);
-                Bppq[a] = poly<kMaxP>(cf->bpp[a], cf->nb, pp);
+                Bp[a] = poly<NP>(cf->bp[a], phi);
+                Bpp[a] = poly<NP>(cf->bpp[a], phi);
+                Bpq[a] = poly<NP>(cf->bp[a], pp);
+                Bppq[a] = poly<NP>(cf->bpp[a], pp);
             }
             TC Apb[3][3];
 #pragma unroll
@@ -294,14 +298,13 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
                 }
             TC Gbp[6];
             gbar_of<D>(Ap, Apb, Gbp);
-            pb += gbar_scatter<D, KVAR>(cf, pp, Gbp, gk);
+            pb += gbar_scatter<D, KVAR, NP>(cf, pp, Gbp, gk);
         }
         {
             TC Gb[6];
             gbar_of<D>(A, Ab, Gb);
-            phib += gbar_scatter<D, KVAR>(cf, phi, Gb, gk);
+            phib += gbar_scatter<D, KVAR, NP>(cf, phi, Gb, gk);
         }
-        const TC pin = (TC)pi_next[n];   // p_{s+1} = phi - phi_ref
 #pragma unroll
         for (int k = 0; k < Q; ++k) psi_out[(uint64_t)k * g.plane + n] = hb[k] + phib + pin;
         pi_out[n] = (double)pb;
@@ -321,19 +324,28 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
         double v = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) v += sh[threadIdx.x][w];
-        gk_part[(size_t)blockIdx.x * 6 + threadIdx.x] = v;
+        // each workgroup owns its slot: accumulate over the reversed sweeps,
+        // folded once when the gradient is read
+        gk_part[(size_t)blockIdx.x * 6 + threadIdx.x] += v;
     }
 }
 
+// zero the per-workgroup K0 slots (a kernel, so that the adjoint can be
+// captured in a graph without memset nodes)
+static __global__ void __launch_bounds__(kBlock)
+k_zero(double *__restrict__ p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = 0.0;
+}
+
 // dL/dphi0 = sum_k psi_0,k dfeq_k/dphi(phi0) + pi_0   (adjoint of Eq. 40)
-template <int Q, typename TC>
+template <int Q, typename TC, int NP>
 __global__ void __launch_bounds__(kBlock)
 k_adjoint_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict__ phi0,
                const TC *__restrict__ psi0, const double *__restrict__ pi0, double *__restrict__ out) {
     const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
     TC dfe[Q];
-    eq_derivative<Q>(cf, (TC)phi0[n], dfe);
+    eq_derivative<Q, NP>(cf, (TC)phi0[n], dfe);
     double acc = pi0[n];
 #pragma unroll
     for (int k = 0; k < Q; ++k) acc += (double)(psi0[(uint64_t)k * g.plane + n] * dfe[k]);
@@ -343,6 +355,7 @@ k_adjoint_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__r
 template <int Q, typename TC>
 __global__ void __launch_bounds__(kBlock)
 k_seed(const Geom g, const double *__restrict__ gphi, TC *__restrict__ psi, double *__restrict__ pi) {
+    // psi_T,k = dL/dphi(T) for every k (phi = sum_k g_k), pi_T = 0
     const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
     const TC v = (TC)gphi[n];

@@ -28,6 +28,7 @@ hipError_t launch_adjoint_q9(const Dims &, const Geom &, const void *, const voi
 hipError_t launch_adjoint_init_q9(const Dims &, const Geom &, const void *, const double *, const void *,
                                   const double *, double *, hipStream_t);
 hipError_t launch_seed_q9(const Dims &, const Geom &, const double *, void *, double *, hipStream_t);
+hipError_t launch_zero(double *, uint32_t, hipStream_t);
 }  // namespace lbm
 
 using namespace lbm;
@@ -66,6 +67,7 @@ struct lbm_ctx {
     double *d_red_part = nullptr, *d_red_out = nullptr, *d_adj_part = nullptr, *d_k0acc = nullptr;
     void *f[2] = {nullptr, nullptr};
     void *p = nullptr;
+    const double *phi0 = nullptr;
     int cur = 0;
     long long t = 0;
     int check_every = 0;
@@ -271,6 +273,15 @@ int validate(const lbm_desc *d, Dims &dm) {
     if (!(d->kpoly[0] > 0.0)) return fail(LBM_E_INVALID, "kpoly[0] must be positive (K(0) positive definite)");
     if (d->scheme == LBM_SCHEME_B && src)
         return fail(LBM_E_UNSUPPORTED, "Scheme B with a source is not built on the GPU");
+    {
+        int nb = 0;
+        for (int a = 0; a < dim; ++a) nb = std::max(nb, top_count(d->b[a], LBM_MAXP));
+        // C-bar = C + d/3 D: degree 2 (nb - 1) - 1 and the degree of dpoly
+        const int ncb = std::max(nb > 1 ? 2 * nb - 2 : 1, top_count(d->dpoly, LBM_MAXP));
+        dm.lowdeg = nb <= 4 && ncb <= 6 && top_count(d->kpoly, LBM_MAXP) <= 4 &&
+                    top_count(d->rpoly, LBM_MAXP) <= 4;
+    }
+    dm.nt = false;
     dm.q = q;
     dm.prec = d->precision;
     dm.eqr = eq && !(d->flags & LBM_FLAG_MOMENT_PATH);
@@ -336,8 +347,8 @@ hipError_t make_graph(lbm_ctx *c, int start) {
 namespace lbm {
 
 // Validation and packed constants of one description (used by the batch API).
-int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, void *coefs_out,
-                 size_t *coef_bytes) {
+int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, bool *lowdeg,
+                 void *coefs_out, size_t *coef_bytes) {
     Dims dm;
     const int rc = validate(d, dm);
     if (rc != LBM_OK) return rc;
@@ -358,6 +369,7 @@ int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar,
     *eqr = dm.eqr;
     *src = dm.src;
     *kvar = dm.kvar;
+    *lowdeg = dm.lowdeg;
     return LBM_OK;
 }
 
@@ -381,11 +393,18 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     Geom &g = c->g;
     g.nx = desc->nx; g.ny = desc->ny; g.nz = desc->nz;
     g.N = (uint32_t)((size_t)desc->nx * desc->ny * desc->nz);
-    g.plane = g.N;
+    g.plane = plane_stride(g.N, dm.q, storage_size(dm.prec), desc->plane_pad);
     g.fx.set(g.nx);
     g.fxy.set(g.nx * g.ny);
     g.nblocks = (g.N + kBlock - 1) / kBlock;
+    g.chunk = 1;
     g.remap = (desc->flags & LBM_FLAG_NO_XCD_REMAP) ? 0 : 1;
+    {
+        // streaming accesses by default when the two distribution buffers and
+        // the history exceed the 256 MB Infinity Cache
+        const double bytes = 2.0 * dm.q * (double)g.plane * storage_size(dm.prec) + (double)g.N * hist_size(dm.prec);
+        c->dm.nt = bytes > 256.0 * 1024 * 1024;
+    }
     hipError_t e = hipMalloc(&c->d_coefs, sizeof(Coefs<double>));
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipMalloc(coefficients)"); }
     const size_t scratch = 256 + sizeof(double) * (size_t)(kRedParts * 8 + 8 + kMaxAdjParts * kAdjWidth + 8);
@@ -421,12 +440,18 @@ int lbm_state_bytes(const lbm_ctx *c, size_t *f_bytes, size_t *p_bytes) {
     return LBM_OK;
 }
 
+int lbm_adjoint_bytes(const lbm_ctx *c, size_t *psi_bytes) {
+    if (!c || !psi_bytes) return fail(LBM_E_INVALID, "null argument");
+    *psi_bytes = round256((size_t)c->dm.q * c->g.plane * (c->dm.prec == 0 ? 8 : 4));
+    return LBM_OK;
+}
+
 int lbm_init(lbm_ctx *c, const double *phi0, void *f_a, void *f_b, void *p, void *stream) {
     if (!c || !phi0 || !f_a || !f_b || !p) return fail(LBM_E_INVALID, "null argument");
     if (f_a == f_b) return fail(LBM_E_INVALID, "the two distribution buffers must differ");
     if (((uintptr_t)f_a | (uintptr_t)f_b | (uintptr_t)p) & 255) return fail(LBM_E_INVALID, "buffers must be 256-byte aligned");
     if (c->f[0] != f_a || c->f[1] != f_b || c->p != p) drop_graphs(c);
-    c->f[0] = f_a; c->f[1] = f_b; c->p = p;
+    c->f[0] = f_a; c->f[1] = f_b; c->p = p; c->phi0 = phi0;
     c->cur = 0; c->t = 0; c->bound = true;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = (c->dm.q == 9) ? launch_init_q9(c->dm, c->g, c->d_coefs, phi0, f_a, p, st)
@@ -549,8 +574,9 @@ int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
     hipStream_t st = (hipStream_t)stream;
+    if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
     hipError_t e = launch_seed_q9(c->dm, c->g, gphi, psi, pi, st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->d_k0acc, 0, 8 * sizeof(double), st);
+    if (e == hipSuccess) e = launch_zero(c->d_adj_part, c->g.nblocks * kAdjWidth, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint seed");
     return LBM_OK;
 }
@@ -566,7 +592,6 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = launch_adjoint_q9(c->dm, c->g, c->d_coefs, f_s, p_s, psi_next, pi_next, psi_out, pi_out,
                                      c->d_adj_part, st);
-    if (e == hipSuccess) e = launch_sum_partials(c->d_adj_part, (int)c->g.nblocks, kAdjWidth, c->d_k0acc, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel");
     return LBM_OK;
 }
@@ -585,11 +610,87 @@ int lbm_adjoint_grad_k0(lbm_ctx *c, double out[6], void *stream) {
     if (!c || !out) return fail(LBM_E_INVALID, "null argument");
     hipStream_t st = (hipStream_t)stream;
     double acc[6];
-    hipError_t e = hipMemcpyAsync(acc, c->d_k0acc, 6 * sizeof(double), hipMemcpyDeviceToHost, st);
+    // fold the per-workgroup slots (fixed order: deterministic)
+    hipError_t e = launch_zero(c->d_k0acc, 8, st);
+    if (e == hipSuccess) e = launch_sum_partials(c->d_adj_part, (int)c->g.nblocks, kAdjWidth, c->d_k0acc, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(acc, c->d_k0acc, 6 * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "adjoint gradient copy");
     // kernel order (xx, yy, zz, xy, yz, xz) -> ABI order (xx, xy, yy, xz, yz, zz)
     out[0] = acc[0]; out[1] = acc[3]; out[2] = acc[1]; out[3] = acc[5]; out[4] = acc[4]; out[5] = acc[2];
+    return LBM_OK;
+}
+
+int lbm_set_nontemporal(lbm_ctx *c, int on) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    c->dm.nt = on != 0;
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+int lbm_set_chunk(lbm_ctx *c, int chunk) {
+    if (!c || chunk < 1) return fail(LBM_E_INVALID, "chunk must be >= 1");
+    c->g.chunk = (uint32_t)chunk;
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (!c->bound || !c->phi0) return fail(LBM_E_STATE, "lbm_init has not been called");
+    if (reps < 1) reps = 1;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(LBM_E_HIP, "hipEventCreate");
+    static const int cands[] = {1, 2, 4, 8, 16};
+    float best = 1e30f;
+    int best_chunk = 1;
+    bool best_nt = c->dm.nt;
+    std::string rep;
+    const int nts = (c->dm.eqr && c->dm.lowdeg) ? 2 : 1;
+    for (int ci = 0; ci < 5 * nts; ++ci) {
+        const int ch = cands[ci % 5];
+        if ((uint32_t)ch > c->g.nblocks) continue;
+        c->g.chunk = (uint32_t)ch;
+        c->dm.nt = (ci / 5) == 1;
+        // trial sweeps read the current state and write the other buffer
+        hipError_t e = sweep(c, c->f[c->cur], c->f[c->cur ^ 1], c->p, st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = sweep(c, c->f[c->cur], c->f[c->cur ^ 1], c->p, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+            return hip_fail(e, "tuning sweep");
+        }
+        ms /= reps;
+        char line[96];
+        std::snprintf(line, sizeof(line), "chunk %d nt %d: %.4f ms\n", ch, (int)c->dm.nt, ms);
+        rep += line;
+        if (ms < best) { best = ms; best_chunk = ch; best_nt = c->dm.nt; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->g.chunk = (uint32_t)best_chunk;
+    c->dm.nt = best_nt;
+    drop_graphs(c);
+    char line[96];
+    std::snprintf(line, sizeof(line), "chosen chunk %d nt %d (%.4f ms)", best_chunk, (int)best_nt, best);
+    rep += line;
+    if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
+    // the history buffer was overwritten by the trial sweeps: restart from phi0
+    return lbm_init(c, c->phi0, c->f[0], c->f[1], c->p, stream);
+}
+
+int lbm_probe_copy(const void *src, void *dst, size_t bytes, int grid, void *stream) {
+    if (!src || !dst) return fail(LBM_E_INVALID, "null argument");
+    if (((uintptr_t)src | (uintptr_t)dst | bytes) & 15) return fail(LBM_E_INVALID, "16-byte alignment required");
+    if (grid <= 0) grid = 256 * 16;
+    hipError_t e = launch_copy16(src, dst, bytes / 16, grid, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "copy kernel");
     return LBM_OK;
 }
 

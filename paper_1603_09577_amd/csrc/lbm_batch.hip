@@ -42,7 +42,7 @@ struct TileShape {
 constexpr TileShape kShapes[] = {{256, 1}, {256, 2}, {128, 1}, {512, 1}};
 constexpr int kNumShapes = 4;
 
-template <typename TS, typename TC, bool SRC, bool KVAR, int WG, int NPT>
+template <typename TS, typename TC, bool SRC, bool KVAR, int WG, int NPT, int NP>
 __global__ void __launch_bounds__(WG)
 k_batch_sweep(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ coefs,
               const uint2 *__restrict__ tiles, uint32_t ntiles, uint32_t chunk, int remap,
@@ -59,13 +59,13 @@ k_batch_sweep(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ 
         for (int j = 0; j < NPT; ++j) {
             const uint32_t n = e.y + j * WG + threadIdx.x;
             if (n < g.N)
-                sweep_node<9, TS, TC, true, SRC, KVAR, false>(g, cf, fin + I.f_off, fout + I.f_off,
+                sweep_node<9, TS, TC, true, SRC, KVAR, false, NP>(g, cf, fin + I.f_off, fout + I.f_off,
                                                                p + I.p_off, flag, n);
         }
     }
 }
 
-template <typename TS, typename TC>
+template <typename TS, typename TC, int NP>
 __global__ void __launch_bounds__(256)
 k_batch_init(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ coefs,
              const uint2 *__restrict__ tiles, uint32_t ntiles, int tile_nodes, const double *__restrict__ phi0,
@@ -90,7 +90,7 @@ k_batch_init(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ c
                     off += (c == 1) ? ng.op[a] : ((c == -1) ? ng.om[a] : 0);
                 }
                 const TC ph = (TC)ph0[(uint32_t)((int)n + off)];
-                store_s(f + I.f_off + (uint64_t)k * g.plane + n, feq_one<9>(cf, ph, k));
+                store_s(f + I.f_off + (uint64_t)k * g.plane + n, feq_one<9, NP>(cf, ph, k));
             }
             p[I.p_off + n] = (typename HistType<TS>::T)((TC)ph0[n] - cf->phi_ref);
         }
@@ -127,8 +127,8 @@ using namespace lbm;
 
 namespace lbm {
 // coefficient derivation shared with the single-instance API (lbm_api.hip)
-int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, void *coefs_out,
-                 size_t *coef_bytes);
+int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, bool *lowdeg,
+                 void *coefs_out, size_t *coef_bytes);
 const char *api_error_message();
 int api_fail(int code, const char *msg);
 }  // namespace lbm
@@ -136,7 +136,7 @@ int api_fail(int code, const char *msg);
 struct lbm_batch {
     int count = 0;
     int prec = 0;
-    bool src = false, kvar = false;
+    bool src = false, kvar = false, lowdeg = true;
     size_t coef_stride = 0;
     std::vector<BatchInst> inst;
     std::vector<int> nx, ny;
@@ -177,9 +177,11 @@ hipError_t batch_sweep_launch(lbm_batch *b, const void *fin, void *fout, hipStre
     const uint32_t nblk = (nt + chunk - 1) / chunk;
     const uint2 *tl = b->d_tiles[b->shape];
 #define LBM_BL(TS, TC, S, K, WG, NPT)                                                                   \
-    hipLaunchKernelGGL((k_batch_sweep<TS, TC, S, K, WG, NPT>), dim3(nblk), dim3(WG), 0, st,             \
+    if (b->lowdeg) LBM_BL_NP(TS, TC, S, K, WG, NPT, 4) else LBM_BL_NP(TS, TC, S, K, WG, NPT, 9)
+#define LBM_BL_NP(TS, TC, S, K, WG, NPT, NP)                                                            \
+    hipLaunchKernelGGL((k_batch_sweep<TS, TC, S, K, WG, NPT, NP>), dim3(nblk), dim3(WG), 0, st,         \
                        b->d_inst, (const Coefs<TC> *)b->d_coefs, tl, nt, chunk, b->remap,               \
-                       (const TS *)fin, (TS *)fout, (typename HistType<TS>::T *)b->p, b->d_flag)
+                       (const TS *)fin, (TS *)fout, (typename HistType<TS>::T *)b->p, b->d_flag);
 #define LBM_BL_SHAPE(TS, TC, S, K)                                                                      \
     switch (b->shape) {                                                                                 \
         case 0: LBM_BL(TS, TC, S, K, 256, 1); break;                                                    \
@@ -199,6 +201,7 @@ hipError_t batch_sweep_launch(lbm_batch *b, const void *fin, void *fout, hipStre
 #undef LBM_BL_FLAGS
 #undef LBM_BL_SHAPE
 #undef LBM_BL
+#undef LBM_BL_NP
     return hipGetLastError();
 }
 
@@ -228,20 +231,31 @@ hipError_t make_graph(lbm_batch *b, int start) {
     return e;
 }
 
+#define LBM_INIT_NP(KERNEL, ...)                                                      \
+    do {                                                                              \
+        if (b->lowdeg) {                                                              \
+            constexpr int NPV = 4;                                                    \
+            hipLaunchKernelGGL(KERNEL, __VA_ARGS__);                                  \
+        } else {                                                                      \
+            constexpr int NPV = 9;                                                    \
+            hipLaunchKernelGGL(KERNEL, __VA_ARGS__);                                  \
+        }                                                                             \
+    } while (0)
+
 hipError_t batch_init_launch(lbm_batch *b, hipStream_t st) {
     const uint32_t nt = b->ntiles[0];
     const int tn = kShapes[0].wg * kShapes[0].npt;
     const uint32_t grid = std::min<uint32_t>(nt, 8192);
     if (b->prec == 0)
-        hipLaunchKernelGGL((k_batch_init<double, double>), dim3(grid), dim3(256), 0, st, b->d_inst,
+        LBM_INIT_NP((k_batch_init<double, double, NPV>), dim3(grid), dim3(256), 0, st, b->d_inst,
                            (const Coefs<double> *)b->d_coefs, b->d_tiles[0], nt, tn, b->phi0, (double *)b->f[0],
                            (double *)b->p);
     else if (b->prec == 1)
-        hipLaunchKernelGGL((k_batch_init<float, float>), dim3(grid), dim3(256), 0, st, b->d_inst,
+        LBM_INIT_NP((k_batch_init<float, float, NPV>), dim3(grid), dim3(256), 0, st, b->d_inst,
                            (const Coefs<float> *)b->d_coefs, b->d_tiles[0], nt, tn, b->phi0, (float *)b->f[0],
                            (float *)b->p);
     else
-        hipLaunchKernelGGL((k_batch_init<_Float16, float>), dim3(grid), dim3(256), 0, st, b->d_inst,
+        LBM_INIT_NP((k_batch_init<_Float16, float, NPV>), dim3(grid), dim3(256), 0, st, b->d_inst,
                            (const Coefs<float> *)b->d_coefs, b->d_tiles[0], nt, tn, b->phi0, (_Float16 *)b->f[0],
                            (float *)b->p);
     return hipGetLastError();
@@ -296,30 +310,30 @@ int lbm_batch_create(const lbm_desc *descs, int count, lbm_batch **out) {
             return api_fail(LBM_E_UNSUPPORTED, "batched instances must be periodic");
         }
         int prec = 0;
-        bool eqr = false, src = false, kvar = false;
+        bool eqr = false, src = false, kvar = false, low = false;
         size_t cb = 0;
         std::vector<unsigned char> tmp(sizeof(Coefs<double>));
-        const int rc = derive_coefs(&d, &prec, &eqr, &src, &kvar, tmp.data(), &cb);
+        const int rc = derive_coefs(&d, &prec, &eqr, &src, &kvar, &low, tmp.data(), &cb);
         if (rc != LBM_OK) { delete b; return rc; }
         if (!eqr) { delete b; return api_fail(LBM_E_UNSUPPORTED, "batched instances need equal non-flux rates"); }
         if (i == 0) { b->prec = prec; b->coef_stride = cb; }
         else if (prec != b->prec) { delete b; return api_fail(LBM_E_INVALID, "all instances need the same precision"); }
         b->src = b->src || src;
         b->kvar = b->kvar || kvar;
+        b->lowdeg = b->lowdeg && low;
         coefs.insert(coefs.end(), tmp.begin(), tmp.begin() + cb);
         BatchInst I;
         std::memset(&I, 0, sizeof(I));
         I.g.nx = d.nx; I.g.ny = d.ny; I.g.nz = 1;
         I.g.N = (uint32_t)((size_t)d.nx * d.ny);
-        I.g.plane = I.g.N;
+        I.g.plane = plane_stride(I.g.N, 9, ssize(prec), d.plane_pad);
         I.g.fx.set(I.g.nx);
         I.g.fxy.set(I.g.N);
         I.g.nblocks = 0;
         I.g.remap = 0;
         I.f_off = foff;
         I.p_off = poff;
-        foff += 9ull * I.g.N;
-        foff = (foff + 63) & ~63ull;   // keep every instance's planes 256-byte aligned in FP32
+        foff += 9ull * I.g.plane;      // plane strides keep every plane 256-byte aligned
         poff += I.g.N;
         b->inst.push_back(I);
         b->nx.push_back(d.nx);
@@ -380,7 +394,7 @@ void lbm_batch_destroy(lbm_batch *b) {
 int lbm_batch_layout(const lbm_batch *b, size_t *f_bytes, size_t *p_bytes, long long *total_nodes) {
     if (!b) return api_fail(LBM_E_INVALID, "null batch");
     const BatchInst &last = b->inst.back();
-    const uint64_t fel = last.f_off + 9ull * last.g.N;
+    const uint64_t fel = last.f_off + 9ull * last.g.plane;
     if (f_bytes) *f_bytes = r256(fel * ssize(b->prec));
     if (p_bytes) *p_bytes = r256(b->total_nodes * hsize(b->prec));
     if (total_nodes) *total_nodes = (long long)b->total_nodes;

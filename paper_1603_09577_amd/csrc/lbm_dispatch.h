@@ -16,13 +16,26 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
     const auto *fi = (const TS *)fin;
     auto *fo = (TS *)fout;
     auto *pp = (TP *)p;
-    const dim3 grid(g.nblocks), block(kBlock);
-    const int code = (dm.eqr ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
-#define LBM_SWEEP(E, S, K, W)                                                                          \
-    case (E * 8 + S * 4 + K * 2 + W):                                                                  \
-        hipLaunchKernelGGL((k_sweep<Q, TS, TC, E, S, K, W>), grid, block, 0, st, g, cf, fi, fo, pp, flag); \
+    const dim3 grid((g.nblocks + g.chunk - 1) / g.chunk), block(kBlock);
+    // short polynomials (all degrees <= 3) get the branch-free 4-term kernels
+    // non-temporal accesses: equal-rate short-polynomial kernels only
+    const int code = (dm.eqr ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) |
+                     ((dm.eqr && dm.lowdeg) ? 16 : 0) | ((dm.eqr && dm.lowdeg && dm.nt) ? 32 : 0);
+#define LBM_SWEEP_X(E, S, K, W, NP, NT, TAG)                                                          \
+    case (TAG + E * 8 + S * 4 + K * 2 + W):                                                           \
+        hipLaunchKernelGGL((k_sweep<Q, TS, TC, E, S, K, W, NP, NT>), grid, block, 0, st, g, cf, fi, fo, pp, flag); \
         break;
+#define LBM_SWEEP_NP(E, S, K, W, NP, TAG) LBM_SWEEP_X(E, S, K, W, NP, false, TAG)
+#define LBM_SWEEP(E, S, K, W) LBM_SWEEP_NP(E, S, K, W, 9, 0)
     switch (code) {
+        LBM_SWEEP_X(1, 0, 0, 0, 4, true, 48) LBM_SWEEP_X(1, 0, 0, 1, 4, true, 48)
+        LBM_SWEEP_X(1, 0, 1, 0, 4, true, 48) LBM_SWEEP_X(1, 0, 1, 1, 4, true, 48)
+        LBM_SWEEP_X(1, 1, 0, 0, 4, true, 48) LBM_SWEEP_X(1, 1, 0, 1, 4, true, 48)
+        LBM_SWEEP_X(1, 1, 1, 0, 4, true, 48) LBM_SWEEP_X(1, 1, 1, 1, 4, true, 48)
+        LBM_SWEEP_NP(1, 0, 0, 0, 4, 16) LBM_SWEEP_NP(1, 0, 0, 1, 4, 16)
+        LBM_SWEEP_NP(1, 0, 1, 0, 4, 16) LBM_SWEEP_NP(1, 0, 1, 1, 4, 16)
+        LBM_SWEEP_NP(1, 1, 0, 0, 4, 16) LBM_SWEEP_NP(1, 1, 0, 1, 4, 16)
+        LBM_SWEEP_NP(1, 1, 1, 0, 4, 16) LBM_SWEEP_NP(1, 1, 1, 1, 4, 16)
         LBM_SWEEP(0, 0, 0, 0) LBM_SWEEP(0, 0, 0, 1) LBM_SWEEP(0, 0, 1, 0) LBM_SWEEP(0, 0, 1, 1)
         LBM_SWEEP(0, 1, 0, 0) LBM_SWEEP(0, 1, 0, 1) LBM_SWEEP(0, 1, 1, 0) LBM_SWEEP(0, 1, 1, 1)
         LBM_SWEEP(1, 0, 0, 0) LBM_SWEEP(1, 0, 0, 1) LBM_SWEEP(1, 0, 1, 0) LBM_SWEEP(1, 0, 1, 1)
@@ -30,6 +43,8 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
         default: return hipErrorInvalidValue;
     }
 #undef LBM_SWEEP
+#undef LBM_SWEEP_NP
+#undef LBM_SWEEP_X
     return hipGetLastError();
 }
 
@@ -39,10 +54,14 @@ hipError_t init_typed(const Dims &dm, const Geom &g, const void *coefs, const do
     using TP = typename HistType<TS>::T;
     const auto *cf = (const Coefs<TC> *)coefs;
     const dim3 grid(g.nblocks), block(kBlock);
-    if (dm.wall)
-        hipLaunchKernelGGL((k_init<Q, TS, TC, true>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
+    if (dm.wall && dm.lowdeg)
+        hipLaunchKernelGGL((k_init<Q, TS, TC, true, 4>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
+    else if (dm.wall)
+        hipLaunchKernelGGL((k_init<Q, TS, TC, true, 9>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
+    else if (dm.lowdeg)
+        hipLaunchKernelGGL((k_init<Q, TS, TC, false, 4>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
     else
-        hipLaunchKernelGGL((k_init<Q, TS, TC, false>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
+        hipLaunchKernelGGL((k_init<Q, TS, TC, false, 9>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
     return hipGetLastError();
 }
 
@@ -69,13 +88,19 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
     const auto *pn = (const TC *)psi_next;
     auto *po = (TC *)psi_out;
     const dim3 grid(g.nblocks), block(kBlock);
-    const int code = (dm.eqr ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
-#define LBM_ADJ(E, S, K, W)                                                                           \
-    case (E * 8 + S * 4 + K * 2 + W):                                                                 \
-        hipLaunchKernelGGL((k_adjoint<Q, TS, TC, E, S, K, W>), grid, block, 0, st, g, cf, fs, ps, pn, \
-                           pi_next, po, pi_out, gk_part);                                             \
+    const int code = (dm.eqr ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) |
+                     ((dm.eqr && dm.lowdeg) ? 16 : 0);
+#define LBM_ADJ_NP(E, S, K, W, NP, TAG)                                                                 \
+    case (TAG + E * 8 + S * 4 + K * 2 + W):                                                             \
+        hipLaunchKernelGGL((k_adjoint<Q, TS, TC, E, S, K, W, NP>), grid, block, 0, st, g, cf, fs, ps, pn, \
+                           pi_next, po, pi_out, gk_part);                                               \
         break;
+#define LBM_ADJ(E, S, K, W) LBM_ADJ_NP(E, S, K, W, 9, 0)
     switch (code) {
+        LBM_ADJ_NP(1, 0, 0, 0, 4, 16) LBM_ADJ_NP(1, 0, 0, 1, 4, 16)
+        LBM_ADJ_NP(1, 0, 1, 0, 4, 16) LBM_ADJ_NP(1, 0, 1, 1, 4, 16)
+        LBM_ADJ_NP(1, 1, 0, 0, 4, 16) LBM_ADJ_NP(1, 1, 0, 1, 4, 16)
+        LBM_ADJ_NP(1, 1, 1, 0, 4, 16) LBM_ADJ_NP(1, 1, 1, 1, 4, 16)
         LBM_ADJ(0, 0, 0, 0) LBM_ADJ(0, 0, 0, 1) LBM_ADJ(0, 0, 1, 0) LBM_ADJ(0, 0, 1, 1)
         LBM_ADJ(0, 1, 0, 0) LBM_ADJ(0, 1, 0, 1) LBM_ADJ(0, 1, 1, 0) LBM_ADJ(0, 1, 1, 1)
         LBM_ADJ(1, 0, 0, 0) LBM_ADJ(1, 0, 0, 1) LBM_ADJ(1, 0, 1, 0) LBM_ADJ(1, 0, 1, 1)
@@ -83,20 +108,31 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
         default: return hipErrorInvalidValue;
     }
 #undef LBM_ADJ
+#undef LBM_ADJ_NP
     return hipGetLastError();
 }
 
 template <int Q, typename TS, typename TC>
-hipError_t adjoint_init_typed(const Dims &, const Geom &g, const void *coefs, const double *phi0,
+hipError_t adjoint_init_typed(const Dims &dm, const Geom &g, const void *coefs, const double *phi0,
                               const void *psi0, const double *pi0, double *out, hipStream_t st) {
-    hipLaunchKernelGGL((k_adjoint_init<Q, TC>), dim3(g.nblocks), dim3(kBlock), 0, st, g,
-                       (const Coefs<TC> *)coefs, phi0, (const TC *)psi0, pi0, out);
+    if (dm.lowdeg)
+        hipLaunchKernelGGL((k_adjoint_init<Q, TC, 4>), dim3(g.nblocks), dim3(kBlock), 0, st, g,
+                           (const Coefs<TC> *)coefs, phi0, (const TC *)psi0, pi0, out);
+    else
+        hipLaunchKernelGGL((k_adjoint_init<Q, TC, 9>), dim3(g.nblocks), dim3(kBlock), 0, st, g,
+                           (const Coefs<TC> *)coefs, phi0, (const TC *)psi0, pi0, out);
     return hipGetLastError();
 }
 
 template <int Q, typename TS, typename TC>
 hipError_t seed_typed(const Dims &, const Geom &g, const double *gphi, void *psi, double *pi, hipStream_t st) {
     hipLaunchKernelGGL((k_seed<Q, TC>), dim3(g.nblocks), dim3(kBlock), 0, st, g, gphi, (TC *)psi, pi);
+    return hipGetLastError();
+}
+
+inline hipError_t zero_doubles(double *p, uint32_t n, hipStream_t st) {
+    const uint32_t grid = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_zero, dim3(grid < 1024 ? grid : 1024), dim3(kBlock), 0, st, p, n);
     return hipGetLastError();
 }
 

@@ -33,7 +33,8 @@ struct Geom {
     uint32_t nx, ny, nz, N;
     uint64_t plane;       // elements between consecutive direction planes
     FastDiv fx, fxy;      // division by nx and by nx*ny
-    uint32_t nblocks;     // workgroups of one sweep
+    uint32_t nblocks;     // 256-node blocks of one sweep
+    uint32_t chunk;       // consecutive blocks swept by one workgroup (>= 1)
     int remap;            // XCD-aware block order
 };
 
@@ -67,7 +68,28 @@ struct Dims {
     bool src;             // R != 0 (Scheme-A history needed)
     bool kvar;            // k(phi) not constant: A per node
     bool wall;            // walls on the last axis
+    bool lowdeg;          // every polynomial of degree <= 3 (C-bar <= 5)
+    bool nt;              // non-temporal distribution accesses
 };
+
+// Elements between consecutive direction planes.  A plane stride that is a
+// multiple of the L2 set span (4 MB, 16 ways, 128-byte lines: 256 KiB) puts
+// the same offset of every plane in one cache set and on one memory channel;
+// the default pad shifts consecutive planes by about span / q bytes (an odd
+// multiple of 256 bytes), which spreads the q concurrent streams.
+inline uint64_t plane_stride(uint64_t n, int q, size_t elem, int pad_req) {
+    const uint64_t align = 256 / elem;                      // keep planes 256-byte aligned
+    uint64_t base = (n + align - 1) / align * align;
+    if (pad_req < 0) return base;
+    if (pad_req > 0) return base + ((uint64_t)pad_req + align - 1) / align * align;
+    const uint64_t span = 256 * 1024;
+    uint64_t want = span / (uint64_t)q / 256;               // shift per plane, in 256-byte units
+    if ((want & 1) == 0) ++want;
+    const uint64_t cur = (base * elem) % span;
+    const uint64_t target = want * 256;
+    const uint64_t pad_bytes = (target + span - cur) % span;
+    return base + pad_bytes / elem;
+}
 
 // Kernel launchers (defined per lattice in sweep_d2q9.hip / sweep_d3q19.hip).
 hipError_t launch_init(const Dims &dm, const Geom &g, const void *coefs, const double *phi0,
@@ -88,6 +110,7 @@ hipError_t launch_seed(const Dims &dm, const Geom &g, const double *gphi, void *
 // Generic FP64 reductions (lbm_reduce.hip).
 hipError_t launch_reduce(const double *phi, const double *ref, uint32_t n, double *part,
                          int nparts, double *out, hipStream_t st);
+hipError_t launch_copy16(const void *src, void *dst, size_t n16, int grid, hipStream_t st);
 hipError_t launch_sum_partials(const double *part, int nparts, int width, double *acc,
                                hipStream_t st);
 

@@ -27,22 +27,35 @@ struct HistType { using T = float; };
 template <>
 struct HistType<double> { using T = double; };
 
-template <typename TC, typename TS>
-__device__ __forceinline__ TC load_s(const TS *p) { return (TC)(*p); }
+// Plain or non-temporal (streaming) accesses of the distribution planes.  The
+// streaming form skips cache allocation: a gain when the state is far larger
+// than the caches, a loss when it would stay resident in them.
+template <typename TC, bool NT = false, typename TS>
+__device__ __forceinline__ TC load_s(const TS *p) {
+    if (NT) return (TC)__builtin_nontemporal_load(p);
+    return (TC)(*p);
+}
 
-template <typename TS, typename TC>
-__device__ __forceinline__ void store_s(TS *p, TC v) { *p = (TS)v; }
+template <bool NT = false, typename TS, typename TC>
+__device__ __forceinline__ void store_s(TS *p, TC v) {
+    if (NT) __builtin_nontemporal_store((TS)v, p);
+    else *p = (TS)v;
+}
 
-// sum_{p < n} c[p] x^p by Horner, unrolled to the maximum count; the uniform
-// count n turns the unused terms into skipped scalar branches.
-template <int MAXN, typename T>
-__device__ __forceinline__ T poly(const T *c, int n, T x) {
-    T acc = T(0);
+// sum_{p < N} c[p] x^p by Horner over a compile-time length: no branches;
+// the host picks the short length whenever every polynomial fits in it (the
+// coefficients beyond a polynomial's degree are zero).
+template <int N, typename T>
+__device__ __forceinline__ T poly(const T *c, T x) {
+    T acc = c[N - 1];
 #pragma unroll
-    for (int p = MAXN - 1; p >= 0; --p)
-        if (p < n) acc = acc * x + c[p];
+    for (int p = N - 2; p >= 0; --p) acc = acc * x + c[p];
     return acc;
 }
+
+// coefficient counts: NP for B, D, K, R and their derivatives, NC for C-bar
+template <int NP>
+struct PolyLen { static constexpr int NC = 2 * NP - 2; };
 
 // Workgroup order that gives each XCD one contiguous run of the domain, so
 // the neighbouring rows and planes a workgroup reads sit in its own L2.
@@ -53,12 +66,17 @@ __device__ __forceinline__ uint32_t block_index(uint32_t b, uint32_t nb, int rem
     return xcd * q + (xcd < r ? xcd : r) + i;
 }
 
+// 1/x: correctly rounded in FP64; the hardware reciprocal (1 ulp) in FP32,
+// whose error is far below the FP32-storage error of the sweep.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Symmetric inverse of G (2x2 or 3x3), symmetric storage (xx, yy, zz, xy, yz, xz).
 template <int DIM, typename T>
 __device__ __forceinline__ void sym_inverse(const T *G, T *A) {
     if (DIM == 2) {
         const T det = G[0] * G[1] - G[3] * G[3];
-        const T id = T(1) / det;
+        const T id = recip(det);
         A[0] = G[1] * id;
         A[1] = G[0] * id;
         A[3] = -G[3] * id;
@@ -71,17 +89,17 @@ __device__ __forceinline__ void sym_inverse(const T *G, T *A) {
         const T c12 = G[3] * G[5] - G[0] * G[4];
         const T c02 = G[3] * G[4] - G[5] * G[1];
         const T det = G[0] * c00 + G[3] * c01 + G[5] * c02;
-        const T id = T(1) / det;
+        const T id = recip(det);
         A[0] = c00 * id; A[1] = c11 * id; A[2] = c22 * id;
         A[3] = c01 * id; A[4] = c12 * id; A[5] = c02 * id;
     }
 }
 
 // Flux block A at phi (Eq. 26): A = (g0 k(phi) + I/2)^-1, or the constant.
-template <int DIM, bool KVAR, typename TC>
+template <int DIM, bool KVAR, int NP, typename TC>
 __device__ __forceinline__ void ablock(const Coefs<TC> *__restrict__ cf, TC phi, TC *A) {
     if (KVAR) {
-        const TC kv = poly<kMaxP>(cf->kp, cf->nk, phi);
+        const TC kv = poly<NP>(cf->kp, phi);
         TC G[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) G[i] = cf->g0[i] * kv + (i < 3 ? TC(0.5) : TC(0));
@@ -94,18 +112,18 @@ __device__ __forceinline__ void ablock(const Coefs<TC> *__restrict__ cf, TC phi,
 
 // Equilibrium offsets feq_k - w_k phi_ref (Eq. 3 with c = 1, cs^2 = 1/3):
 // w_k [ (phi - phi_ref) + 3 c.B + 9/2 ((Cbar - phi/3 I) : (c c - I/3)) ].
-template <int Q, typename TC>
+template <int Q, int NP, typename TC>
 __device__ __forceinline__ void equilibrium(const Coefs<TC> *__restrict__ cf, TC phi, TC phio,
                                             TC *feq) {
     using L = Lattice<Q>;
     constexpr int D = L::dim;
     TC B[3], E[6];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) B[a] = (a < D) ? poly<kMaxP>(cf->b[a], cf->nb, phi) : TC(0);
+    for (int a = 0; a < 3; ++a) B[a] = (a < D) ? poly<NP>(cf->b[a], phi) : TC(0);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         const bool used = (D == 3) || (i == 0 || i == 1 || i == 3);
-        E[i] = used ? poly<kMaxC>(cf->cb[i], cf->ncb, phi) : TC(0);
+        E[i] = used ? poly<PolyLen<NP>::NC>(cf->cb[i], phi) : TC(0);
     }
     const TC third = phi * TC(1.0 / 3.0);
     E[0] -= third; E[1] -= third;
@@ -130,12 +148,12 @@ __device__ __forceinline__ void equilibrium(const Coefs<TC> *__restrict__ cf, TC
 
 // Scheme-A source pieces at one time level: R(phi) and Btilde = (I - A/2) B'
 // (Eq. 28 with gamma = 0).
-template <int DIM, typename TC>
+template <int DIM, int NP, typename TC>
 __device__ __forceinline__ void source_terms(const Coefs<TC> *__restrict__ cf, TC phi, const TC *A,
                                              TC *Bt, TC &R) {
     TC Bp[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Bp[a] = (a < DIM) ? poly<kMaxP>(cf->bp[a], cf->nb, phi) : TC(0);
+    for (int a = 0; a < 3; ++a) Bp[a] = (a < DIM) ? poly<NP>(cf->bp[a], phi) : TC(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         TC acc = Bp[a];
@@ -143,7 +161,7 @@ __device__ __forceinline__ void source_terms(const Coefs<TC> *__restrict__ cf, T
         for (int b = 0; b < DIM; ++b) acc -= TC(0.5) * A[sym(a, b)] * Bp[b];
         Bt[a] = (a < DIM) ? acc : TC(0);
     }
-    R = poly<kMaxP>(cf->r, cf->nr, phi);
+    R = poly<NP>(cf->r, phi);
 }
 
 struct NodeGeo {
@@ -183,7 +201,7 @@ __device__ __forceinline__ NodeGeo node_geometry(const Geom &g, uint32_t n) {
 }
 
 // Gather g_k(x) (offset form) with periodic wrap and anti-bounce-back walls.
-template <int Q, bool WALL, typename TS, typename TC>
+template <int Q, bool WALL, bool NT = false, typename TS, typename TC>
 __device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restrict__ cf,
                                        const TS *__restrict__ fin, const NodeGeo &ng, TC *h) {
     using L = Lattice<Q>;
@@ -198,9 +216,9 @@ __device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restric
         }
         const int cl = L::c(k, D - 1);
         if (WALL && ((cl == 1 && ng.lo) || (cl == -1 && ng.hi))) {
-            h[k] = -load_s<TC>(fin + (uint64_t)L::opp(k) * g.plane + ng.n) + cf->ew[cl == 1 ? 0 : 1][k];
+            h[k] = -load_s<TC, NT>(fin + (uint64_t)L::opp(k) * g.plane + ng.n) + cf->ew[cl == 1 ? 0 : 1][k];
         } else {
-            h[k] = load_s<TC>(fin + (uint64_t)k * g.plane + (uint32_t)((int)ng.n + off));
+            h[k] = load_s<TC, NT>(fin + (uint64_t)k * g.plane + (uint32_t)((int)ng.n + off));
         }
     }
 }
@@ -209,7 +227,7 @@ __device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restric
 // the sweep
 // ---------------------------------------------------------------------------
 // One node of the sweep (shared by the single-instance and batched kernels).
-template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL>
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT = false>
 __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__restrict__ cf,
                                            const TS *__restrict__ fin, TS *__restrict__ fout,
                                            typename HistType<TS>::T *p, int *flag, uint32_t n) {
@@ -218,7 +236,9 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     const NodeGeo ng = node_geometry<Q, WALL>(g, n);
 
     TC h[Q];
-    gather<Q, WALL>(g, cf, fin, ng, h);
+    gather<Q, WALL, NT>(g, cf, fin, ng, h);
+    // history read issued together with the gathers, so its latency overlaps theirs
+    const TC pp_off = SRC ? (TC)p[n] : TC(0);
 
     TC phio = TC(0);
 #pragma unroll
@@ -226,9 +246,9 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     const TC phi = cf->phi_ref + phio;
 
     TC A[6];
-    ablock<D, KVAR>(cf, phi, A);
+    ablock<D, KVAR, NP>(cf, phi, A);
     TC feq[Q];
-    equilibrium<Q>(cf, phi, phio, feq);
+    equilibrium<Q, NP>(cf, phi, phio, feq);
 
     TC out[Q];
     if (EQR) {
@@ -312,10 +332,10 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     if (SRC) {
         // Scheme A: + 3/2 R_k(t) - 1/2 R_k(t - 1), R_k = w_k (1 + 3 c.Btilde) R (Eq. 9)
         TC Bt[3], R, Btp[3], Rp, Ap[6];
-        source_terms<D>(cf, phi, A, Bt, R);
-        const TC pp = cf->phi_ref + (TC)p[n];
-        ablock<D, KVAR>(cf, pp, Ap);
-        source_terms<D>(cf, pp, Ap, Btp, Rp);
+        source_terms<D, NP>(cf, phi, A, Bt, R);
+        const TC pp = cf->phi_ref + pp_off;
+        ablock<D, KVAR, NP>(cf, pp, Ap);
+        source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
         const TC r1 = TC(1.5) * R, r0 = TC(0.5) * Rp;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
@@ -331,27 +351,32 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     }
 
 #pragma unroll
-    for (int k = 0; k < Q; ++k) store_s(fout + (uint64_t)k * g.plane + n, out[k]);
+    for (int k = 0; k < Q; ++k) store_s<NT>(fout + (uint64_t)k * g.plane + n, out[k]);
 
     if (!__builtin_isfinite(phio)) *flag = 1;
 }
 
-template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL>
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin,
         TS *__restrict__ fout, typename HistType<TS>::T *p, int *flag) {
-    const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
-    if (n >= g.N) return;
-    sweep_node<Q, TS, TC, EQR, SRC, KVAR, WALL>(g, cf, fin, fout, p, flag, n);
+    // each workgroup sweeps `chunk` consecutive blocks; with the XCD-aware
+    // order every XCD covers one contiguous slab of the domain
+    const uint32_t first = block_index(blockIdx.x, gridDim.x, g.remap) * g.chunk;
+    for (uint32_t i = 0; i < g.chunk; ++i) {
+        const uint32_t n = (first + i) * kBlock + threadIdx.x;
+        if (n >= g.N) return;
+        sweep_node<Q, TS, TC, EQR, SRC, KVAR, WALL, NP, NT>(g, cf, fin, fout, p, flag, n);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // initialisation (Eq. 40) in the gather convention
 // ---------------------------------------------------------------------------
-template <int Q, typename TC>
+template <int Q, int NP, typename TC>
 __device__ __forceinline__ TC feq_one(const Coefs<TC> *__restrict__ cf, TC phi, int kk) {
     TC feq[Q];
-    equilibrium<Q>(cf, phi, phi - cf->phi_ref, feq);
+    equilibrium<Q, NP>(cf, phi, phi - cf->phi_ref, feq);
     TC v = feq[0];
 #pragma unroll
     for (int k = 1; k < Q; ++k)
@@ -359,7 +384,7 @@ __device__ __forceinline__ TC feq_one(const Coefs<TC> *__restrict__ cf, TC phi, 
     return v;
 }
 
-template <int Q, typename TS, typename TC, bool WALL>
+template <int Q, typename TS, typename TC, bool WALL, int NP>
 __global__ void __launch_bounds__(kBlock)
 k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict__ phi0,
        TS *__restrict__ f, typename HistType<TS>::T *p) {
@@ -376,7 +401,7 @@ k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict_
         TC v;
         if (WALL && ((cl == 1 && ng.hi) || (cl == -1 && ng.lo))) {
             const TC ph = (TC)phi0[n];
-            v = cf->ew[cl == 1 ? 1 : 0][k] - feq_one<Q>(cf, ph, L::opp(k));
+            v = cf->ew[cl == 1 ? 1 : 0][k] - feq_one<Q, NP>(cf, ph, L::opp(k));
         } else {
             int off = 0;
 #pragma unroll
@@ -385,7 +410,7 @@ k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict_
                 off += (c == 1) ? ng.op[a] : ((c == -1) ? ng.om[a] : 0);
             }
             const TC ph = (TC)phi0[(uint32_t)((int)n + off)];
-            v = feq_one<Q>(cf, ph, k);
+            v = feq_one<Q, NP>(cf, ph, k);
         }
         store_s(f + (uint64_t)k * g.plane + n, v);
     }

@@ -39,4 +39,6 @@ hipError_t launch_seed_q9(const Dims &dm, const Geom &g, const double *gphi, voi
     LBM_BY_PREC_ADJ(seed_typed, dm, g, gphi, psi, pi, st)
 }
 
+hipError_t launch_zero(double *p, uint32_t n, hipStream_t st) { return zero_doubles(p, n, st); }
+
 }  // namespace lbm

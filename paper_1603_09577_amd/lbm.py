@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm.so")
+# PAPER_LBM_LIB selects another build of the same library (e.g. a variant)
+LIB_PATH = os.environ.get("PAPER_LBM_LIB") or os.path.join(HERE, "liblbm.so")
 MAXP = 9
 
 LBM_OK, LBM_E_INVALID, LBM_E_UNSUPPORTED, LBM_E_HIP, LBM_E_DIVERGED, LBM_E_STATE = 0, -1, -2, -3, -4, -5
@@ -23,13 +24,14 @@ FLAG_NO_GRAPH = 4
 
 # every symbol include/lbm.h declares
 EXPORTS = [
-    "lbm_create", "lbm_state_bytes", "lbm_init", "lbm_step", "lbm_sweep", "lbm_get_phi",
+    "lbm_create", "lbm_state_bytes", "lbm_adjoint_bytes", "lbm_init", "lbm_step", "lbm_sweep", "lbm_get_phi",
     "lbm_phi_of", "lbm_current", "lbm_set_current", "lbm_set_check", "lbm_set_k0",
     "lbm_reduce", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_init",
     "lbm_adjoint_grad_k0", "lbm_destroy", "lbm_last_error",
     "lbm_batch_create", "lbm_batch_layout", "lbm_batch_instance", "lbm_batch_init",
     "lbm_batch_step", "lbm_batch_get_phi", "lbm_batch_tune", "lbm_batch_set_shape",
-    "lbm_batch_get_shape", "lbm_batch_destroy",
+    "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
+    "lbm_set_nontemporal",
 ]
 
 
@@ -61,6 +63,7 @@ class LbmDesc(ctypes.Structure):
         ("kpoly", ctypes.c_double * MAXP),
         ("rpoly", ctypes.c_double * MAXP),
         ("flags", ctypes.c_int),
+        ("plane_pad", ctypes.c_int),
     ]
 
 
@@ -81,6 +84,7 @@ def load():
     sig = {
         "lbm_create": ([ctypes.POINTER(LbmDesc), ctypes.POINTER(_VP)], ctypes.c_int),
         "lbm_state_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_adjoint_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_init": ([_VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
         "lbm_step": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
         "lbm_sweep": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
@@ -111,6 +115,10 @@ def load():
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                  ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "lbm_batch_destroy": ([_VP], None),
+        "lbm_probe_copy": ([_VP, _VP, ctypes.c_size_t, ctypes.c_int, _VP], ctypes.c_int),
+        "lbm_set_chunk": ([_VP, ctypes.c_int], ctypes.c_int),
+        "lbm_set_nontemporal": ([_VP, ctypes.c_int], ctypes.c_int),
+        "lbm_tune": ([_VP, ctypes.c_int, _VP, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -168,6 +176,7 @@ def desc_from_spec(spec, flags=0):
             d.dten[a][c] = dten[a, c] if a < dten.shape[0] and c < dten.shape[1] else 0.0
             d.k0[a][c] = k0[a, c] if a < k0.shape[0] and c < k0.shape[1] else 0.0
     d.flags = int(flags | spec.get("flags", 0))
+    d.plane_pad = int(spec.get("plane_pad", 0))
     return d
 
 
@@ -256,6 +265,18 @@ class Lbm:
     def set_current(self, which, t):
         _check(self.lib.lbm_set_current(self.ctx, int(which), int(t)))
 
+    def set_nontemporal(self, on):
+        _check(self.lib.lbm_set_nontemporal(self.ctx, int(bool(on))))
+
+    def set_chunk(self, chunk):
+        _check(self.lib.lbm_set_chunk(self.ctx, int(chunk)))
+
+    def tune(self, reps=5, stream=None):
+        """Autotune the launch shape; restarts from the phi0 given to init."""
+        buf = ctypes.create_string_buffer(4096)
+        _check(self.lib.lbm_tune(self.ctx, int(reps), _stream(stream), buf, len(buf)))
+        return buf.value.decode()
+
     def set_check(self, every):
         _check(self.lib.lbm_set_check(self.ctx, int(every)))
 
@@ -273,8 +294,9 @@ class Lbm:
     def adjoint_buffers(self):
         """(psi, pi) buffers of the adjoint variables."""
         import torch
-        psi_bytes = self.q * self.N * (8 if self.desc.precision == 0 else 4)
-        psi = torch.empty(((psi_bytes + 255) // 256) * 256, dtype=torch.uint8, device=self.device)
+        nb = ctypes.c_size_t()
+        _check(self.lib.lbm_adjoint_bytes(self.ctx, ctypes.byref(nb)))
+        psi = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         pi = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         return psi, pi
 
@@ -301,10 +323,28 @@ class Lbm:
 
     # -- views ---------------------------------------------------------------
     def storage_view(self, buf):
-        """Typed [q, N] view of a distribution buffer (offsets f - w phi_ref)."""
+        """Typed [q, N] view of a distribution buffer (offsets f - w phi_ref);
+        planes are padded apart, so the view is strided."""
         import torch
         dt = {0: torch.float64, 1: torch.float32, 2: torch.float16}[self.desc.precision]
-        return buf.view(dt)[: self.q * self.N].view(self.q, self.N)
+        t = buf.view(dt)
+        plane = self.plane_elems()
+        return t[: self.q * plane].view(self.q, plane)[:, : self.N]
+
+    def plane_elems(self):
+        """Elements between consecutive direction planes."""
+        import torch
+        dt = {0: torch.float64, 1: torch.float32, 2: torch.float16}[self.desc.precision]
+        nb = ctypes.c_size_t()
+        _check(self.lib.lbm_adjoint_bytes(self.ctx, ctypes.byref(nb)))
+        # psi uses the same plane stride in the compute type
+        return nb.value // (8 if self.desc.precision == 0 else 4) // self.q
+
+
+def probe_copy(src, dst, grid=0, stream=None):
+    """Plain 16-byte-per-lane device copy of src into dst (torch tensors)."""
+    n = min(src.numel() * src.element_size(), dst.numel() * dst.element_size())
+    _check(load().lbm_probe_copy(_ptr(src), _ptr(dst), ctypes.c_size_t(n & ~15), int(grid), _stream(stream)))
 
 
 class Batch:

@@ -230,3 +230,25 @@ def test_graph_replay_identical_to_direct_launches():
     c = lbm.Lbm(spec, flags=lbm.FLAG_NO_XCD_REMAP).init(phi0)
     c.step(100)
     assert torch.equal(a.phi(), c.phi())
+
+
+def test_launch_variants_identical():
+    """Non-temporal accesses, chunked workgroups and the autotuned shape change
+    only how the sweep is launched: results are bit-identical."""
+    lbm = _lbm()
+    for spec, phi0 in ((W.spec_nonlinear_2d(150, 90, precision="f32"), W.noise_field((90, 150), 20)),
+                       (W.C3((20, 18, 22))[0], W.C3((20, 18, 22))[1])):
+        say(f"[gpu] launch variants {spec['shape']}")
+        ref = lbm.Lbm(spec).init(phi0)
+        ref.step(70)
+        want = ref.phi()
+        for nt, chunk in ((1, 1), (0, 3), (1, 5)):
+            s = lbm.Lbm(spec).init(phi0)
+            s.set_nontemporal(nt)
+            s.set_chunk(chunk)
+            s.step(70)
+            assert torch.equal(s.phi(), want), (nt, chunk)
+        s = lbm.Lbm(spec).init(phi0)
+        s.tune(reps=2)
+        s.step(70)
+        assert torch.equal(s.phi(), want)
