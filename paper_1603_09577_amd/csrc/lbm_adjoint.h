@@ -118,10 +118,6 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
         const TC phi = cf->phi_ref + phio;
         TC A[6];
         ablock<D, KVAR, NP>(cf, phi, A);
-        TC feq[Q], dlt[Q];
-        equilibrium<Q, NP>(cf, phi, phio, feq);
-#pragma unroll
-        for (int k = 0; k < Q; ++k) dlt[k] = h[k] - feq[k];
 
         // ---- lambda = dL/d(out) by transposed streaming ----
         TC lam[Q];
@@ -145,46 +141,153 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) Ab[a][b] = TC(0);
-        TC db[Q];   // adjoint of dlt = h - feq
+        TC phib = TC(0), pb = TC(0);
+        TC hb[Q];
+
         if (EQR) {
+            // Forward (see sweep_node):
+            //   out_k = (1 - s) g_k + w_k (s phio + Se + 9/2 s (E : c_k c_k - tr E / 3))
+            //           + c_k . (w_k (3 s B + Vo) - v),  v = (A - s I)(j - B) / |c_a|^2,
+            //   Se = 3/2 R - 1/2 Rp, Vo = 9/2 R Bt - 3/2 Rp Btp, Bt = (I - A/2) B'.
+            // Its adjoint needs only moments of lambda:
+            //   L0w = sum w lam, L1 = sum c lam, L1w = sum w c lam, L2w = sum w c c lam.
             const TC s = cf->srate;
-            TC jd[3], vb[3], jdb[3];
+            constexpr TC inv_nc = TC(1.0 / L::jnorm);
+            TC L0w = TC(0), L1[3] = {TC(0), TC(0), TC(0)}, L1w[3] = {TC(0), TC(0), TC(0)};
+            TC L2w[6] = {TC(0), TC(0), TC(0), TC(0), TC(0), TC(0)};
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const TC wl = TC(L::w(k)) * lam[k];
+                L0w += wl;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const int c = L::c(k, a);
+                    if (c) { L1[a] += TC(c) * lam[k]; L1w[a] += TC(c) * wl; }
+                }
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = a; b < D; ++b) {
+                        const int cc = L::c(k, a) * L::c(k, b);
+                        if (cc) L2w[sym(a, b)] += TC(cc) * wl;
+                    }
+            }
+            // forward pieces at phi
+            TC B[3], Bp[3], Bpp[3], jd[3];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                TC acc = TC(0), accl = TC(0);
+                B[a] = poly<NP>(cf->b[a], phi);
+                Bp[a] = poly<NP>(cf->bp[a], phi);
+                Bpp[a] = poly<NP>(cf->bpp[a], phi);
+                TC acc = TC(0);
 #pragma unroll
                 for (int k = 0; k < Q; ++k) {
                     const int c = L::c(k, a);
-                    if (c) { acc += TC(c) * dlt[k]; accl += TC(c) * lam[k]; }
+                    if (c == 1) acc += h[k];
+                    else if (c == -1) acc -= h[k];
                 }
-                jd[a] = acc;
-                vb[a] = -accl;   // out = h - s dlt - c.v
+                jd[a] = acc - B[a];
             }
+            // u = (A - s I) L1 / |c|^2: adjoint of j (with a minus) and of B
+            TC u[3];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 TC acc = TC(0);
 #pragma unroll
-                for (int b = 0; b < D; ++b) acc += (A[sym(a, b)] - (a == b ? s : TC(0))) * vb[b];
-                jdb[a] = acc * TC(1.0 / L::jnorm);
+                for (int b = 0; b < D; ++b) acc += (A[sym(a, b)] - (a == b ? s : TC(0))) * L1[b];
+                u[a] = acc * inv_nc;
             }
 #pragma unroll
             for (int a = 0; a < D; ++a)
 #pragma unroll
-                for (int b = 0; b < D; ++b) Ab[a][b] += vb[a] * jd[b] * TC(1.0 / L::jnorm);
+                for (int b = 0; b < D; ++b) Ab[a][b] -= L1[a] * jd[b] * inv_nc;
+            // phio, B, E
+            phib = s * L0w;
+#pragma unroll
+            for (int a = 0; a < D; ++a) phib += (TC(3) * s * L1w[a] + u[a]) * Bp[a];
+            {
+                const TC s45 = TC(4.5) * s;
+                TC tr = TC(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    // dE_aa/dphi = Cbar'_aa - 1/3, weight 9/2 s (L2w_aa - L0w / 3)
+                    const TC cbd = poly<PolyLen<NP>::NC>(cf->cbd[a], phi) - TC(1.0 / 3.0);
+                    tr += s45 * (L2w[a] - L0w * TC(1.0 / 3.0)) * cbd;
+                }
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = a + 1; b < D; ++b)
+                        tr += s45 * TC(2) * L2w[sym(a, b)] * poly<PolyLen<NP>::NC>(cf->cbd[sym(a, b)], phi);
+                phib += tr;
+            }
+            if (SRC) {
+                TC Bt[3], R, Btp[3], Rp, Ap[6];
+                source_terms<D, NP>(cf, phi, A, Bt, R);
+                const TC pp = cf->phi_ref + pp_off;
+                ablock<D, KVAR, NP>(cf, pp, Ap);
+                source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
+                TC t1 = TC(0), t1p = TC(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) { t1 += L1w[a] * Bt[a]; t1p += L1w[a] * Btp[a]; }
+                const TC Rb = TC(1.5) * L0w + TC(4.5) * t1;
+                const TC Rpb = TC(-0.5) * L0w - TC(1.5) * t1p;
+                phib += Rb * poly<NP>(cf->rp, phi);
+                pb += Rpb * poly<NP>(cf->rp, pp);
+                TC Btb[3], Btpb[3], Bpq[3], Bppq[3];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    Btb[a] = TC(4.5) * R * L1w[a];
+                    Btpb[a] = TC(-1.5) * Rp * L1w[a];
+                    Bpq[a] = poly<NP>(cf->bp[a], pp);
+                    Bppq[a] = poly<NP>(cf->bpp[a], pp);
+                }
+                TC Apb[3][3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) Apb[a][b] = TC(0);
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    TC acc = Btb[b], accp = Btpb[b];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        acc -= TC(0.5) * A[sym(a, b)] * Btb[a];
+                        accp -= TC(0.5) * Ap[sym(a, b)] * Btpb[a];
+                    }
+                    phib += acc * Bpp[b];
+                    pb += accp * Bppq[b];
+                }
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        Ab[a][b] -= TC(0.5) * Btb[a] * Bp[b];
+                        Apb[a][b] -= TC(0.5) * Btpb[a] * Bpq[b];
+                    }
+                TC Gbp[6];
+                gbar_of<D>(Ap, Apb, Gbp);
+                pb += gbar_scatter<D, KVAR, NP>(cf, pp, Gbp, gk);
+            }
+            const TC oms = TC(1) - s;
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                TC acc = -s * lam[k];
+                TC cu = TC(0);
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     const int c = L::c(k, a);
-                    if (c) acc += TC(c) * jdb[a];
+                    if (c) cu += TC(c) * u[a];
                 }
-                db[k] = acc;
+                hb[k] = oms * lam[k] - cu;
             }
         } else {
+            TC feq[Q], dlt[Q];
+            equilibrium<Q, NP>(cf, phi, phio, feq);
+#pragma unroll
+            for (int k = 0; k < Q; ++k) dlt[k] = h[k] - feq[k];
             // out = h - M^T N^-1 S M dlt: u = N^-1 M lambda, rbar = -u,
             // mbar = S^T rbar, dbar = M^T mbar, Abar_ab += rbar_ja m_jb
-            TC m[Q], u[Q];
+            TC m[Q], u[Q], db[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 TC acc = TC(0), accl = TC(0);
@@ -220,85 +323,79 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
                 }
                 db[k] = acc;
             }
-        }
-        // h enters directly (out = h - ...) and through dlt
-        TC hb[Q];
+            // h enters directly (out = h - ...) and through dlt; feq through
+            // dlt with a minus sign, and feq depends on phi only
 #pragma unroll
-        for (int k = 0; k < Q; ++k) hb[k] = lam[k] + db[k];
-        // feq enters through dlt with a minus sign; feq depends on phi only
-        TC phib = TC(0);
-        {
-            TC dfe[Q];
-            eq_derivative<Q, NP>(cf, phi, dfe);
+            for (int k = 0; k < Q; ++k) hb[k] = lam[k] + db[k];
+            {
+                TC dfe[Q];
+                eq_derivative<Q, NP>(cf, phi, dfe);
 #pragma unroll
-            for (int k = 0; k < Q; ++k) phib -= db[k] * dfe[k];
-        }
-
-        TC pb = TC(0);
-        if (SRC) {
-            TC Bt[3], R, Btp[3], Rp, Ap[6];
-            source_terms<D, NP>(cf, phi, A, Bt, R);
-            const TC pp = cf->phi_ref + pp_off;
-            ablock<D, KVAR, NP>(cf, pp, Ap);
-            source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
-            TC S1 = TC(0), T1[3] = {TC(0), TC(0), TC(0)};
+                for (int k = 0; k < Q; ++k) phib -= db[k] * dfe[k];
+            }
+            if (SRC) {
+                TC Bt[3], R, Btp[3], Rp, Ap[6];
+                source_terms<D, NP>(cf, phi, A, Bt, R);
+                const TC pp = cf->phi_ref + pp_off;
+                ablock<D, KVAR, NP>(cf, pp, Ap);
+                source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
+                TC S1 = TC(0), T1[3] = {TC(0), TC(0), TC(0)};
 #pragma unroll
-            for (int k = 0; k < Q; ++k) {
-                const TC wl = TC(L::w(k)) * lam[k];
-                S1 += wl;
+                for (int k = 0; k < Q; ++k) {
+                    const TC wl = TC(L::w(k)) * lam[k];
+                    S1 += wl;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const int c = L::c(k, a);
+                        if (c) T1[a] += TC(c) * wl;
+                    }
+                }
+                // time level t: + 3/2 R (S1 + 3 T1.Bt);  level t-1: - 1/2 Rp (S1 + 3 T1.Btp)
+                TC tb = TC(0), tbp = TC(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) { tb += T1[a] * Bt[a]; tbp += T1[a] * Btp[a]; }
+                const TC Rb = TC(1.5) * (S1 + TC(3) * tb);
+                const TC Rpb = TC(-0.5) * (S1 + TC(3) * tbp);
+                TC Btb[3], Btpb[3];
+#pragma unroll
+                for (int a = 0; a < D; ++a) { Btb[a] = TC(4.5) * R * T1[a]; Btpb[a] = TC(-1.5) * Rp * T1[a]; }
+                phib += Rb * poly<NP>(cf->rp, phi);
+                pb += Rpb * poly<NP>(cf->rp, pp);
+                TC Bp[3], Bpp[3], Bpq[3], Bppq[3];
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    const int c = L::c(k, a);
-                    if (c) T1[a] += TC(c) * wl;
+                    Bp[a] = poly<NP>(cf->bp[a], phi);
+                    Bpp[a] = poly<NP>(cf->bpp[a], phi);
+                    Bpq[a] = poly<NP>(cf->bp[a], pp);
+                    Bppq[a] = poly<NP>(cf->bpp[a], pp);
                 }
-            }
-            // time level t: + 3/2 R (S1 + 3 T1.Bt);  level t-1: - 1/2 Rp (S1 + 3 T1.Btp)
-            TC tb = TC(0), tbp = TC(0);
+                TC Apb[3][3];
 #pragma unroll
-            for (int a = 0; a < D; ++a) { tb += T1[a] * Bt[a]; tbp += T1[a] * Btp[a]; }
-            const TC Rb = TC(1.5) * (S1 + TC(3) * tb);
-            const TC Rpb = TC(-0.5) * (S1 + TC(3) * tbp);
-            TC Btb[3], Btpb[3];
+                for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int a = 0; a < D; ++a) { Btb[a] = TC(4.5) * R * T1[a]; Btpb[a] = TC(-1.5) * Rp * T1[a]; }
-            // R(phi), R(p)
-            phib += Rb * poly<NP>(cf->rp, phi);
-            pb += Rpb * poly<NP>(cf->rp, pp);
-            // Btilde = B' - A B' / 2
-            TC Bp[3], Bpp[3], Bpq[3], Bppq[3];
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                Bp[a] = poly<NP>(cf->bp[a], phi);
-                Bpp[a] = poly<NP>(cf->bpp[a], phi);
-                Bpq[a] = poly<NP>(cf->bp[a], pp);
-                Bppq[a] = poly<NP>(cf->bpp[a], pp);
-            }
-            TC Apb[3][3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) Apb[a][b] = TC(0);
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                TC acc = Btb[b], accp = Btpb[b];
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    acc -= TC(0.5) * A[sym(a, b)] * Btb[a];
-                    accp -= TC(0.5) * Ap[sym(a, b)] * Btpb[a];
-                }
-                phib += acc * Bpp[b];
-                pb += accp * Bppq[b];
-            }
-#pragma unroll
-            for (int a = 0; a < D; ++a)
+                    for (int b = 0; b < 3; ++b) Apb[a][b] = TC(0);
 #pragma unroll
                 for (int b = 0; b < D; ++b) {
-                    Ab[a][b] -= TC(0.5) * Btb[a] * Bp[b];
-                    Apb[a][b] -= TC(0.5) * Btpb[a] * Bpq[b];
+                    TC acc = Btb[b], accp = Btpb[b];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        acc -= TC(0.5) * A[sym(a, b)] * Btb[a];
+                        accp -= TC(0.5) * Ap[sym(a, b)] * Btpb[a];
+                    }
+                    phib += acc * Bpp[b];
+                    pb += accp * Bppq[b];
                 }
-            TC Gbp[6];
-            gbar_of<D>(Ap, Apb, Gbp);
-            pb += gbar_scatter<D, KVAR, NP>(cf, pp, Gbp, gk);
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        Ab[a][b] -= TC(0.5) * Btb[a] * Bp[b];
+                        Apb[a][b] -= TC(0.5) * Btpb[a] * Bpq[b];
+                    }
+                TC Gbp[6];
+                gbar_of<D>(Ap, Apb, Gbp);
+                pb += gbar_scatter<D, KVAR, NP>(cf, pp, Gbp, gk);
+            }
         }
         {
             TC Gb[6];

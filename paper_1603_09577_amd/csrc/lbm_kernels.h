@@ -247,28 +247,58 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
 
     TC A[6];
     ablock<D, KVAR, NP>(cf, phi, A);
-    TC feq[Q];
-    equilibrium<Q, NP>(cf, phi, phio, feq);
 
     TC out[Q];
     if (EQR) {
-        // All non-flux rates equal s: (M^-1 S M)(g - feq) = s (g - feq)
-        // + c_k . (A - s I)(j - B) / |c_a|^2, since the rows of M are
-        // orthogonal and the flux rows are c_a (the density row drops out in
-        // Scheme A because sum g = sum feq).
+        // All non-flux rates equal s.  With orthogonal rows and the flux rows
+        // equal to c_a, (M^-1 S M)(g - feq) = s (g - feq) + c_k . v with
+        // v = (A - s I)(j - B) / |c_a|^2 (the density row drops out in Scheme A
+        // since sum g = sum feq = phi).  Adding s feq_k and the Scheme-A source
+        // and splitting every term into its part even and odd under
+        // c_k -> -c_k gives
+        //   out_k = (1 - s) g_k + w_k (s phio + Se + 9/2 s (E : c_k c_k - tr E / 3))
+        //           + c_k . (w_k (3 s B + Vo) - v),
+        // E = Cbar - phi/3 I, Se = 3/2 R(t) - 1/2 R(t-1) and
+        // Vo = 3 (3/2 R(t) Btilde(t) - 1/2 R(t-1) Btilde(t-1)).  Opposite
+        // directions share the even part and negate the odd one.
         const TC s = cf->srate;
-        TC jd[3];
+        TC B[3], E[6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) B[a] = (a < D) ? poly<NP>(cf->b[a], phi) : TC(0);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const bool used = (D == 3) || (i == 0 || i == 1 || i == 3);
+            E[i] = used ? poly<PolyLen<NP>::NC>(cf->cb[i], phi) : TC(0);
+        }
+        const TC third = phi * TC(1.0 / 3.0);
+        E[0] -= third; E[1] -= third;
+        if (D == 3) E[2] -= third;
+        const TC trE3 = (E[0] + E[1] + E[2]) * TC(1.0 / 3.0);
+        TC Se = TC(0), Vo[3] = {TC(0), TC(0), TC(0)};
+        if (SRC) {
+            TC Bt[3], R, Btp[3], Rp, Ap[6];
+            source_terms<D, NP>(cf, phi, A, Bt, R);
+            const TC pp = cf->phi_ref + pp_off;
+            ablock<D, KVAR, NP>(cf, pp, Ap);
+            source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
+            Se = TC(1.5) * R - TC(0.5) * Rp;
+#pragma unroll
+            for (int a = 0; a < D; ++a) Vo[a] = TC(4.5) * R * Bt[a] - TC(1.5) * Rp * Btp[a];
+            p[n] = (typename HistType<TS>::T)phio;
+        }
+        // j - B, with j the first moment of the gathered populations
+        TC jd[3], v[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             TC acc = TC(0);
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
                 const int c = L::c(k, a);
-                if (c) acc += TC(c) * (h[k] - feq[k]);
+                if (c == 1) acc += h[k];
+                else if (c == -1) acc -= h[k];
             }
-            jd[a] = (a < D) ? acc : TC(0);
+            jd[a] = (a < D) ? acc - B[a] : TC(0);
         }
-        TC v[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             TC acc = TC(0);
@@ -276,19 +306,39 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
             for (int b = 0; b < D; ++b) acc += (A[sym(a, b)] - (a == b ? s : TC(0))) * jd[b];
             v[a] = acc * TC(1.0 / L::jnorm);
         }
+        const TC base = s * phio + Se;
+        const TC s45 = TC(4.5) * s;
+        const TC oms = TC(1) - s;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-            TC cv = TC(0);
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                const int c = L::c(k, a);
-                if (c) cv += TC(c) * v[a];
+            const int kb = L::opp(k);
+            if (kb < k) continue;
+            const int x = L::cx(k), y = L::cy(k), z = L::cz(k);
+            TC ccE = -trE3;
+            if (x) ccE += E[0];
+            if (y) ccE += E[1];
+            if (z) ccE += E[2];
+            if (x && y) ccE += TC(2 * x * y) * E[3];
+            if (y && z) ccE += TC(2 * y * z) * E[4];
+            if (x && z) ccE += TC(2 * x * z) * E[5];
+            const TC w = TC(L::w(k));
+            const TC even = w * (base + s45 * ccE);
+            if (kb == k) {
+                out[k] = oms * h[k] + even;
+                continue;
             }
-            out[k] = h[k] - s * (h[k] - feq[k]) - cv;
+            TC odd = TC(0);
+            if (x) odd += TC(x) * (w * (TC(3) * s * B[0] + Vo[0]) - v[0]);
+            if (y) odd += TC(y) * (w * (TC(3) * s * B[1] + Vo[1]) - v[1]);
+            if (z) odd += TC(z) * (w * (TC(3) * s * B[2] + Vo[2]) - v[2]);
+            out[k] = oms * h[k] + even + odd;
+            out[kb] = oms * h[kb] + even - odd;
         }
     } else {
         // m = M (g - feq); relax with S (diagonal rates, block A on the flux
         // rows, Eq. 17); back with M^-1 = M^T N^-1 (orthogonal rows).
+        TC feq[Q];
+        equilibrium<Q, NP>(cf, phi, phio, feq);
         TC dlt[Q], m[Q], r[Q];
 #pragma unroll
         for (int k = 0; k < Q; ++k) dlt[k] = h[k] - feq[k];
@@ -329,7 +379,7 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
         }
     }
 
-    if (SRC) {
+    if (SRC && !EQR) {
         // Scheme A: + 3/2 R_k(t) - 1/2 R_k(t - 1), R_k = w_k (1 + 3 c.Btilde) R (Eq. 9)
         TC Bt[3], R, Btp[3], Rp, Ap[6];
         source_terms<D, NP>(cf, phi, A, Bt, R);
