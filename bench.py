@@ -211,6 +211,123 @@ def cpu_baseline(spec, phi0, target_s=12.0):
                       f"(first step untimed), OpenMP over nodes"}, orc.phi(p, f), n + 1
 
 
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries: the committed profiles are written from the raw CSVs
+# of the three profiled runs named in PROFILE_COMMANDS.
+# ---------------------------------------------------------------------------
+
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- "
+             "python3 bench.py --no-cpu --steps 1000 --warmup 50",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch --output-format csv -- "
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19",
+    "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write --output-format csv -- "
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19",
+}
+
+# workload label -> (kernel name prefix in the trace, algorithmic bytes per launch)
+PROFILED = {
+    "nonlinear2d-1024 f32": ("k_sweep<9, float, float, true, true, true, false, 4, false>",
+                             bytes_per_node(9, "f32", True) * 1024 * 1024),
+    "nonlinear2d-1024 f64": ("k_sweep<9, double, double, true, true, true, false, 4, false>",
+                             bytes_per_node(9, "f64", True) * 1024 * 1024),
+    "d3q19-256 f32": ("k_sweep<19, float, float, true, false, false, true, 4, true>",
+                      bytes_per_node(19, "f32", False) * 256 ** 3),
+    "d3q19-256 f64": ("k_sweep<19, double, double, true, false, false, true, 4, true>",
+                      bytes_per_node(19, "f64", False) * 256 ** 3),
+    "adjoint2d-512 f64": ("k_adjoint<9, double, double, true, true, true, false, 4>",
+                          adjoint_bytes_per_node(9, "f64", True) * 512 * 512),
+    "adjoint2d-512 f32": ("k_adjoint<9, float, float, true, true, true, false, 4>",
+                          adjoint_bytes_per_node(9, "f32", True) * 512 * 512),
+}
+
+
+def summarize_profiles(gdir, copy_bytes=1 << 30):
+    """Write profiles/pmc_traffic.json, profiles/sweep_kernels_kernel_trace.md
+    and profiles/sweep_kernels_hbm_traffic.md from the CSV output of the
+    three runs in PROFILE_COMMANDS (under `gdir`).  FETCH_SIZE and WRITE_SIZE
+    are scaled by what they read for the library copy kernel moving
+    `copy_bytes` each way."""
+    import csv
+    import statistics as stats
+
+    def kname(n):
+        return n.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").strip()
+
+    trace = list(csv.DictReader(open(os.path.join(gdir, "prof_trace", "trace_kernel_stats.csv"))))
+    avg_us = {kname(r["Name"]): float(r["AverageNs"]) / 1e3 for r in trace}
+
+    def counters(sub, stem, cname):
+        agg = {}
+        for r in csv.DictReader(open(os.path.join(gdir, sub, f"{stem}_counter_collection.csv"))):
+            if r.get("Counter_Name") == cname:
+                agg.setdefault(kname(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        return agg
+
+    fetch = counters("pmc_fetch", "fetch", "FETCH_SIZE")
+    write = counters("pmc_write", "write", "WRITE_SIZE")
+    copy = next(k for k in fetch if "k_copy16" in k)
+    fscale = copy_bytes / (stats.median(fetch[copy]) * 1024)
+    wscale = copy_bytes / (stats.median(write[copy]) * 1024)
+    out = {"kernel_hash": kernel_hash(), "fetch_scale": fscale, "write_scale": wscale,
+           "calibration": f"library copy kernel k_copy16 of {copy_bytes} bytes each way",
+           "commands": PROFILE_COMMANDS, "workloads": {}}
+    rows = []
+    for label, (kn, alg) in PROFILED.items():
+        hits = [k for k in fetch if kn in k]
+        if not hits or hits[0] not in write:
+            continue
+        k = hits[0]
+        fv, wv = stats.median(fetch[k]), stats.median(write[k])
+        t = fv * 1024 * fscale + wv * 1024 * wscale
+        tr = next((v for n, v in avg_us.items() if kn in n), None)
+        out["workloads"][label] = {"kernel": kn, "fetch_kib": fv, "write_kib": wv,
+                                   "traffic_bytes_per_launch": t, "algorithmic_bytes_per_launch": alg,
+                                   "dispatches": len(fetch[k]), "trace_avg_us": tr}
+        rows.append((label, kn, len(fetch[k]), fv, wv, t, alg, tr))
+    pdir = os.path.join(ROOT, "profiles")
+    with open(os.path.join(pdir, "pmc_traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+
+    md = ["# HBM traffic of the sweep and adjoint kernels (rocprofv3 counters)", "",
+          "Two passes, one counter each, from the repository root with `TMPDIR=/tmp`:", "",
+          "    " + PROFILE_COMMANDS["fetch"], "    " + PROFILE_COMMANDS["write"], "",
+          "Summarised by `python3 bench.py --summarize-profiles gpurun_out`.", "",
+          f"Calibration: the same run executes the library copy kernel `k_copy16`, which reads and "
+          f"writes {copy_bytes / 2**30:g} GiB. FETCH_SIZE reads {1 / fscale:.4f} of the bytes it "
+          f"fetches (scale x{fscale:.3f}); WRITE_SIZE reads {1 / wscale:.4f} of the bytes it writes "
+          f"(scale x{wscale:.3f}).", "",
+          "Values are medians per dispatch. Traffic = scaled fetch + scaled write. Algorithmic bytes = "
+          "bytes per node update x nodes per launch; the trace column is the average kernel time from "
+          "the kernel-trace run and the bandwidth is algorithmic bytes over it.", "",
+          "| workload | kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | traffic MB | "
+          "algorithmic MB | traffic / algorithmic | trace avg us | GB/s (algorithmic) |",
+          "|---|---|---|---|---|---|---|---|---|---|"]
+    for label, kn, nd, fv, wv, t, alg, tr in rows:
+        bw = f"{alg / (tr * 1e-6) / 1e9:.0f}" if tr else "-"
+        trs = f"{tr:.2f}" if tr else "-"
+        md.append(f"| {label} | `{kn}` | {nd} | {fv:.1f} | {wv:.1f} | {t / 1e6:.2f} | {alg / 1e6:.2f} | "
+                  f"{t / alg:.3f} | {trs} | {bw} |")
+    md += ["", f"Kernel-source hash `{out['kernel_hash']}`; `bench.py` reports `traffic` only while the "
+           "sources hash to it. Machine-readable copy: `pmc_traffic.json`."]
+    with open(os.path.join(pdir, "sweep_kernels_hbm_traffic.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+
+    tl = ["# Kernel trace: fused sweep, adjoint and batch kernels (MI355X, gfx950)", "",
+          "From the repository root with `TMPDIR=/tmp`:", "", "    " + PROFILE_COMMANDS["trace"], "",
+          "Summarised by `python3 bench.py --summarize-profiles gpurun_out`. The run includes the "
+          "autotuners' trial launches. Template arguments of the sweep:", "",
+          "    k_sweep<Q, storage, compute, equal-rate, source, K(phi), walls, polynomial length, non-temporal>",
+          "", "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in trace[:20]:
+        tl.append(f"| `{kname(r['Name'])[:110]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                  f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                  f"{float(r['Percentage']):.1f} |")
+    with open(os.path.join(pdir, "sweep_kernels_kernel_trace.md"), "w") as fh:
+        fh.write("\n".join(tl) + "\n")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,7 +339,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain copy (practical bandwidth, counter calibration)")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="write the profiles/ summaries from rocprofv3 output under DIR and exit (no GPU)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        out = summarize_profiles(args.summarize_profiles, args.copy_bytes)
+        print(json.dumps({k: v["traffic_bytes_per_launch"] / v["algorithmic_bytes_per_launch"]
+                          for k, v in out["workloads"].items()}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
@@ -232,13 +356,13 @@ def main():
 
     torch.cuda.set_device(0)
     K, Wm = args.steps, args.warmup
-    spec32, phi0, _ = W.C2(1024, precision="f32")
-    spec64, _, _ = W.C2(1024, precision="f64")
+    spec32, phi0, _ = W.nonlinear_2d(1024, precision="f32")
+    spec64, _, _ = W.nonlinear_2d(1024, precision="f64")
 
-    head, sim32, phi32 = run_forward(torch, lbm, spec32, phi0, K, Wm, "C2 f32")
-    print(f"# C2 f32: {head['mlups']:.0f} MLUPS, {head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
-    f64, sim64, phi64 = run_forward(torch, lbm, spec64, phi0, K, Wm, "C2 f64")
-    print(f"# C2 f64: {f64['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    head, sim32, phi32 = run_forward(torch, lbm, spec32, phi0, K, Wm, "nonlinear2d-1024 f32")
+    print(f"# nonlinear2d-1024 f32: {head['mlups']:.0f} MLUPS, {head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    f64, sim64, phi64 = run_forward(torch, lbm, spec64, phi0, K, Wm, "nonlinear2d-1024 f64")
+    print(f"# nonlinear2d-1024 f64: {f64['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     # both ran warmup + K steps from the same phi0: error of FP32 storage
     # against the FP64 path after the same number of steps
     err32 = float(torch.linalg.norm(phi32 - phi64) / torch.linalg.norm(phi64))
@@ -248,21 +372,21 @@ def main():
     if args.quick:
         only = set()
     if "adjoint" in only:
-        spec5, p5, _, _ = W.C5()
-        extra["adjoint_f64"] = run_adjoint(torch, lbm, spec5, p5, 200, 20, "C5 adjoint f64")
-        spec5f, _, _, _ = W.C5(precision="f32")
-        extra["adjoint_f32"] = run_adjoint(torch, lbm, spec5f, p5, 200, 20, "C5 adjoint f32")
+        spec5, p5, _, _ = W.adjoint_2d()
+        extra["adjoint_f64"] = run_adjoint(torch, lbm, spec5, p5, 200, 20, "adjoint2d-512 f64")
+        spec5f, _, _, _ = W.adjoint_2d(precision="f32")
+        extra["adjoint_f32"] = run_adjoint(torch, lbm, spec5f, p5, 200, 20, "adjoint2d-512 f32")
         print(f"# adjoint f64 {extra['adjoint_f64']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     if "d3q19" in only:
-        spec3, p3, _ = W.C3(precision="f32")
-        d3, s3, _ = run_forward(torch, lbm, spec3, p3, 200, 20, "C3 f32")
+        spec3, p3, _ = W.d3q19_walls(precision="f32")
+        d3, s3, _ = run_forward(torch, lbm, spec3, p3, 200, 20, "d3q19-256 f32")
         del s3
         extra["d3q19_f32"] = d3
-        spec3d, _, _ = W.C3(precision="f64")
-        d3d, s3d, _ = run_forward(torch, lbm, spec3d, p3, 100, 10, "C3 f64")
+        spec3d, _, _ = W.d3q19_walls(precision="f64")
+        d3d, s3d, _ = run_forward(torch, lbm, spec3d, p3, 100, 10, "d3q19-256 f64")
         del s3d
         extra["d3q19_f64"] = d3d
-        print(f"# C3 f32 {d3['mlups']:.0f} / f64 {d3d['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        print(f"# d3q19-256 f32 {d3['mlups']:.0f} / f64 {d3d['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if "batch" in only:
         extra["batch_f32"] = run_batch(torch, lbm, W, 1000 if args.steps >= 1000 else args.steps)
@@ -283,7 +407,7 @@ def main():
         extra["rel_l2_vs_oracle"] = {"steps": ncpu, **errs}
 
     per = head["ms_per_step"] / 1e3
-    traffic = traffic_from_profiles("C2 f32")
+    traffic = traffic_from_profiles("nonlinear2d-1024 f32")
     line = {
         "metric": METRIC,
         "value": head["mlups"],

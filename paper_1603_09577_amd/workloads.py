@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "spec_linear_gaussian", "spec_nonlinear_2d", "spec_d3q19_aniso",
     "gaussian_hill", "noise_field", "gaussians_3d", "random_spd3",
-    "C1", "C2", "C3", "C5", "C5B", "batch_specs",
+    "hill_linear_64", "nonlinear_2d", "d3q19_walls", "adjoint_2d", "adjoint_2d_sourcefree", "batch_specs",
 ]
 
 
@@ -167,7 +167,7 @@ def gaussians_3d(n=(256, 256, 256), seed=3, count=8):
 # the five workloads (plus the non-degenerate gradient variant)
 # ----------------------------------------------------------------------------
 
-def C1():
+def hill_linear_64():
     """D2Q9, linear isotropic CDE, periodic 64 x 64, u = (0.05, 0.02),
     kappa = 0.01, Gaussian hill (amplitude 1, sigma 6, centred), R = 0,
     s1 = s2 = 1.2, 1000 steps."""
@@ -175,29 +175,29 @@ def C1():
     return spec, gaussian_hill(64, 6.0), 1000
 
 
-def C2(n=1024, precision="f64"):
+def nonlinear_2d(n=1024, precision="f64"):
     """D2Q9 nonlinear anisotropic CDE, periodic n x n, phi0 = 0.5 + 0.1 U[-1, 1)
     (seed 2), Scheme A source, 5000 steps."""
     spec = spec_nonlinear_2d(n, precision=precision)
     return spec, noise_field((n, n), 2), 5000
 
 
-def C3(n=(256, 256, 256), precision="f64"):
+def d3q19_walls(n=(256, 256, 256), precision="f64"):
     """D3Q19 anisotropic CDE, periodic x/y, phi_w = 0 walls on z, K from seed 3,
     u = (0.03, 0, 0.01), sum of 8 Gaussians (seed 3), 2000 steps."""
     spec = spec_d3q19_aniso(n, K=random_spd3(3), precision=precision, phi_ref=0.0)
     return spec, gaussians_3d(n, 3), 2000
 
 
-def C5(n=512, precision="f64"):
-    """Adjoint workload: C2 physics on n x n (seed 5), target phi* from seed 6,
+def adjoint_2d(n=512, precision="f64"):
+    """Adjoint workload: the nonlinear 2-D physics on n x n (seed 5), target phi* from seed 6,
     2000 steps, sqrt(T) = 45-step checkpoints."""
     spec = spec_nonlinear_2d(n, precision=precision)
     return spec, noise_field((n, n), 5), noise_field((n, n), 6), 2000
 
 
-def C5B(n=512, precision="f64", nsteps=2000):
-    """Non-degenerate gradient variant of C5: R = 0, so the sensitivities do
+def adjoint_2d_sourcefree(n=512, precision="f64", nsteps=2000):
+    """Non-degenerate gradient variant of the adjoint workload: R = 0, so the sensitivities do
     not vanish; the target is a forward run of the same model from seed 6."""
     spec = spec_nonlinear_2d(n, precision=precision, source=False)
     return spec, noise_field((n, n), 5), noise_field((n, n), 6), nsteps

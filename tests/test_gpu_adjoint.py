@@ -150,8 +150,8 @@ def _fd_check(spec, phi0, target, T, ndir=16, seed=7, eps=2e-3):
 def test_adjoint_finite_differences_full_c5():
     """The adjoint workload at full size (512 x 512, 2000 steps, 45-step
     checkpoints), FP64: adjoint vs central differences on 16 directions."""
-    spec, phi0, target, T = W.C5()
-    say(f"[gpu adjoint] C5 full FD, T={T}")
+    spec, phi0, target, T = W.adjoint_2d()
+    say(f"[gpu adjoint] adjoint2d 512 FD, T={T}")
     worst = _fd_check(spec, phi0, target, T)
     assert worst <= 1e-6
 
@@ -159,7 +159,7 @@ def test_adjoint_finite_differences_full_c5():
 def test_adjoint_finite_differences_c5b_reduced():
     """Source-free variant (sensitivities do not decay with the logistic
     source), 256 x 256, 800 steps."""
-    spec, phi0, target, T = W.C5B(256, nsteps=800)
-    say(f"[gpu adjoint] C5b 256 FD, T={T}")
+    spec, phi0, target, T = W.adjoint_2d_sourcefree(256, nsteps=800)
+    say(f"[gpu adjoint] adjoint2d source-free 256 FD, T={T}")
     worst = _fd_check(spec, phi0, target, T)
     assert worst <= 1e-6

@@ -74,8 +74,8 @@ def compare(spec, phi0, snapshots, tol, flags=0, name=""):
 
 def test_c1_full_fp64_moment_path():
     """Linear Gaussian hill, 64 x 64, 1000 steps, s1 = s2 = 1.2 (moment path)."""
-    spec, phi0, T = W.C1()
-    compare(spec, phi0, (1, 250, 500, T), 1e-12, name="C1")
+    spec, phi0, T = W.hill_linear_64()
+    compare(spec, phi0, (1, 250, 500, T), 1e-12, name="hill_linear_64")
 
 
 @pytest.mark.parametrize("flags", [0, 1])
@@ -119,10 +119,10 @@ def test_nonlinear_reduced_storage(prec, tol):
 def test_c2_full_size_fp64_and_fp32():
     """The benchmark configuration (1024 x 1024) for a few steps: FP64 <= 1e-12
     and FP32 offsets <= 1e-5 against the oracle at full size."""
-    spec, phi0, _ = W.C2(1024)
-    compare(spec, phi0, (1, 4), 1e-12, name="C2-full-f64")
-    spec32, _, _ = W.C2(1024, precision="f32")
-    compare(spec32, phi0, (1, 4), 1e-5, name="C2-full-f32")
+    spec, phi0, _ = W.nonlinear_2d(1024)
+    compare(spec, phi0, (1, 4), 1e-12, name="nonlinear2d-1024-f64")
+    spec32, _, _ = W.nonlinear_2d(1024, precision="f32")
+    compare(spec32, phi0, (1, 4), 1e-5, name="nonlinear2d-1024-f32")
 
 
 # ---------------------------------------------------------------------------
@@ -130,8 +130,8 @@ def test_c2_full_size_fp64_and_fp32():
 # ---------------------------------------------------------------------------
 
 def test_d3q19_walls_fp64():
-    """C3 physics on a ragged 21 x 18 x 26 grid with z walls (equal rates)."""
-    spec, phi0, _ = W.C3((21, 18, 26))
+    """D3Q19 wall-bounded anisotropic physics on a ragged 21 x 18 x 26 grid with z walls (equal rates)."""
+    spec, phi0, _ = W.d3q19_walls((21, 18, 26))
     compare(spec, phi0, (1, 30, 150), 1e-12, name="d3q19-walls")
 
 
@@ -153,16 +153,16 @@ def test_d3q19_everything_fp64():
 
 
 def test_d3q19_fp32():
-    spec, phi0, _ = W.C3((32, 24, 40), precision="f32")
+    spec, phi0, _ = W.d3q19_walls((32, 24, 40), precision="f32")
     compare(spec, phi0, (1, 50, 200), 1e-5, name="d3q19-f32")
 
 
 def test_c3_full_size_two_steps():
     """The D3Q19 benchmark grid (256^3, walls) for two steps, FP64 and FP32."""
-    spec, phi0, _ = W.C3()
-    compare(spec, phi0, (2,), 1e-12, name="C3-full-f64")
-    spec32, _, _ = W.C3(precision="f32")
-    compare(spec32, phi0, (2,), 1e-5, name="C3-full-f32")
+    spec, phi0, _ = W.d3q19_walls()
+    compare(spec, phi0, (2,), 1e-12, name="d3q19-256-f64")
+    spec32, _, _ = W.d3q19_walls(precision="f32")
+    compare(spec32, phi0, (2,), 1e-5, name="d3q19-256-f32")
 
 
 # ---------------------------------------------------------------------------
@@ -188,7 +188,7 @@ def test_every_node_written():
     """Poison the destination with NaN: one sweep must overwrite every value."""
     lbm = _lbm()
     for spec, phi0 in ((W.spec_nonlinear_2d(77, 29), W.noise_field((29, 77), 18)),
-                       (W.C3((9, 7, 11))[0], W.C3((9, 7, 11))[1])):
+                       (W.d3q19_walls((9, 7, 11))[0], W.d3q19_walls((9, 7, 11))[1])):
         say(f"[gpu] poison {spec['shape']}")
         sim = lbm.Lbm(spec).init(phi0)
         view = sim.storage_view(sim.f[1])
@@ -237,7 +237,7 @@ def test_launch_variants_identical():
     only how the sweep is launched: results are bit-identical."""
     lbm = _lbm()
     for spec, phi0 in ((W.spec_nonlinear_2d(150, 90, precision="f32"), W.noise_field((90, 150), 20)),
-                       (W.C3((20, 18, 22))[0], W.C3((20, 18, 22))[1])):
+                       (W.d3q19_walls((20, 18, 22))[0], W.d3q19_walls((20, 18, 22))[1])):
         say(f"[gpu] launch variants {spec['shape']}")
         ref = lbm.Lbm(spec).init(phi0)
         ref.step(70)

@@ -410,7 +410,7 @@ def _hill_run(n, K, u, sigma0, T, q=9, rates=1.0):
 
 
 def test_gaussian_hill_c1_accuracy_and_order():
-    """Eq. 58-60 (C1 physics): GRE against the image-summed closed form, and
+    """Eq. 58-60 (linear Gaussian hill physics): GRE against the image-summed closed form, and
     second order under diffusive refinement (sigma0, u, T scaled; kappa fixed,
     so the rates are fixed): Sec. 3.4 Fig. 11 slope 2."""
     K = 0.01 * np.eye(2)
