@@ -249,6 +249,7 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     ablock<D, KVAR, NP>(cf, phi, A);
 
     TC out[Q];
+    TC Se = TC(0);  // mass the Scheme-A source adds this step: 3/2 R(t) - 1/2 R(t-1)
     if (EQR) {
         // All non-flux rates equal s.  With orthogonal rows and the flux rows
         // equal to c_a, (M^-1 S M)(g - feq) = s (g - feq) + c_k . v with
@@ -274,7 +275,7 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
         E[0] -= third; E[1] -= third;
         if (D == 3) E[2] -= third;
         const TC trE3 = (E[0] + E[1] + E[2]) * TC(1.0 / 3.0);
-        TC Se = TC(0), Vo[3] = {TC(0), TC(0), TC(0)};
+        TC Vo[3] = {TC(0), TC(0), TC(0)};
         if (SRC) {
             TC Bt[3], R, Btp[3], Rp, Ap[6];
             source_terms<D, NP>(cf, phi, A, Bt, R);
@@ -387,6 +388,7 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
         ablock<D, KVAR, NP>(cf, pp, Ap);
         source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
         const TC r1 = TC(1.5) * R, r0 = TC(0.5) * Rp;
+        Se = r1 - r0;
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             TC cb1 = TC(0), cb0 = TC(0);
@@ -398,6 +400,18 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
             out[k] += TC(L::w(k)) * (r1 * (TC(1) + TC(3) * cb1) - r0 * (TC(1) + TC(3) * cb0));
         }
         p[n] = (typename HistType<TS>::T)phio;
+    }
+
+    // Mass balance.  Collision conserves sum_k g_k and the Scheme-A source adds
+    // exactly Se to it (Eq. 9 sums to R over k), so the rest population takes
+    // the remainder.  The map is unchanged in exact arithmetic; in FP32 it
+    // stops the drift that rounded weights (sum_k w_k = 1 + O(1e-8)) would
+    // otherwise add to the mass at every step.
+    {
+        TC moving = TC(0);
+#pragma unroll
+        for (int k = 1; k < Q; ++k) moving += out[k];
+        out[0] = (phio + Se) - moving;
     }
 
 #pragma unroll
