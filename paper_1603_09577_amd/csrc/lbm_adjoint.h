@@ -406,24 +406,27 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
         for (int k = 0; k < Q; ++k) psi_out[(uint64_t)k * g.plane + n] = hb[k] + phib + pin;
         pi_out[n] = (double)pb;
     }
-    // K0 partials of this workgroup: (3/d) is applied here, FP64 accumulation
-    __shared__ double sh[6][kBlock / 64];
+    // K0 partials of this workgroup: (3/d) is applied here, FP64 accumulation.
+    // In 2-D only xx, yy and xy (slots 0, 1, 3) can be non-zero.
+    constexpr int NK = D == 2 ? 3 : 6;
+    __shared__ double sh[NK][kBlock / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        double v = (double)gk[i] * (double)cf->k0scale;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) sh[i][wv] = v;
+    for (int j = 0; j < NK; ++j) {
+        const int i = (D == 2 && j == 2) ? 3 : j;
+        const double v = wave_total((double)gk[i] * (double)cf->k0scale);
+        if (lane == 0) sh[j][wv] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < NK) {
+        const int j = threadIdx.x;
+        const int i = (D == 2 && j == 2) ? 3 : j;
         double v = 0.0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) v += sh[threadIdx.x][w];
+        for (int w = 0; w < kBlock / 64; ++w) v += sh[j][w];
         // each workgroup owns its slot: accumulate over the reversed sweeps,
         // folded once when the gradient is read
-        gk_part[(size_t)blockIdx.x * 6 + threadIdx.x] += v;
+        gk_part[(size_t)blockIdx.x * 6 + i] += v;
     }
 }
 
