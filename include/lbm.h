@@ -174,6 +174,22 @@ int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_l
 /* Divergence check every `every` steps inside lbm_step (0 = off). */
 int lbm_set_check(lbm_ctx *ctx, int every);
 
+/* Re-centre the stored offsets of the current state (asynchronous, on the
+ * device): phi_ref moves to the mean of phi (from the phi history when the run
+ * keeps one, else from the stored populations), every stored value gains
+ * w_k (old - new) and the history old - new, and the wall terms are rewritten.
+ * The distributions f_k themselves are unchanged in exact arithmetic, so every
+ * result of Eq. 2 is the same; what changes is the size of the stored numbers,
+ * which bounds the rounding of FP16 (and FP32) storage when phi drifts far
+ * from phi_ref under a source or through walls.  Afterwards the adjoint calls
+ * and lbm_set_k0 return LBM_E_STATE until the next lbm_init, which restores
+ * the description's phi_ref.  Errors: LBM_E_STATE before lbm_init. */
+int lbm_recenter(lbm_ctx *ctx, void *stream);
+
+/* Re-centre automatically inside lbm_step every `every` steps, counted from
+ * lbm_init (0 = never).  Default: 256 for LBM_F16 storage, 0 otherwise. */
+int lbm_set_recenter(lbm_ctx *ctx, int every);
+
 /* Replace K0 (keeps every other parameter); same validation as lbm_create. */
 int lbm_set_k0(lbm_ctx *ctx, const double k0[9]);
 

@@ -12,24 +12,6 @@
 #include "lbm_internal.h"
 #include "lbm_lattice.h"
 
-namespace lbm {
-hipError_t launch_sweep_q9(const Dims &, const Geom &, const void *, const void *, void *, void *, int *,
-                           hipStream_t);
-hipError_t launch_sweep_q19(const Dims &, const Geom &, const void *, const void *, void *, void *, int *,
-                            hipStream_t);
-hipError_t launch_init_q9(const Dims &, const Geom &, const void *, const double *, void *, void *,
-                          hipStream_t);
-hipError_t launch_init_q19(const Dims &, const Geom &, const void *, const double *, void *, void *,
-                           hipStream_t);
-hipError_t launch_phi_q9(const Dims &, const Geom &, const void *, const void *, double *, hipStream_t);
-hipError_t launch_phi_q19(const Dims &, const Geom &, const void *, const void *, double *, hipStream_t);
-hipError_t launch_adjoint_q9(const Dims &, const Geom &, const void *, const void *, const void *,
-                             const void *, const double *, void *, double *, double *, hipStream_t);
-hipError_t launch_adjoint_init_q9(const Dims &, const Geom &, const void *, const double *, const void *,
-                                  const double *, double *, hipStream_t);
-hipError_t launch_seed_q9(const Dims &, const Geom &, const double *, void *, double *, hipStream_t);
-hipError_t launch_zero(double *, uint32_t, hipStream_t);
-}  // namespace lbm
 
 using namespace lbm;
 
@@ -51,6 +33,7 @@ constexpr int kRedParts = 1024;       // partial rows of the phi reductions
 constexpr int kAdjWidth = 6;          // K0 gradient entries per adjoint partial
 constexpr int kMaxAdjParts = 65536;   // workgroups covered by the adjoint partials
 constexpr int kGraphSteps = 32;       // sweeps per captured graph (even: ends on the start buffer)
+constexpr int kRecenterF16 = 256;     // default re-centring interval for FP16 storage (steps)
 
 }  // namespace
 
@@ -61,16 +44,20 @@ struct lbm_ctx {
     size_t coef_bytes;
     unsigned char host_coefs[sizeof(Coefs<double>)];
     void *d_coefs = nullptr;
-    // device scratch: [flag int (256 B)] [reduce partials] [reduce out 8] [adj partials] [k0 acc 6]
+    // device scratch: [flag int (256 B)] [reduce partials] [reduce out 8] [adj partials] [k0 acc 8]
+    // [offset shift 8]
     void *d_scratch = nullptr;
     int *d_flag = nullptr;
     double *d_red_part = nullptr, *d_red_out = nullptr, *d_adj_part = nullptr, *d_k0acc = nullptr;
+    double *d_shift = nullptr;
     void *f[2] = {nullptr, nullptr};
     void *p = nullptr;
     const double *phi0 = nullptr;
     int cur = 0;
     long long t = 0;
     int check_every = 0;
+    int recenter_every = 0;   // steps between re-centrings of the stored offsets (0: never)
+    bool recentered = false;  // phi_ref on the device differs from the description's
     bool bound = false;
     // graphs of kGraphSteps sweeps starting from buffer 0 / 1, captured on an
     // internal stream and launched on the caller's stream
@@ -126,7 +113,7 @@ void sym_inv_host(const double *G, double *A, int dim) {
 
 struct HostModel {
     double b[3][kMaxP], bp[3][kMaxP], bpp[3][kMaxP], cb[6][kMaxC], cbd[6][kMaxC], g0[6], kp[kMaxP],
-        kdp[kMaxP], a[6], r[kMaxP], rp[kMaxP], ew[2][19], s[19], phi_ref, srate, k0scale;
+        kdp[kMaxP], a[6], r[kMaxP], rp[kMaxP], ew[2][19], ewp[2][19], s[19], phi_ref, srate, k0scale;
     int nb, ncb, nk, nr;
 };
 
@@ -202,6 +189,7 @@ void derive(const lbm_desc &d, const Dims &dm, HostModel &m) {
             for (int a = 0; a < 3; ++a) cc += c[a] * c[a] * E[a];
             cc += 2.0 * (c[0] * c[1] * E[3] + c[1] * c[2] * E[4] + c[0] * c[2] * E[5]);
             const double ep = w * (pw + 4.5 * cc);
+            m.ewp[side][k] = 2.0 * ep;
             m.ew[side][k] = 2.0 * (ep - w * d.phi_ref);
         }
     }
@@ -224,7 +212,7 @@ void pack(const HostModel &m, Coefs<TC> &c) {
         c.kp[p] = (TC)m.kp[p]; c.kdp[p] = (TC)m.kdp[p]; c.r[p] = (TC)m.r[p]; c.rp[p] = (TC)m.rp[p];
     }
     for (int s = 0; s < 2; ++s)
-        for (int k = 0; k < 19; ++k) c.ew[s][k] = (TC)m.ew[s][k];
+        for (int k = 0; k < 19; ++k) { c.ew[s][k] = (TC)m.ew[s][k]; c.ewp[s][k] = (TC)m.ewp[s][k]; }
     for (int i = 0; i < 19; ++i) c.s[i] = (TC)m.s[i];
     c.phi_ref = (TC)m.phi_ref;
     c.srate = (TC)m.srate;
@@ -342,6 +330,54 @@ hipError_t make_graph(lbm_ctx *c, int start) {
     return e;
 }
 
+// Re-centre the stored offsets of the current state on the mean of phi
+// (device-side: no host synchronisation, so it may sit between graph launches).
+hipError_t recenter(lbm_ctx *c, hipStream_t st) {
+    int parts = (int)std::min<uint32_t>(kRedParts, c->g.nblocks);
+    if (parts < 1) parts = 1;
+    hipError_t e = c->dm.q == 9
+                       ? launch_recenter_q9(c->dm, c->g, c->d_coefs, c->f[c->cur], c->p, c->d_red_part, parts,
+                                            c->d_shift, st)
+                       : launch_recenter_q19(c->dm, c->g, c->d_coefs, c->f[c->cur], c->p, c->d_red_part, parts,
+                                             c->d_shift, st);
+    if (e == hipSuccess) c->recentered = true;
+    return e;
+}
+
+// n sweeps from the current buffer: whole graphs of kGraphSteps sweeps, then
+// single launches (with the optional divergence check).
+int advance(lbm_ctx *c, int nsteps, hipStream_t st) {
+    const bool graphs = c->check_every == 0 && !(c->desc.flags & LBM_FLAG_NO_GRAPH);
+    while (graphs && nsteps >= kGraphSteps) {
+        if (!c->gexec[c->cur]) {
+            hipError_t e = make_graph(c, c->cur);
+            if (e != hipSuccess) return hip_fail(e, "graph capture");
+        }
+        hipError_t e = hipGraphLaunch(c->gexec[c->cur], st);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        c->t += kGraphSteps;
+        nsteps -= kGraphSteps;
+    }
+    for (int i = 0; i < nsteps; ++i) {
+        hipError_t e = sweep(c, c->f[c->cur], c->f[c->cur ^ 1], c->p, st);
+        if (e != hipSuccess) return hip_fail(e, "sweep kernel");
+        c->cur ^= 1;
+        ++c->t;
+        if (c->check_every > 0 && c->t % c->check_every == 0) {
+            int flag = 0;
+            e = hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "divergence check");
+            if (flag) {
+                char buf[96];
+                std::snprintf(buf, sizeof(buf), "non-finite phi by step %lld", c->t);
+                return fail(LBM_E_DIVERGED, buf);
+            }
+        }
+    }
+    return LBM_OK;
+}
+
 }  // namespace
 
 namespace lbm {
@@ -407,7 +443,7 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     }
     hipError_t e = hipMalloc(&c->d_coefs, sizeof(Coefs<double>));
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipMalloc(coefficients)"); }
-    const size_t scratch = 256 + sizeof(double) * (size_t)(kRedParts * 8 + 8 + kMaxAdjParts * kAdjWidth + 8);
+    const size_t scratch = 256 + sizeof(double) * (size_t)(kRedParts * 8 + 8 + kMaxAdjParts * kAdjWidth + 16);
     e = hipMalloc(&c->d_scratch, scratch);
     if (e != hipSuccess) { (void)hipFree(c->d_coefs); delete c; return hip_fail(e, "hipMalloc(scratch)"); }
     char *base = (char *)c->d_scratch;
@@ -416,6 +452,8 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     c->d_red_out = c->d_red_part + kRedParts * 8;
     c->d_adj_part = c->d_red_out + 8;
     c->d_k0acc = c->d_adj_part + (size_t)kMaxAdjParts * kAdjWidth;
+    c->d_shift = c->d_k0acc + 8;
+    c->recenter_every = dm.prec == 2 ? kRecenterF16 : 0;
     e = hipMemset(c->d_scratch, 0, scratch);
     if (e != hipSuccess) { lbm_destroy(c); return hip_fail(e, "hipMemset(scratch)"); }
     rc = upload_coefs(c);
@@ -454,6 +492,12 @@ int lbm_init(lbm_ctx *c, const double *phi0, void *f_a, void *f_b, void *p, void
     c->f[0] = f_a; c->f[1] = f_b; c->p = p; c->phi0 = phi0;
     c->cur = 0; c->t = 0; c->bound = true;
     hipStream_t st = (hipStream_t)stream;
+    if (c->recentered) {
+        // back to the description's phi_ref (the host copy was never changed)
+        hipError_t e = hipMemcpyAsync(c->d_coefs, c->host_coefs, c->coef_bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(coefficients)");
+        c->recentered = false;
+    }
     hipError_t e = (c->dm.q == 9) ? launch_init_q9(c->dm, c->g, c->d_coefs, phi0, f_a, p, st)
                                   : launch_init_q19(c->dm, c->g, c->d_coefs, phi0, f_a, p, st);
     if (e != hipSuccess) return hip_fail(e, "init kernel");
@@ -467,34 +511,36 @@ int lbm_step(lbm_ctx *c, int nsteps, void *stream) {
     if (!c->bound) return fail(LBM_E_STATE, "lbm_init has not been called");
     if (nsteps < 0) return fail(LBM_E_INVALID, "negative step count");
     hipStream_t st = (hipStream_t)stream;
-    const bool graphs = c->check_every == 0 && !(c->desc.flags & LBM_FLAG_NO_GRAPH);
-    while (graphs && nsteps >= kGraphSteps) {
-        if (!c->gexec[c->cur]) {
-            hipError_t e = make_graph(c, c->cur);
-            if (e != hipSuccess) return hip_fail(e, "graph capture");
+    while (nsteps > 0) {
+        int n = nsteps;
+        const int K = c->recenter_every;
+        if (K > 0) {
+            const long long left = K - (c->t % K);
+            if (left < n) n = (int)left;
         }
-        hipError_t e = hipGraphLaunch(c->gexec[c->cur], st);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-        c->t += kGraphSteps;
-        nsteps -= kGraphSteps;
-    }
-    for (int i = 0; i < nsteps; ++i) {
-        hipError_t e = sweep(c, c->f[c->cur], c->f[c->cur ^ 1], c->p, st);
-        if (e != hipSuccess) return hip_fail(e, "sweep kernel");
-        c->cur ^= 1;
-        ++c->t;
-        if (c->check_every > 0 && c->t % c->check_every == 0) {
-            int flag = 0;
-            e = hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return hip_fail(e, "divergence check");
-            if (flag) {
-                char buf[96];
-                std::snprintf(buf, sizeof(buf), "non-finite phi by step %lld", c->t);
-                return fail(LBM_E_DIVERGED, buf);
-            }
+        const int rc = advance(c, n, st);
+        if (rc != LBM_OK) return rc;
+        nsteps -= n;
+        if (K > 0 && c->t % K == 0) {
+            hipError_t e = recenter(c, st);
+            if (e != hipSuccess) return hip_fail(e, "re-centring kernels");
         }
     }
+    return LBM_OK;
+}
+
+int lbm_recenter(lbm_ctx *c, void *stream) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (!c->bound) return fail(LBM_E_STATE, "lbm_init has not been called");
+    hipError_t e = recenter(c, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "re-centring kernels");
+    return LBM_OK;
+}
+
+int lbm_set_recenter(lbm_ctx *c, int every) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (every < 0) return fail(LBM_E_INVALID, "negative re-centring interval");
+    c->recenter_every = every;
     return LBM_OK;
 }
 
@@ -547,6 +593,7 @@ int lbm_set_check(lbm_ctx *c, int every) {
 
 int lbm_set_k0(lbm_ctx *c, const double k0[9]) {
     if (!c || !k0) return fail(LBM_E_INVALID, "null argument");
+    if (c->recentered) return fail(LBM_E_STATE, "offsets were re-centred: call lbm_init before lbm_set_k0");
     lbm_desc d = c->desc;
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) d.k0[a][b] = k0[a * 3 + b];
@@ -573,6 +620,8 @@ int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void
     if (!c || !gphi || !psi || !pi) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    if (c->recentered)
+        return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipStream_t st = (hipStream_t)stream;
     if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
     hipError_t e = launch_seed_q9(c->dm, c->g, gphi, psi, pi, st);
@@ -588,6 +637,8 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
     if (psi_next == psi_out) return fail(LBM_E_INVALID, "psi_next and psi_out must differ");
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    if (c->recentered)
+        return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = launch_adjoint_q9(c->dm, c->g, c->d_coefs, f_s, p_s, psi_next, pi_next, psi_out, pi_out,
@@ -601,6 +652,8 @@ int lbm_adjoint_init(lbm_ctx *c, const double *phi0, const void *psi0, const dou
     if (!c || !phi0 || !psi0 || !pi0 || !gphi0) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    if (c->recentered)
+        return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipError_t e = launch_adjoint_init_q9(c->dm, c->g, c->d_coefs, phi0, psi0, pi0, gphi0, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint init kernel");
     return LBM_OK;

@@ -130,6 +130,19 @@ hipError_t seed_typed(const Dims &, const Geom &g, const double *gphi, void *psi
     return hipGetLastError();
 }
 
+template <int Q, typename TS, typename TC>
+hipError_t recenter_typed(const Dims &dm, const Geom &g, void *coefs, void *f, void *p, double *part, int nparts,
+                          double *shift, hipStream_t st) {
+    using TP = typename HistType<TS>::T;
+    hipLaunchKernelGGL((k_offset_sum<Q, TS>), dim3(nparts), dim3(kBlock), 0, st, g, (const TS *)f,
+                       (const TP *)p, dm.src ? 1 : 0, part);
+    hipLaunchKernelGGL((k_recenter_fold<Q, TC>), dim3(1), dim3(kBlock), 0, st, (Coefs<TC> *)coefs, part, nparts,
+                       g.N, shift);
+    hipLaunchKernelGGL((k_shift<Q, TS, TC>), dim3(g.nblocks), dim3(kBlock), 0, st, g, (const double *)shift,
+                       (TS *)f, (TP *)p);
+    return hipGetLastError();
+}
+
 inline hipError_t zero_doubles(double *p, uint32_t n, hipStream_t st) {
     const uint32_t grid = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_zero, dim3(grid < 1024 ? grid : 1024), dim3(kBlock), 0, st, p, n);

@@ -54,6 +54,7 @@ struct Coefs {
     TC r[kMaxP];          // R(phi)
     TC rp[kMaxP];         // R'(phi)
     TC ew[2][19];         // anti-bounce-back wall terms 2 (e+_k(phi_w) - w_k phi_ref)
+    TC ewp[2][19];        // 2 e+_k(phi_w): the wall terms without the offset
     TC s[19];             // diagonal rates in moment order
     TC phi_ref;
     TC srate;             // common non-flux rate (equal-rate path)
@@ -91,21 +92,30 @@ inline uint64_t plane_stride(uint64_t n, int q, size_t elem, int pad_req) {
     return base + pad_bytes / elem;
 }
 
-// Kernel launchers (defined per lattice in sweep_d2q9.hip / sweep_d3q19.hip).
-hipError_t launch_init(const Dims &dm, const Geom &g, const void *coefs, const double *phi0,
-                       void *f, void *p, hipStream_t st);
-hipError_t launch_sweep(const Dims &dm, const Geom &g, const void *coefs, const void *fin,
-                        void *fout, void *p, int *flag, hipStream_t st);
-hipError_t launch_phi(const Dims &dm, const Geom &g, const void *coefs, const void *f,
-                      double *phi, hipStream_t st);
-hipError_t launch_adjoint(const Dims &dm, const Geom &g, const void *coefs, const void *f,
-                          const void *p, const void *psi_next, const double *pi_next,
-                          void *psi_out, double *pi_out, double *gk_part, hipStream_t st);
-hipError_t launch_adjoint_init(const Dims &dm, const Geom &g, const void *coefs,
-                               const double *phi0, const void *psi0, const double *pi0,
-                               double *gphi0, hipStream_t st);
-hipError_t launch_seed(const Dims &dm, const Geom &g, const double *gphi, void *psi,
-                       double *pi, hipStream_t st);
+// Kernel launchers, one set per lattice (sweep_d2q9.hip, sweep_d3q19.hip).
+#define LBM_LAUNCHERS(SFX)                                                                              \
+    hipError_t launch_sweep_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *fin,   \
+                                  void *fout, void *p, int *flag, hipStream_t st);                      \
+    hipError_t launch_init_##SFX(const Dims &dm, const Geom &g, const void *coefs, const double *phi0, \
+                                 void *f, void *p, hipStream_t st);                                     \
+    hipError_t launch_phi_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *f,       \
+                                double *phi, hipStream_t st);                                           \
+    hipError_t launch_recenter_##SFX(const Dims &dm, const Geom &g, void *coefs, void *f, void *p,     \
+                                     double *part, int nparts, double *shift, hipStream_t st);
+LBM_LAUNCHERS(q9)
+LBM_LAUNCHERS(q19)
+#undef LBM_LAUNCHERS
+
+// The adjoint is built for D2Q9.
+hipError_t launch_adjoint_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f,
+                             const void *p, const void *psi_next, const double *pi_next,
+                             void *psi_out, double *pi_out, double *gk_part, hipStream_t st);
+hipError_t launch_adjoint_init_q9(const Dims &dm, const Geom &g, const void *coefs,
+                                  const double *phi0, const void *psi0, const double *pi0,
+                                  double *gphi0, hipStream_t st);
+hipError_t launch_seed_q9(const Dims &dm, const Geom &g, const double *gphi, void *psi,
+                          double *pi, hipStream_t st);
+hipError_t launch_zero(double *p, uint32_t n, hipStream_t st);
 
 // Generic FP64 reductions (lbm_reduce.hip).
 hipError_t launch_reduce(const double *phi, const double *ref, uint32_t n, double *part,

@@ -497,4 +497,120 @@ k_phi(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
     phi[n] = (double)cf->phi_ref + acc;
 }
 
+// ---------------------------------------------------------------------------
+// Sum of an FP64 value over the 64 lanes of a wave (every lane must be
+// active), returned in every lane.  Inside each row of 16 lanes the DPP quad
+// swaps (lane ^ 1, lane ^ 2) and the half-row and row mirrors pair every
+// quad, then every half-row, with its partner, leaving the row sum in all 16
+// lanes; the four row sums are then read from lanes 0, 16, 32 and 48.  No
+// LDS traffic and a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm (1, 0, 3, 2)
+    v += dpp_f64<0x4E>(v);   // quad_perm (2, 3, 0, 1)
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
+// ---------------------------------------------------------------------------
+// Re-centring of the stored offsets h_k = f_k - w_k phi_ref.  Moving phi_ref
+// to the current mean of phi keeps the stored magnitudes at the size of the
+// fluctuations of phi, which is what bounds the rounding of short storage
+// formats when phi drifts (source terms, walls).  In exact arithmetic nothing
+// the method computes changes: with delta = old - new,
+//   h_k += w_k delta,  P += delta,  wall terms 2 e+_k(phi_w) - 2 w_k new,
+// so every gathered population, phi, and the Scheme-A history are the same.
+// ---------------------------------------------------------------------------
+
+// Per-workgroup FP64 sums of the offset mass: the history P (one value per
+// node, phi of the previous step less phi_ref) when the run keeps one, else
+// the sum over the stored populations.
+template <int Q, typename TS>
+__global__ void __launch_bounds__(kBlock)
+k_offset_sum(const Geom g, const TS *__restrict__ f, const typename HistType<TS>::T *__restrict__ p,
+             int use_hist, double *__restrict__ part) {
+    double acc = 0.0;
+    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < g.N; n += gridDim.x * kBlock) {
+        if (use_hist) {
+            acc += (double)p[n];
+        } else {
+#pragma unroll
+            for (int k = 0; k < Q; ++k) acc += (double)f[(uint64_t)k * g.plane + n];
+        }
+    }
+    __shared__ double sh[kBlock / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// One workgroup: fold the partial sums in a fixed order, move phi_ref to the
+// mean and rewrite the wall terms; the shift old - new goes to shift[0].
+template <int Q, typename TC>
+__global__ void __launch_bounds__(kBlock)
+k_recenter_fold(Coefs<TC> *cf, const double *__restrict__ part, int nparts, uint32_t N,
+                double *__restrict__ shift) {
+    using L = Lattice<Q>;
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kBlock) acc += part[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double old = (double)cf->phi_ref;
+    const TC nref = (TC)(old + sh[0] / (double)N);
+    __syncthreads();  // every lane has read phi_ref before it is rewritten
+    if (threadIdx.x < 2 * Q) {
+        const int side = threadIdx.x / Q, k = threadIdx.x % Q;
+        cf->ew[side][k] = (TC)((double)cf->ewp[side][k] - 2.0 * L::w(k) * (double)nref);
+    }
+    if (threadIdx.x == 0) {
+        cf->phi_ref = nref;
+        shift[0] = old - (double)nref;
+    }
+}
+
+template <int Q, typename TS, typename TC>
+__global__ void __launch_bounds__(kBlock)
+k_shift(const Geom g, const double *__restrict__ shift, TS *__restrict__ f,
+        typename HistType<TS>::T *__restrict__ p) {
+    using L = Lattice<Q>;
+    using TP = typename HistType<TS>::T;
+    const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const double d = shift[0];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        TS *q = f + (uint64_t)k * g.plane + n;
+        *q = (TS)((TC)*q + (TC)(L::w(k) * d));
+    }
+    p[n] = (TP)((double)p[n] + d);
+}
+
 }  // namespace lbm

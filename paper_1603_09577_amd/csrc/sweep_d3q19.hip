@@ -19,4 +19,9 @@ hipError_t launch_phi_q19(const Dims &dm, const Geom &g, const void *coefs, cons
     LBM_BY_PREC(phi_typed, dm, g, coefs, f, phi, st)
 }
 
+hipError_t launch_recenter_q19(const Dims &dm, const Geom &g, void *coefs, void *f, void *p, double *part,
+                              int nparts, double *shift, hipStream_t st) {
+    LBM_BY_PREC(recenter_typed, dm, g, coefs, f, p, part, nparts, shift, st)
+}
+
 }  // namespace lbm

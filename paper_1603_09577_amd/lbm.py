@@ -31,7 +31,7 @@ EXPORTS = [
     "lbm_batch_create", "lbm_batch_layout", "lbm_batch_instance", "lbm_batch_init",
     "lbm_batch_step", "lbm_batch_get_phi", "lbm_batch_tune", "lbm_batch_set_shape",
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
-    "lbm_set_nontemporal",
+    "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter",
 ]
 
 
@@ -119,6 +119,8 @@ def load():
         "lbm_set_chunk": ([_VP, ctypes.c_int], ctypes.c_int),
         "lbm_set_nontemporal": ([_VP, ctypes.c_int], ctypes.c_int),
         "lbm_tune": ([_VP, ctypes.c_int, _VP, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+        "lbm_recenter": ([_VP, _VP], ctypes.c_int),
+        "lbm_set_recenter": ([_VP, ctypes.c_int], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -279,6 +281,14 @@ class Lbm:
 
     def set_check(self, every):
         _check(self.lib.lbm_set_check(self.ctx, int(every)))
+
+    def recenter(self, stream=None):
+        """Move phi_ref to the mean of phi and shift the stored offsets to match."""
+        _check(self.lib.lbm_recenter(self.ctx, _stream(stream)))
+
+    def set_recenter(self, every):
+        """Re-centre inside step() every `every` steps (0 = never)."""
+        _check(self.lib.lbm_set_recenter(self.ctx, int(every)))
 
     def set_k0(self, k0):
         arr = (ctypes.c_double * 9)(*np.asarray(k0, dtype=np.float64).reshape(-1).tolist())
