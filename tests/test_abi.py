@@ -107,3 +107,8 @@ def test_null_arguments(L):
     assert L.lbm_step(None, 1, None) == lbm.LBM_E_INVALID
     assert L.lbm_get_phi(None, None, None) == lbm.LBM_E_INVALID
     assert L.lbm_adjoint_step(None, None, None, None, None, None, None, None) == lbm.LBM_E_INVALID
+    assert L.lbm_recenter(None, None) == lbm.LBM_E_INVALID
+    assert L.lbm_set_recenter(None, 5) == lbm.LBM_E_INVALID
+    assert L.lbm_set_check(None, 5) == lbm.LBM_E_INVALID
+    assert L.lbm_tune(None, 1, None, None, 0) == lbm.LBM_E_INVALID
+    assert L.lbm_batch_step(None, 1, None) == lbm.LBM_E_INVALID

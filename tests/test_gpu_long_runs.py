@@ -1,0 +1,101 @@
+"""Full-length runs against stored oracle summaries.
+
+tests/golden/long_runs.json is written by tests/golden/make_long_runs.py,
+which runs only the CPU oracle (FP64) for the whole step count and keeps, at
+each snapshot, the sums of phi and phi^2, block means over a coarse grid and
+phi at seeded sample nodes.  Here the GPU path runs the same workload from the
+same seeded phi0, in the launch configuration the benchmark uses (autotuned,
+graph-replayed), and the same summaries are compared:
+
+    FP64 storage   samples / block means relative L2 <= 1e-12, sums <= 1e-12
+    FP32 offsets   <= 1e-5
+    FP16 offsets   reported, with loose per-workload bounds (see TOL)
+
+Workloads: the nonlinear anisotropic D2Q9 case with the Scheme-A source at
+its full 1024 x 1024 size and 5000 steps; the D3Q19 case with walls, at the
+full 2000 steps on a 64^3 grid (the full-length 256^3 oracle run is out of
+reach of the host; the 256^3 size is covered for two steps elementwise in
+test_gpu_parity.py).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1603_09577_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "long_runs.json")
+# FP16 bounds are loose sanity bounds on a reported figure: the 2-D workload
+# is re-centred (it has a source) and ends near 5e-4; the D3Q19 field keeps
+# O(1) structure on a zero background, so its stored values cannot be made
+# small and 10-bit rounding accumulates to about 4e-3 over 2000 steps.
+TOL = {"f64": 1e-12, "f32": 1e-5, ("nonlinear2d-1024", "f16"): 2e-3, ("d3q19-walls-64", "f16"): 1e-2}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def load():
+    if not os.path.exists(GOLDEN):
+        pytest.fail(f"{GOLDEN} missing: run tests/golden/make_long_runs.py")
+    return json.load(open(GOLDEN))
+
+
+def workload(name, precision):
+    if name == "nonlinear2d-1024":
+        spec, phi0, _ = W.nonlinear_2d(1024, precision=precision)
+    elif name == "d3q19-walls-64":
+        spec, phi0, _ = W.d3q19_walls((64, 64, 64), precision=precision)
+    else:
+        raise KeyError(name)
+    return spec, phi0
+
+
+def summaries(phi, edge, idx):
+    f = phi.double()
+    shp = []
+    for n in f.shape:
+        shp += [n // edge, edge]
+    blocks = f.reshape(shp).mean(dim=tuple(range(1, 2 * f.dim(), 2))).reshape(-1)
+    flat = f.reshape(-1)
+    return (float(f.sum()), float((f * f).sum()), blocks.cpu().numpy(),
+            flat[torch.as_tensor(idx, device=flat.device)].cpu().numpy())
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("name", ["nonlinear2d-1024", "d3q19-walls-64"])
+def test_full_length_against_oracle(name, precision):
+    from paper_1603_09577_amd import lbm
+    g = load()[name]
+    spec, phi0 = workload(name, precision)
+    assert list(phi0.shape) == g["shape"]
+    sim = lbm.Lbm(spec).init(phi0)
+    sim.tune(reps=5)          # the launch configuration the benchmark times
+    tol = TOL.get((name, precision), TOL.get(precision))
+    t = 0
+    worst = 0.0
+    for s in sorted(int(k) for k in g["snapshots"]):
+        sim.step(s - t)
+        t = s
+        ref = g["snapshots"][str(s)]
+        gs, gq, gb, gv = summaries(sim.phi(), g["block_edge"], g["idx"])
+        e_vals = rel(gv, ref["vals"])
+        e_blk = rel(gb, ref["blocks"])
+        e_sum = abs(gs - ref["sum"]) / abs(ref["sum"])
+        e_sq = abs(gq - ref["sumsq"]) / abs(ref["sumsq"])
+        say(f"[gpu long run] {name} {precision} step {s}: samples {e_vals:.2e} blocks {e_blk:.2e} "
+            f"sum {e_sum:.2e} sumsq {e_sq:.2e}")
+        worst = max(worst, e_vals, e_blk, e_sum, e_sq)
+    assert worst <= tol, f"{name} {precision}: {worst:.3e} > {tol}"
