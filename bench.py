@@ -174,7 +174,7 @@ def copy_probe(torch, lbm, nbytes=1 << 30, reps=20):
     a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     out = {"bytes_per_copy": 2 * nbytes}
-    for grid in (0, 256 * 64):
+    for grid in (0, 256 * 16):
         for _ in range(3):
             lbm.probe_copy(a, b, grid)
         torch.cuda.synchronize()
@@ -185,7 +185,7 @@ def copy_probe(torch, lbm, nbytes=1 << 30, reps=20):
         e1.record()
         torch.cuda.synchronize()
         per = e0.elapsed_time(e1) / 1e3 / reps
-        out[f"gbs_grid{grid or 4096}"] = 2 * nbytes / per / 1e9
+        out["gbs_one_chunk_per_workgroup" if grid == 0 else f"gbs_grid{grid}"] = 2 * nbytes / per / 1e9
     out["gbs"] = max(v for k, v in out.items() if k.startswith("gbs_"))
     return out
 
@@ -366,6 +366,11 @@ def main():
     # both ran warmup + K steps from the same phi0: error of FP32 storage
     # against the FP64 path after the same number of steps
     err32 = float(torch.linalg.norm(phi32 - phi64) / torch.linalg.norm(phi64))
+    spec16, _, _ = W.nonlinear_2d(1024, precision="f16")
+    f16, sim16, phi16 = run_forward(torch, lbm, spec16, phi0, K, Wm, "nonlinear2d-1024 f16")
+    err16 = float(torch.linalg.norm(phi16 - phi64) / torch.linalg.norm(phi64))
+    del sim16, phi16
+    print(f"# nonlinear2d-1024 f16: {f16['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
     extra = {}
     only = set(w for w in args.only.split(",") if w) or {"adjoint", "d3q19", "batch"}
@@ -438,7 +443,10 @@ def main():
                  "achieved_gbs": f64["achieved_gbs"], "hbm_frac": f64["hbm_frac"]},
         "fp32_vs_fp64_mlups": head["mlups"] / f64["mlups"],
         "fp32_rel_l2_vs_fp64_after_run": err32,
-        "nonfinite": head["nonfinite"] + f64["nonfinite"],
+        "fp16": {"mlups": f16["mlups"], "ms_per_step": f16["ms_per_step"], "achieved_gbs": f16["achieved_gbs"],
+                 "hbm_frac": f16["hbm_frac"], "rel_l2_vs_fp64_after_run": err16,
+                 "storage": "f16 offsets, re-centred every 256 steps"},
+        "nonfinite": head["nonfinite"] + f64["nonfinite"] + f16["nonfinite"],
         **extra,
     }
     print(json.dumps(line))

@@ -187,7 +187,11 @@ int lbm_set_check(lbm_ctx *ctx, int every);
 int lbm_recenter(lbm_ctx *ctx, void *stream);
 
 /* Re-centre automatically inside lbm_step every `every` steps, counted from
- * lbm_init (0 = never).  Default: 256 for LBM_F16 storage, 0 otherwise. */
+ * lbm_init (0 = never).  Default: 256 for LBM_F16 storage with a source term
+ * (R != 0: the whole field moves away from phi_ref), 0 otherwise (the mean is
+ * then fixed, or moves only through walls, and a field that is mostly at one
+ * level with structure elsewhere is stored best against that level, not
+ * against its mean). */
 int lbm_set_recenter(lbm_ctx *ctx, int every);
 
 /* Replace K0 (keeps every other parameter); same validation as lbm_create. */
@@ -236,9 +240,11 @@ void lbm_destroy(lbm_ctx *ctx);
 const char *lbm_last_error(void);
 
 /* Measurement aid: plain device copy of `bytes` (multiple of 16, 16-byte
- * aligned pointers) with `grid` workgroups of 256 lanes (<= 0: 4096), 16
- * bytes per lane per iteration.  Gives the practical bandwidth of a
- * read-once / write-once stream and calibrates the traffic counters. */
+ * aligned pointers) in chunks of 16 KiB, each copied by one workgroup of 256
+ * lanes (four coalesced 16-byte loads per lane, then the stores); `grid`
+ * workgroups loop over the chunks (<= 0 or more than the chunks: one
+ * workgroup per chunk).  Gives the practical bandwidth of a read-once /
+ * write-once stream and calibrates the traffic counters. */
 int lbm_probe_copy(const void *src, void *dst, size_t bytes, int grid, void *stream);
 
 /* ---- batches of independent D2Q9 instances ------------------------------- *

@@ -33,7 +33,7 @@ constexpr int kRedParts = 1024;       // partial rows of the phi reductions
 constexpr int kAdjWidth = 6;          // K0 gradient entries per adjoint partial
 constexpr int kMaxAdjParts = 65536;   // workgroups covered by the adjoint partials
 constexpr int kGraphSteps = 32;       // sweeps per captured graph (even: ends on the start buffer)
-constexpr int kRecenterF16 = 256;     // default re-centring interval for FP16 storage (steps)
+constexpr int kRecenterF16 = 256;     // default re-centring interval, FP16 storage with a source (steps)
 
 }  // namespace
 
@@ -453,7 +453,9 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     c->d_adj_part = c->d_red_out + 8;
     c->d_k0acc = c->d_adj_part + (size_t)kMaxAdjParts * kAdjWidth;
     c->d_shift = c->d_k0acc + 8;
-    c->recenter_every = dm.prec == 2 ? kRecenterF16 : 0;
+    // a source moves the whole field away from phi_ref; without one the mean
+    // drifts only through walls and centring on it can enlarge the stored values
+    c->recenter_every = (dm.prec == 2 && dm.src) ? kRecenterF16 : 0;
     e = hipMemset(c->d_scratch, 0, scratch);
     if (e != hipSuccess) { lbm_destroy(c); return hip_fail(e, "hipMemset(scratch)"); }
     rc = upload_coefs(c);
@@ -741,8 +743,11 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
 int lbm_probe_copy(const void *src, void *dst, size_t bytes, int grid, void *stream) {
     if (!src || !dst) return fail(LBM_E_INVALID, "null argument");
     if (((uintptr_t)src | (uintptr_t)dst | bytes) & 15) return fail(LBM_E_INVALID, "16-byte alignment required");
-    if (grid <= 0) grid = 256 * 16;
-    hipError_t e = launch_copy16(src, dst, bytes / 16, grid, (hipStream_t)stream);
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return LBM_OK;
+    const size_t chunks = (n16 + 4 * 256 - 1) / (4 * 256);
+    if (grid <= 0 || (size_t)grid > chunks) grid = (int)std::min<size_t>(chunks, 1u << 30);
+    hipError_t e = launch_copy16(src, dst, n16, grid, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "copy kernel");
     return LBM_OK;
 }

@@ -91,18 +91,24 @@ k_sum_partials(const double *__restrict__ part, int nparts, int width, double *_
     }
 }
 
-// Plain copy, 16 bytes per lane per iteration: the practical bandwidth of a
-// read-once write-once stream and the reference for the traffic counters.
+// Plain copy, the practical bandwidth of a read-once write-once stream and
+// the reference for the traffic counters.  The buffer is cut into chunks of
+// 1024 x 16 bytes; a workgroup copies whole chunks (four coalesced 16-byte
+// loads per lane in flight, then the four stores), one chunk per workgroup
+// when the grid covers them all, else looping over them.
 __global__ void __launch_bounds__(kBlock)
 k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n16) {
-    // four independent 16-byte loads in flight per lane, coalesced per wave
-    const size_t S = (size_t)gridDim.x * kBlock;
-    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    for (; i + 3 * S < n16; i += 4 * S) {
-        const uint4 a = src[i], b = src[i + S], c = src[i + 2 * S], d = src[i + 3 * S];
-        dst[i] = a; dst[i + S] = b; dst[i + 2 * S] = c; dst[i + 3 * S] = d;
+    constexpr size_t kChunk = 4 * kBlock;
+    const size_t nchunks = (n16 + kChunk - 1) / kChunk;
+    for (size_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const size_t i = c * kChunk + threadIdx.x;
+        if (i + 3 * kBlock < n16) {
+            const uint4 a = src[i], b = src[i + kBlock], d = src[i + 2 * kBlock], e = src[i + 3 * kBlock];
+            dst[i] = a; dst[i + kBlock] = b; dst[i + 2 * kBlock] = d; dst[i + 3 * kBlock] = e;
+        } else {
+            for (size_t j = i; j < n16; j += kBlock) dst[j] = src[j];
+        }
     }
-    for (; i < n16; i += S) dst[i] = src[i];
 }
 
 }  // namespace
