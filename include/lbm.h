@@ -62,7 +62,10 @@ extern "C" {
 
 #define LBM_FLAG_MOMENT_PATH 1 /* always use the moment-space collision even
                                   when all non-flux rates are equal          */
-#define LBM_FLAG_NO_XCD_REMAP 2 /* launch blocks in plain order             */
+#define LBM_FLAG_NO_XCD_REMAP 2 /* launch blocks in the hardware's round-robin
+                                  XCD order (default: one contiguous slab per
+                                  XCD while the state fits the 256 MB Infinity
+                                  Cache, round-robin beyond; lbm_tune times both) */
 #define LBM_FLAG_NO_GRAPH 4   /* lbm_step launches every sweep directly
                                  instead of replaying captured graphs       */
 
@@ -165,10 +168,13 @@ int lbm_set_chunk(lbm_ctx *ctx, int chunk);
  * they would keep a cache-resident state out of the cache). */
 int lbm_set_nontemporal(lbm_ctx *ctx, int on);
 
-/* Autotuner (synchronous): times the sweep for chunk = 1, 2, 4, 8, 16, with
- * and without non-temporal accesses, on the bound buffers, keeps the fastest, writes the timings into `report` (may be
- * NULL) and re-initialises the state from the phi0 given to lbm_init (step
- * counter back to 0; phi0 must still be valid). */
+/* Autotuner (synchronous): times the sweep on the bound buffers for chunk =
+ * 1, 2, 4, 8, 16 workgroup blocks, with and without non-temporal accesses,
+ * and with the XCD-aware block order (one contiguous slab per XCD) or the
+ * hardware's round-robin order (unless LBM_FLAG_NO_XCD_REMAP pins the
+ * latter); keeps the fastest, writes the timings into `report` (may be NULL)
+ * and re-initialises the state from the phi0 given to lbm_init (step counter
+ * back to 0; phi0 must still be valid). */
 int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_len);
 
 /* Divergence check every `every` steps inside lbm_step (0 = off). */
