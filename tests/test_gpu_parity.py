@@ -233,8 +233,9 @@ def test_graph_replay_identical_to_direct_launches():
 
 
 def test_launch_variants_identical():
-    """Non-temporal accesses, chunked workgroups and the autotuned shape change
-    only how the sweep is launched: results are bit-identical."""
+    """Non-temporal accesses, chunked workgroups, the XCD block order and the
+    autotuned shape change only how the sweep is launched: results are
+    bit-identical."""
     lbm = _lbm()
     for spec, phi0 in ((W.spec_nonlinear_2d(150, 90, precision="f32"), W.noise_field((90, 150), 20)),
                        (W.d3q19_walls((20, 18, 22))[0], W.d3q19_walls((20, 18, 22))[1])):
@@ -242,12 +243,13 @@ def test_launch_variants_identical():
         ref = lbm.Lbm(spec).init(phi0)
         ref.step(70)
         want = ref.phi()
-        for nt, chunk in ((1, 1), (0, 3), (1, 5)):
-            s = lbm.Lbm(spec).init(phi0)
+        for nt, chunk, fl in ((1, 1, 0), (0, 3, 0), (1, 5, 0), (0, 3, lbm.FLAG_NO_XCD_REMAP),
+                              (1, 2, lbm.FLAG_NO_XCD_REMAP)):
+            s = lbm.Lbm(spec, flags=fl).init(phi0)
             s.set_nontemporal(nt)
             s.set_chunk(chunk)
             s.step(70)
-            assert torch.equal(s.phi(), want), (nt, chunk)
+            assert torch.equal(s.phi(), want), (nt, chunk, fl)
         s = lbm.Lbm(spec).init(phi0)
         s.tune(reps=2)
         s.step(70)
