@@ -57,8 +57,11 @@ extern "C" {
 
 #define LBM_SCHEME_A 0        /* Remark II, gamma = 0: explicit time difference
                                  of the source, needs phi of the last step   */
-#define LBM_SCHEME_B 1        /* Remark II, gamma = 1 (GPU: only with R = 0,
-                                 where it coincides with Scheme A)           */
+#define LBM_SCHEME_B 1        /* Remark II, gamma = 1: Btilde = B', stored
+                                 fbar = f - R_k/2 (Eq. 33), Eq. 34, phi from
+                                 Eq. 35; R must not depend on phi (constant
+                                 rpoly[0] plus an optional field, see
+                                 lbm_set_fields)                              */
 
 #define LBM_FLAG_MOMENT_PATH 1 /* always use the moment-space collision even
                                   when all non-flux rates are equal          */
@@ -199,6 +202,25 @@ int lbm_recenter(lbm_ctx *ctx, void *stream);
  * level with structure elsewhere is stored best against that level, not
  * against its mean). */
 int lbm_set_recenter(lbm_ctx *ctx, int every);
+
+/* Per-node fields, read by lbm_init, lbm_step, lbm_sweep and lbm_get_phi
+ * (device pointers owned by the caller; NULL unbinds):
+ *  - k0_field: FP64, per node (2-D) xx, yy, xy or (3-D) xx, yy, zz, xy, yz, xz,
+ *    [nz][ny][nx][3 or 6].  K(x, phi) = K0(x) kpoly(phi) replaces the
+ *    description's k0; A is formed per node by Eq. 26 (the variable diffusion
+ *    tensor of Sec. 3.5).  Each K0(x) must be symmetric positive definite; it
+ *    is not checked (a non-finite phi shows in lbm_set_check).
+ *  - r_field: FP64 [nz][ny][nx], an external source added to R: R(x, t) =
+ *    rpoly[0] + r_field(x) (Eq. 1; Scheme B only, where Eq. 35 is then
+ *    explicit).  Its contents are R at the current time: a sweep from t to
+ *    t + 1 reads R(x, t), and lbm_get_phi reads it as R(x, t) of the state it
+ *    converts, so a time-dependent source is rewritten between steps (on the
+ *    same stream).
+ * Scheme B with a source, or a K0 field, runs the general kernel (any
+ * polynomial length, no streaming hints).  The adjoint calls refuse them.
+ * Errors: LBM_E_INVALID (misaligned), LBM_E_UNSUPPORTED (r_field with
+ * Scheme A). */
+int lbm_set_fields(lbm_ctx *ctx, const double *k0_field, const double *r_field);
 
 /* Replace K0 (keeps every other parameter); same validation as lbm_create. */
 int lbm_set_k0(lbm_ctx *ctx, const double k0[9]);

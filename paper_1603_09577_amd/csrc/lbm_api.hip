@@ -58,6 +58,8 @@ struct lbm_ctx {
     int check_every = 0;
     int recenter_every = 0;   // steps between re-centrings of the stored offsets (0: never)
     bool recentered = false;  // phi_ref on the device differs from the description's
+    // per-node fields (caller-owned, FP64): K0(x) and the external source R(x, t)
+    const double *kfield = nullptr, *rfield = nullptr;
     bool bound = false;
     // graphs of kGraphSteps sweeps starting from buffer 0 / 1, captured on an
     // internal stream and launched on the caller's stream
@@ -259,8 +261,11 @@ int validate(const lbm_desc *d, Dims &dm) {
         if (p > 0 && d->kpoly[p] != 0.0) kvar = true;
     }
     if (!(d->kpoly[0] > 0.0)) return fail(LBM_E_INVALID, "kpoly[0] must be positive (K(0) positive definite)");
-    if (d->scheme == LBM_SCHEME_B && src)
-        return fail(LBM_E_UNSUPPORTED, "Scheme B with a source is not built on the GPU");
+    if (d->scheme == LBM_SCHEME_B)
+        for (int p = 1; p < LBM_MAXP; ++p)
+            if (d->rpoly[p] != 0.0)
+                return fail(LBM_E_UNSUPPORTED,
+                            "Scheme B with R depending on phi (Eq. 35 implicit) is not built on the GPU");
     {
         int nb = 0;
         for (int a = 0; a < dim; ++a) nb = std::max(nb, top_count(d->b[a], LBM_MAXP));
@@ -276,6 +281,7 @@ int validate(const lbm_desc *d, Dims &dm) {
     dm.src = src;
     dm.kvar = kvar;
     dm.wall = wall;
+    dm.sb = d->scheme == LBM_SCHEME_B;
     return LBM_OK;
 }
 
@@ -298,7 +304,21 @@ int upload_coefs(lbm_ctx *c) {
     return LBM_OK;
 }
 
+// Launch dimensions: Scheme B matters only with a source (with R = 0 it is
+// Scheme A exactly).
+Dims eff_dims(const lbm_ctx *c) {
+    Dims d = c->dm;
+    d.sb = c->dm.sb && (c->dm.src || c->rfield);
+    return d;
+}
+
+bool general_path(const lbm_ctx *c) { return c->kfield || eff_dims(c).sb; }
+
 hipError_t sweep(lbm_ctx *c, const void *fin, void *fout, void *p, hipStream_t st) {
+    const Dims d = eff_dims(c);
+    if (general_path(c))
+        return c->dm.q == 9 ? launch_sweep_gen_q9(d, c->g, c->d_coefs, fin, fout, p, c->d_flag, c->kfield, c->rfield, st)
+                            : launch_sweep_gen_q19(d, c->g, c->d_coefs, fin, fout, p, c->d_flag, c->kfield, c->rfield, st);
     return c->dm.q == 9 ? launch_sweep_q9(c->dm, c->g, c->d_coefs, fin, fout, p, c->d_flag, st)
                         : launch_sweep_q19(c->dm, c->g, c->d_coefs, fin, fout, p, c->d_flag, st);
 }
@@ -335,10 +355,11 @@ hipError_t make_graph(lbm_ctx *c, int start) {
 hipError_t recenter(lbm_ctx *c, hipStream_t st) {
     int parts = (int)std::min<uint32_t>(kRedParts, c->g.nblocks);
     if (parts < 1) parts = 1;
+    const Dims d = eff_dims(c);
     hipError_t e = c->dm.q == 9
-                       ? launch_recenter_q9(c->dm, c->g, c->d_coefs, c->f[c->cur], c->p, c->d_red_part, parts,
+                       ? launch_recenter_q9(d, c->g, c->d_coefs, c->f[c->cur], c->p, c->d_red_part, parts,
                                             c->d_shift, st)
-                       : launch_recenter_q19(c->dm, c->g, c->d_coefs, c->f[c->cur], c->p, c->d_red_part, parts,
+                       : launch_recenter_q19(d, c->g, c->d_coefs, c->f[c->cur], c->p, c->d_red_part, parts,
                                              c->d_shift, st);
     if (e == hipSuccess) c->recentered = true;
     return e;
@@ -505,8 +526,9 @@ int lbm_init(lbm_ctx *c, const double *phi0, void *f_a, void *f_b, void *p, void
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(coefficients)");
         c->recentered = false;
     }
-    hipError_t e = (c->dm.q == 9) ? launch_init_q9(c->dm, c->g, c->d_coefs, phi0, f_a, p, st)
-                                  : launch_init_q19(c->dm, c->g, c->d_coefs, phi0, f_a, p, st);
+    const Dims d = eff_dims(c);
+    hipError_t e = (c->dm.q == 9) ? launch_init_q9(d, c->g, c->d_coefs, phi0, f_a, p, c->rfield, st)
+                                  : launch_init_q19(d, c->g, c->d_coefs, phi0, f_a, p, c->rfield, st);
     if (e != hipSuccess) return hip_fail(e, "init kernel");
     e = hipMemsetAsync(c->d_flag, 0, sizeof(int), st);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(flag)");
@@ -551,6 +573,17 @@ int lbm_set_recenter(lbm_ctx *c, int every) {
     return LBM_OK;
 }
 
+int lbm_set_fields(lbm_ctx *c, const double *k0_field, const double *r_field) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (((uintptr_t)k0_field | (uintptr_t)r_field) & 7) return fail(LBM_E_INVALID, "fields must be 8-byte aligned");
+    if (r_field && !c->dm.sb)
+        return fail(LBM_E_UNSUPPORTED, "an external source field needs Scheme B (Scheme A would also need R(t - 1))");
+    if (k0_field != c->kfield || r_field != c->rfield) drop_graphs(c);
+    c->kfield = k0_field;
+    c->rfield = r_field;
+    return LBM_OK;
+}
+
 int lbm_sweep(lbm_ctx *c, const void *f_in, void *f_out, void *p, void *stream) {
     if (!c || !f_in || !f_out || !p) return fail(LBM_E_INVALID, "null argument");
     if (f_in == f_out) return fail(LBM_E_INVALID, "f_in and f_out must differ");
@@ -561,8 +594,9 @@ int lbm_sweep(lbm_ctx *c, const void *f_in, void *f_out, void *p, void *stream) 
 
 int lbm_phi_of(lbm_ctx *c, const void *f, double *phi, void *stream) {
     if (!c || !f || !phi) return fail(LBM_E_INVALID, "null argument");
-    hipError_t e = (c->dm.q == 9) ? launch_phi_q9(c->dm, c->g, c->d_coefs, f, phi, (hipStream_t)stream)
-                                  : launch_phi_q19(c->dm, c->g, c->d_coefs, f, phi, (hipStream_t)stream);
+    const Dims d = eff_dims(c);
+    hipError_t e = (c->dm.q == 9) ? launch_phi_q9(d, c->g, c->d_coefs, f, phi, c->rfield, (hipStream_t)stream)
+                                  : launch_phi_q19(d, c->g, c->d_coefs, f, phi, c->rfield, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "phi kernel");
     return LBM_OK;
 }
@@ -627,6 +661,7 @@ int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void
     if (!c || !gphi || !psi || !pi) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources or per-node fields");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipStream_t st = (hipStream_t)stream;
@@ -644,6 +679,7 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
     if (psi_next == psi_out) return fail(LBM_E_INVALID, "psi_next and psi_out must differ");
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources or per-node fields");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
@@ -659,6 +695,7 @@ int lbm_adjoint_init(lbm_ctx *c, const double *phi0, const void *psi0, const dou
     if (!c || !phi0 || !psi0 || !pi0 || !gphi0) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources or per-node fields");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipError_t e = launch_adjoint_init_q9(c->dm, c->g, c->d_coefs, phi0, psi0, pi0, gphi0, (hipStream_t)stream);

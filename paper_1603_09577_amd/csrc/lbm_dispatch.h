@@ -48,32 +48,65 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
     return hipGetLastError();
 }
 
+// Scheme B and/or per-node fields: the general kernel (any polynomial length).
+template <int Q, typename TS, typename TC>
+hipError_t sweep_gen_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                           void *p, int *flag, const double *kfield, const double *rfield, hipStream_t st) {
+    using TP = typename HistType<TS>::T;
+    const auto *cf = (const Coefs<TC> *)coefs;
+    const auto *fi = (const TS *)fin;
+    auto *fo = (TS *)fout;
+    auto *pp = (TP *)p;
+    const dim3 grid(g.nblocks), block(kBlock);
+    const int code = (dm.eqr ? 4 : 0) | (dm.wall ? 2 : 0) | (dm.sb ? 1 : 0);
+#define LBM_GEN(E, W, B)                                                                            \
+    case (E * 4 + W * 2 + B):                                                                       \
+        hipLaunchKernelGGL((k_sweep_gen<Q, TS, TC, E, W, B>), grid, block, 0, st, g, cf, fi, fo, pp, flag, \
+                           kfield, rfield);                                                         \
+        break;
+    switch (code) {
+        LBM_GEN(0, 0, 0) LBM_GEN(0, 0, 1) LBM_GEN(0, 1, 0) LBM_GEN(0, 1, 1)
+        LBM_GEN(1, 0, 0) LBM_GEN(1, 0, 1) LBM_GEN(1, 1, 0) LBM_GEN(1, 1, 1)
+        default: return hipErrorInvalidValue;
+    }
+#undef LBM_GEN
+    return hipGetLastError();
+}
+
 template <int Q, typename TS, typename TC>
 hipError_t init_typed(const Dims &dm, const Geom &g, const void *coefs, const double *phi0, void *f,
-                      void *p, hipStream_t st) {
+                      void *p, const double *rfield, hipStream_t st) {
     using TP = typename HistType<TS>::T;
     const auto *cf = (const Coefs<TC> *)coefs;
     const dim3 grid(g.nblocks), block(kBlock);
-    if (dm.wall && dm.lowdeg)
-        hipLaunchKernelGGL((k_init<Q, TS, TC, true, 4>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
-    else if (dm.wall)
-        hipLaunchKernelGGL((k_init<Q, TS, TC, true, 9>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
-    else if (dm.lowdeg)
-        hipLaunchKernelGGL((k_init<Q, TS, TC, false, 4>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
-    else
-        hipLaunchKernelGGL((k_init<Q, TS, TC, false, 9>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p);
+    const bool low = dm.lowdeg && !dm.sb;
+#define LBM_INIT(W, NP, B) \
+    hipLaunchKernelGGL((k_init<Q, TS, TC, W, NP, B>), grid, block, 0, st, g, cf, phi0, (TS *)f, (TP *)p, rfield)
+    if (dm.sb) {
+        if (dm.wall) LBM_INIT(true, 9, true);
+        else LBM_INIT(false, 9, true);
+    } else if (dm.wall && low) LBM_INIT(true, 4, false);
+    else if (dm.wall) LBM_INIT(true, 9, false);
+    else if (low) LBM_INIT(false, 4, false);
+    else LBM_INIT(false, 9, false);
+#undef LBM_INIT
     return hipGetLastError();
 }
 
 template <int Q, typename TS, typename TC>
 hipError_t phi_typed(const Dims &dm, const Geom &g, const void *coefs, const void *f, double *phi,
-                     hipStream_t st) {
+                     const double *rfield, hipStream_t st) {
     const auto *cf = (const Coefs<TC> *)coefs;
     const dim3 grid(g.nblocks), block(kBlock);
-    if (dm.wall)
-        hipLaunchKernelGGL((k_phi<Q, TS, TC, true>), grid, block, 0, st, g, cf, (const TS *)f, phi);
+    const TS *fs = (const TS *)f;
+    if (dm.wall && dm.sb)
+        hipLaunchKernelGGL((k_phi<Q, TS, TC, true, true>), grid, block, 0, st, g, cf, fs, phi, rfield);
+    else if (dm.wall)
+        hipLaunchKernelGGL((k_phi<Q, TS, TC, true, false>), grid, block, 0, st, g, cf, fs, phi, rfield);
+    else if (dm.sb)
+        hipLaunchKernelGGL((k_phi<Q, TS, TC, false, true>), grid, block, 0, st, g, cf, fs, phi, rfield);
     else
-        hipLaunchKernelGGL((k_phi<Q, TS, TC, false>), grid, block, 0, st, g, cf, (const TS *)f, phi);
+        hipLaunchKernelGGL((k_phi<Q, TS, TC, false, false>), grid, block, 0, st, g, cf, fs, phi, rfield);
     return hipGetLastError();
 }
 
@@ -135,7 +168,7 @@ hipError_t recenter_typed(const Dims &dm, const Geom &g, void *coefs, void *f, v
                           double *shift, hipStream_t st) {
     using TP = typename HistType<TS>::T;
     hipLaunchKernelGGL((k_offset_sum<Q, TS>), dim3(nparts), dim3(kBlock), 0, st, g, (const TS *)f,
-                       (const TP *)p, dm.src ? 1 : 0, part);
+                       (const TP *)p, (dm.src && !dm.sb) ? 1 : 0, part);
     hipLaunchKernelGGL((k_recenter_fold<Q, TC>), dim3(1), dim3(kBlock), 0, st, (Coefs<TC> *)coefs, part, nparts,
                        g.N, shift);
     hipLaunchKernelGGL((k_shift<Q, TS, TC>), dim3(g.nblocks), dim3(kBlock), 0, st, g, (const double *)shift,

@@ -71,6 +71,7 @@ struct Dims {
     bool wall;            // walls on the last axis
     bool lowdeg;          // every polynomial of degree <= 3 (C-bar <= 5)
     bool nt;              // non-temporal distribution accesses
+    bool sb;              // Scheme B (Eq. 33-35): stored fbar, explicit source
 };
 
 // Elements between consecutive direction planes.  A plane stride that is a
@@ -96,10 +97,13 @@ inline uint64_t plane_stride(uint64_t n, int q, size_t elem, int pad_req) {
 #define LBM_LAUNCHERS(SFX)                                                                              \
     hipError_t launch_sweep_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *fin,   \
                                   void *fout, void *p, int *flag, hipStream_t st);                      \
+    hipError_t launch_sweep_gen_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *fin, \
+                                      void *fout, void *p, int *flag, const double *kfield,             \
+                                      const double *rfield, hipStream_t st);                            \
     hipError_t launch_init_##SFX(const Dims &dm, const Geom &g, const void *coefs, const double *phi0, \
-                                 void *f, void *p, hipStream_t st);                                     \
+                                 void *f, void *p, const double *rfield, hipStream_t st);               \
     hipError_t launch_phi_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *f,       \
-                                double *phi, hipStream_t st);                                           \
+                                double *phi, const double *rfield, hipStream_t st);                     \
     hipError_t launch_recenter_##SFX(const Dims &dm, const Geom &g, void *coefs, void *f, void *p,     \
                                      double *part, int nparts, double *shift, hipStream_t st);
 LBM_LAUNCHERS(q9)

@@ -110,6 +110,33 @@ __device__ __forceinline__ void ablock(const Coefs<TC> *__restrict__ cf, TC phi,
     }
 }
 
+// A = (g0n k(phi) + I/2)^-1 (Eq. 26) with a per-node g0n = 3 K0(x) / d.
+template <int DIM, int NP, typename TC>
+__device__ __forceinline__ void ablock_field(const Coefs<TC> *__restrict__ cf, const TC *g0n, TC phi, TC *A) {
+    const TC kv = poly<NP>(cf->kp, phi);
+    TC G[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) G[i] = g0n[i] * kv + (i < 3 ? TC(0.5) : TC(0));
+    sym_inverse<DIM>(G, A);
+}
+
+// Per-node 3 K0(x) / d from a field of K0 (2-D: xx, yy, xy; 3-D: xx, yy, zz,
+// xy, yz, xz per node, FP64), in the symmetric order (xx, yy, zz, xy, yz, xz).
+template <int DIM, typename TC>
+__device__ __forceinline__ void g0_of_field(const Coefs<TC> *__restrict__ cf, const double *kfield, uint32_t n,
+                                            TC *g0n) {
+    constexpr int NK = DIM == 2 ? 3 : 6;
+    const double *kf = kfield + (size_t)n * NK;
+    const TC sc = cf->k0scale;
+    if (DIM == 2) {
+        g0n[0] = sc * (TC)kf[0]; g0n[1] = sc * (TC)kf[1]; g0n[3] = sc * (TC)kf[2];
+        g0n[2] = g0n[4] = g0n[5] = TC(0);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) g0n[i] = sc * (TC)kf[i];
+    }
+}
+
 // Equilibrium offsets feq_k - w_k phi_ref (Eq. 3 with c = 1, cs^2 = 1/3):
 // w_k [ (phi - phi_ref) + 3 c.B + 9/2 ((Cbar - phi/3 I) : (c c - I/3)) ].
 template <int Q, int NP, typename TC>
@@ -227,10 +254,18 @@ __device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restric
 // the sweep
 // ---------------------------------------------------------------------------
 // One node of the sweep (shared by the single-instance and batched kernels).
-template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT = false>
+//
+// SB: Scheme B (Eq. 33-35): the stored variable is fbar = f - R_k / 2, phi =
+// sum fbar + R / 2 with R = R0 + an external field R(x, t) (explicit in phi),
+// Btilde = B', and the source enters as M^-1 (I - S/2) M R_k (Eq. 34).  SRC
+// then stays false (it is the Scheme-A source with its phi history).
+// KF: K0 per node from `kfield` (A per node by Eq. 26).
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT = false,
+          bool SB = false, bool KF = false>
 __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__restrict__ cf,
                                            const TS *__restrict__ fin, TS *__restrict__ fout,
-                                           typename HistType<TS>::T *p, int *flag, uint32_t n) {
+                                           typename HistType<TS>::T *p, int *flag, uint32_t n,
+                                           const double *kfield = nullptr, const double *rfield = nullptr) {
     using L = Lattice<Q>;
     constexpr int D = L::dim;
     const NodeGeo ng = node_geometry<Q, WALL>(g, n);
@@ -239,17 +274,26 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     gather<Q, WALL, NT>(g, cf, fin, ng, h);
     // history read issued together with the gathers, so its latency overlaps theirs
     const TC pp_off = SRC ? (TC)p[n] : TC(0);
+    TC g0n[6];
+    const bool kfon = KF && kfield != nullptr;   // uniform across the launch
+    if (kfon) g0_of_field<D>(cf, kfield, n, g0n);
+    // Scheme B: R at this node and time (explicit in phi), Eq. 35
+    const TC Rx = SB ? cf->r[0] + (rfield ? (TC)rfield[n] : TC(0)) : TC(0);
 
     TC phio = TC(0);
 #pragma unroll
     for (int k = 0; k < Q; ++k) phio += h[k];
+    if (SB) phio += TC(0.5) * Rx;
     const TC phi = cf->phi_ref + phio;
 
     TC A[6];
-    ablock<D, KVAR, NP>(cf, phi, A);
+    if (kfon) ablock_field<D, NP>(cf, g0n, phi, A);
+    else ablock<D, KVAR, NP>(cf, phi, A);
 
     TC out[Q];
-    TC Se = TC(0);  // mass the Scheme-A source adds this step: 3/2 R(t) - 1/2 R(t-1)
+    // mass the source adds this step: Scheme A 3/2 R(t) - 1/2 R(t-1); Scheme B
+    // R / 2 on top of phi - phi_ref (the stored sum is phi - R/2 before, phi + R/2 after)
+    TC Se = TC(0);
     if (EQR) {
         // All non-flux rates equal s.  With orthogonal rows and the flux rows
         // equal to c_a, (M^-1 S M)(g - feq) = s (g - feq) + c_k . v with
@@ -276,18 +320,31 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
         if (D == 3) E[2] -= third;
         const TC trE3 = (E[0] + E[1] + E[2]) * TC(1.0 / 3.0);
         TC Vo[3] = {TC(0), TC(0), TC(0)};
+        TC jsh[3] = {TC(0), TC(0), TC(0)};   // Scheme B: R B' / 2, the part of j the shift removed
         if (SRC) {
             TC Bt[3], R, Btp[3], Rp, Ap[6];
             source_terms<D, NP>(cf, phi, A, Bt, R);
             const TC pp = cf->phi_ref + pp_off;
-            ablock<D, KVAR, NP>(cf, pp, Ap);
+            if (kfon) ablock_field<D, NP>(cf, g0n, pp, Ap);
+            else ablock<D, KVAR, NP>(cf, pp, Ap);
             source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
             Se = TC(1.5) * R - TC(0.5) * Rp;
 #pragma unroll
             for (int a = 0; a < D; ++a) Vo[a] = TC(4.5) * R * Bt[a] - TC(1.5) * Rp * Btp[a];
             p[n] = (typename HistType<TS>::T)phio;
         }
-        // j - B, with j the first moment of the gathered populations
+        if (SB) {
+            // (1 - s/2) R_k = w_k (1 - s/2) R + c_k . 3 w_k (1 - s/2) R B'
+            const TC hs = (TC(1) - TC(0.5) * s) * Rx;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const TC bp = poly<NP>(cf->bp[a], phi);
+                Vo[a] = TC(3) * hs * bp;
+                jsh[a] = TC(0.5) * Rx * bp;
+            }
+        }
+        // j - B, with j the first moment of the gathered populations (Scheme B:
+        // of f = fbar + R_k / 2, i.e. plus R B' / 2)
         TC jd[3], v[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -298,7 +355,7 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
                 if (c == 1) acc += h[k];
                 else if (c == -1) acc -= h[k];
             }
-            jd[a] = (a < D) ? acc - B[a] : TC(0);
+            jd[a] = (a < D) ? acc + jsh[a] - B[a] : TC(0);
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -307,7 +364,11 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
             for (int b = 0; b < D; ++b) acc += (A[sym(a, b)] - (a == b ? s : TC(0))) * jd[b];
             v[a] = acc * TC(1.0 / L::jnorm);
         }
-        const TC base = s * phio + Se;
+        // even source part: Scheme A Se; Scheme B (1 - s/2) R.  Mass target
+        // below: Scheme A phio + Se; Scheme B phio + R/2 (sum of the gathered
+        // fbar is phio - R/2, the collision returns phio + R/2).
+        const TC base = s * phio + (SB ? (TC(1) - TC(0.5) * s) * Rx : Se);
+        if (SB) Se = TC(0.5) * Rx;
         const TC s45 = TC(4.5) * s;
         const TC oms = TC(1) - s;
 #pragma unroll
@@ -364,6 +425,47 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
             for (int b = 0; b < D; ++b) acc += A[sym(a, b)] * m[L::jrow[b]];
             r[L::jrow[a]] = acc;
         }
+        if (SB) {
+            // r -= (I - S/2) M R_k, R_k = w_k R (1 + 3 c_k . B') (Eq. 9, Btilde = B')
+            TC Bp[3] = {TC(0), TC(0), TC(0)};
+#pragma unroll
+            for (int a = 0; a < D; ++a) Bp[a] = poly<NP>(cf->bp[a], phi);
+            TC Rk[Q], mR[Q], sR[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                TC cb = TC(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const int c = L::c(k, a);
+                    if (c) cb += TC(c) * Bp[a];
+                }
+                Rk[k] = TC(L::w(k)) * Rx * (TC(1) + TC(3) * cb);
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                TC acc = TC(0);
+#pragma unroll
+                for (int k = 0; k < Q; ++k) {
+                    const int mm = L::M(i, k);
+                    if (mm == 1) acc += Rk[k];
+                    else if (mm == -1) acc -= Rk[k];
+                    else if (mm) acc += TC(mm) * Rk[k];
+                }
+                mR[i] = acc;
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) sR[i] = cf->s[i] * mR[i];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                TC acc = TC(0);
+#pragma unroll
+                for (int b = 0; b < D; ++b) acc += A[sym(a, b)] * mR[L::jrow[b]];
+                sR[L::jrow[a]] = acc;
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) r[i] -= mR[i] - TC(0.5) * sR[i];
+            Se = TC(0.5) * Rx;
+        }
 #pragma unroll
         for (int i = 0; i < Q; ++i) r[i] *= TC(1.0 / L::N(i));
 #pragma unroll
@@ -385,7 +487,8 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
         TC Bt[3], R, Btp[3], Rp, Ap[6];
         source_terms<D, NP>(cf, phi, A, Bt, R);
         const TC pp = cf->phi_ref + pp_off;
-        ablock<D, KVAR, NP>(cf, pp, Ap);
+        if (kfon) ablock_field<D, NP>(cf, g0n, pp, Ap);
+        else ablock<D, KVAR, NP>(cf, pp, Ap);
         source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
         const TC r1 = TC(1.5) * R, r0 = TC(0.5) * Rp;
         Se = r1 - r0;
@@ -434,6 +537,18 @@ k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f
     }
 }
 
+// The general sweep: Scheme B and/or per-node fields.  Polynomials of any
+// length, K(phi) evaluated per node, Scheme-A history kept when SB is off.
+template <int Q, typename TS, typename TC, bool EQR, bool WALL, bool SB>
+__global__ void __launch_bounds__(kBlock)
+k_sweep_gen(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin,
+            TS *__restrict__ fout, typename HistType<TS>::T *p, int *flag, const double *kfield,
+            const double *rfield) {
+    const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    sweep_node<Q, TS, TC, EQR, !SB, true, WALL, 9, false, SB, true>(g, cf, fin, fout, p, flag, n, kfield, rfield);
+}
+
 // ---------------------------------------------------------------------------
 // initialisation (Eq. 40) in the gather convention
 // ---------------------------------------------------------------------------
@@ -448,10 +563,23 @@ __device__ __forceinline__ TC feq_one(const Coefs<TC> *__restrict__ cf, TC phi, 
     return v;
 }
 
-template <int Q, typename TS, typename TC, bool WALL, int NP>
+// Scheme B: R_k / 2 at a node (Eq. 9 with Btilde = B', R explicit in phi).
+template <int Q, int NP, typename TC>
+__device__ __forceinline__ TC half_source_one(const Coefs<TC> *__restrict__ cf, TC phi, TC R, int kk) {
+    using L = Lattice<Q>;
+    TC cb = TC(0);
+#pragma unroll
+    for (int a = 0; a < L::dim; ++a) {
+        const int c = L::c(kk, a);
+        if (c) cb += TC(c) * poly<NP>(cf->bp[a], phi);
+    }
+    return TC(0.5) * TC(L::w(kk)) * R * (TC(1) + TC(3) * cb);
+}
+
+template <int Q, typename TS, typename TC, bool WALL, int NP, bool SB = false>
 __global__ void __launch_bounds__(kBlock)
 k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict__ phi0,
-       TS *__restrict__ f, typename HistType<TS>::T *p) {
+       TS *__restrict__ f, typename HistType<TS>::T *p, const double *rfield = nullptr) {
     using L = Lattice<Q>;
     constexpr int D = L::dim;
     const uint32_t n = blockIdx.x * kBlock + threadIdx.x;
@@ -465,7 +593,10 @@ k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict_
         TC v;
         if (WALL && ((cl == 1 && ng.hi) || (cl == -1 && ng.lo))) {
             const TC ph = (TC)phi0[n];
-            v = cf->ew[cl == 1 ? 1 : 0][k] - feq_one<Q, NP>(cf, ph, L::opp(k));
+            TC e = feq_one<Q, NP>(cf, ph, L::opp(k));
+            // Scheme B stores fbar = feq - R_k / 2 (Eq. 33)
+            if (SB) e -= half_source_one<Q, NP>(cf, ph, cf->r[0] + (rfield ? (TC)rfield[n] : TC(0)), L::opp(k));
+            v = cf->ew[cl == 1 ? 1 : 0][k] - e;
         } else {
             int off = 0;
 #pragma unroll
@@ -473,19 +604,21 @@ k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict_
                 const int c = L::c(k, a);
                 off += (c == 1) ? ng.op[a] : ((c == -1) ? ng.om[a] : 0);
             }
-            const TC ph = (TC)phi0[(uint32_t)((int)n + off)];
+            const uint32_t src = (uint32_t)((int)n + off);
+            const TC ph = (TC)phi0[src];
             v = feq_one<Q, NP>(cf, ph, k);
+            if (SB) v -= half_source_one<Q, NP>(cf, ph, cf->r[0] + (rfield ? (TC)rfield[src] : TC(0)), k);
         }
         store_s(f + (uint64_t)k * g.plane + n, v);
     }
     if (p) p[n] = (typename HistType<TS>::T)((TC)phi0[n] - cf->phi_ref);
 }
 
-// phi = phi_ref + sum_k g_k, accumulated in FP64.
-template <int Q, typename TS, typename TC, bool WALL>
+// phi = phi_ref + sum_k g_k (Scheme B: + R / 2, Eq. 35), accumulated in FP64.
+template <int Q, typename TS, typename TC, bool WALL, bool SB = false>
 __global__ void __launch_bounds__(kBlock)
 k_phi(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
-      double *__restrict__ phi) {
+      double *__restrict__ phi, const double *rfield = nullptr) {
     const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
     if (n >= g.N) return;
     const NodeGeo ng = node_geometry<Q, WALL>(g, n);
@@ -494,6 +627,7 @@ k_phi(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) acc += (double)h[k];
+    if (SB) acc += 0.5 * ((double)cf->r[0] + (rfield ? rfield[n] : 0.0));
     phi[n] = (double)cf->phi_ref + acc;
 }
 

@@ -10,13 +10,18 @@ hipError_t launch_sweep_q19(const Dims &dm, const Geom &g, const void *coefs, co
 }
 
 hipError_t launch_init_q19(const Dims &dm, const Geom &g, const void *coefs, const double *phi0,
-                           void *f, void *p, hipStream_t st) {
-    LBM_BY_PREC(init_typed, dm, g, coefs, phi0, f, p, st)
+                           void *f, void *p, const double *rfield, hipStream_t st) {
+    LBM_BY_PREC(init_typed, dm, g, coefs, phi0, f, p, rfield, st)
 }
 
 hipError_t launch_phi_q19(const Dims &dm, const Geom &g, const void *coefs, const void *f,
-                          double *phi, hipStream_t st) {
-    LBM_BY_PREC(phi_typed, dm, g, coefs, f, phi, st)
+                          double *phi, const double *rfield, hipStream_t st) {
+    LBM_BY_PREC(phi_typed, dm, g, coefs, f, phi, rfield, st)
+}
+
+hipError_t launch_sweep_gen_q19(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                               void *p, int *flag, const double *kfield, const double *rfield, hipStream_t st) {
+    LBM_BY_PREC(sweep_gen_typed, dm, g, coefs, fin, fout, p, flag, kfield, rfield, st)
 }
 
 hipError_t launch_recenter_q19(const Dims &dm, const Geom &g, void *coefs, void *f, void *p, double *part,

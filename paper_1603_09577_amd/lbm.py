@@ -31,7 +31,7 @@ EXPORTS = [
     "lbm_batch_create", "lbm_batch_layout", "lbm_batch_instance", "lbm_batch_init",
     "lbm_batch_step", "lbm_batch_get_phi", "lbm_batch_tune", "lbm_batch_set_shape",
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
-    "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter",
+    "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields",
 ]
 
 
@@ -121,6 +121,7 @@ def load():
         "lbm_tune": ([_VP, ctypes.c_int, _VP, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
         "lbm_recenter": ([_VP, _VP], ctypes.c_int),
         "lbm_set_recenter": ([_VP, ctypes.c_int], ctypes.c_int),
+        "lbm_set_fields": ([_VP, _VP, _VP], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -289,6 +290,23 @@ class Lbm:
     def set_recenter(self, every):
         """Re-centre inside step() every `every` steps (0 = never)."""
         _check(self.lib.lbm_set_recenter(self.ctx, int(every)))
+
+    def set_fields(self, k0_field=None, r_field=None):
+        """Bind per-node fields (FP64 device tensors, kept alive here): K0(x) as
+        [..., 3] (2-D: xx, yy, xy) or [..., 6] (3-D: xx, yy, zz, xy, yz, xz), and
+        an external source R(x) (Scheme B), [nz][ny][nx] or [ny][nx].  Rewrite
+        the source tensor in place between steps for R(x, t)."""
+        import torch
+        for t in (k0_field, r_field):
+            if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or t.device.type != "cuda"):
+                raise ValueError("fields must be contiguous float64 CUDA tensors")
+        nk = 3 if self.q == 9 else 6
+        if k0_field is not None and k0_field.numel() != self.N * nk:
+            raise ValueError(f"k0_field needs {nk} values per node")
+        if r_field is not None and r_field.numel() != self.N:
+            raise ValueError("r_field needs one value per node")
+        self._fields = (k0_field, r_field)
+        _check(self.lib.lbm_set_fields(self.ctx, _ptr(k0_field), _ptr(r_field)))
 
     def set_k0(self, k0):
         arr = (ctypes.c_double * 9)(*np.asarray(k0, dtype=np.float64).reshape(-1).tolist())

@@ -87,10 +87,11 @@ def test_unsupported_combinations(L):
     assert _create(L, sp)[0] == lbm.LBM_E_UNSUPPORTED
     sp = dict(spec)
     sp["scheme"] = "B"
-    assert _create(L, sp)[0] == lbm.LBM_E_UNSUPPORTED        # Scheme B with a source
-    sp["rpoly"] = []
-    rc, msg = _create(L, sp)
-    assert rc in (lbm.LBM_OK, lbm.LBM_E_HIP), msg               # valid; needs a GPU
+    assert _create(L, sp)[0] == lbm.LBM_E_UNSUPPORTED        # Scheme B with R(phi): Eq. 35 implicit
+    for rp in ([], [1e-3]):                                     # no source, constant source
+        sp["rpoly"] = rp
+        rc, msg = _create(L, sp)
+        assert rc in (lbm.LBM_OK, lbm.LBM_E_HIP), msg           # valid; needs a GPU
     sp = W.spec_d3q19_aniso((8, 8, 8), K=np.diag([0.01, 0.02, 0.03]))
     sp["bc"] = ["periodic", "abb", "periodic"]
     assert _create(L, sp)[0] == lbm.LBM_E_UNSUPPORTED
