@@ -593,3 +593,28 @@ def test_adjoint_gradient_vs_finite_differences():
         h = 1e-7
         fd = (loss(phi0, k0 + h * dk) - loss(phi0, k0 - h * dk)) / (2 * h)
         assert abs(fd - gk[name]) < 1e-6 * max(abs(fd), 1e-12), (name, fd, gk[name])
+
+
+def test_gaussian_hill_printed_gre_full_size():
+    """Sec. 3.4 at the paper's own size: isotropic K = 1e-3 I, u = (0.01, 0.01),
+    sigma0 = 0.01 on the periodic [-1, 1]^2 with 400 distinct nodes per axis
+    (the printed 401 x 401 with node 400 = node 0) and c = 1, T = 10 (2000
+    steps), rates of Eq. 41.  The GRE of Eq. 39 against Eq. 60 is the printed
+    1.199e-4 to its four digits."""
+    printed = json.load(open(GOLDEN))["gaussian_hill_gre_approach1"]["value"][0]
+    n, L = 400, 2.0
+    dx = L / n
+    dt = dx
+    s0 = 0.01
+    x = -1 + np.arange(n) * dx
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    kl = 1e-3 * dt / dx ** 2
+    spec = dict(lattice=9, shape=(n, n), bc=["periodic"] * 3, scheme="B", d=1.0, s=[0.0] + [1.0] * 8,
+                b=[[0.0, 0.01 * dt / dx], [0.0, 0.01 * dt / dx]], dpoly=[0, 1], dten=np.eye(3).tolist(),
+                k0=(kl * np.eye(3)).tolist(), kpoly=[1.0], rpoly=[])
+    phT, _ = orc.run(orc.params_from_spec(spec), np.exp(-(X * X + Y * Y) / (2 * s0 * s0)), 2000)
+    T = 2000 * dt
+    sig = s0 * s0 + 2e-3 * T
+    exact = s0 * s0 / sig * np.exp(-((X - 0.01 * T) ** 2 + (Y - 0.01 * T) ** 2) / (2 * sig))
+    g = _gre(phT, exact)
+    assert abs(g / printed - 1) < 5e-4, g
