@@ -34,6 +34,7 @@ class Params(ctypes.Structure):
         ("k0", (ctypes.c_double * 3) * 3),
         ("kpoly", ctypes.c_double * MAXP),
         ("rpoly", ctypes.c_double * MAXP),
+        ("variant", ctypes.c_int),
     ]
 
 
@@ -90,7 +91,7 @@ def params_from_spec(spec, basis=0):
     Keys: lattice (9 | 19), shape (nx, ny[, nz]), bc (per axis "periodic" |
     "abb"), phi_wall ([[lo, hi]] * 3), scheme ("A" | "B"), d, s (rates in
     moment-row order), b (per axis polynomial coefficients of B), dpoly, dten,
-    k0, kpoly, rpoly.
+    k0, kpoly, rpoly, variant ("standard" | "remark3": Eq. 36-38).
     """
     p = Params()
     q = int(spec["lattice"])
@@ -105,6 +106,7 @@ def params_from_spec(spec, basis=0):
         p.phi_wall[a][0] = float(pw[a][0])
         p.phi_wall[a][1] = float(pw[a][1])
     p.scheme = {"A": 0, "B": 1}[spec.get("scheme", "A")]
+    p.variant = {"standard": 0, "remark3": 1}[spec.get("variant", "standard")]
     p.d = float(spec.get("d", 1.0))
     s = _pad(spec["s"], 19)
     for i in range(19):

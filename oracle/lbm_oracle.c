@@ -256,6 +256,7 @@ int orc_check(const orc_params *p)
     if (nwall > 1) return -1;
     if (p->q == 9 && p->bc[2] != 0) return -1;
     if (p->scheme != 0 && p->scheme != 1) return -1;
+    if (p->variant != 0 && p->variant != 1) return -1;
     if (p->scheme == 1)
         for (int i = 1; i < ORC_MAXP; ++i) if (p->rpoly[i] != 0.0) return -2; /* Eq. 35 implicit */
     return 0;

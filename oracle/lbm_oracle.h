@@ -38,6 +38,9 @@ typedef struct orc_params {
     double k0[3][3];           /* K(phi, x) = K0 * kpoly(phi)                   */
     double kpoly[ORC_MAXP];
     double rpoly[ORC_MAXP];    /* R(phi) = rpoly(phi)  (+ optional field R(x,t)) */
+    int variant;               /* 0: equilibrium of Eq. 3; 1: Remark III (Eq. 36-38):
+                                  C = 0 in the equilibrium and the source G_k of
+                                  Eq. 37 with an explicit time difference of B    */
 } orc_params;
 
 /* 0 on success, negative on an invalid parameter set. */

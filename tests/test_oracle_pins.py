@@ -391,7 +391,7 @@ def _gre(num, ana):
     return np.abs(ana - num).sum() / np.abs(ana).sum()
 
 
-def _hill_run(n, K, u, sigma0, T, q=9, rates=1.0):
+def _hill_run(n, K, u, sigma0, T, q=9, rates=1.0, variant="standard", dten=None):
     dim = 2 if q == 9 else 3
     shape = (n,) * dim
     k0 = np.zeros((3, 3))
@@ -399,7 +399,8 @@ def _hill_run(n, K, u, sigma0, T, q=9, rates=1.0):
     bl = [[0.0, u[a]] for a in range(dim)]
     s = [0.0] + [rates] * (q - 1)
     spec = dict(lattice=q, shape=shape, bc=["periodic"] * 3, scheme="A", d=1.0, s=s, b=bl,
-                dpoly=[0, 1], dten=np.eye(3).tolist(), k0=k0.tolist(), kpoly=[1.0], rpoly=[])
+                dpoly=[0, 1], dten=(np.eye(3) if dten is None else dten).tolist(), k0=k0.tolist(),
+                kpoly=[1.0], rpoly=[], variant=variant)
     p = orc.params_from_spec(spec)
     centre = [n / 2.0] * dim
     # oracle fields are [z][y][x] / [y][x]; closed form built in (x, y, z) index order
@@ -618,3 +619,59 @@ def test_gaussian_hill_printed_gre_full_size():
     exact = s0 * s0 / sig * np.exp(-((X - 0.01 * T) ** 2 + (Y - 0.01 * T) ** 2) / (2 * sig))
     g = _gre(phT, exact)
     assert abs(g / printed - 1) < 5e-4, g
+
+
+# ---------------------------------------------------------------------------
+# Remark III (Eq. 36-38): C = 0 in the equilibrium, source G_k of Eq. 37
+# ---------------------------------------------------------------------------
+
+def _remark3_spec(n, b, variant, rpoly=(), scheme="A"):
+    return dict(lattice=9, shape=(n, n), bc=["periodic"] * 3, scheme=scheme, d=1.0, s=[0.0] + [1.0] * 8,
+                b=b, dpoly=[0, 1], dten=np.eye(3).tolist(), k0=(0.03 * np.eye(3)).tolist(),
+                kpoly=[1.0, 0.0, 1.0], rpoly=list(rpoly), variant=variant)
+
+
+def test_remark3_is_the_standard_scheme_without_convection():
+    """B = 0: C = 0 and dB/dt = 0, so Eq. 36-38 is Eq. 2-3 exactly."""
+    phi0 = W.noise_field((24, 24), 41)
+    a = orc.run(orc.params_from_spec(_remark3_spec(24, [[0.0], [0.0]], "standard", [0.01, 0.02])), phi0, 30)[0]
+    b = orc.run(orc.params_from_spec(_remark3_spec(24, [[0.0], [0.0]], "remark3", [0.01, 0.02])), phi0, 30)[0]
+    assert np.abs(a - b).max() == 0.0
+
+
+@pytest.mark.parametrize("scheme", ["A", "B"])
+def test_remark3_conserves_mass(scheme):
+    """G_k is odd in c_k (Eq. 37), so it adds nothing to sum_k f_k: with a
+    nonlinear B and no source the total phi stays put."""
+    phi0 = W.noise_field((26, 26), 42)
+    spec = _remark3_spec(26, [[0.0, 0.0, 0.3], [0.0, 0.0, -0.2]], "remark3", scheme=scheme)
+    f_hist = orc.run(orc.params_from_spec(spec), phi0, 60, snapshots=(1, 60))[1]
+    s0 = phi0.sum()
+    for t in (1, 60):
+        assert abs(f_hist[t].sum() - s0) < 1e-12 * abs(s0)
+
+
+def test_remark3_needs_its_source_term():
+    """With a convection large enough for C = phi u u to matter (u = (0.2, 0.1)
+    in lattice units), Remark III is as close to Eq. 60 as the standard model,
+    while the same equilibrium without G_k (emulated by the standard model
+    with d cs^2 D reduced by phi u u, which cancels C in C-bar) is several
+    times further off: G_k carries the part of the flux that C carried."""
+    K = np.array([[0.01, 0.005], [0.005, 0.015]])
+    u = (0.2, 0.1)
+    g_std = _hill_run(96, K, u, 8.0, 300)
+    g_r3 = _hill_run(96, K, u, 8.0, 300, variant="remark3")
+    dten = np.eye(3)
+    dten[:2, :2] -= 3.0 * np.outer(u, u)
+    g_nog = _hill_run(96, K, u, 8.0, 300, dten=dten)
+    assert g_r3 < 1.2 * g_std, (g_r3, g_std)
+    assert g_nog > 3.0 * g_r3, (g_nog, g_r3)
+
+
+def test_remark3_second_order():
+    """Remark III recovers Eq. 1 (Chapman-Enskog, Sec. 2.3): second order on the
+    full-tensor Gaussian hill under diffusive refinement."""
+    K = 0.01 * np.array([[1.0, 1.0], [1.0, 2.0]])
+    gres = [_hill_run(32 * r, K, (0.04 / r, -0.03 / r), 3.0 * r, 100 * r * r, variant="remark3") for r in (1, 2, 4)]
+    order = [math.log2(gres[i] / gres[i + 1]) for i in range(2)]
+    assert all(1.7 < o < 2.3 for o in order), (gres, order)
