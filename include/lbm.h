@@ -71,6 +71,12 @@ extern "C" {
                                   Cache, round-robin beyond; lbm_tune times both) */
 #define LBM_FLAG_NO_GRAPH 4   /* lbm_step launches every sweep directly
                                  instead of replaying captured graphs       */
+#define LBM_FLAG_REMARK3 8    /* Remark III (Eq. 36-38): equilibrium with C = 0
+                                 (Eq. 38) plus the source G_k of Eq. 37, dB/dt
+                                 as the difference over the last step (from
+                                 the phi history); for a B whose C of Eq. 7 is
+                                 not wanted.  General kernel; no adjoint, no
+                                 batches                                      */
 
 #define LBM_MAXP 9            /* polynomial coefficients per function        */
 

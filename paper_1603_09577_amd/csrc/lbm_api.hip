@@ -139,10 +139,12 @@ void derive(const lbm_desc &d, const Dims &dm, HostModel &m) {
     // Eq. 7 integrated term by term from C(0) = 0:
     //   C_ab = sum_{p,r>=1} p r b_ap b_br / (p + r - 1) phi^(p + r - 1),
     // plus d cs^2 D_ab(phi) to form C-bar (Eq. 16 notation).
+    // Remark III (Eq. 38): C = 0, C-bar = d cs^2 D only
+    const bool with_c = !(d.flags & LBM_FLAG_REMARK3);
     for (int i = 0; i < 6; ++i) {
         const int a = pa[i], b = pb[i];
         if (a >= dim || b >= dim) continue;
-        for (int p = 1; p < kMaxP; ++p)
+        for (int p = 1; p < kMaxP && with_c; ++p)
             for (int r = 1; r < kMaxP; ++r) {
                 const double v = m.b[a][p] * m.b[b][r];
                 if (v != 0.0) m.cb[i][p + r - 1] += p * r * v / (p + r - 1);
@@ -312,13 +314,17 @@ Dims eff_dims(const lbm_ctx *c) {
     return d;
 }
 
-bool general_path(const lbm_ctx *c) { return c->kfield || eff_dims(c).sb; }
+bool remark3(const lbm_ctx *c) { return (c->desc.flags & LBM_FLAG_REMARK3) != 0; }
+
+bool general_path(const lbm_ctx *c) { return c->kfield || eff_dims(c).sb || remark3(c); }
 
 hipError_t sweep(lbm_ctx *c, const void *fin, void *fout, void *p, hipStream_t st) {
     const Dims d = eff_dims(c);
     if (general_path(c))
-        return c->dm.q == 9 ? launch_sweep_gen_q9(d, c->g, c->d_coefs, fin, fout, p, c->d_flag, c->kfield, c->rfield, st)
-                            : launch_sweep_gen_q19(d, c->g, c->d_coefs, fin, fout, p, c->d_flag, c->kfield, c->rfield, st);
+        return c->dm.q == 9 ? launch_sweep_gen_q9(d, c->g, c->d_coefs, fin, fout, p, c->d_flag, c->kfield, c->rfield,
+                                                  remark3(c), st)
+                            : launch_sweep_gen_q19(d, c->g, c->d_coefs, fin, fout, p, c->d_flag, c->kfield, c->rfield,
+                                                   remark3(c), st);
     return c->dm.q == 9 ? launch_sweep_q9(c->dm, c->g, c->d_coefs, fin, fout, p, c->d_flag, st)
                         : launch_sweep_q19(c->dm, c->g, c->d_coefs, fin, fout, p, c->d_flag, st);
 }
@@ -661,7 +667,7 @@ int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void
     if (!c || !gphi || !psi || !pi) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
-    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources or per-node fields");
+    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipStream_t st = (hipStream_t)stream;
@@ -679,7 +685,7 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
     if (psi_next == psi_out) return fail(LBM_E_INVALID, "psi_next and psi_out must differ");
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
-    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources or per-node fields");
+    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
@@ -695,7 +701,7 @@ int lbm_adjoint_init(lbm_ctx *c, const double *phi0, const void *psi0, const dou
     if (!c || !phi0 || !psi0 || !pi0 || !gphi0) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
-    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources or per-node fields");
+    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipError_t e = launch_adjoint_init_q9(c->dm, c->g, c->d_coefs, phi0, psi0, pi0, gphi0, (hipStream_t)stream);

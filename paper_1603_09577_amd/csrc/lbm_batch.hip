@@ -316,6 +316,10 @@ int lbm_batch_create(const lbm_desc *descs, int count, lbm_batch **out) {
         const int rc = derive_coefs(&d, &prec, &eqr, &src, &kvar, &low, tmp.data(), &cb);
         if (rc != LBM_OK) { delete b; return rc; }
         if (!eqr) { delete b; return api_fail(LBM_E_UNSUPPORTED, "batched instances need equal non-flux rates"); }
+        if (d.flags & LBM_FLAG_REMARK3) {
+            delete b;
+            return api_fail(LBM_E_UNSUPPORTED, "batched instances use the equilibrium of Eq. 3 (no Remark III)");
+        }
         if (d.scheme == LBM_SCHEME_B && src) {
             delete b;
             return api_fail(LBM_E_UNSUPPORTED, "batched instances run Scheme A (Scheme B only without a source)");

@@ -51,7 +51,8 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
 // Scheme B and/or per-node fields: the general kernel (any polynomial length).
 template <int Q, typename TS, typename TC>
 hipError_t sweep_gen_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                           void *p, int *flag, const double *kfield, const double *rfield, hipStream_t st) {
+                           void *p, int *flag, const double *kfield, const double *rfield, bool remark3,
+                           hipStream_t st) {
     using TP = typename HistType<TS>::T;
     const auto *cf = (const Coefs<TC> *)coefs;
     const auto *fi = (const TS *)fin;
@@ -62,7 +63,7 @@ hipError_t sweep_gen_typed(const Dims &dm, const Geom &g, const void *coefs, con
 #define LBM_GEN(E, W, B)                                                                            \
     case (E * 4 + W * 2 + B):                                                                       \
         hipLaunchKernelGGL((k_sweep_gen<Q, TS, TC, E, W, B>), grid, block, 0, st, g, cf, fi, fo, pp, flag, \
-                           kfield, rfield);                                                         \
+                           kfield, rfield, remark3 ? 1 : 0);                                        \
         break;
     switch (code) {
         LBM_GEN(0, 0, 0) LBM_GEN(0, 0, 1) LBM_GEN(0, 1, 0) LBM_GEN(0, 1, 1)

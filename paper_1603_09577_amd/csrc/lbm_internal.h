@@ -99,7 +99,7 @@ inline uint64_t plane_stride(uint64_t n, int q, size_t elem, int pad_req) {
                                   void *fout, void *p, int *flag, hipStream_t st);                      \
     hipError_t launch_sweep_gen_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *fin, \
                                       void *fout, void *p, int *flag, const double *kfield,             \
-                                      const double *rfield, hipStream_t st);                            \
+                                      const double *rfield, bool remark3, hipStream_t st);              \
     hipError_t launch_init_##SFX(const Dims &dm, const Geom &g, const void *coefs, const double *phi0, \
                                  void *f, void *p, const double *rfield, hipStream_t st);               \
     hipError_t launch_phi_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *f,       \

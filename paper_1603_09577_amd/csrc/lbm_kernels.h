@@ -260,12 +260,17 @@ __device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restric
 // Btilde = B', and the source enters as M^-1 (I - S/2) M R_k (Eq. 34).  SRC
 // then stays false (it is the Scheme-A source with its phi history).
 // KF: K0 per node from `kfield` (A per node by Eq. 26).
+// rem3 (uniform across a launch): Remark III, Eq. 36-38.  The equilibrium has
+// C = 0 (the host leaves C out of C-bar) and the source
+// G_k = w_k c_k . (I - A/2) dB/dt / cs^2 (Eq. 37) is added, with dB/dt the
+// difference B(phi(t)) - B(phi(t - 1)) over the last step from the phi history.
 template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT = false,
           bool SB = false, bool KF = false>
 __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__restrict__ cf,
                                            const TS *__restrict__ fin, TS *__restrict__ fout,
                                            typename HistType<TS>::T *p, int *flag, uint32_t n,
-                                           const double *kfield = nullptr, const double *rfield = nullptr) {
+                                           const double *kfield = nullptr, const double *rfield = nullptr,
+                                           bool rem3 = false) {
     using L = Lattice<Q>;
     constexpr int D = L::dim;
     const NodeGeo ng = node_geometry<Q, WALL>(g, n);
@@ -273,7 +278,7 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     TC h[Q];
     gather<Q, WALL, NT>(g, cf, fin, ng, h);
     // history read issued together with the gathers, so its latency overlaps theirs
-    const TC pp_off = SRC ? (TC)p[n] : TC(0);
+    const TC pp_off = (SRC || rem3) ? (TC)p[n] : TC(0);
     TC g0n[6];
     const bool kfon = KF && kfield != nullptr;   // uniform across the launch
     if (kfon) g0_of_field<D>(cf, kfield, n, g0n);
@@ -342,6 +347,21 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
                 Vo[a] = TC(3) * hs * bp;
                 jsh[a] = TC(0.5) * Rx * bp;
             }
+        }
+        if (rem3) {
+            // Remark III: c_k . 3 w_k (I - A/2) (B(phi) - B(phi(t - 1)))
+            const TC pp = cf->phi_ref + pp_off;
+            TC dB[3] = {TC(0), TC(0), TC(0)};
+#pragma unroll
+            for (int a = 0; a < D; ++a) dB[a] = poly<NP>(cf->b[a], phi) - poly<NP>(cf->b[a], pp);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                TC acc = dB[a];
+#pragma unroll
+                for (int b = 0; b < D; ++b) acc -= TC(0.5) * A[sym(a, b)] * dB[b];
+                Vo[a] += TC(3) * acc;
+            }
+            if (!SRC) p[n] = (typename HistType<TS>::T)phio;
         }
         // j - B, with j the first moment of the gathered populations (Scheme B:
         // of f = fbar + R_k / 2, i.e. plus R B' / 2)
@@ -505,6 +525,32 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
         p[n] = (typename HistType<TS>::T)phio;
     }
 
+    if (rem3 && !EQR) {
+        // Remark III: + G_k = 3 w_k c_k . (I - A/2) (B(phi) - B(phi(t - 1)))
+        const TC pp = cf->phi_ref + pp_off;
+        TC dB[3] = {TC(0), TC(0), TC(0)}, gq[3] = {TC(0), TC(0), TC(0)};
+#pragma unroll
+        for (int a = 0; a < D; ++a) dB[a] = poly<NP>(cf->b[a], phi) - poly<NP>(cf->b[a], pp);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            TC acc = dB[a];
+#pragma unroll
+            for (int b = 0; b < D; ++b) acc -= TC(0.5) * A[sym(a, b)] * dB[b];
+            gq[a] = TC(3) * acc;
+        }
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            TC cg = TC(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int c = L::c(k, a);
+                if (c) cg += TC(c) * gq[a];
+            }
+            out[k] += TC(L::w(k)) * cg;
+        }
+        if (!SRC) p[n] = (typename HistType<TS>::T)phio;
+    }
+
     // Mass balance.  Collision conserves sum_k g_k and the Scheme-A source adds
     // exactly Se to it (Eq. 9 sums to R over k), so the rest population takes
     // the remainder.  The map is unchanged in exact arithmetic; in FP32 it
@@ -543,10 +589,11 @@ template <int Q, typename TS, typename TC, bool EQR, bool WALL, bool SB>
 __global__ void __launch_bounds__(kBlock)
 k_sweep_gen(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin,
             TS *__restrict__ fout, typename HistType<TS>::T *p, int *flag, const double *kfield,
-            const double *rfield) {
+            const double *rfield, int remark3) {
     const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
     if (n >= g.N) return;
-    sweep_node<Q, TS, TC, EQR, !SB, true, WALL, 9, false, SB, true>(g, cf, fin, fout, p, flag, n, kfield, rfield);
+    sweep_node<Q, TS, TC, EQR, !SB, true, WALL, 9, false, SB, true>(g, cf, fin, fout, p, flag, n, kfield, rfield,
+                                                                   remark3 != 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,8 +20,9 @@ hipError_t launch_phi_q19(const Dims &dm, const Geom &g, const void *coefs, cons
 }
 
 hipError_t launch_sweep_gen_q19(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                               void *p, int *flag, const double *kfield, const double *rfield, hipStream_t st) {
-    LBM_BY_PREC(sweep_gen_typed, dm, g, coefs, fin, fout, p, flag, kfield, rfield, st)
+                               void *p, int *flag, const double *kfield, const double *rfield, bool remark3,
+                               hipStream_t st) {
+    LBM_BY_PREC(sweep_gen_typed, dm, g, coefs, fin, fout, p, flag, kfield, rfield, remark3, st)
 }
 
 hipError_t launch_recenter_q19(const Dims &dm, const Geom &g, void *coefs, void *f, void *p, double *part,

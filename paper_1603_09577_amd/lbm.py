@@ -21,6 +21,7 @@ PRECISIONS = {"f64": 0, "f32": 1, "f16": 2}
 FLAG_MOMENT_PATH = 1
 FLAG_NO_XCD_REMAP = 2
 FLAG_NO_GRAPH = 4
+FLAG_REMARK3 = 8
 
 # every symbol include/lbm.h declares
 EXPORTS = [
@@ -178,7 +179,7 @@ def desc_from_spec(spec, flags=0):
         for c in range(3):
             d.dten[a][c] = dten[a, c] if a < dten.shape[0] and c < dten.shape[1] else 0.0
             d.k0[a][c] = k0[a, c] if a < k0.shape[0] and c < k0.shape[1] else 0.0
-    d.flags = int(flags | spec.get("flags", 0))
+    d.flags = int(flags | spec.get("flags", 0) | (FLAG_REMARK3 if spec.get("variant") == "remark3" else 0))
     d.plane_pad = int(spec.get("plane_pad", 0))
     return d
 
