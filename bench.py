@@ -393,6 +393,13 @@ def main():
         extra["d3q19_f64"] = d3d
         print(f"# d3q19-256 f32 {d3['mlups']:.0f} / f64 {d3d['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
+        # reversed sweep of the same D3Q19 workload (walls, full K)
+        extra["adjoint_d3q19_f32"] = run_adjoint(torch, lbm, spec3, p3, 40, 4, "adjoint d3q19-256 f32")
+        torch.cuda.empty_cache()
+        extra["adjoint_d3q19_f64"] = run_adjoint(torch, lbm, spec3d, p3, 20, 2, "adjoint d3q19-256 f64")
+        print(f"# adjoint d3q19-256 f32 {extra['adjoint_d3q19_f32']['mlups']:.0f} / "
+              f"f64 {extra['adjoint_d3q19_f64']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
     if "batch" in only:
         extra["batch_f32"] = run_batch(torch, lbm, W, 1000 if args.steps >= 1000 else args.steps)
         print(f"# batch {extra['batch_f32']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)

@@ -238,7 +238,7 @@ int lbm_set_k0(lbm_ctx *ctx, const double k0[9]);
 int lbm_reduce(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev, double out[8],
                void *stream);
 
-/* ---- discrete adjoint (D2Q9, F64 and F32) -------------------------------- *
+/* ---- discrete adjoint (D2Q9 and D3Q19, F64 and F32) ---------------------- *
  * Sweep s maps the state X_s = (f_s, p_s) to X_{s+1}: it gathers g_s from f_s,
  * collides with history p_s and stores f_{s+1}; p_{s+1} = sum_k g_s,k.
  * With L a function of phi(T) = sum_k g_T,k, the adjoint variables are
@@ -247,7 +247,9 @@ int lbm_reduce(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev, doubl
  *   pi_s  = dL/dp_s  (FP64 [nz][ny][nx]).
  * psi_s equals the gradient with respect to the pre-collision distributions
  * of step s.  Gradients with respect to K0 accumulate into a per-context FP64
- * accumulator (lbm_adjoint_grad_k0).  Not defined for FP16 storage. */
+ * accumulator (lbm_adjoint_grad_k0).  Not defined for FP16 storage, Scheme B
+ * sources, per-node fields or Remark III (LBM_E_UNSUPPORTED), nor after the
+ * offsets were re-centred (LBM_E_STATE). */
 
 /* psi_T from dL/dphi(T) (FP64 field): psi_T,k = gphi for every k, pi_T = 0;
  * clears the K0 accumulator.  Seed, step and init launch kernels only (no
@@ -267,7 +269,7 @@ int lbm_adjoint_init(lbm_ctx *ctx, const double *phi0_dev, const void *psi0, con
                      double *gphi0_dev, void *stream);
 
 /* Accumulated dL/dK0 (synchronous): out = (xx, xy, yy, xz, yz, zz), the
- * symmetric entries each treated as one parameter. */
+ * symmetric entries each treated as one parameter (D2Q9: the z entries are 0). */
 int lbm_adjoint_grad_k0(lbm_ctx *ctx, double out[6], void *stream);
 
 void lbm_destroy(lbm_ctx *ctx);

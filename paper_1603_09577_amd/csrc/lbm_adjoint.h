@@ -94,10 +94,11 @@ __device__ __forceinline__ TC gbar_scatter(const Coefs<TC> *__restrict__ cf, TC 
     return acc * kd;
 }
 
-// FP64: 4 waves per SIMD at the cost of a few spilled registers measured
-// faster than 3 waves without spills
+// Occupancy: D2Q9 is held at 4 waves per SIMD (it fits 128 registers without
+// spills); D3Q19 keeps 19 populations, their adjoints and the outputs live and
+// is allowed down to 2.
 template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Q == 9 ? 4 : 2, 8)))
 k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fs,
           const typename HistType<TS>::T *__restrict__ ps, const TC *__restrict__ psi_next,
           const double *pi_next, TC *__restrict__ psi_out, double *pi_out, double *__restrict__ gk_part) {

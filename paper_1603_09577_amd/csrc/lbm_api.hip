@@ -665,14 +665,14 @@ int lbm_reduce(lbm_ctx *c, const double *phi, const double *ref, double out[8], 
 
 int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void *stream) {
     if (!c || !gphi || !psi || !pi) return fail(LBM_E_INVALID, "null argument");
-    if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
     if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipStream_t st = (hipStream_t)stream;
     if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
-    hipError_t e = launch_seed_q9(c->dm, c->g, gphi, psi, pi, st);
+    hipError_t e = c->dm.q == 9 ? launch_seed_q9(c->dm, c->g, gphi, psi, pi, st)
+                                : launch_seed_q19(c->dm, c->g, gphi, psi, pi, st);
     if (e == hipSuccess) e = launch_zero(c->d_adj_part, c->g.nblocks * kAdjWidth, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint seed");
     return LBM_OK;
@@ -683,15 +683,16 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
     if (!c || !f_s || !p_s || !psi_next || !pi_next || !psi_out || !pi_out)
         return fail(LBM_E_INVALID, "null argument");
     if (psi_next == psi_out) return fail(LBM_E_INVALID, "psi_next and psi_out must differ");
-    if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
     if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_adjoint_q9(c->dm, c->g, c->d_coefs, f_s, p_s, psi_next, pi_next, psi_out, pi_out,
-                                     c->d_adj_part, st);
+    hipError_t e = c->dm.q == 9 ? launch_adjoint_q9(c->dm, c->g, c->d_coefs, f_s, p_s, psi_next, pi_next, psi_out,
+                                                    pi_out, c->d_adj_part, st)
+                                : launch_adjoint_q19(c->dm, c->g, c->d_coefs, f_s, p_s, psi_next, pi_next, psi_out,
+                                                     pi_out, c->d_adj_part, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel");
     return LBM_OK;
 }
@@ -699,12 +700,13 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
 int lbm_adjoint_init(lbm_ctx *c, const double *phi0, const void *psi0, const double *pi0, double *gphi0,
                      void *stream) {
     if (!c || !phi0 || !psi0 || !pi0 || !gphi0) return fail(LBM_E_INVALID, "null argument");
-    if (c->dm.q != 9) return fail(LBM_E_UNSUPPORTED, "the adjoint is built for D2Q9 only");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
     if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
-    hipError_t e = launch_adjoint_init_q9(c->dm, c->g, c->d_coefs, phi0, psi0, pi0, gphi0, (hipStream_t)stream);
+    hipError_t e = c->dm.q == 9
+                       ? launch_adjoint_init_q9(c->dm, c->g, c->d_coefs, phi0, psi0, pi0, gphi0, (hipStream_t)stream)
+                       : launch_adjoint_init_q19(c->dm, c->g, c->d_coefs, phi0, psi0, pi0, gphi0, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint init kernel");
     return LBM_OK;
 }

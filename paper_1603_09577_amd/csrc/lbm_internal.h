@@ -105,20 +105,19 @@ inline uint64_t plane_stride(uint64_t n, int q, size_t elem, int pad_req) {
     hipError_t launch_phi_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *f,       \
                                 double *phi, const double *rfield, hipStream_t st);                     \
     hipError_t launch_recenter_##SFX(const Dims &dm, const Geom &g, void *coefs, void *f, void *p,     \
-                                     double *part, int nparts, double *shift, hipStream_t st);
+                                     double *part, int nparts, double *shift, hipStream_t st);          \
+    hipError_t launch_adjoint_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *f,   \
+                                    const void *p, const void *psi_next, const double *pi_next,         \
+                                    void *psi_out, double *pi_out, double *gk_part, hipStream_t st);    \
+    hipError_t launch_adjoint_init_##SFX(const Dims &dm, const Geom &g, const void *coefs,             \
+                                         const double *phi0, const void *psi0, const double *pi0,       \
+                                         double *gphi0, hipStream_t st);                                \
+    hipError_t launch_seed_##SFX(const Dims &dm, const Geom &g, const double *gphi, void *psi,         \
+                                 double *pi, hipStream_t st);
 LBM_LAUNCHERS(q9)
 LBM_LAUNCHERS(q19)
 #undef LBM_LAUNCHERS
 
-// The adjoint is built for D2Q9.
-hipError_t launch_adjoint_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f,
-                             const void *p, const void *psi_next, const double *pi_next,
-                             void *psi_out, double *pi_out, double *gk_part, hipStream_t st);
-hipError_t launch_adjoint_init_q9(const Dims &dm, const Geom &g, const void *coefs,
-                                  const double *phi0, const void *psi0, const double *pi0,
-                                  double *gphi0, hipStream_t st);
-hipError_t launch_seed_q9(const Dims &dm, const Geom &g, const double *gphi, void *psi,
-                          double *pi, hipStream_t st);
 hipError_t launch_zero(double *p, uint32_t n, hipStream_t st);
 
 // Generic FP64 reductions (lbm_reduce.hip).

@@ -30,4 +30,21 @@ hipError_t launch_recenter_q19(const Dims &dm, const Geom &g, void *coefs, void 
     LBM_BY_PREC(recenter_typed, dm, g, coefs, f, p, part, nparts, shift, st)
 }
 
+
+hipError_t launch_adjoint_q19(const Dims &dm, const Geom &g, const void *coefs, const void *f, const void *p,
+                              const void *psi_next, const double *pi_next, void *psi_out, double *pi_out,
+                              double *gk_part, hipStream_t st) {
+    LBM_BY_PREC_ADJ(adjoint_typed, dm, g, coefs, f, p, psi_next, pi_next, psi_out, pi_out, gk_part, st)
+}
+
+hipError_t launch_adjoint_init_q19(const Dims &dm, const Geom &g, const void *coefs, const double *phi0,
+                                   const void *psi0, const double *pi0, double *out, hipStream_t st) {
+    LBM_BY_PREC_ADJ(adjoint_init_typed, dm, g, coefs, phi0, psi0, pi0, out, st)
+}
+
+hipError_t launch_seed_q19(const Dims &dm, const Geom &g, const double *gphi, void *psi, double *pi,
+                           hipStream_t st) {
+    LBM_BY_PREC_ADJ(seed_typed, dm, g, gphi, psi, pi, st)
+}
+
 }  // namespace lbm

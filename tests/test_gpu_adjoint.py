@@ -24,9 +24,26 @@ def say(msg):
     sys.stdout.flush()
 
 
+KEYS2 = ("xx", "xy", "yy")
+KEYS3 = ("xx", "xy", "yy", "xz", "yz", "zz")
+IDX = {"xx": (0, 0), "xy": (0, 1), "yy": (1, 1), "xz": (0, 2), "yz": (1, 2), "zz": (2, 2)}
+
+
+def keys_of(spec):
+    return KEYS2 if spec["lattice"] == 9 else KEYS3
+
+
 def k0_entries(spec):
     k = np.asarray(spec["k0"])
-    return np.array([k[0, 0], k[0, 1], k[1, 1]])
+    return np.array([k[IDX[n]] for n in keys_of(spec)])
+
+
+def k0_matrix(spec, kent):
+    km = np.asarray(spec["k0"], dtype=np.float64).copy()
+    for n, v in zip(keys_of(spec), kent):
+        a, b = IDX[n]
+        km[a, b] = km[b, a] = v
+    return km
 
 
 def gpu_gradient(spec, phi0, target, T, seg=None, flags=0):
@@ -46,7 +63,7 @@ def gpu_gradient(spec, phi0, target, T, seg=None, flags=0):
 def oracle_gradient(spec, phi0, target, T):
     p = orc.params_from_spec(spec)
     phiT, g0, gk = orc.gradient(p, phi0, T, lambda ph: ph - target)
-    return 0.5 * ((phiT - target) ** 2).sum(), g0, np.array([gk["xx"], gk["xy"], gk["yy"]])
+    return 0.5 * ((phiT - target) ** 2).sum(), g0, np.array([gk[n] for n in keys_of(spec)])
 
 
 def rel(a, b):
@@ -115,9 +132,7 @@ def _fd_check(spec, phi0, target, T, ndir=16, seed=7, eps=2e-3):
     k0 = np.asarray(spec["k0"], dtype=np.float64)
 
     def run(ph0, kent):
-        km = k0.copy()
-        km[0, 0], km[0, 1], km[1, 0], km[1, 1] = kent[0], kent[1], kent[1], kent[2]
-        sim.set_k0(km)
+        sim.set_k0(k0_matrix(spec, kent))
         sim.init(ph0)
         sim.step(T)
         return sim.phi().clone()
@@ -134,7 +149,7 @@ def _fd_check(spec, phi0, target, T, ndir=16, seed=7, eps=2e-3):
     for i in range(ndir):
         vp = rng.standard_normal(phi0.shape)
         vp /= np.linalg.norm(vp)
-        vk = rng.standard_normal(3)
+        vk = rng.standard_normal(len(ke))
         vk /= np.linalg.norm(vk)
         vk *= np.linalg.norm(ke)
         vpt = torch.tensor(vp, device="cuda")
@@ -162,4 +177,49 @@ def test_adjoint_finite_differences_c5b_reduced():
     spec, phi0, target, T = W.adjoint_2d_sourcefree(256, nsteps=800)
     say(f"[gpu adjoint] adjoint2d source-free 256 FD, T={T}")
     worst = _fd_check(spec, phi0, target, T)
+    assert worst <= 1e-6
+
+
+def _d3q19_adjoint_spec(n, precision="f64"):
+    """D3Q19 with walls, nonlinear B, K(phi) and a Scheme-A source: every term
+    of the reversed sweep in three dimensions."""
+    spec = W.spec_d3q19_aniso(n, precision=precision, phi_ref=0.5)
+    spec["phi_wall"] = [[0, 0], [0, 0], [0.45, 0.6]]
+    spec["b"] = [[0.0, 0.03, 0.04], [0.0, -0.02, 0.03], [0.0, 0.01, -0.02]]
+    spec["kpoly"] = [1.0, 0.0, 0.5]
+    spec["rpoly"] = [0.0, 2e-3, -2e-3]
+    return spec
+
+
+def test_adjoint_d3q19_matches_oracle():
+    n = (9, 7, 11)
+    spec = _d3q19_adjoint_spec(n)
+    rng = np.random.default_rng(27)
+    shape = n[::-1]
+    phi0 = 0.5 + 0.1 * rng.uniform(-1, 1, shape)
+    target = 0.5 + 0.1 * rng.uniform(-1, 1, shape)
+    T = 17
+    say(f"[gpu adjoint] D3Q19 walls {n} T={T}")
+    lg, gg, kg = gpu_gradient(spec, phi0, target, T, seg=5)
+    lo, go, ko = oracle_gradient(spec, phi0, target, T)
+    say(f"    loss {lg:.15e} / {lo:.15e}  dphi0 {rel(gg, go):.2e}  dK0 {rel(kg, ko):.2e}")
+    assert abs(lg - lo) <= 1e-12 * abs(lo)
+    assert rel(gg, go) <= 1e-10 and rel(kg, ko) <= 1e-10
+    say("[gpu adjoint] D3Q19 fp32 vs fp64 oracle")
+    lg32, gg32, kg32 = gpu_gradient(_d3q19_adjoint_spec(n, "f32"), phi0, target, T)
+    say(f"    fp32 adjoint: dphi0 rel {rel(gg32, go):.2e}  dK0 rel {rel(kg32, ko):.2e}")
+    assert rel(gg32, go) <= 1e-4 and rel(kg32, ko) <= 1e-3
+
+
+def test_adjoint_d3q19_finite_differences():
+    """48^3 with walls, 120 steps: adjoint vs central differences of the GPU
+    forward run along 8 joint (phi0, K0) directions, FP64."""
+    n = (48, 48, 48)
+    spec = _d3q19_adjoint_spec(n)
+    shape = n[::-1]
+    rng = np.random.default_rng(28)
+    phi0 = 0.5 + 0.1 * rng.uniform(-1, 1, shape)
+    target = 0.5 + 0.1 * rng.uniform(-1, 1, shape)
+    say("[gpu adjoint] D3Q19 48^3 FD, T=120")
+    worst = _fd_check(spec, phi0, target, 120, ndir=8, seed=29)
     assert worst <= 1e-6

@@ -596,6 +596,37 @@ def test_adjoint_gradient_vs_finite_differences():
         assert abs(fd - gk[name]) < 1e-6 * max(abs(fd), 1e-12), (name, fd, gk[name])
 
 
+
+def test_adjoint_gradient_vs_finite_differences_d3q19():
+    """The same on D3Q19 with walls: dL/dphi0 and all six K0 entries."""
+    spec = _adjoint_problem(19)
+    rng = np.random.default_rng(8)
+    shape = (5, 3, 4)
+    phi0 = 0.5 + 0.1 * rng.uniform(-1, 1, shape)
+    target = 0.5 + 0.1 * rng.uniform(-1, 1, shape)
+    T = 8
+    p = orc.params_from_spec(spec)
+    phiT, gphi0, gk = orc.gradient(p, phi0, T, lambda ph: ph - target)
+
+    def loss(ph0, k0):
+        sp = dict(spec)
+        sp["k0"] = k0.tolist()
+        ph, _ = orc.run(orc.params_from_spec(sp), ph0, T)
+        return 0.5 * ((ph - target) ** 2).sum()
+
+    k0 = np.asarray(spec["k0"])
+    v = rng.standard_normal(shape)
+    h = 1e-6
+    fd = (loss(phi0 + h * v, k0) - loss(phi0 - h * v, k0)) / (2 * h)
+    assert abs(fd - (gphi0 * v).sum()) < 1e-7 * abs(fd)
+    for name, (a, b) in {"xx": (0, 0), "xy": (0, 1), "yy": (1, 1), "xz": (0, 2), "yz": (1, 2),
+                         "zz": (2, 2)}.items():
+        dk = np.zeros((3, 3))
+        dk[a, b] = dk[b, a] = 1.0
+        h = 1e-7
+        fd = (loss(phi0, k0 + h * dk) - loss(phi0, k0 - h * dk)) / (2 * h)
+        assert abs(fd - gk[name]) < 1e-6 * max(abs(fd), 1e-12), (name, fd, gk[name])
+
 def test_gaussian_hill_printed_gre_full_size():
     """Sec. 3.4 at the paper's own size: isotropic K = 1e-3 I, u = (0.01, 0.01),
     sigma0 = 0.01 on the periodic [-1, 1]^2 with 400 distinct nodes per axis
