@@ -209,6 +209,19 @@ int lbm_recenter(lbm_ctx *ctx, void *stream);
  * against its mean). */
 int lbm_set_recenter(lbm_ctx *ctx, int every);
 
+/* New Dirichlet values of the two walls (anti-bounce-back, half a link beyond
+ * the first and last node of the wall axis; Sec. 3.6), for time-dependent
+ * walls.  Asynchronous on `stream` (one small kernel rewrites the wall terms
+ * in the device constants, so it may sit between captured graphs).
+ * Timing: the state after the sweep from t to t + 1 holds the post-collision
+ * values of step t, and the next gather (the next sweep, or lbm_get_phi)
+ * streams them with the wall values set at that moment.  So a schedule
+ * phi_w(t) used in the streaming of step t is followed by setting phi_w(t)
+ * right after the sweep of step t.  The first gather after lbm_init only
+ * undoes the initial layout and must see the wall values lbm_init saw.
+ * Errors: LBM_E_INVALID (no walls, non-finite values). */
+int lbm_set_phi_wall(lbm_ctx *ctx, double phi_lo, double phi_hi, void *stream);
+
 /* Per-node fields, read by lbm_init, lbm_step, lbm_sweep and lbm_get_phi
  * (device pointers owned by the caller; NULL unbinds):
  *  - k0_field: FP64, per node (2-D) xx, yy, xy or (3-D) xx, yy, zz, xy, yz, xz,

@@ -125,6 +125,24 @@ double polyval(const double *c, int n, double x) {
     return acc;
 }
 
+// e+_k(pw): the even part of Eq. 3 at a wall value, from the C-bar
+// polynomials already in m (so Remark III's C = 0 carries over).
+double wall_even(const HostModel &m, const Dims &dm, double pw, int k) {
+    const int dim = dm.q == 9 ? 2 : 3;
+    double E[6];
+    for (int i = 0; i < 6; ++i) E[i] = polyval(m.cb[i], kMaxC, pw) - (i < dim ? pw / 3.0 : 0.0);
+    if (dim == 2) E[2] = 0.0;
+    const double tr3 = (E[0] + E[1] + E[2]) / 3.0;
+    int c[3];
+    double w;
+    if (dm.q == 9) { c[0] = Lattice<9>::cx(k); c[1] = Lattice<9>::cy(k); c[2] = 0; w = Lattice<9>::w(k); }
+    else { c[0] = Lattice<19>::cx(k); c[1] = Lattice<19>::cy(k); c[2] = Lattice<19>::cz(k); w = Lattice<19>::w(k); }
+    double cc = -tr3;
+    for (int a = 0; a < 3; ++a) cc += c[a] * c[a] * E[a];
+    cc += 2.0 * (c[0] * c[1] * E[3] + c[1] * c[2] * E[4] + c[0] * c[2] * E[5]);
+    return w * (pw + 4.5 * cc);
+}
+
 // All derived constants of a description (FP64).
 void derive(const lbm_desc &d, const Dims &dm, HostModel &m) {
     std::memset(&m, 0, sizeof(m));
@@ -176,27 +194,13 @@ void derive(const lbm_desc &d, const Dims &dm, HostModel &m) {
     // anti-bounce-back constants: 2 (e+_k(phi_w) - w_k phi_ref), e+ the even
     // part of Eq. 3 at the wall value
     const int la = dim - 1;
-    for (int side = 0; side < 2; ++side) {
-        const double pw = d.phi_wall[la][side];
-        double Cb[6];
-        for (int i = 0; i < 6; ++i) Cb[i] = polyval(m.cb[i], kMaxC, pw);
-        double E[6];
-        for (int i = 0; i < 6; ++i) E[i] = Cb[i] - (i < dim ? pw / 3.0 : 0.0);
-        if (dim == 2) E[2] = 0.0;
-        const double tr3 = (E[0] + E[1] + E[2]) / 3.0;
+    for (int side = 0; side < 2; ++side)
         for (int k = 0; k < dm.q; ++k) {
-            int c[3];
-            double w;
-            if (dm.q == 9) { c[0] = Lattice<9>::cx(k); c[1] = Lattice<9>::cy(k); c[2] = 0; w = Lattice<9>::w(k); }
-            else { c[0] = Lattice<19>::cx(k); c[1] = Lattice<19>::cy(k); c[2] = Lattice<19>::cz(k); w = Lattice<19>::w(k); }
-            double cc = -tr3;
-            for (int a = 0; a < 3; ++a) cc += c[a] * c[a] * E[a];
-            cc += 2.0 * (c[0] * c[1] * E[3] + c[1] * c[2] * E[4] + c[0] * c[2] * E[5]);
-            const double ep = w * (pw + 4.5 * cc);
+            const double w = dm.q == 9 ? Lattice<9>::w(k) : Lattice<19>::w(k);
+            const double ep = wall_even(m, dm, d.phi_wall[la][side], k);
             m.ewp[side][k] = 2.0 * ep;
             m.ew[side][k] = 2.0 * (ep - w * d.phi_ref);
         }
-    }
     for (int i = 0; i < 19; ++i) m.s[i] = (i < dm.q) ? d.s[i] : 0.0;
     m.srate = d.s[1];
     m.phi_ref = d.phi_ref;
@@ -285,6 +289,22 @@ int validate(const lbm_desc *d, Dims &dm) {
     dm.wall = wall;
     dm.sb = d->scheme == LBM_SCHEME_B;
     return LBM_OK;
+}
+
+// Derive and pack the constants of c->desc into c->host_coefs (no upload).
+void pack_host(lbm_ctx *c, HostModel &m) {
+    derive(c->desc, c->dm, m);
+    if (c->dm.prec == 0) {
+        Coefs<double> cf;
+        pack(m, cf);
+        std::memcpy(c->host_coefs, &cf, sizeof(cf));
+        c->coef_bytes = sizeof(cf);
+    } else {
+        Coefs<float> cf;
+        pack(m, cf);
+        std::memcpy(c->host_coefs, &cf, sizeof(cf));
+        c->coef_bytes = sizeof(cf);
+    }
 }
 
 int upload_coefs(lbm_ctx *c) {
@@ -576,6 +596,24 @@ int lbm_set_recenter(lbm_ctx *c, int every) {
     if (!c) return fail(LBM_E_INVALID, "null context");
     if (every < 0) return fail(LBM_E_INVALID, "negative re-centring interval");
     c->recenter_every = every;
+    return LBM_OK;
+}
+
+int lbm_set_phi_wall(lbm_ctx *c, double phi_lo, double phi_hi, void *stream) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (!c->dm.wall) return fail(LBM_E_INVALID, "the description has no walls");
+    if (!std::isfinite(phi_lo) || !std::isfinite(phi_hi)) return fail(LBM_E_INVALID, "non-finite wall value");
+    const int la = (c->dm.q == 9 ? 2 : 3) - 1;
+    c->desc.phi_wall[la][0] = phi_lo;
+    c->desc.phi_wall[la][1] = phi_hi;
+    HostModel m;
+    pack_host(c, m);   // the host copy (restored by lbm_init) carries the new values too
+    double ewp[2 * 19];
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < 19; ++k) ewp[s * 19 + k] = m.ewp[s][k];
+    hipError_t e = c->dm.q == 9 ? launch_set_wall_q9(c->dm, c->d_coefs, ewp, (hipStream_t)stream)
+                                : launch_set_wall_q19(c->dm, c->d_coefs, ewp, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "wall kernel");
     return LBM_OK;
 }
 

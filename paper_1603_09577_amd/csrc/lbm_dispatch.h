@@ -177,6 +177,15 @@ hipError_t recenter_typed(const Dims &dm, const Geom &g, void *coefs, void *f, v
     return hipGetLastError();
 }
 
+template <int Q, typename TS, typename TC>
+hipError_t set_wall_typed(const Dims &, void *coefs, const double *ewp, hipStream_t st) {
+    WallTerms w;
+    for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < 19; ++k) w.ewp[s][k] = ewp[s * 19 + k];
+    hipLaunchKernelGGL((k_set_wall<Q, TC>), dim3(1), dim3(64), 0, st, (Coefs<TC> *)coefs, w);
+    return hipGetLastError();
+}
+
 inline hipError_t zero_doubles(double *p, uint32_t n, hipStream_t st) {
     const uint32_t grid = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_zero, dim3(grid < 1024 ? grid : 1024), dim3(kBlock), 0, st, p, n);

@@ -113,7 +113,8 @@ inline uint64_t plane_stride(uint64_t n, int q, size_t elem, int pad_req) {
                                          const double *phi0, const void *psi0, const double *pi0,       \
                                          double *gphi0, hipStream_t st);                                \
     hipError_t launch_seed_##SFX(const Dims &dm, const Geom &g, const double *gphi, void *psi,         \
-                                 double *pi, hipStream_t st);
+                                 double *pi, hipStream_t st);                                           \
+    hipError_t launch_set_wall_##SFX(const Dims &dm, void *coefs, const double *ewp, hipStream_t st);
 LBM_LAUNCHERS(q9)
 LBM_LAUNCHERS(q19)
 #undef LBM_LAUNCHERS

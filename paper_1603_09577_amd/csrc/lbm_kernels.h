@@ -679,6 +679,26 @@ k_phi(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
 }
 
 // ---------------------------------------------------------------------------
+// Anti-bounce-back wall terms rewritten on the device (time-dependent wall
+// values): 2 e+_k(phi_w) for both walls arrive as a kernel argument, and the
+// stored offset form 2 e+_k - 2 w_k phi_ref uses the phi_ref on the device.
+// ---------------------------------------------------------------------------
+struct WallTerms {
+    double ewp[2][19];
+};
+
+template <int Q, typename TC>
+__global__ void __launch_bounds__(64) k_set_wall(Coefs<TC> *cf, WallTerms w) {
+    using L = Lattice<Q>;
+    const int t = threadIdx.x;
+    if (t < 2 * Q) {
+        const int side = t / Q, k = t % Q;
+        cf->ewp[side][k] = (TC)w.ewp[side][k];
+        cf->ew[side][k] = (TC)(w.ewp[side][k] - 2.0 * L::w(k) * (double)cf->phi_ref);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Sum of an FP64 value over the 64 lanes of a wave (every lane must be
 // active), returned in every lane.  Inside each row of 16 lanes the DPP quad
 // swaps (lane ^ 1, lane ^ 2) and the half-row and row mirrors pair every

@@ -52,4 +52,9 @@ hipError_t launch_seed_q9(const Dims &dm, const Geom &g, const double *gphi, voi
 
 hipError_t launch_zero(double *p, uint32_t n, hipStream_t st) { return zero_doubles(p, n, st); }
 
+
+hipError_t launch_set_wall_q9(const Dims &dm, void *coefs, const double *ewp, hipStream_t st) {
+    LBM_BY_PREC(set_wall_typed, dm, coefs, ewp, st)
+}
+
 }  // namespace lbm

@@ -47,4 +47,9 @@ hipError_t launch_seed_q19(const Dims &dm, const Geom &g, const double *gphi, vo
     LBM_BY_PREC_ADJ(seed_typed, dm, g, gphi, psi, pi, st)
 }
 
+
+hipError_t launch_set_wall_q19(const Dims &dm, void *coefs, const double *ewp, hipStream_t st) {
+    LBM_BY_PREC(set_wall_typed, dm, coefs, ewp, st)
+}
+
 }  // namespace lbm

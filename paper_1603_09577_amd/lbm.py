@@ -32,7 +32,7 @@ EXPORTS = [
     "lbm_batch_create", "lbm_batch_layout", "lbm_batch_instance", "lbm_batch_init",
     "lbm_batch_step", "lbm_batch_get_phi", "lbm_batch_tune", "lbm_batch_set_shape",
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
-    "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields",
+    "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields", "lbm_set_phi_wall",
 ]
 
 
@@ -123,6 +123,7 @@ def load():
         "lbm_recenter": ([_VP, _VP], ctypes.c_int),
         "lbm_set_recenter": ([_VP, ctypes.c_int], ctypes.c_int),
         "lbm_set_fields": ([_VP, _VP, _VP], ctypes.c_int),
+        "lbm_set_phi_wall": ([_VP, ctypes.c_double, ctypes.c_double, _VP], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -291,6 +292,10 @@ class Lbm:
     def set_recenter(self, every):
         """Re-centre inside step() every `every` steps (0 = never)."""
         _check(self.lib.lbm_set_recenter(self.ctx, int(every)))
+
+    def set_phi_wall(self, lo, hi, stream=None):
+        """New Dirichlet values of the two walls, used by the next gather."""
+        _check(self.lib.lbm_set_phi_wall(self.ctx, float(lo), float(hi), _stream(stream)))
 
     def set_fields(self, k0_field=None, r_field=None):
         """Bind per-node fields (FP64 device tensors, kept alive here): K0(x) as
