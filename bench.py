@@ -5,8 +5,13 @@
 Headline workload: D2Q9 MRT, nonlinear anisotropic CDE with the Scheme-A
 source on a periodic 1024 x 1024 grid (B = 0.5 phi^2 (1, 1),
 K = K0 (1 + phi^2), R = 0.1 phi (1 - phi), phi0 = 0.5 + 0.1 U[-1, 1) seed 2),
-distributions stored as FP32 offsets.  One step = one fused sweep over the
-grid.  The same run in FP64 storage, the reversed (adjoint) sweep on the
+distributions stored as FP32 offsets.  One step = one time step of every
+node: one fused sweep, or half of a pass that runs two time steps (the
+autotuner's choice where it is faster; the results are bit-identical).  The
+roofline object describes the kernel launched, with that kernel's algorithmic
+bytes (a two-step pass reads and writes the state once for two updates);
+single sweeps are reported beside it.  The same run in FP64 storage, the
+reversed (adjoint) sweep on the
 512 x 512 adjoint workload, the D3Q19 sweep on 256^3 with walls, a plain copy
 kernel (practical HBM ceiling) and the CPU oracle on a bounded sample are
 reported beside it.  Inputs are synthetic and resident in HBM before timing.
@@ -83,9 +88,15 @@ def time_steps(torch, sim, steps, warmup):
     return e0.elapsed_time(e1) / 1e3 / steps, wall
 
 
-def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True):
+def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_step=None):
+    """Time `steps` sweeps.  With tune, the launch shape is the autotuner's
+    (which may pick two time steps per pass); two_step forces that choice."""
     sim = lbm.Lbm(spec).init(phi0)
     rep = sim.tune(reps=20).splitlines()[-1] if tune else "untuned"
+    if two_step is not None:
+        sim.set_two_step(two_step)
+        rep += f"; two steps per pass forced {'on' if two_step else 'off'}"
+    two = (" two 1" in rep) if two_step is None else bool(two_step)
     per, wall = time_steps(torch, sim, steps, warmup)
     N = sim.N
     prec = spec.get("precision", "f64")
@@ -93,10 +104,17 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True):
     bpn = bytes_per_node(sim.q, prec, src)
     out = {
         "label": label, "nodes": N, "steps": steps, "ms_per_step": per * 1e3,
-        "mlups": N / per / 1e6, "bytes_per_node": bpn,
-        "achieved_gbs": bpn * N / per / 1e9, "wall_s": wall, "tuner": rep,
+        "mlups": N / per / 1e6, "bytes_per_node": bpn, "two_step": two,
+        "wall_s": wall, "tuner": rep,
     }
+    # algorithmic bytes of the launched kernel: a single sweep reads and writes
+    # the state once per step; a two-step pass once per two steps
+    launch_bytes = bpn * N
+    launch_s = 2 * per if two else per
+    out["achieved_gbs"] = launch_bytes / launch_s / 1e9
     out["hbm_frac"] = out["achieved_gbs"] / PEAK_HBM_GBS
+    # per node update at the single-sweep bytes (the HBM roofline of one sweep per step)
+    out["per_update_hbm_frac"] = bpn * N / per / 1e9 / PEAK_HBM_GBS
     phi = sim.phi()
     r = sim.reduce(phi)
     out["nonfinite"] = int(r["nonfinite"])
@@ -227,6 +245,10 @@ PROFILE_COMMANDS = {
 
 # workload label -> (kernel name prefix in the trace, algorithmic bytes per launch)
 PROFILED = {
+    "nonlinear2d-1024 f32 two-step": ("k_sweep2<float, float, true, true, 4, 14>",
+                                      bytes_per_node(9, "f32", True) * 1024 * 1024),
+    "nonlinear2d-1024 f64 two-step": ("k_sweep2<double, double, true, true, 4, 6>",
+                                      bytes_per_node(9, "f64", True) * 1024 * 1024),
     "nonlinear2d-1024 f32": ("k_sweep<9, float, float, true, true, true, false, 4, false>",
                              bytes_per_node(9, "f32", True) * 1024 * 1024),
     "nonlinear2d-1024 f64": ("k_sweep<9, double, double, true, true, true, false, 4, false>",
@@ -360,6 +382,8 @@ def main():
     spec64, _, _ = W.nonlinear_2d(1024, precision="f64")
 
     head, sim32, phi32 = run_forward(torch, lbm, spec32, phi0, K, Wm, "nonlinear2d-1024 f32")
+    single32, s1, _ = run_forward(torch, lbm, spec32, phi0, K, Wm, "nonlinear2d-1024 f32 single", two_step=False)
+    del s1
     print(f"# nonlinear2d-1024 f32: {head['mlups']:.0f} MLUPS, {head['achieved_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
     f64, sim64, phi64 = run_forward(torch, lbm, spec64, phi0, K, Wm, "nonlinear2d-1024 f64")
     print(f"# nonlinear2d-1024 f64: {f64['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
@@ -419,7 +443,7 @@ def main():
         extra["rel_l2_vs_oracle"] = {"steps": ncpu, **errs}
 
     per = head["ms_per_step"] / 1e3
-    traffic = traffic_from_profiles("nonlinear2d-1024 f32")
+    traffic = traffic_from_profiles("nonlinear2d-1024 f32 two-step" if head["two_step"] else "nonlinear2d-1024 f32")
     line = {
         "metric": METRIC,
         "value": head["mlups"],
@@ -442,15 +466,22 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": head["achieved_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": head["hbm_frac"], "traffic": traffic,
-            "kernel": "k_sweep<9, float, float, EQR, SRC, KVAR, !WALL>",
+            "kernel": ("k_sweep2<float, float, SRC, KVAR, NP 4, 14 rows> (two steps per pass)" if head["two_step"]
+                       else "k_sweep<9, float, float, EQR, SRC, KVAR, !WALL>"),
             "bytes_per_node": head["bytes_per_node"], "nodes_per_launch": head["nodes"],
+            "steps_per_launch": 2 if head["two_step"] else 1,
+            "per_update_frac": head["per_update_hbm_frac"],
         },
+        "single_step": {"mlups": single32["mlups"], "ms_per_step": single32["ms_per_step"],
+                        "achieved_gbs": single32["achieved_gbs"], "hbm_frac": single32["hbm_frac"]},
         "cpu_baseline": cpu,
-        "fp64": {"mlups": f64["mlups"], "ms_per_step": f64["ms_per_step"],
-                 "achieved_gbs": f64["achieved_gbs"], "hbm_frac": f64["hbm_frac"]},
+        "fp64": {"mlups": f64["mlups"], "ms_per_step": f64["ms_per_step"], "two_step": f64["two_step"],
+                 "achieved_gbs": f64["achieved_gbs"], "hbm_frac": f64["hbm_frac"],
+                 "per_update_hbm_frac": f64["per_update_hbm_frac"]},
         "fp32_vs_fp64_mlups": head["mlups"] / f64["mlups"],
         "fp32_rel_l2_vs_fp64_after_run": err32,
-        "fp16": {"mlups": f16["mlups"], "ms_per_step": f16["ms_per_step"], "achieved_gbs": f16["achieved_gbs"],
+        "fp16": {"mlups": f16["mlups"], "ms_per_step": f16["ms_per_step"], "two_step": f16["two_step"],
+                 "achieved_gbs": f16["achieved_gbs"],
                  "hbm_frac": f16["hbm_frac"], "rel_l2_vs_fp64_after_run": err16,
                  "storage": "f16 offsets, re-centred every 256 steps"},
         "nonfinite": head["nonfinite"] + f64["nonfinite"] + f16["nonfinite"],

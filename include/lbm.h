@@ -181,10 +181,26 @@ int lbm_set_nontemporal(lbm_ctx *ctx, int on);
  * 1, 2, 4, 8, 16 workgroup blocks, with and without non-temporal accesses,
  * and with the XCD-aware block order (one contiguous slab per XCD) or the
  * hardware's round-robin order (unless LBM_FLAG_NO_XCD_REMAP pins the
- * latter); keeps the fastest, writes the timings into `report` (may be NULL)
- * and re-initialises the state from the phi0 given to lbm_init (step counter
+ * latter), and, where allowed, two time steps per pass (lbm_set_two_step);
+ * keeps the fastest, writes the timings into `report` (may be NULL) and
+ * re-initialises the state from the phi0 given to lbm_init (step counter
  * back to 0; phi0 must still be valid). */
 int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_len);
+
+/* Two time steps per pass inside lbm_step (D2Q9, periodic axes, equal
+ * non-flux rates, nx >= 64, ny >= 16 (FP64: 8)).  A workgroup runs step t on a
+ * tile with a one-node halo, keeps the post-collision populations in LDS
+ * (rounded to the storage type as a store would round them), runs step t + 1
+ * on the tile and stores only that result: every update is the single-sweep
+ * arithmetic on the same inputs, so results equal single sweeps bit for bit,
+ * while the state crosses HBM once per two steps.  Passes run in pairs (four
+ * steps) through a second phi history buffer owned by the context, so state
+ * and history end in the same buffers as after single sweeps; remaining steps
+ * use single sweeps.  On by default where it applies (lbm_tune times it
+ * against single sweeps); not used with a divergence check, Scheme B sources,
+ * per-node fields or Remark III.
+ * Errors: LBM_E_UNSUPPORTED when the run does not qualify. */
+int lbm_set_two_step(lbm_ctx *ctx, int on);
 
 /* Divergence check every `every` steps inside lbm_step (0 = off). */
 int lbm_set_check(lbm_ctx *ctx, int every);

@@ -60,6 +60,10 @@ struct lbm_ctx {
     bool recentered = false;  // phi_ref on the device differs from the description's
     // per-node fields (caller-owned, FP64): K0(x) and the external source R(x, t)
     const double *kfield = nullptr, *rfield = nullptr;
+    // two time steps per pass (D2Q9 periodic equal-rate runs): a second phi
+    // history buffer owned by the context, and whether the path is on
+    void *p2 = nullptr;
+    bool two_ok = false, two = false;
     bool bound = false;
     // graphs of kGraphSteps sweeps starting from buffer 0 / 1, captured on an
     // internal stream and launched on the caller's stream
@@ -338,6 +342,18 @@ bool remark3(const lbm_ctx *c) { return (c->desc.flags & LBM_FLAG_REMARK3) != 0;
 
 bool general_path(const lbm_ctx *c) { return c->kfield || eff_dims(c).sb || remark3(c); }
 
+bool two_active(const lbm_ctx *c) { return c->two && c->two_ok && !general_path(c) && c->check_every == 0; }
+
+// Four steps as two passes of two steps each: f[start] -> f[start ^ 1] with the
+// history p -> p2, then back; state and history end where four single sweeps
+// would leave them.
+hipError_t sweep_pair(lbm_ctx *c, int start, hipStream_t st) {
+    hipError_t e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, c->p2, c->d_flag, st);
+    if (e == hipSuccess)
+        e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], c->p2, c->p, c->d_flag, st);
+    return e;
+}
+
 hipError_t sweep(lbm_ctx *c, const void *fin, void *fout, void *p, hipStream_t st) {
     const Dims d = eff_dims(c);
     if (general_path(c))
@@ -363,9 +379,13 @@ hipError_t make_graph(lbm_ctx *c, int start) {
     if (e != hipSuccess) return e;
     int cur = start;
     hipError_t le = hipSuccess;
-    for (int i = 0; i < kGraphSteps && le == hipSuccess; ++i) {
-        le = sweep(c, c->f[cur], c->f[cur ^ 1], c->p, c->cap);
-        cur ^= 1;
+    if (two_active(c)) {
+        for (int i = 0; i < kGraphSteps / 4 && le == hipSuccess; ++i) le = sweep_pair(c, start, c->cap);
+    } else {
+        for (int i = 0; i < kGraphSteps && le == hipSuccess; ++i) {
+            le = sweep(c, c->f[cur], c->f[cur ^ 1], c->p, c->cap);
+            cur ^= 1;
+        }
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(c->cap, &graph);
@@ -404,6 +424,12 @@ int advance(lbm_ctx *c, int nsteps, hipStream_t st) {
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
         c->t += kGraphSteps;
         nsteps -= kGraphSteps;
+    }
+    while (two_active(c) && nsteps >= 4) {
+        hipError_t e = sweep_pair(c, c->cur, st);
+        if (e != hipSuccess) return hip_fail(e, "two-step sweep kernel");
+        c->t += 4;
+        nsteps -= 4;
     }
     for (int i = 0; i < nsteps; ++i) {
         hipError_t e = sweep(c, c->f[c->cur], c->f[c->cur ^ 1], c->p, st);
@@ -493,6 +519,8 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
         c->dm.nt = bytes > 256.0 * 1024 * 1024;
         if (c->dm.nt) g.remap = 0;
     }
+    c->two_ok = dm.q == 9 && !dm.wall && dm.eqr && desc->nx >= 64 && desc->ny >= two_step_rows_of(dm.prec) + 2;
+    c->two = c->two_ok;   // on by default where it applies (bit-identical; lbm_tune re-decides)
     hipError_t e = hipMalloc(&c->d_coefs, sizeof(Coefs<double>));
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipMalloc(coefficients)"); }
     const size_t scratch = 256 + sizeof(double) * (size_t)(kRedParts * 8 + 8 + kMaxAdjParts * kAdjWidth + 16);
@@ -510,6 +538,10 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     c->recenter_every = (dm.prec == 2 && dm.src) ? kRecenterF16 : 0;
     e = hipMemset(c->d_scratch, 0, scratch);
     if (e != hipSuccess) { lbm_destroy(c); return hip_fail(e, "hipMemset(scratch)"); }
+    if (c->two_ok) {
+        e = hipMalloc(&c->p2, round256((size_t)g.N * hist_size(dm.prec)));
+        if (e != hipSuccess) { lbm_destroy(c); return hip_fail(e, "hipMalloc(second history)"); }
+    }
     rc = upload_coefs(c);
     if (rc != LBM_OK) { lbm_destroy(c); return rc; }
     *out = c;
@@ -522,6 +554,7 @@ void lbm_destroy(lbm_ctx *c) {
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->d_coefs) (void)hipFree(c->d_coefs);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
+    if (c->p2) (void)hipFree(c->p2);
     delete c;
 }
 
@@ -589,6 +622,16 @@ int lbm_recenter(lbm_ctx *c, void *stream) {
     if (!c->bound) return fail(LBM_E_STATE, "lbm_init has not been called");
     hipError_t e = recenter(c, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "re-centring kernels");
+    return LBM_OK;
+}
+
+int lbm_set_two_step(lbm_ctx *c, int on) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (on && !c->two_ok)
+        return fail(LBM_E_UNSUPPORTED, "two steps per pass need D2Q9, periodic axes, equal non-flux rates and a grid "
+                                       "of at least 64 x (tile rows + 2)");
+    if ((on != 0) != c->two) drop_graphs(c);
+    c->two = on != 0;
     return LBM_OK;
 }
 
@@ -820,14 +863,40 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
         rep += line;
         if (ms < best) { best = ms; best_chunk = ch; best_nt = c->dm.nt; best_remap = c->g.remap; }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // two steps per pass: time pairs of passes (four steps), per step
+    bool best_two = false;
     c->g.chunk = (uint32_t)best_chunk;
     c->dm.nt = best_nt;
+    if (c->two_ok && !general_path(c)) {
+        const int pair_reps = std::max(1, reps / 4);
+        for (int ri = 0; ri < remaps; ++ri) {
+            c->g.remap = (remaps == 2 && ri == 0) ? 1u : 0u;
+            hipError_t e = sweep_pair(c, c->cur, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < pair_reps && e == hipSuccess; ++r) e = sweep_pair(c, c->cur, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+                return hip_fail(e, "tuning two-step sweep");
+            }
+            ms /= 4 * pair_reps;
+            char line[96];
+            std::snprintf(line, sizeof(line), "two steps per pass remap %u: %.4f ms per step\n", c->g.remap, ms);
+            rep += line;
+            if (ms < best) { best = ms; best_two = true; best_remap = c->g.remap; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     c->g.remap = best_remap;
+    c->two = best_two;
     drop_graphs(c);
-    char line[96];
-    std::snprintf(line, sizeof(line), "chosen chunk %d nt %d remap %u (%.4f ms)", best_chunk, (int)best_nt, best_remap, best);
+    char line[128];
+    std::snprintf(line, sizeof(line), "chosen chunk %d nt %d remap %u two %d (%.4f ms)", best_chunk, (int)best_nt,
+                  best_remap, (int)best_two, best);
     rep += line;
     if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
     // the history buffer was overwritten by the trial sweeps: restart from phi0

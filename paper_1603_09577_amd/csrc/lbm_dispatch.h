@@ -48,6 +48,39 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
     return hipGetLastError();
 }
 
+// Two steps per pass (D2Q9, periodic, equal rates): tile height by storage
+// size (the LDS tile is 9 x (TH + 2) x 64 values).
+template <typename TS>
+constexpr int two_step_rows() { return sizeof(TS) == 8 ? 6 : 14; }
+
+template <int Q, typename TS, typename TC>
+hipError_t sweep2_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                        const void *pin, void *pout, int *flag, hipStream_t st) {
+    if (Q != 9 || !dm.eqr || dm.wall) return hipErrorNotSupported;
+    using TP = typename HistType<TS>::T;
+    constexpr int TH = two_step_rows<TS>();
+    const auto *cf = (const Coefs<TC> *)coefs;
+    const uint32_t tiles_x = (g.nx + 61) / 62, tiles_y = (g.ny + TH - 1) / TH;
+    const dim3 grid(tiles_x * tiles_y), block(kBlock);
+    const TS *fi = (const TS *)fin;
+    TS *fo = (TS *)fout;
+    const TP *pi = (const TP *)pin;
+    TP *po = (TP *)pout;
+    const int code = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.lowdeg ? 1 : 0);
+#define LBM_SW2(S, K, NP, TAG)                                                                       \
+    case (S * 4 + K * 2 + TAG):                                                                      \
+        hipLaunchKernelGGL((k_sweep2<TS, TC, S, K, NP, TH>), grid, block, 0, st, g, cf, fi, fo, pi, po, tiles_x, \
+                           flag);                                                                    \
+        break;
+    switch (code) {
+        LBM_SW2(0, 0, 9, 0) LBM_SW2(0, 1, 9, 0) LBM_SW2(1, 0, 9, 0) LBM_SW2(1, 1, 9, 0)
+        LBM_SW2(0, 0, 4, 1) LBM_SW2(0, 1, 4, 1) LBM_SW2(1, 0, 4, 1) LBM_SW2(1, 1, 4, 1)
+        default: return hipErrorInvalidValue;
+    }
+#undef LBM_SW2
+    return hipGetLastError();
+}
+
 // Scheme B and/or per-node fields: the general kernel (any polynomial length).
 template <int Q, typename TS, typename TC>
 hipError_t sweep_gen_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,

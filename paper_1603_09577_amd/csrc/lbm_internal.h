@@ -121,6 +121,11 @@ LBM_LAUNCHERS(q19)
 
 hipError_t launch_zero(double *p, uint32_t n, hipStream_t st);
 
+// Two time steps per pass, D2Q9 only (sweep_d2q9.hip); rows per tile by precision.
+hipError_t launch_sweep2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                            const void *pin, void *pout, int *flag, hipStream_t st);
+int two_step_rows_of(int prec);
+
 // Generic FP64 reductions (lbm_reduce.hip).
 hipError_t launch_reduce(const double *phi, const double *ref, uint32_t n, double *part,
                          int nparts, double *out, hipStream_t st);

@@ -264,21 +264,15 @@ __device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restric
 // C = 0 (the host leaves C out of C-bar) and the source
 // G_k = w_k c_k . (I - A/2) dB/dt / cs^2 (Eq. 37) is added, with dB/dt the
 // difference B(phi(t)) - B(phi(t - 1)) over the last step from the phi history.
-template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT = false,
-          bool SB = false, bool KF = false>
-__device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__restrict__ cf,
-                                           const TS *__restrict__ fin, TS *__restrict__ fout,
-                                           typename HistType<TS>::T *p, int *flag, uint32_t n,
-                                           const double *kfield = nullptr, const double *rfield = nullptr,
-                                           bool rem3 = false) {
+// The per-node collision of one sweep on gathered populations h (offset
+// form), with the phi history pp_off = phi(t - 1) - phi_ref: writes the
+// post-collision populations to out and returns phio = phi - phi_ref, which
+// the caller stores as the history when SRC or rem3 (see sweep_node).
+template <int Q, typename TC, bool EQR, bool SRC, bool KVAR, int NP, bool SB = false, bool KF = false>
+__device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, const TC *h, TC pp_off, uint32_t n,
+                                           const double *kfield, const double *rfield, bool rem3, TC *out) {
     using L = Lattice<Q>;
     constexpr int D = L::dim;
-    const NodeGeo ng = node_geometry<Q, WALL>(g, n);
-
-    TC h[Q];
-    gather<Q, WALL, NT>(g, cf, fin, ng, h);
-    // history read issued together with the gathers, so its latency overlaps theirs
-    const TC pp_off = (SRC || rem3) ? (TC)p[n] : TC(0);
     TC g0n[6];
     const bool kfon = KF && kfield != nullptr;   // uniform across the launch
     if (kfon) g0_of_field<D>(cf, kfield, n, g0n);
@@ -295,7 +289,6 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     if (kfon) ablock_field<D, NP>(cf, g0n, phi, A);
     else ablock<D, KVAR, NP>(cf, phi, A);
 
-    TC out[Q];
     // mass the source adds this step: Scheme A 3/2 R(t) - 1/2 R(t-1); Scheme B
     // R / 2 on top of phi - phi_ref (the stored sum is phi - R/2 before, phi + R/2 after)
     TC Se = TC(0);
@@ -336,7 +329,6 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
             Se = TC(1.5) * R - TC(0.5) * Rp;
 #pragma unroll
             for (int a = 0; a < D; ++a) Vo[a] = TC(4.5) * R * Bt[a] - TC(1.5) * Rp * Btp[a];
-            p[n] = (typename HistType<TS>::T)phio;
         }
         if (SB) {
             // (1 - s/2) R_k = w_k (1 - s/2) R + c_k . 3 w_k (1 - s/2) R B'
@@ -361,7 +353,6 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
                 for (int b = 0; b < D; ++b) acc -= TC(0.5) * A[sym(a, b)] * dB[b];
                 Vo[a] += TC(3) * acc;
             }
-            if (!SRC) p[n] = (typename HistType<TS>::T)phio;
         }
         // j - B, with j the first moment of the gathered populations (Scheme B:
         // of f = fbar + R_k / 2, i.e. plus R B' / 2)
@@ -522,7 +513,6 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
             }
             out[k] += TC(L::w(k)) * (r1 * (TC(1) + TC(3) * cb1) - r0 * (TC(1) + TC(3) * cb0));
         }
-        p[n] = (typename HistType<TS>::T)phio;
     }
 
     if (rem3 && !EQR) {
@@ -548,7 +538,6 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
             }
             out[k] += TC(L::w(k)) * cg;
         }
-        if (!SRC) p[n] = (typename HistType<TS>::T)phio;
     }
 
     // Mass balance.  Collision conserves sum_k g_k and the Scheme-A source adds
@@ -562,6 +551,26 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
         for (int k = 1; k < Q; ++k) moving += out[k];
         out[0] = (phio + Se) - moving;
     }
+
+    return phio;
+}
+
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT = false,
+          bool SB = false, bool KF = false>
+__device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__restrict__ cf,
+                                           const TS *__restrict__ fin, TS *__restrict__ fout,
+                                           typename HistType<TS>::T *p, int *flag, uint32_t n,
+                                           const double *kfield = nullptr, const double *rfield = nullptr,
+                                           bool rem3 = false) {
+    const NodeGeo ng = node_geometry<Q, WALL>(g, n);
+
+    TC h[Q];
+    gather<Q, WALL, NT>(g, cf, fin, ng, h);
+    // history read issued together with the gathers, so its latency overlaps theirs
+    const TC pp_off = (SRC || rem3) ? (TC)p[n] : TC(0);
+    TC out[Q];
+    const TC phio = collide_node<Q, TC, EQR, SRC, KVAR, NP, SB, KF>(cf, h, pp_off, n, kfield, rfield, rem3, out);
+    if (SRC || rem3) p[n] = (typename HistType<TS>::T)phio;
 
 #pragma unroll
     for (int k = 0; k < Q; ++k) store_s<NT>(fout + (uint64_t)k * g.plane + n, out[k]);
@@ -581,6 +590,80 @@ k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f
         if (n >= g.N) return;
         sweep_node<Q, TS, TC, EQR, SRC, KVAR, WALL, NP, NT>(g, cf, fin, fout, p, flag, n);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps per pass (D2Q9, periodic, equal non-flux rates).  A
+// workgroup owns a tile of 62 x TH nodes.  Phase 1 runs step t on the tile
+// plus a one-node halo (64 x (TH + 2) nodes) from the stored state, and keeps
+// the post-collision populations and the new phi history in LDS, rounded to
+// the storage and history types exactly as a store would round them.  Phase 2
+// runs step t + 1 on the tile, gathering from LDS, and stores only its result.
+// Every node update is the single-sweep arithmetic on the same inputs, so the
+// result equals two single sweeps bit for bit; the state is read and written
+// once per two steps.  The phi history is read at halo nodes, which another
+// tile may already have advanced, so it is read from `pin` and written to
+// `pout` (two history buffers, alternating).
+// ---------------------------------------------------------------------------
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH>
+__global__ void __launch_bounds__(kBlock)
+k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
+         const typename HistType<TS>::T *__restrict__ pin, typename HistType<TS>::T *__restrict__ pout,
+         uint32_t tiles_x, int *flag) {
+    using L = Lattice<9>;
+    using TP = typename HistType<TS>::T;
+    constexpr int TX = 64, TR = TH + 2;
+    static_assert(TR % (kBlock / 64) == 0, "tile rows must split evenly over the waves");
+    __shared__ TS lf[9][TR][TX];
+    __shared__ TP lp[TR][TX];
+    const uint32_t tile = block_index(blockIdx.x, gridDim.x, g.remap);
+    const uint32_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int x0 = (int)(tx * (TX - 2)), y0 = (int)(ty * TH);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nx = (int)g.nx, ny = (int)g.ny;
+    bool bad = false;
+    // phase 1 (x0 - 1 + lane lies in [-1, nx + 61] and nx >= 64: one wrap)
+    int xg = x0 - 1 + lane;
+    xg = xg < 0 ? xg + nx : (xg >= nx ? xg - nx : xg);
+#pragma unroll
+    for (int i = 0; i < TR / (kBlock / 64); ++i) {
+        const int r = wv + i * (kBlock / 64);
+        int yg = y0 - 1 + r;   // in [-1, ny + TH - 1], ny >= TH + 2: one wrap
+        yg = yg < 0 ? yg + ny : (yg >= ny ? yg - ny : yg);
+        const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
+        const NodeGeo ng = node_geometry<9, false>(g, n);
+        TC h[9];
+        gather<9, false>(g, cf, fin, ng, h);
+        const TC pp_off = SRC ? (TC)pin[n] : TC(0);
+        TC out[9];
+        const TC phio = collide_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, n, nullptr, nullptr, false, out);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
+        lp[r][lane] = (TP)phio;
+        bad |= !__builtin_isfinite(phio);
+    }
+    __syncthreads();
+    // phase 2: interior lanes 1..62, rows 1..TH
+    if (lane >= 1 && lane <= TX - 2) {
+        const int x = x0 + lane - 1;
+        for (int r = 1 + wv; r <= TH; r += kBlock / 64) {
+            const int y = y0 + r - 1;
+            TC h[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) h[k] = (TC)lf[k][r - L::cy(k)][lane - L::cx(k)];
+            const TC pp_off = SRC ? (TC)lp[r][lane] : TC(0);
+            TC out[9];
+            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, 0u, nullptr, nullptr, false, out);
+            bad |= !__builtin_isfinite(phio);
+            if (x < nx && y < ny) {
+                const uint32_t m = (uint32_t)y * g.nx + (uint32_t)x;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) store_s(fout + (uint64_t)k * g.plane + m, out[k]);
+                if (SRC) pout[m] = (TP)phio;
+            }
+        }
+    }
+    if (bad) *flag = 1;
 }
 
 // The general sweep: Scheme B and/or per-node fields.  Polynomials of any

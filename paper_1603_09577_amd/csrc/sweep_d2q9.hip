@@ -57,4 +57,12 @@ hipError_t launch_set_wall_q9(const Dims &dm, void *coefs, const double *ewp, hi
     LBM_BY_PREC(set_wall_typed, dm, coefs, ewp, st)
 }
 
+
+hipError_t launch_sweep2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                            const void *pin, void *pout, int *flag, hipStream_t st) {
+    LBM_BY_PREC(sweep2_typed, dm, g, coefs, fin, fout, pin, pout, flag, st)
+}
+
+int two_step_rows_of(int prec) { return prec == 0 ? two_step_rows<double>() : two_step_rows<float>(); }
+
 }  // namespace lbm

@@ -33,6 +33,7 @@ EXPORTS = [
     "lbm_batch_step", "lbm_batch_get_phi", "lbm_batch_tune", "lbm_batch_set_shape",
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
     "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields", "lbm_set_phi_wall",
+    "lbm_set_two_step",
 ]
 
 
@@ -124,6 +125,7 @@ def load():
         "lbm_set_recenter": ([_VP, ctypes.c_int], ctypes.c_int),
         "lbm_set_fields": ([_VP, _VP, _VP], ctypes.c_int),
         "lbm_set_phi_wall": ([_VP, ctypes.c_double, ctypes.c_double, _VP], ctypes.c_int),
+        "lbm_set_two_step": ([_VP, ctypes.c_int], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -281,6 +283,10 @@ class Lbm:
         buf = ctypes.create_string_buffer(4096)
         _check(self.lib.lbm_tune(self.ctx, int(reps), _stream(stream), buf, len(buf)))
         return buf.value.decode()
+
+    def set_two_step(self, on):
+        """Two time steps per pass inside step() (D2Q9 periodic equal-rate runs)."""
+        _check(self.lib.lbm_set_two_step(self.ctx, int(bool(on))))
 
     def set_check(self, every):
         _check(self.lib.lbm_set_check(self.ctx, int(every)))

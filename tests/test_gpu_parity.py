@@ -254,3 +254,47 @@ def test_launch_variants_identical():
         s.tune(reps=2)
         s.step(70)
         assert torch.equal(s.phi(), want)
+
+
+@pytest.mark.parametrize("nx,ny,prec,source", [(100, 37, "f32", True), (190, 23, "f64", True),
+                                               (130, 50, "f16", True), (64, 16, "f32", False),
+                                               (257, 91, "f64", False)])
+def test_two_step_passes_bit_identical(nx, ny, prec, source):
+    """Two time steps per pass (LDS tiles of 62 x 14 or 62 x 6 nodes with a
+    one-node halo) against single sweeps: the same arithmetic on the same
+    inputs, so phi, the stored state and the phi history agree bit for bit,
+    across graph replays, passes in pairs and single-sweep remainders; and the
+    result matches the oracle."""
+    lbm = _lbm()
+    spec = W.spec_nonlinear_2d(nx, ny, source=source, precision=prec)
+    phi0 = W.noise_field((ny, nx), 71)
+    say(f"[gpu] two-step passes {nx}x{ny} {prec} source={source}")
+    a = lbm.Lbm(spec).init(phi0)
+    a.set_two_step(False)
+    b = lbm.Lbm(spec).init(phi0)
+    b.set_two_step(True)
+    t = 0
+    for s in (4, 8, 37, 70):
+        a.step(s - t)
+        b.step(s - t)
+        t = s
+        assert torch.equal(a.phi(), b.phi()), s
+        wa, _ = a.current()
+        wb, _ = b.current()
+        assert wa == wb
+        assert torch.equal(a.storage_view(a.f[wa]), b.storage_view(b.f[wb])), s
+        if source:   # the N history values (the buffer tail is padding)
+            hdt = torch.float64 if prec == "f64" else torch.float32
+            assert torch.equal(a.p.view(hdt)[: a.N], b.p.view(hdt)[: b.N]), s
+    if prec == "f64":
+        ref = oracle_run(spec, phi0, (70,))[70]
+        assert rel_l2(b.phi().cpu().numpy(), ref) <= 1e-12
+
+
+def test_two_step_refused_where_it_does_not_apply():
+    lbm = _lbm()
+    for spec in (W.d3q19_walls((20, 18, 22))[0], W.spec_nonlinear_2d(40, 30)):
+        s = lbm.Lbm(spec)
+        with pytest.raises(lbm.LbmError) as ei:
+            s.set_two_step(True)
+        assert ei.value.code == lbm.LBM_E_UNSUPPORTED
