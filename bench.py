@@ -278,6 +278,14 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
 
     trace = list(csv.DictReader(open(os.path.join(gdir, "prof_trace", "trace_kernel_stats.csv"))))
     avg_us = {kname(r["Name"]): float(r["AverageNs"]) / 1e3 for r in trace}
+    # per-dispatch durations: the median is not moved by the autotuner's trials
+    durs = {}
+    tpath = os.path.join(gdir, "prof_trace", "trace_kernel_trace.csv")
+    if os.path.exists(tpath):
+        for r in csv.DictReader(open(tpath)):
+            durs.setdefault(kname(r["Kernel_Name"]), []).append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    med_us = {k: stats.median(v) for k, v in durs.items()}
 
     def counters(sub, stem, cname):
         agg = {}
@@ -302,10 +310,12 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
         k = hits[0]
         fv, wv = stats.median(fetch[k]), stats.median(write[k])
         t = fv * 1024 * fscale + wv * 1024 * wscale
-        tr = next((v for n, v in avg_us.items() if kn in n), None)
+        tr = next((v for n, v in med_us.items() if kn in n), None)
+        if tr is None:
+            tr = next((v for n, v in avg_us.items() if kn in n), None)
         out["workloads"][label] = {"kernel": kn, "fetch_kib": fv, "write_kib": wv,
                                    "traffic_bytes_per_launch": t, "algorithmic_bytes_per_launch": alg,
-                                   "dispatches": len(fetch[k]), "trace_avg_us": tr}
+                                   "dispatches": len(fetch[k]), "trace_median_us": tr}
         rows.append((label, kn, len(fetch[k]), fv, wv, t, alg, tr))
     pdir = os.path.join(ROOT, "profiles")
     with open(os.path.join(pdir, "pmc_traffic.json"), "w") as fh:
@@ -320,10 +330,11 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
           f"fetches (scale x{fscale:.3f}); WRITE_SIZE reads {1 / wscale:.4f} of the bytes it writes "
           f"(scale x{wscale:.3f}).", "",
           "Values are medians per dispatch. Traffic = scaled fetch + scaled write. Algorithmic bytes = "
-          "bytes per node update x nodes per launch; the trace column is the average kernel time from "
-          "the kernel-trace run and the bandwidth is algorithmic bytes over it.", "",
+          "bytes per node update x nodes per launch (a two-step pass: one read and one write of the state "
+          "for two updates); the trace column is the median kernel time from the kernel-trace run and the "
+          "bandwidth is algorithmic bytes over it.", "",
           "| workload | kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | traffic MB | "
-          "algorithmic MB | traffic / algorithmic | trace avg us | GB/s (algorithmic) |",
+          "algorithmic MB | traffic / algorithmic | trace median us | GB/s (algorithmic) |",
           "|---|---|---|---|---|---|---|---|---|---|"]
     for label, kn, nd, fv, wv, t, alg, tr in rows:
         bw = f"{alg / (tr * 1e-6) / 1e9:.0f}" if tr else "-"
@@ -340,9 +351,11 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
           "Summarised by `python3 bench.py --summarize-profiles gpurun_out`. The run includes the "
           "autotuners' trial launches. Template arguments of the sweep:", "",
           "    k_sweep<Q, storage, compute, equal-rate, source, K(phi), walls, polynomial length, non-temporal>",
-          "", "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+          "", "| kernel | calls | avg us | median us | min us | max us | share % |", "|---|---|---|---|---|---|---|"]
     for r in trace[:20]:
+        med = med_us.get(kname(r["Name"]))
         tl.append(f"| `{kname(r['Name'])[:110]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                  f"{'-' if med is None else f'{med:.2f}'} | "
                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                   f"{float(r['Percentage']):.1f} |")
     with open(os.path.join(pdir, "sweep_kernels_kernel_trace.md"), "w") as fh:
