@@ -292,6 +292,23 @@ int lbm_adjoint_seed(lbm_ctx *ctx, const double *gphi_dev, void *psi, double *pi
 int lbm_adjoint_step(lbm_ctx *ctx, const void *f_s, const void *p_s, const void *psi_next,
                      const double *pi_next, void *psi_out, double *pi_out, void *stream);
 
+/* Two reversed sweeps in one launch: sweep s from (f_s, p_s) and (psi_{s+1},
+ * pi_{s+1}), then sweep s - 1 from (f_sm1, p_sm1) = (f_{s-1}, p_{s-1}),
+ * giving (psi_{s-1}, pi_{s-1}) in (psi_out, pi_out) and adding dL/dK0 of both
+ * sweeps.  psi and pi equal those of two lbm_adjoint_step calls bit for bit;
+ * the K0 sums agree up to the order of FP64 additions.  The intermediate
+ * (psi_s, pi_s) lives in workgroup memory only.  Applies to D2Q9 with
+ * periodic axes and equal non-flux rates, nx >= 64 and ny >= 16 (F32) or 8
+ * (F64) (lbm_adjoint_pair_ok tells in advance; elsewhere LBM_E_UNSUPPORTED).
+ * psi_out must differ from psi_next and pi_out from pi_next (LBM_E_INVALID):
+ * neighbouring tiles read pi_{s+1} during the launch. */
+int lbm_adjoint_step2(lbm_ctx *ctx, const void *f_s, const void *p_s, const void *f_sm1, const void *p_sm1,
+                      const void *psi_next, const double *pi_next, void *psi_out, double *pi_out,
+                      void *stream);
+
+/* *ok = 1 if lbm_adjoint_step2 applies to this context, else 0. */
+int lbm_adjoint_pair_ok(const lbm_ctx *ctx, int *ok);
+
 /* Adjoint of the initialisation (Eq. 40): dL/dphi0 = sum_k psi_0,k dfeq_k/dphi
  * + pi_0, into gphi0_dev (FP64). */
 int lbm_adjoint_init(lbm_ctx *ctx, const double *phi0_dev, const void *psi0, const double *pi0,

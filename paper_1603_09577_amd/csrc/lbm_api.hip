@@ -64,6 +64,7 @@ struct lbm_ctx {
     // history buffer owned by the context, and whether the path is on
     void *p2 = nullptr;
     bool two_ok = false, two = false;
+    uint32_t adj_slots = 0;   // K0 partial slots: workgroups of the one- and two-sweep adjoints
     bool bound = false;
     // graphs of kGraphSteps sweeps starting from buffer 0 / 1, captured on an
     // internal stream and launched on the caller's stream
@@ -283,6 +284,8 @@ int validate(const lbm_desc *d, Dims &dm) {
         const int ncb = std::max(nb > 1 ? 2 * nb - 2 : 1, top_count(d->dpoly, LBM_MAXP));
         dm.lowdeg = nb <= 4 && ncb <= 6 && top_count(d->kpoly, LBM_MAXP) <= 4 &&
                     top_count(d->rpoly, LBM_MAXP) <= 4;
+        dm.deg3 = nb <= 3 && ncb <= 4 && top_count(d->kpoly, LBM_MAXP) <= 3 &&
+                  top_count(d->rpoly, LBM_MAXP) <= 3;
     }
     dm.nt = false;
     dm.q = q;
@@ -521,6 +524,11 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     }
     c->two_ok = dm.q == 9 && !dm.wall && dm.eqr && desc->nx >= 64 && desc->ny >= two_step_rows_of(dm.prec) + 2;
     c->two = c->two_ok;   // on by default where it applies (bit-identical; lbm_tune re-decides)
+    {
+        const uint32_t th = (uint32_t)adjoint_pair_rows(dm.prec, g.nx, g.ny);
+        const uint32_t tiles = ((g.nx + 61) / 62) * ((g.ny + th - 1) / th);
+        c->adj_slots = c->two_ok && tiles > g.nblocks ? tiles : g.nblocks;
+    }
     hipError_t e = hipMalloc(&c->d_coefs, sizeof(Coefs<double>));
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipMalloc(coefficients)"); }
     const size_t scratch = 256 + sizeof(double) * (size_t)(kRedParts * 8 + 8 + kMaxAdjParts * kAdjWidth + 16);
@@ -751,10 +759,10 @@ int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipStream_t st = (hipStream_t)stream;
-    if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
+    if (c->adj_slots > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
     hipError_t e = c->dm.q == 9 ? launch_seed_q9(c->dm, c->g, gphi, psi, pi, st)
                                 : launch_seed_q19(c->dm, c->g, gphi, psi, pi, st);
-    if (e == hipSuccess) e = launch_zero(c->d_adj_part, c->g.nblocks * kAdjWidth, st);
+    if (e == hipSuccess) e = launch_zero(c->d_adj_part, c->adj_slots * kAdjWidth, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint seed");
     return LBM_OK;
 }
@@ -768,13 +776,45 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
     if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
-    if (c->g.nblocks > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
+    if (c->adj_slots > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = c->dm.q == 9 ? launch_adjoint_q9(c->dm, c->g, c->d_coefs, f_s, p_s, psi_next, pi_next, psi_out,
                                                     pi_out, c->d_adj_part, st)
                                 : launch_adjoint_q19(c->dm, c->g, c->d_coefs, f_s, p_s, psi_next, pi_next, psi_out,
                                                      pi_out, c->d_adj_part, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel");
+    return LBM_OK;
+}
+
+// Two reversed sweeps per launch: the forward pass's tile conditions.
+static bool adjoint_pair_applies(const lbm_ctx *c) {
+    return c->two_ok && c->dm.prec != 2 && c->adj_slots <= (uint32_t)kMaxAdjParts;
+}
+
+int lbm_adjoint_pair_ok(const lbm_ctx *c, int *ok) {
+    if (!c || !ok) return fail(LBM_E_INVALID, "null argument");
+    *ok = adjoint_pair_applies(c) && !general_path(c) ? 1 : 0;
+    return LBM_OK;
+}
+
+int lbm_adjoint_step2(lbm_ctx *c, const void *f_s, const void *p_s, const void *f_sm1, const void *p_sm1,
+                      const void *psi_next, const double *pi_next, void *psi_out, double *pi_out, void *stream) {
+    if (!c || !f_s || !p_s || !f_sm1 || !p_sm1 || !psi_next || !pi_next || !psi_out || !pi_out)
+        return fail(LBM_E_INVALID, "null argument");
+    if (psi_next == psi_out) return fail(LBM_E_INVALID, "psi_next and psi_out must differ");
+    if ((const void *)pi_next == (const void *)pi_out)
+        return fail(LBM_E_INVALID, "pi_next and pi_out must differ for two sweeps per launch");
+    if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
+    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
+    if (c->recentered)
+        return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
+    if (!adjoint_pair_applies(c))
+        return fail(LBM_E_UNSUPPORTED,
+                    "two reversed sweeps per launch need D2Q9, periodic axes, equal rates and nx >= 64, "
+                    "ny >= tile rows + 2");
+    hipError_t e = launch_adjoint2_q9(c->dm, c->g, c->d_coefs, f_s, p_s, f_sm1, p_sm1, psi_next, pi_next, psi_out,
+                                      pi_out, c->d_adj_part, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint pair kernel");
     return LBM_OK;
 }
 
@@ -798,7 +838,7 @@ int lbm_adjoint_grad_k0(lbm_ctx *c, double out[6], void *stream) {
     double acc[6];
     // fold the per-workgroup slots (fixed order: deterministic)
     hipError_t e = launch_zero(c->d_k0acc, 8, st);
-    if (e == hipSuccess) e = launch_sum_partials(c->d_adj_part, (int)c->g.nblocks, kAdjWidth, c->d_k0acc, st);
+    if (e == hipSuccess) e = launch_sum_partials(c->d_adj_part, (int)c->adj_slots, kAdjWidth, c->d_k0acc, st);
     if (e == hipSuccess) e = hipMemcpyAsync(acc, c->d_k0acc, 6 * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "adjoint gradient copy");

@@ -17,6 +17,25 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
     auto *fo = (TS *)fout;
     auto *pp = (TP *)p;
     const dim3 grid((g.nblocks + g.chunk - 1) / g.chunk), block(kBlock);
+    // D2Q9 with every polynomial of degree <= 2: 3-term kernels
+    if constexpr (Q == 9) {
+        if (dm.eqr && dm.deg3) {
+            const int c3 = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) | (dm.nt ? 8 : 0);
+#define LBM_SWEEP3(S, K, W, NT)                                                                       \
+    case (NT * 8 + S * 4 + K * 2 + W):                                                                \
+        hipLaunchKernelGGL((k_sweep<Q, TS, TC, true, S, K, W, 3, NT>), grid, block, 0, st, g, cf, fi, fo, pp, flag); \
+        break;
+            switch (c3) {
+                LBM_SWEEP3(0, 0, 0, 0) LBM_SWEEP3(0, 0, 1, 0) LBM_SWEEP3(0, 1, 0, 0) LBM_SWEEP3(0, 1, 1, 0)
+                LBM_SWEEP3(1, 0, 0, 0) LBM_SWEEP3(1, 0, 1, 0) LBM_SWEEP3(1, 1, 0, 0) LBM_SWEEP3(1, 1, 1, 0)
+                LBM_SWEEP3(0, 0, 0, 1) LBM_SWEEP3(0, 0, 1, 1) LBM_SWEEP3(0, 1, 0, 1) LBM_SWEEP3(0, 1, 1, 1)
+                LBM_SWEEP3(1, 0, 0, 1) LBM_SWEEP3(1, 0, 1, 1) LBM_SWEEP3(1, 1, 0, 1) LBM_SWEEP3(1, 1, 1, 1)
+                default: return hipErrorInvalidValue;
+            }
+#undef LBM_SWEEP3
+            return hipGetLastError();
+        }
+    }
     // short polynomials (all degrees <= 3) get the branch-free 4-term kernels
     // non-temporal accesses: equal-rate short-polynomial kernels only
     const int code = (dm.eqr ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) |
@@ -66,7 +85,7 @@ hipError_t sweep2_typed(const Dims &dm, const Geom &g, const void *coefs, const 
     TS *fo = (TS *)fout;
     const TP *pi = (const TP *)pin;
     TP *po = (TP *)pout;
-    const int code = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.lowdeg ? 1 : 0);
+    const int code = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.deg3 ? 8 : (dm.lowdeg ? 1 : 0));
 #define LBM_SW2(S, K, NP, TAG)                                                                       \
     case (S * 4 + K * 2 + TAG):                                                                      \
         hipLaunchKernelGGL((k_sweep2<TS, TC, S, K, NP, TH>), grid, block, 0, st, g, cf, fi, fo, pi, po, tiles_x, \
@@ -75,6 +94,7 @@ hipError_t sweep2_typed(const Dims &dm, const Geom &g, const void *coefs, const 
     switch (code) {
         LBM_SW2(0, 0, 9, 0) LBM_SW2(0, 1, 9, 0) LBM_SW2(1, 0, 9, 0) LBM_SW2(1, 1, 9, 0)
         LBM_SW2(0, 0, 4, 1) LBM_SW2(0, 1, 4, 1) LBM_SW2(1, 0, 4, 1) LBM_SW2(1, 1, 4, 1)
+        LBM_SW2(0, 0, 3, 8) LBM_SW2(0, 1, 3, 8) LBM_SW2(1, 0, 3, 8) LBM_SW2(1, 1, 3, 8)
         default: return hipErrorInvalidValue;
     }
 #undef LBM_SW2
@@ -155,6 +175,23 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
     const auto *pn = (const TC *)psi_next;
     auto *po = (TC *)psi_out;
     const dim3 grid(g.nblocks), block(kBlock);
+    if constexpr (Q == 9) {
+        if (dm.eqr && dm.deg3) {
+            const int c3 = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
+#define LBM_ADJ3(S, K, W)                                                                               \
+    case (S * 4 + K * 2 + W):                                                                           \
+        hipLaunchKernelGGL((k_adjoint<Q, TS, TC, true, S, K, W, 3>), grid, block, 0, st, g, cf, fs, ps, pn, \
+                           pi_next, po, pi_out, gk_part);                                               \
+        break;
+            switch (c3) {
+                LBM_ADJ3(0, 0, 0) LBM_ADJ3(0, 0, 1) LBM_ADJ3(0, 1, 0) LBM_ADJ3(0, 1, 1)
+                LBM_ADJ3(1, 0, 0) LBM_ADJ3(1, 0, 1) LBM_ADJ3(1, 1, 0) LBM_ADJ3(1, 1, 1)
+                default: return hipErrorInvalidValue;
+            }
+#undef LBM_ADJ3
+            return hipGetLastError();
+        }
+    }
     const int code = (dm.eqr ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) |
                      ((dm.eqr && dm.lowdeg) ? 16 : 0);
 #define LBM_ADJ_NP(E, S, K, W, NP, TAG)                                                                 \
@@ -177,6 +214,60 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
 #undef LBM_ADJ
 #undef LBM_ADJ_NP
     return hipGetLastError();
+}
+
+// Two reversed sweeps per pass (D2Q9, periodic, equal rates): sweep s with
+// (f1, p1), then sweep s - 1 with (f0, p0); TH tile rows.
+template <typename TS, typename TC, int TH>
+hipError_t adjoint2_rows(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
+                         const void *f0, const void *p0, const void *psi_next, const double *pi_next,
+                         void *psi_out, double *pi_out, double *gk_part, hipStream_t st) {
+    using TP = typename HistType<TS>::T;
+    const auto *cf = (const Coefs<TC> *)coefs;
+    const uint32_t tiles_x = (g.nx + 61) / 62, tiles_y = (g.ny + TH - 1) / TH;
+    const dim3 grid(tiles_x * tiles_y), block(kBlock);
+    const auto *a1 = (const TS *)f1, *a0 = (const TS *)f0;
+    const auto *q1 = (const TP *)p1, *q0 = (const TP *)p0;
+    const auto *pn = (const TC *)psi_next;
+    auto *po = (TC *)psi_out;
+    const int code = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.deg3 ? 8 : (dm.lowdeg ? 1 : 0));
+#define LBM_ADJ2(S, K, NP, TAG)                                                                      \
+    case (S * 4 + K * 2 + TAG):                                                                      \
+        hipLaunchKernelGGL((k_adjoint2<TS, TC, S, K, NP, TH>), grid, block, 0, st, g, cf, a1, q1, a0, q0, pn, \
+                           pi_next, po, pi_out, gk_part, tiles_x);                                   \
+        break;
+    switch (code) {
+        LBM_ADJ2(0, 0, 9, 0) LBM_ADJ2(0, 1, 9, 0) LBM_ADJ2(1, 0, 9, 0) LBM_ADJ2(1, 1, 9, 0)
+        LBM_ADJ2(0, 0, 4, 1) LBM_ADJ2(0, 1, 4, 1) LBM_ADJ2(1, 0, 4, 1) LBM_ADJ2(1, 1, 4, 1)
+        LBM_ADJ2(0, 0, 3, 8) LBM_ADJ2(0, 1, 3, 8) LBM_ADJ2(1, 0, 3, 8) LBM_ADJ2(1, 1, 3, 8)
+        default: return hipErrorInvalidValue;
+    }
+#undef LBM_ADJ2
+    return hipGetLastError();
+}
+
+// Tile rows of the two-sweep adjoint: 6 in FP64 (workgroup memory); in FP32
+// 14 when that still gives 1024 tiles (4 workgroups per CU), else 6.
+inline int adjoint_pair_rows_for(int prec, uint32_t nx, uint32_t ny) {
+    if (prec == 0) return 6;
+    return ((nx + 61) / 62) * ((ny + 13) / 14) >= 1024 ? 14 : 6;
+}
+
+template <int Q, typename TS, typename TC>
+hipError_t adjoint2_typed(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
+                          const void *f0, const void *p0, const void *psi_next, const double *pi_next,
+                          void *psi_out, double *pi_out, double *gk_part, hipStream_t st) {
+    static_assert(Q == 9, "two reversed sweeps per pass are D2Q9 only");
+    if constexpr (sizeof(TC) == 8) {
+        return adjoint2_rows<TS, TC, 6>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out, gk_part,
+                                        st);
+    } else {
+        if (adjoint_pair_rows_for(dm.prec, g.nx, g.ny) == 14)
+            return adjoint2_rows<TS, TC, 14>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
+                                             gk_part, st);
+        return adjoint2_rows<TS, TC, 6>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out, gk_part,
+                                        st);
+    }
 }
 
 template <int Q, typename TS, typename TC>

@@ -70,6 +70,7 @@ struct Dims {
     bool kvar;            // k(phi) not constant: A per node
     bool wall;            // walls on the last axis
     bool lowdeg;          // every polynomial of degree <= 3 (C-bar <= 5)
+    bool deg3 = false;    // every polynomial of degree <= 2 (C-bar <= 3): 3-term kernels (D2Q9)
     bool nt;              // non-temporal distribution accesses
     bool sb;              // Scheme B (Eq. 33-35): stored fbar, explicit source
 };
@@ -125,6 +126,12 @@ hipError_t launch_zero(double *p, uint32_t n, hipStream_t st);
 hipError_t launch_sweep2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
                             const void *pin, void *pout, int *flag, hipStream_t st);
 int two_step_rows_of(int prec);
+int adjoint_pair_rows(int prec, uint32_t nx, uint32_t ny);
+// Two reversed sweeps per pass (sweep s, then s - 1), D2Q9 only; tile rows
+// by compute type and grid size (adjoint_pair_rows).
+hipError_t launch_adjoint2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
+                              const void *f0, const void *p0, const void *psi_next, const double *pi_next,
+                              void *psi_out, double *pi_out, double *gk_part, hipStream_t st);
 
 // Generic FP64 reductions (lbm_reduce.hip).
 hipError_t launch_reduce(const double *phi, const double *ref, uint32_t n, double *part,

@@ -20,6 +20,12 @@
 #include "lbm_internal.h"
 #include "lbm_lattice.h"
 
+// Multiply-adds fuse only within one source expression (as the language
+// allows), never across statements: the rounding of a node update is then
+// the same in every kernel it is inlined into, which is what makes the
+// one-sweep, two-sweep and batched kernels agree bit for bit.
+#pragma clang fp contract(on)
+
 namespace lbm {
 
 template <typename TS>
@@ -54,8 +60,15 @@ __device__ __forceinline__ T poly(const T *c, T x) {
 }
 
 // coefficient counts: NP for B, D, K, R and their derivatives, NC for C-bar
+// (the host packs exact derivatives, so a derivative of an NP-term polynomial
+// has NP - 1 terms)
 template <int NP>
-struct PolyLen { static constexpr int NC = 2 * NP - 2; };
+struct PolyLen {
+    static constexpr int NC = 2 * NP - 2;                // C-bar
+    static constexpr int ND = NP > 1 ? NP - 1 : 1;       // B', k', R'
+    static constexpr int ND2 = NP > 2 ? NP - 2 : 1;      // B''
+    static constexpr int NCD = NC > 1 ? NC - 1 : 1;      // C-bar'
+};
 
 // Workgroup order that gives each XCD one contiguous run of the domain, so
 // the neighbouring rows and planes a workgroup reads sit in its own L2.
@@ -180,7 +193,7 @@ __device__ __forceinline__ void source_terms(const Coefs<TC> *__restrict__ cf, T
                                              TC *Bt, TC &R) {
     TC Bp[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Bp[a] = (a < DIM) ? poly<NP>(cf->bp[a], phi) : TC(0);
+    for (int a = 0; a < 3; ++a) Bp[a] = (a < DIM) ? poly<PolyLen<NP>::ND>(cf->bp[a], phi) : TC(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         TC acc = Bp[a];
@@ -335,7 +348,7 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
             const TC hs = (TC(1) - TC(0.5) * s) * Rx;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const TC bp = poly<NP>(cf->bp[a], phi);
+                const TC bp = poly<PolyLen<NP>::ND>(cf->bp[a], phi);
                 Vo[a] = TC(3) * hs * bp;
                 jsh[a] = TC(0.5) * Rx * bp;
             }
@@ -440,7 +453,7 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
             // r -= (I - S/2) M R_k, R_k = w_k R (1 + 3 c_k . B') (Eq. 9, Btilde = B')
             TC Bp[3] = {TC(0), TC(0), TC(0)};
 #pragma unroll
-            for (int a = 0; a < D; ++a) Bp[a] = poly<NP>(cf->bp[a], phi);
+            for (int a = 0; a < D; ++a) Bp[a] = poly<PolyLen<NP>::ND>(cf->bp[a], phi);
             TC Rk[Q], mR[Q], sR[Q];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
@@ -701,7 +714,7 @@ __device__ __forceinline__ TC half_source_one(const Coefs<TC> *__restrict__ cf, 
 #pragma unroll
     for (int a = 0; a < L::dim; ++a) {
         const int c = L::c(kk, a);
-        if (c) cb += TC(c) * poly<NP>(cf->bp[a], phi);
+        if (c) cb += TC(c) * poly<PolyLen<NP>::ND>(cf->bp[a], phi);
     }
     return TC(0.5) * TC(L::w(kk)) * R * (TC(1) + TC(3) * cb);
 }
@@ -802,6 +815,25 @@ __device__ __forceinline__ double lane_f64(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane((int)b, lane);
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float lane_f32(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Sum over the 64 lanes of a wave, the same in every lane (same pattern in
+// both precisions).
+__device__ __forceinline__ float wave_total(float v) {
+    v += dpp_f32<0xB1>(v);
+    v += dpp_f32<0x4E>(v);
+    v += dpp_f32<0x141>(v);
+    v += dpp_f32<0x140>(v);
+    return (lane_f32(v, 0) + lane_f32(v, 16)) + (lane_f32(v, 32) + lane_f32(v, 48));
 }
 
 __device__ __forceinline__ double wave_total(double v) {

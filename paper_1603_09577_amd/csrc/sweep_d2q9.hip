@@ -63,6 +63,15 @@ hipError_t launch_sweep2_q9(const Dims &dm, const Geom &g, const void *coefs, co
     LBM_BY_PREC(sweep2_typed, dm, g, coefs, fin, fout, pin, pout, flag, st)
 }
 
+hipError_t launch_adjoint2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
+                              const void *f0, const void *p0, const void *psi_next, const double *pi_next,
+                              void *psi_out, double *pi_out, double *gk_part, hipStream_t st) {
+    if (!dm.eqr || dm.wall) return hipErrorInvalidValue;
+    LBM_BY_PREC_ADJ(adjoint2_typed, dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out, gk_part, st)
+}
+
+int adjoint_pair_rows(int prec, uint32_t nx, uint32_t ny) { return adjoint_pair_rows_for(prec, nx, ny); }
+
 int two_step_rows_of(int prec) { return prec == 0 ? two_step_rows<double>() : two_step_rows<float>(); }
 
 }  // namespace lbm

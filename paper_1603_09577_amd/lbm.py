@@ -33,7 +33,7 @@ EXPORTS = [
     "lbm_batch_step", "lbm_batch_get_phi", "lbm_batch_tune", "lbm_batch_set_shape",
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
     "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields", "lbm_set_phi_wall",
-    "lbm_set_two_step",
+    "lbm_set_two_step", "lbm_adjoint_step2", "lbm_adjoint_pair_ok",
 ]
 
 
@@ -126,6 +126,8 @@ def load():
         "lbm_set_fields": ([_VP, _VP, _VP], ctypes.c_int),
         "lbm_set_phi_wall": ([_VP, ctypes.c_double, ctypes.c_double, _VP], ctypes.c_int),
         "lbm_set_two_step": ([_VP, ctypes.c_int], ctypes.c_int),
+        "lbm_adjoint_step2": ([_VP] * 10, ctypes.c_int),
+        "lbm_adjoint_pair_ok": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -346,6 +348,57 @@ class Lbm:
     def adjoint_step(self, f_s, p_s, psi_next, pi_next, psi_out, pi_out, stream=None):
         _check(self.lib.lbm_adjoint_step(self.ctx, _ptr(f_s), _ptr(p_s), _ptr(psi_next), _ptr(pi_next),
                                          _ptr(psi_out), _ptr(pi_out), _stream(stream)))
+
+    @property
+    def adjoint_pair_ok(self):
+        """Whether adjoint_step2 (two reversed sweeps per launch) applies."""
+        ok = ctypes.c_int()
+        _check(self.lib.lbm_adjoint_pair_ok(self.ctx, ctypes.byref(ok)))
+        return bool(ok.value)
+
+    def adjoint_pairs_faster(self, reps=4):
+        """Whether two reversed sweeps per launch beat two one-sweep launches
+        here: both are timed once on scratch buffers (zero adjoint variables,
+        the current forward state) and the answer is kept.  The trial adds to
+        the K0 sums, so call it before lbm_adjoint_seed, which clears them."""
+        import torch
+        if getattr(self, "_adj_pairs", None) is not None:
+            return self._adj_pairs
+        if not self.adjoint_pair_ok:
+            self._adj_pairs = False
+            return False
+        which, _ = self.current()
+        f, p = self.f[which], self.p
+        a, pa = self.adjoint_buffers()
+        b, pb = self.adjoint_buffers()
+        a.zero_(); pa.zero_(); b.zero_(); pb.zero_()
+
+        def singles():
+            for _ in range(reps):
+                self.adjoint_step(f, p, a, pa, b, pa)
+                self.adjoint_step(f, p, b, pa, a, pa)
+
+        def pairs():
+            for _ in range(reps):
+                self.adjoint_step2(f, p, f, p, a, pa, b, pb)
+                self.adjoint_step2(f, p, f, p, b, pb, a, pa)
+
+        singles(); pairs()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(); singles(); ev[1].record()
+        ev[2].record(); pairs(); ev[3].record()
+        torch.cuda.synchronize()
+        per_single = ev[0].elapsed_time(ev[1]) / (2 * reps)
+        per_pair = ev[2].elapsed_time(ev[3]) / (4 * reps)
+        self._adj_pairs = per_pair < per_single
+        return self._adj_pairs
+
+    def adjoint_step2(self, f_s, p_s, f_sm1, p_sm1, psi_next, pi_next, psi_out, pi_out, stream=None):
+        """Reversed sweeps s and s - 1 in one launch: (psi_{s+1}, pi_{s+1}) ->
+        (psi_{s-1}, pi_{s-1}); pi_out must differ from pi_next."""
+        _check(self.lib.lbm_adjoint_step2(self.ctx, _ptr(f_s), _ptr(p_s), _ptr(f_sm1), _ptr(p_sm1),
+                                          _ptr(psi_next), _ptr(pi_next), _ptr(psi_out), _ptr(pi_out),
+                                          _stream(stream)))
 
     def adjoint_init(self, phi0, psi0, pi0, out=None, stream=None):
         import torch

@@ -1,0 +1,171 @@
+"""Two reversed sweeps per launch (lbm_adjoint_step2).
+
+* psi and pi equal those of two one-sweep launches bit for bit (FP64 and
+  FP32, with and without the Scheme-A source, ragged tiles in x and y, and a
+  grid with more tiles than one-sweep workgroups); the K0 sums agree up to
+  the order of additions (FP64 <= 1e-12 relative; FP32 terms are summed over
+  a wave in FP32, <= 1e-6),
+* the checkpointed rollout gives the same dL/dphi0 with and without pairs,
+  and matches the oracle's adjoint (<= 1e-10) on a grid where pairs apply,
+* the call is refused where it does not apply.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_1603_09577_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def planes(sim, psi):
+    """The q planes of a psi buffer, N values each (the plane padding is never written)."""
+    v = psi.view(sim.compute_dtype)
+    plane = v.numel() // sim.q
+    return v.view(sim.q, plane)[:, :sim.N]
+
+
+def consecutive_states(sim):
+    """(f_{s-1}, p_{s-1}) and (f_s, p_s), one forward sweep apart."""
+    which, _ = sim.current()
+    fa, pa = sim.f[which].clone(), sim.p.clone()
+    fb, pb = torch.empty_like(fa), pa.clone()
+    sim.sweep(fa, fb, pb)
+    return (fa, pa), (fb, pb)
+
+
+CASES = [
+    ("f64", 100, 37, True), ("f64", 128, 64, True), ("f64", 100, 37, False),
+    ("f32", 100, 37, True), ("f32", 64, 16, True), ("f32", 190, 45, False),
+    ("f32", 1024, 848, True),    # 1037 tiles of 14 rows (smaller grids take 6-row tiles)
+]
+
+
+@pytest.mark.parametrize("prec,nx,ny,source", CASES)
+def test_pair_equals_two_single_sweeps(prec, nx, ny, source):
+    from paper_1603_09577_amd import lbm
+    say(f"[gpu adjoint pairs] {prec} {nx}x{ny} source={source}")
+    spec = W.spec_nonlinear_2d(nx, ny, precision=prec, source=source)
+    sim = lbm.Lbm(spec).init(W.noise_field((ny, nx), 31))
+    assert sim.adjoint_pair_ok
+    sim.step(6)
+    (fa, pa), (fb, pb) = consecutive_states(sim)
+    rng = np.random.default_rng(32)
+    g = torch.tensor(rng.standard_normal((ny, nx)), dtype=torch.float64, device="cuda")
+    # a non-trivial (psi_{s+1}, pi_{s+1}): one reversed sweep after the seed
+    x_psi, x_pi = sim.adjoint_buffers()
+    t_psi, t_pi = sim.adjoint_buffers()
+    sim.adjoint_seed(g, t_psi, t_pi)
+    sim.adjoint_step(fb, pb, t_psi, t_pi, x_psi, x_pi)
+    # one-sweep launches: sweep s with (fb, pb), then s - 1 with (fa, pa)
+    y1_psi, y1_pi = sim.adjoint_buffers()
+    y2_psi, y2_pi = sim.adjoint_buffers()
+    sim.adjoint_seed(g, t_psi, t_pi)      # clears the K0 accumulator
+    sim.adjoint_step(fb, pb, x_psi, x_pi, y1_psi, y1_pi)
+    sim.adjoint_step(fa, pa, y1_psi, y1_pi, y2_psi, y2_pi)
+    gk_single = sim.adjoint_grad_k0()
+    # the pair
+    z_psi, z_pi = sim.adjoint_buffers()
+    sim.adjoint_seed(g, t_psi, t_pi)
+    sim.adjoint_step2(fb, pb, fa, pa, x_psi, x_pi, z_psi, z_pi)
+    gk_pair = sim.adjoint_grad_k0()
+    torch.cuda.synchronize()
+    a, b = planes(sim, y2_psi), planes(sim, z_psi)
+    nbad = int((a != b).sum())
+    say(f"    psi mismatches {nbad}, pi max diff {float((y2_pi - z_pi).abs().max()):.3e}")
+    assert nbad == 0
+    assert torch.equal(y2_pi, z_pi)
+    ks = ("xx", "xy", "yy")
+    e = rel([gk_pair[k] for k in ks], [gk_single[k] for k in ks])
+    say(f"    K0 sums rel diff {e:.2e}")
+    assert e <= (1e-12 if prec == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_rollout_with_pairs_equals_without(prec):
+    from paper_1603_09577_amd import lbm
+    from paper_1603_09577_amd.rollout import rollout
+    nx, ny, T, seg = 100, 37, 11, 4     # segments of 4, 4, 3: pairs and a single sweep
+    spec = W.spec_nonlinear_2d(nx, ny, precision=prec)
+    phi0 = W.noise_field((ny, nx), 33)
+    target = W.noise_field((ny, nx), 34)
+    out = []
+    for pairs in (False, True):
+        sim = lbm.Lbm(spec)
+        p0 = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+        k0 = torch.tensor([spec["k0"][0][0], spec["k0"][0][1], spec["k0"][1][1]], dtype=torch.float64,
+                          requires_grad=True)
+        phiT = rollout(sim, p0, k0, T, seg, pairs=pairs)
+        loss = 0.5 * ((phiT - torch.tensor(target, device="cuda")) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        out.append((p0.grad.cpu().numpy(), k0.grad.numpy()))
+    say(f"[gpu adjoint pairs] rollout {prec}: dphi0 max diff {np.abs(out[0][0] - out[1][0]).max():.3e}, "
+        f"dK0 rel {rel(out[1][1], out[0][1]):.2e}")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert rel(out[1][1], out[0][1]) <= (1e-12 if prec == "f64" else 1e-6)
+
+
+def test_rollout_with_pairs_matches_oracle():
+    from paper_1603_09577_amd import lbm
+    from paper_1603_09577_amd.rollout import rollout
+    nx, ny, T = 70, 24, 9
+    spec = W.spec_nonlinear_2d(nx, ny)
+    phi0 = W.noise_field((ny, nx), 35)
+    target = W.noise_field((ny, nx), 36)
+    sim = lbm.Lbm(spec)
+    assert sim.adjoint_pair_ok
+    p0 = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
+    k0 = torch.tensor([spec["k0"][0][0], spec["k0"][0][1], spec["k0"][1][1]], dtype=torch.float64,
+                      requires_grad=True)
+    phiT = rollout(sim, p0, k0, T, 4)
+    loss = 0.5 * ((phiT - torch.tensor(target, device="cuda")) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    p = orc.params_from_spec(spec)
+    _, go, gk = orc.gradient(p, phi0, T, lambda ph: ph - target)
+    ko = np.array([gk[k] for k in ("xx", "xy", "yy")])
+    e0, ek = rel(p0.grad.cpu().numpy(), go), rel(k0.grad.numpy(), ko)
+    say(f"[gpu adjoint pairs] vs oracle 70x24 T={T}: dphi0 {e0:.2e} dK0 {ek:.2e}")
+    assert e0 <= 1e-10 and ek <= 1e-10
+
+
+def test_pair_refused_where_it_does_not_apply():
+    from paper_1603_09577_amd import lbm
+    # pi_out == pi_next
+    spec = W.spec_nonlinear_2d(100, 37)
+    sim = lbm.Lbm(spec).init(W.noise_field((37, 100), 37))
+    (fa, pa), (fb, pb) = consecutive_states(sim)
+    psi, pi = sim.adjoint_buffers()
+    psi2, _ = sim.adjoint_buffers()
+    with pytest.raises(lbm.LbmError) as ei:
+        sim.adjoint_step2(fb, pb, fa, pa, psi, pi, psi2, pi)
+    assert ei.value.code == lbm.LBM_E_INVALID
+    # narrow grid, walls, D3Q19
+    for s in (W.spec_nonlinear_2d(40, 37),
+              dict(W.spec_nonlinear_2d(100, 37), bc=["periodic", "abb", "periodic"],
+                   phi_wall=[[0, 0], [0.3, 0.7], [0, 0]]),
+              W.spec_d3q19_aniso((16, 16, 16), phi_wall=0.3)):
+        sim = lbm.Lbm(s)
+        assert not sim.adjoint_pair_ok
+        ny, nx = sim.shape[-2], sim.shape[-1]
+        sim.init(np.full(sim.shape, 0.5))
+        which, _ = sim.current()
+        psi, pi = sim.adjoint_buffers()
+        psi2, pi2 = sim.adjoint_buffers()
+        with pytest.raises(lbm.LbmError) as ei:
+            sim.adjoint_step2(sim.f[which], sim.p, sim.f[which], sim.p, psi, pi, psi2, pi2)
+        assert ei.value.code == lbm.LBM_E_UNSUPPORTED
