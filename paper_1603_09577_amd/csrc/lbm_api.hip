@@ -64,6 +64,7 @@ struct lbm_ctx {
     // history buffer owned by the context, and whether the path is on
     void *p2 = nullptr;
     bool two_ok = false, two = false;
+    int two_rows = 0;         // tile rows of two-step passes (0: the default for the storage type)
     uint32_t adj_slots = 0;   // K0 partial slots: workgroups of the one- and two-sweep adjoints
     bool bound = false;
     // graphs of kGraphSteps sweeps starting from buffer 0 / 1, captured on an
@@ -351,9 +352,11 @@ bool two_active(const lbm_ctx *c) { return c->two && c->two_ok && !general_path(
 // history p -> p2, then back; state and history end where four single sweeps
 // would leave them.
 hipError_t sweep_pair(lbm_ctx *c, int start, hipStream_t st) {
-    hipError_t e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, c->p2, c->d_flag, st);
+    hipError_t e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, c->p2, c->d_flag,
+                                    c->two_rows, st);
     if (e == hipSuccess)
-        e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], c->p2, c->p, c->d_flag, st);
+        e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], c->p2, c->p, c->d_flag,
+                             c->two_rows, st);
     return e;
 }
 
@@ -522,7 +525,11 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
         c->dm.nt = bytes > 256.0 * 1024 * 1024;
         if (c->dm.nt) g.remap = 0;
     }
-    c->two_ok = dm.q == 9 && !dm.wall && dm.eqr && desc->nx >= 64 && desc->ny >= two_step_rows_of(dm.prec) + 2;
+    // every array a kernel indexes (planes of f and psi, p, pi: at most 8-byte
+    // elements, at most `plane` of them) spans < 4 GiB: 32-bit byte offsets
+    c->dm.o32 = (uint64_t)g.plane * 8u < (1ull << 32);
+    c->two_ok = dm.q == 9 && !dm.wall && dm.eqr && c->dm.o32 && desc->nx >= 64 &&
+                desc->ny >= two_step_rows_of(dm.prec) + 2;
     c->two = c->two_ok;   // on by default where it applies (bit-identical; lbm_tune re-decides)
     {
         const uint32_t th = (uint32_t)adjoint_pair_rows(dm.prec, g.nx, g.ny);
@@ -633,13 +640,18 @@ int lbm_recenter(lbm_ctx *c, void *stream) {
     return LBM_OK;
 }
 
-int lbm_set_two_step(lbm_ctx *c, int on) {
+int lbm_set_two_step(lbm_ctx *c, int mode) {
     if (!c) return fail(LBM_E_INVALID, "null context");
-    if (on && !c->two_ok)
+    if (mode < 0) return fail(LBM_E_INVALID, "mode must be 0, 1 or a tile height");
+    if (mode && !c->two_ok)
         return fail(LBM_E_UNSUPPORTED, "two steps per pass need D2Q9, periodic axes, equal non-flux rates and a grid "
                                        "of at least 64 x (tile rows + 2)");
-    if ((on != 0) != c->two) drop_graphs(c);
-    c->two = on != 0;
+    const int rows = mode > 1 ? mode : 0;
+    if (rows && !two_step_rows_allowed(c->dm.prec, rows, c->dm.deg3))
+        return fail(LBM_E_INVALID, "tile height not available for this storage type and polynomial length");
+    drop_graphs(c);
+    c->two = mode != 0;
+    c->two_rows = rows;
     return LBM_OK;
 }
 
@@ -905,12 +917,18 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
     }
     // two steps per pass: time pairs of passes (four steps), per step
     bool best_two = false;
+    int best_rows = 0;
     c->g.chunk = (uint32_t)best_chunk;
     c->dm.nt = best_nt;
     if (c->two_ok && !general_path(c)) {
         const int pair_reps = std::max(1, reps / 4);
-        for (int ri = 0; ri < remaps; ++ri) {
-            c->g.remap = (remaps == 2 && ri == 0) ? 1u : 0u;
+        static const int row_cands[] = {0, 10, 6};
+        for (int ri = 0; ri < remaps * 3; ++ri) {
+            const int rows = row_cands[ri / remaps];
+            if (rows && ((uint32_t)rows + 2 > c->g.ny || !two_step_rows_allowed(c->dm.prec, rows, c->dm.deg3)))
+                continue;
+            c->two_rows = rows;
+            c->g.remap = (remaps == 2 && ri % remaps == 0) ? 1u : 0u;
             hipError_t e = sweep_pair(c, c->cur, st);
             if (e == hipSuccess) e = hipEventRecord(e0, st);
             for (int r = 0; r < pair_reps && e == hipSuccess; ++r) e = sweep_pair(c, c->cur, st);
@@ -924,19 +942,22 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
             }
             ms /= 4 * pair_reps;
             char line[96];
-            std::snprintf(line, sizeof(line), "two steps per pass remap %u: %.4f ms per step\n", c->g.remap, ms);
+            std::snprintf(line, sizeof(line), "two steps per pass rows %d remap %u: %.4f ms per step\n",
+                          rows ? rows : two_step_rows_of(c->dm.prec), c->g.remap, ms);
             rep += line;
-            if (ms < best) { best = ms; best_two = true; best_remap = c->g.remap; }
+            if (ms < best) { best = ms; best_two = true; best_remap = c->g.remap; best_rows = rows; }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->g.remap = best_remap;
     c->two = best_two;
+    c->two_rows = best_rows;
     drop_graphs(c);
-    char line[128];
-    std::snprintf(line, sizeof(line), "chosen chunk %d nt %d remap %u two %d (%.4f ms)", best_chunk, (int)best_nt,
-                  best_remap, (int)best_two, best);
+    char line[160];
+    std::snprintf(line, sizeof(line), "chosen chunk %d nt %d remap %u two %d rows %d (%.4f ms)", best_chunk,
+                  (int)best_nt, best_remap, (int)best_two,
+                  best_two ? (best_rows ? best_rows : two_step_rows_of(c->dm.prec)) : 0, best);
     rep += line;
     if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
     // the history buffer was overwritten by the trial sweeps: restart from phi0

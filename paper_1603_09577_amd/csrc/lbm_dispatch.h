@@ -17,13 +17,13 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
     auto *fo = (TS *)fout;
     auto *pp = (TP *)p;
     const dim3 grid((g.nblocks + g.chunk - 1) / g.chunk), block(kBlock);
-    // D2Q9 with every polynomial of degree <= 2: 3-term kernels
+    // D2Q9 with every polynomial of degree <= 2: 3-term kernels (32-bit offsets)
     if constexpr (Q == 9) {
-        if (dm.eqr && dm.deg3) {
+        if (dm.eqr && dm.deg3 && dm.o32) {
             const int c3 = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) | (dm.nt ? 8 : 0);
 #define LBM_SWEEP3(S, K, W, NT)                                                                       \
     case (NT * 8 + S * 4 + K * 2 + W):                                                                \
-        hipLaunchKernelGGL((k_sweep<Q, TS, TC, true, S, K, W, 3, NT>), grid, block, 0, st, g, cf, fi, fo, pp, flag); \
+        hipLaunchKernelGGL((k_sweep<Q, TS, TC, true, S, K, W, 3, NT, true>), grid, block, 0, st, g, cf, fi, fo, pp, flag); \
         break;
             switch (c3) {
                 LBM_SWEEP3(0, 0, 0, 0) LBM_SWEEP3(0, 0, 1, 0) LBM_SWEEP3(0, 1, 0, 0) LBM_SWEEP3(0, 1, 1, 0)
@@ -72,12 +72,10 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
 template <typename TS>
 constexpr int two_step_rows() { return sizeof(TS) == 8 ? 6 : 14; }
 
-template <int Q, typename TS, typename TC>
-hipError_t sweep2_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                        const void *pin, void *pout, int *flag, hipStream_t st) {
-    if (Q != 9 || !dm.eqr || dm.wall) return hipErrorNotSupported;
+template <typename TS, typename TC, int TH>
+hipError_t sweep2_rows(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                       const void *pin, void *pout, int *flag, hipStream_t st) {
     using TP = typename HistType<TS>::T;
-    constexpr int TH = two_step_rows<TS>();
     const auto *cf = (const Coefs<TC> *)coefs;
     const uint32_t tiles_x = (g.nx + 61) / 62, tiles_y = (g.ny + TH - 1) / TH;
     const dim3 grid(tiles_x * tiles_y), block(kBlock);
@@ -91,14 +89,45 @@ hipError_t sweep2_typed(const Dims &dm, const Geom &g, const void *coefs, const 
         hipLaunchKernelGGL((k_sweep2<TS, TC, S, K, NP, TH>), grid, block, 0, st, g, cf, fi, fo, pi, po, tiles_x, \
                            flag);                                                                    \
         break;
-    switch (code) {
-        LBM_SW2(0, 0, 9, 0) LBM_SW2(0, 1, 9, 0) LBM_SW2(1, 0, 9, 0) LBM_SW2(1, 1, 9, 0)
-        LBM_SW2(0, 0, 4, 1) LBM_SW2(0, 1, 4, 1) LBM_SW2(1, 0, 4, 1) LBM_SW2(1, 1, 4, 1)
-        LBM_SW2(0, 0, 3, 8) LBM_SW2(0, 1, 3, 8) LBM_SW2(1, 0, 3, 8) LBM_SW2(1, 1, 3, 8)
-        default: return hipErrorInvalidValue;
+    if constexpr (TH == two_step_rows<TS>()) {
+        switch (code) {
+            LBM_SW2(0, 0, 9, 0) LBM_SW2(0, 1, 9, 0) LBM_SW2(1, 0, 9, 0) LBM_SW2(1, 1, 9, 0)
+            LBM_SW2(0, 0, 4, 1) LBM_SW2(0, 1, 4, 1) LBM_SW2(1, 0, 4, 1) LBM_SW2(1, 1, 4, 1)
+            LBM_SW2(0, 0, 3, 8) LBM_SW2(0, 1, 3, 8) LBM_SW2(1, 0, 3, 8) LBM_SW2(1, 1, 3, 8)
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        // other tile heights: the 3-term kernels only
+        switch (code) {
+            LBM_SW2(0, 0, 3, 8) LBM_SW2(0, 1, 3, 8) LBM_SW2(1, 0, 3, 8) LBM_SW2(1, 1, 3, 8)
+            default: return hipErrorInvalidValue;
+        }
     }
 #undef LBM_SW2
     return hipGetLastError();
+}
+
+// Tile heights a two-step pass may use: the default by storage size, and for
+// 4- and 2-byte storage with 3-term polynomials also 10 and 6 rows (smaller
+// tiles: more workgroups per CU, more halo work).
+template <typename TS>
+constexpr bool two_step_rows_ok(int rows, bool deg3) {
+    return rows == two_step_rows<TS>() || (sizeof(TS) < 8 && deg3 && (rows == 10 || rows == 6));
+}
+
+template <int Q, typename TS, typename TC>
+hipError_t sweep2_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                        const void *pin, void *pout, int *flag, int rows, hipStream_t st) {
+    if (Q != 9 || !dm.eqr || dm.wall) return hipErrorNotSupported;
+    if (rows == 0) rows = two_step_rows<TS>();
+    if (!two_step_rows_ok<TS>(rows, dm.deg3)) return hipErrorInvalidValue;
+    if constexpr (sizeof(TS) == 8) {
+        return sweep2_rows<TS, TC, 6>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+    } else {
+        if (rows == 10) return sweep2_rows<TS, TC, 10>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+        if (rows == 6) return sweep2_rows<TS, TC, 6>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+        return sweep2_rows<TS, TC, 14>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+    }
 }
 
 // Scheme B and/or per-node fields: the general kernel (any polynomial length).
@@ -176,11 +205,11 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
     auto *po = (TC *)psi_out;
     const dim3 grid(g.nblocks), block(kBlock);
     if constexpr (Q == 9) {
-        if (dm.eqr && dm.deg3) {
+        if (dm.eqr && dm.deg3 && dm.o32) {
             const int c3 = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
 #define LBM_ADJ3(S, K, W)                                                                               \
     case (S * 4 + K * 2 + W):                                                                           \
-        hipLaunchKernelGGL((k_adjoint<Q, TS, TC, true, S, K, W, 3>), grid, block, 0, st, g, cf, fs, ps, pn, \
+        hipLaunchKernelGGL((k_adjoint<Q, TS, TC, true, S, K, W, 3, true>), grid, block, 0, st, g, cf, fs, ps, pn, \
                            pi_next, po, pi_out, gk_part);                                               \
         break;
             switch (c3) {

@@ -71,6 +71,7 @@ struct Dims {
     bool wall;            // walls on the last axis
     bool lowdeg;          // every polynomial of degree <= 3 (C-bar <= 5)
     bool deg3 = false;    // every polynomial of degree <= 2 (C-bar <= 3): 3-term kernels (D2Q9)
+    bool o32 = false;     // every indexed array spans < 4 GiB: 32-bit byte offsets (the 3-term and two-step kernels)
     bool nt;              // non-temporal distribution accesses
     bool sb;              // Scheme B (Eq. 33-35): stored fbar, explicit source
 };
@@ -124,7 +125,9 @@ hipError_t launch_zero(double *p, uint32_t n, hipStream_t st);
 
 // Two time steps per pass, D2Q9 only (sweep_d2q9.hip); rows per tile by precision.
 hipError_t launch_sweep2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                            const void *pin, void *pout, int *flag, hipStream_t st);
+                            const void *pin, void *pout, int *flag, int rows, hipStream_t st);
+// tile heights a two-step pass may use (0: the default)
+bool two_step_rows_allowed(int prec, int rows, bool deg3);
 int two_step_rows_of(int prec);
 int adjoint_pair_rows(int prec, uint32_t nx, uint32_t ny);
 // Two reversed sweeps per pass (sweep s, then s - 1), D2Q9 only; tile rows

@@ -17,6 +17,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm_internal.h"
 #include "lbm_lattice.h"
 
@@ -46,6 +48,20 @@ template <bool NT = false, typename TS, typename TC>
 __device__ __forceinline__ void store_s(TS *p, TC v) {
     if (NT) __builtin_nontemporal_store((TS)v, p);
     else *p = (TS)v;
+}
+
+// Element idx of an array starting at `base`.  With O32 the host has checked
+// that every array the kernel indexes spans less than 4 GiB, so the byte
+// offset is formed in 32 bits: an access is then a scalar base plus one
+// 32-bit vector offset, with no 64-bit address arithmetic per access.
+template <bool O32, typename T>
+__device__ __forceinline__ T *at(T *base, uint32_t idx) {
+    if constexpr (O32) {
+        using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+        return reinterpret_cast<T *>(reinterpret_cast<B *>(base) + idx * (uint32_t)sizeof(T));
+    } else {
+        return base + idx;
+    }
 }
 
 // sum_{p < N} c[p] x^p by Horner over a compile-time length: no branches;
@@ -241,7 +257,7 @@ __device__ __forceinline__ NodeGeo node_geometry(const Geom &g, uint32_t n) {
 }
 
 // Gather g_k(x) (offset form) with periodic wrap and anti-bounce-back walls.
-template <int Q, bool WALL, bool NT = false, typename TS, typename TC>
+template <int Q, bool WALL, bool NT = false, bool O32 = false, typename TS, typename TC>
 __device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restrict__ cf,
                                        const TS *__restrict__ fin, const NodeGeo &ng, TC *h) {
     using L = Lattice<Q>;
@@ -256,9 +272,9 @@ __device__ __forceinline__ void gather(const Geom &g, const Coefs<TC> *__restric
         }
         const int cl = L::c(k, D - 1);
         if (WALL && ((cl == 1 && ng.lo) || (cl == -1 && ng.hi))) {
-            h[k] = -load_s<TC, NT>(fin + (uint64_t)L::opp(k) * g.plane + ng.n) + cf->ew[cl == 1 ? 0 : 1][k];
+            h[k] = -load_s<TC, NT>(at<O32>(fin + (uint64_t)L::opp(k) * g.plane, ng.n)) + cf->ew[cl == 1 ? 0 : 1][k];
         } else {
-            h[k] = load_s<TC, NT>(fin + (uint64_t)k * g.plane + (uint32_t)((int)ng.n + off));
+            h[k] = load_s<TC, NT>(at<O32>(fin + (uint64_t)k * g.plane, (uint32_t)((int)ng.n + off)));
         }
     }
 }
@@ -569,7 +585,7 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
 }
 
 template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT = false,
-          bool SB = false, bool KF = false>
+          bool SB = false, bool KF = false, bool O32 = false>
 __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__restrict__ cf,
                                            const TS *__restrict__ fin, TS *__restrict__ fout,
                                            typename HistType<TS>::T *p, int *flag, uint32_t n,
@@ -578,20 +594,20 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     const NodeGeo ng = node_geometry<Q, WALL>(g, n);
 
     TC h[Q];
-    gather<Q, WALL, NT>(g, cf, fin, ng, h);
+    gather<Q, WALL, NT, O32>(g, cf, fin, ng, h);
     // history read issued together with the gathers, so its latency overlaps theirs
-    const TC pp_off = (SRC || rem3) ? (TC)p[n] : TC(0);
+    const TC pp_off = (SRC || rem3) ? (TC)*at<O32>(p, n) : TC(0);
     TC out[Q];
     const TC phio = collide_node<Q, TC, EQR, SRC, KVAR, NP, SB, KF>(cf, h, pp_off, n, kfield, rfield, rem3, out);
-    if (SRC || rem3) p[n] = (typename HistType<TS>::T)phio;
+    if (SRC || rem3) *at<O32>(p, n) = (typename HistType<TS>::T)phio;
 
 #pragma unroll
-    for (int k = 0; k < Q; ++k) store_s<NT>(fout + (uint64_t)k * g.plane + n, out[k]);
+    for (int k = 0; k < Q; ++k) store_s<NT>(at<O32>(fout + (uint64_t)k * g.plane, n), out[k]);
 
     if (!__builtin_isfinite(phio)) *flag = 1;
 }
 
-template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT>
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT, bool O32 = false>
 __global__ void __launch_bounds__(kBlock)
 k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin,
         TS *__restrict__ fout, typename HistType<TS>::T *p, int *flag) {
@@ -601,7 +617,7 @@ k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f
     for (uint32_t i = 0; i < g.chunk; ++i) {
         const uint32_t n = (first + i) * kBlock + threadIdx.x;
         if (n >= g.N) return;
-        sweep_node<Q, TS, TC, EQR, SRC, KVAR, WALL, NP, NT>(g, cf, fin, fout, p, flag, n);
+        sweep_node<Q, TS, TC, EQR, SRC, KVAR, WALL, NP, NT, false, false, O32>(g, cf, fin, fout, p, flag, n);
     }
 }
 
@@ -646,8 +662,8 @@ k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ 
         const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
         const NodeGeo ng = node_geometry<9, false>(g, n);
         TC h[9];
-        gather<9, false>(g, cf, fin, ng, h);
-        const TC pp_off = SRC ? (TC)pin[n] : TC(0);
+        gather<9, false, false, true>(g, cf, fin, ng, h);
+        const TC pp_off = SRC ? (TC)*at<true>(pin, n) : TC(0);
         TC out[9];
         const TC phio = collide_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, n, nullptr, nullptr, false, out);
 #pragma unroll
@@ -671,8 +687,8 @@ k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ 
             if (x < nx && y < ny) {
                 const uint32_t m = (uint32_t)y * g.nx + (uint32_t)x;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) store_s(fout + (uint64_t)k * g.plane + m, out[k]);
-                if (SRC) pout[m] = (TP)phio;
+                for (int k = 0; k < 9; ++k) store_s(at<true>(fout + (uint64_t)k * g.plane, m), out[k]);
+                if (SRC) *at<true>(pout, m) = (TP)phio;
             }
         }
     }

@@ -287,8 +287,10 @@ class Lbm:
         return buf.value.decode()
 
     def set_two_step(self, on):
-        """Two time steps per pass inside step() (D2Q9 periodic equal-rate runs)."""
-        _check(self.lib.lbm_set_two_step(self.ctx, int(bool(on))))
+        """Two time steps per pass inside step() (D2Q9 periodic equal-rate runs):
+        False/True, or a tile height (lbm_set_two_step)."""
+        mode = int(on) if (isinstance(on, int) and not isinstance(on, bool)) else int(bool(on))
+        _check(self.lib.lbm_set_two_step(self.ctx, mode))
 
     def set_check(self, every):
         _check(self.lib.lbm_set_check(self.ctx, int(every)))

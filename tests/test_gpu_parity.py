@@ -256,11 +256,13 @@ def test_launch_variants_identical():
         assert torch.equal(s.phi(), want)
 
 
-@pytest.mark.parametrize("nx,ny,prec,source", [(100, 37, "f32", True), (190, 23, "f64", True),
-                                               (130, 50, "f16", True), (64, 16, "f32", False),
-                                               (257, 91, "f64", False)])
-def test_two_step_passes_bit_identical(nx, ny, prec, source):
-    """Two time steps per pass (LDS tiles of 62 x 14 or 62 x 6 nodes with a
+@pytest.mark.parametrize("nx,ny,prec,source,rows", [(100, 37, "f32", True, 1), (190, 23, "f64", True, 1),
+                                                    (130, 50, "f16", True, 1), (64, 16, "f32", False, 1),
+                                                    (257, 91, "f64", False, 1), (100, 37, "f32", True, 10),
+                                                    (131, 29, "f32", True, 6), (130, 50, "f16", True, 10),
+                                                    (64, 16, "f16", False, 6)])
+def test_two_step_passes_bit_identical(nx, ny, prec, source, rows):
+    """Two time steps per pass (LDS tiles of 62 x 14, 10 or 6 nodes with a
     one-node halo) against single sweeps: the same arithmetic on the same
     inputs, so phi, the stored state and the phi history agree bit for bit,
     across graph replays, passes in pairs and single-sweep remainders; and the
@@ -268,11 +270,11 @@ def test_two_step_passes_bit_identical(nx, ny, prec, source):
     lbm = _lbm()
     spec = W.spec_nonlinear_2d(nx, ny, source=source, precision=prec)
     phi0 = W.noise_field((ny, nx), 71)
-    say(f"[gpu] two-step passes {nx}x{ny} {prec} source={source}")
+    say(f"[gpu] two-step passes {nx}x{ny} {prec} source={source} rows={rows}")
     a = lbm.Lbm(spec).init(phi0)
     a.set_two_step(False)
     b = lbm.Lbm(spec).init(phi0)
-    b.set_two_step(True)
+    b.set_two_step(rows)
     t = 0
     for s in (4, 8, 37, 70):
         a.step(s - t)
@@ -298,3 +300,11 @@ def test_two_step_refused_where_it_does_not_apply():
         with pytest.raises(lbm.LbmError) as ei:
             s.set_two_step(True)
         assert ei.value.code == lbm.LBM_E_UNSUPPORTED
+    # tile heights other than the default: 3-term polynomials, 4- and 2-byte storage only
+    for spec, rows in ((W.spec_nonlinear_2d(100, 37, precision="f64"), 10),
+                       (W.spec_nonlinear_2d(100, 37, precision="f32"), 12),
+                       (W.spec_nonlinear_2d(100, 37, precision="f32", bcoef=0.0) | {"b": [[0, 0, 0, 0.1]] * 2}, 10)):
+        s = lbm.Lbm(spec)
+        with pytest.raises(lbm.LbmError) as ei:
+            s.set_two_step(rows)
+        assert ei.value.code == lbm.LBM_E_INVALID
