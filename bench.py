@@ -98,8 +98,8 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_ste
         sim.set_two_step(two_step)
         rep += f"; two steps per pass forced {'on' if two_step else 'off'}"
     two = (" two 1" in rep) if two_step is None else bool(two_step)
-    m = re.search(r" rows (\d+)", rep)
-    rows = int(m.group(1)) if (two and m) else None
+    m = re.search(r" rows (\d+) waves (\d+)", rep)
+    rows = f"{m.group(1)} rows x {m.group(2)} waves" if (two and m) else None
     per, wall = time_steps(torch, sim, steps, warmup)
     N = sim.N
     prec = spec.get("precision", "f64")
@@ -282,21 +282,21 @@ PROFILE_COMMANDS = {
 
 # workload label -> (kernel name prefix in the trace, algorithmic bytes per launch)
 PROFILED = {
-    "nonlinear2d-1024 f32 two-step": ("k_sweep2<float, float, true, true, 3, 14>",
+    "nonlinear2d-1024 f32 two-step": ("k_sweep2<float, float, true, true, 3, ",
                                       bytes_per_node(9, "f32", True) * 1024 * 1024),
-    "nonlinear2d-1024 f64 two-step": ("k_sweep2<double, double, true, true, 3, 6>",
+    "nonlinear2d-1024 f64 two-step": ("k_sweep2<double, double, true, true, 3, ",
                                       bytes_per_node(9, "f64", True) * 1024 * 1024),
-    "nonlinear2d-1024 f32": ("k_sweep<9, float, float, true, true, true, false, 3, false>",
+    "nonlinear2d-1024 f32": ("k_sweep<9, float, float, true, true, true, false, 3, false, ",
                              bytes_per_node(9, "f32", True) * 1024 * 1024),
-    "nonlinear2d-1024 f64": ("k_sweep<9, double, double, true, true, true, false, 3, false>",
+    "nonlinear2d-1024 f64": ("k_sweep<9, double, double, true, true, true, false, 3, false, ",
                              bytes_per_node(9, "f64", True) * 1024 * 1024),
-    "d3q19-256 f32": ("k_sweep<19, float, float, true, false, false, true, 4, true>",
+    "d3q19-256 f32": ("k_sweep<19, float, float, true, false, false, true, 4, true, ",
                       bytes_per_node(19, "f32", False) * 256 ** 3),
-    "d3q19-256 f64": ("k_sweep<19, double, double, true, false, false, true, 4, true>",
+    "d3q19-256 f64": ("k_sweep<19, double, double, true, false, false, true, 4, true, ",
                       bytes_per_node(19, "f64", False) * 256 ** 3),
-    "adjoint2d-512 f64": ("k_adjoint<9, double, double, true, true, true, false, 3>",
+    "adjoint2d-512 f64": ("k_adjoint<9, double, double, true, true, true, false, 3, ",
                           adjoint_bytes_per_node(9, "f64", True) * 512 * 512),
-    "adjoint2d-512 f32": ("k_adjoint<9, float, float, true, true, true, false, 3>",
+    "adjoint2d-512 f32": ("k_adjoint<9, float, float, true, true, true, false, 3, ",
                           adjoint_bytes_per_node(9, "f32", True) * 512 * 512),
 }
 
@@ -341,15 +341,22 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
            "commands": PROFILE_COMMANDS, "workloads": {}}
     rows = []
     for label, (kn, alg) in PROFILED.items():
-        hits = [k for k in fetch if kn in k]
-        if not hits or hits[0] not in write:
+        # the variant with the most dispatches: the timed run, not the tuner's trials
+        hits = sorted((k for k in fetch if kn in k and k in write), key=lambda k: -len(fetch[k]))
+        if not hits:
             continue
         k = hits[0]
+        prefix, kn = kn, k.replace("lbm::", "")
         fv, wv = stats.median(fetch[k]), stats.median(write[k])
         t = fv * 1024 * fscale + wv * 1024 * wscale
-        tr = next((v for n, v in med_us.items() if kn in n), None)
+        # trace time: the same variant if the trace run timed it most, else the
+        # most-dispatched variant there (traffic does not depend on the tile shape)
+        tk = sorted((n for n in durs if prefix in n), key=lambda n: -len(durs[n]))
+        tr = med_us.get(tk[0]) if tk else None
         if tr is None:
             tr = next((v for n, v in avg_us.items() if kn in n), None)
+        if tk and kn not in tk[0]:
+            kn = f"{kn} (counters); {tk[0].replace('lbm::', '')} (trace)"
         out["workloads"][label] = {"kernel": kn, "fetch_kib": fv, "write_kib": wv,
                                    "traffic_bytes_per_launch": t, "algorithmic_bytes_per_launch": alg,
                                    "dispatches": len(fetch[k]), "trace_median_us": tr}
@@ -516,7 +523,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": head["achieved_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": head["hbm_frac"], "traffic": traffic,
-            "kernel": (f"k_sweep2<float, float, SRC, KVAR, 3-term polynomials, {head['tile_rows']} rows> "
+            "kernel": (f"k_sweep2<float, float, SRC, KVAR, 3-term polynomials, {head['tile_rows']}> "
                        "(two steps per pass)"
                        if head["two_step"] else "k_sweep<9, float, float, EQR, SRC, KVAR, !WALL, 3-term polynomials>"),
             "bytes_per_node": head["bytes_per_node"], "nodes_per_launch": head["nodes"],

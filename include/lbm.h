@@ -199,13 +199,21 @@ int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_l
  * use single sweeps.  On by default where it applies (lbm_tune times it
  * against single sweeps); not used with a divergence check, Scheme B sources,
  * per-node fields or Remark III.
- * mode: 0 off, 1 on with the default tile height (14 rows for 4- and 2-byte
- * storage, 6 for FP64), or a tile height: 10 or 6 for 4- and 2-byte storage
- * when every polynomial has degree <= 2 (more workgroups per CU, more halo
- * work); lbm_tune times them all.
+ * mode: 0 off; k >= 1 on with tile shape k - 1 (lbm_two_step_shape; shape 0,
+ * the default, is 14 rows x 4 waves for 4- and 2-byte storage and 6 x 4 for
+ * FP64).  The other shapes need every polynomial of degree <= 2; lbm_tune
+ * times them all.
  * Errors: LBM_E_UNSUPPORTED when the run does not qualify; LBM_E_INVALID for a
- * tile height that is not available. */
+ * shape that is not available here. */
 int lbm_set_two_step(lbm_ctx *ctx, int mode);
+
+/* Tile shape `shape` of two-step passes for this context's storage type: tile
+ * rows (the tile is 62 x rows nodes, the workgroup's LDS holds 64 x (rows + 2))
+ * and waves per workgroup.  4- and 2-byte storage: 14 x 4, 14 x 8, 10 x 6,
+ * 6 x 4; FP64: 6 x 4, 6 x 8, 14 x 16.  More waves per workgroup
+ * (fewer rows each) fit more waves per CU; fewer rows per tile cost more halo
+ * work.  LBM_E_INVALID past the last shape. */
+int lbm_two_step_shape(const lbm_ctx *ctx, int shape, int *rows, int *waves);
 
 /* Divergence check every `every` steps inside lbm_step (0 = off). */
 int lbm_set_check(lbm_ctx *ctx, int every);

@@ -64,7 +64,7 @@ struct lbm_ctx {
     // history buffer owned by the context, and whether the path is on
     void *p2 = nullptr;
     bool two_ok = false, two = false;
-    int two_rows = 0;         // tile rows of two-step passes (0: the default for the storage type)
+    int two_shape = 0;        // tile shape of two-step passes (two_step_shape_of; 0: the default)
     uint32_t adj_slots = 0;   // K0 partial slots: workgroups of the one- and two-sweep adjoints
     bool bound = false;
     // graphs of kGraphSteps sweeps starting from buffer 0 / 1, captured on an
@@ -353,10 +353,10 @@ bool two_active(const lbm_ctx *c) { return c->two && c->two_ok && !general_path(
 // would leave them.
 hipError_t sweep_pair(lbm_ctx *c, int start, hipStream_t st) {
     hipError_t e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, c->p2, c->d_flag,
-                                    c->two_rows, st);
+                                    c->two_shape, st);
     if (e == hipSuccess)
         e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], c->p2, c->p, c->d_flag,
-                             c->two_rows, st);
+                             c->two_shape, st);
     return e;
 }
 
@@ -640,18 +640,32 @@ int lbm_recenter(lbm_ctx *c, void *stream) {
     return LBM_OK;
 }
 
+// a tile shape usable here: in the table, 3-term polynomials for the
+// non-default shapes, and rows + 2 <= ny
+static bool two_shape_usable(const lbm_ctx *c, int shape) {
+    int rows = 0, waves = 0;
+    if (!two_step_shape_of(c->dm.prec, shape, &rows, &waves)) return false;
+    return (shape == 0 || c->dm.deg3) && (uint32_t)rows + 2 <= c->g.ny;
+}
+
+int lbm_two_step_shape(const lbm_ctx *c, int shape, int *rows, int *waves) {
+    if (!c || !rows || !waves) return fail(LBM_E_INVALID, "null argument");
+    if (!two_step_shape_of(c->dm.prec, shape, rows, waves)) return fail(LBM_E_INVALID, "no such tile shape");
+    return LBM_OK;
+}
+
 int lbm_set_two_step(lbm_ctx *c, int mode) {
     if (!c) return fail(LBM_E_INVALID, "null context");
-    if (mode < 0) return fail(LBM_E_INVALID, "mode must be 0, 1 or a tile height");
+    if (mode < 0) return fail(LBM_E_INVALID, "mode must be 0 (off) or 1 + a tile shape");
     if (mode && !c->two_ok)
         return fail(LBM_E_UNSUPPORTED, "two steps per pass need D2Q9, periodic axes, equal non-flux rates and a grid "
                                        "of at least 64 x (tile rows + 2)");
-    const int rows = mode > 1 ? mode : 0;
-    if (rows && !two_step_rows_allowed(c->dm.prec, rows, c->dm.deg3))
-        return fail(LBM_E_INVALID, "tile height not available for this storage type and polynomial length");
+    const int shape = mode > 0 ? mode - 1 : 0;
+    if (mode && !two_shape_usable(c, shape))
+        return fail(LBM_E_INVALID, "tile shape not available for this storage type, polynomial length or grid");
     drop_graphs(c);
     c->two = mode != 0;
-    c->two_rows = rows;
+    c->two_shape = shape;
     return LBM_OK;
 }
 
@@ -917,17 +931,24 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
     }
     // two steps per pass: time pairs of passes (four steps), per step
     bool best_two = false;
-    int best_rows = 0;
+    int best_shape = 0;
     c->g.chunk = (uint32_t)best_chunk;
     c->dm.nt = best_nt;
     if (c->two_ok && !general_path(c)) {
-        const int pair_reps = std::max(1, reps / 4);
-        static const int row_cands[] = {0, 10, 6};
-        for (int ri = 0; ri < remaps * 3; ++ri) {
-            const int rows = row_cands[ri / remaps];
-            if (rows && ((uint32_t)rows + 2 > c->g.ny || !two_step_rows_allowed(c->dm.prec, rows, c->dm.deg3)))
-                continue;
-            c->two_rows = rows;
+        // four steps per pair; twice the steps of a single-sweep trial, as the
+        // shapes differ by a few per cent
+        const int pair_reps = std::max(2, reps / 2);
+        // shapes in order of preference (FP32 1024^2: 14 x 8 and 6 x 4 within 1%,
+        // 14 x 4 4% and 10 x 6 5% slower; FP64: 6 x 8 and 14 x 16 equal, 6 x 4 4%
+        // slower); a later shape must be 2% faster to replace an earlier one,
+        // so near-ties resolve the same way in every run
+        static const int order4[4] = {1, 3, 0, 2}, order8[3] = {1, 2, 0};
+        const int nshape = c->dm.prec == 0 ? 3 : 4;
+        float best_two_ms = 1e30f;
+        for (int ri = 0; ri < remaps * nshape; ++ri) {
+            const int shape = c->dm.prec == 0 ? order8[ri / remaps] : order4[ri / remaps];
+            if (!two_shape_usable(c, shape)) continue;
+            c->two_shape = shape;
             c->g.remap = (remaps == 2 && ri % remaps == 0) ? 1u : 0u;
             hipError_t e = sweep_pair(c, c->cur, st);
             if (e == hipSuccess) e = hipEventRecord(e0, st);
@@ -941,23 +962,30 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
                 return hip_fail(e, "tuning two-step sweep");
             }
             ms /= 4 * pair_reps;
-            char line[96];
-            std::snprintf(line, sizeof(line), "two steps per pass rows %d remap %u: %.4f ms per step\n",
-                          rows ? rows : two_step_rows_of(c->dm.prec), c->g.remap, ms);
+            int rows = 0, waves = 0;
+            two_step_shape_of(c->dm.prec, shape, &rows, &waves);
+            char line[112];
+            std::snprintf(line, sizeof(line), "two steps per pass rows %d waves %d remap %u: %.4f ms per step\n",
+                          rows, waves, c->g.remap, ms);
             rep += line;
-            if (ms < best) { best = ms; best_two = true; best_remap = c->g.remap; best_rows = rows; }
+            if (ms < 0.98f * best_two_ms || (shape == best_shape && ms < best_two_ms)) {
+                best_two_ms = ms;
+                best_shape = shape;
+                if (ms < best) { best = ms; best_two = true; best_remap = c->g.remap; }
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->g.remap = best_remap;
     c->two = best_two;
-    c->two_rows = best_rows;
+    c->two_shape = best_shape;
     drop_graphs(c);
+    int brows = 0, bwaves = 0;
+    if (best_two) two_step_shape_of(c->dm.prec, best_shape, &brows, &bwaves);
     char line[160];
-    std::snprintf(line, sizeof(line), "chosen chunk %d nt %d remap %u two %d rows %d (%.4f ms)", best_chunk,
-                  (int)best_nt, best_remap, (int)best_two,
-                  best_two ? (best_rows ? best_rows : two_step_rows_of(c->dm.prec)) : 0, best);
+    std::snprintf(line, sizeof(line), "chosen chunk %d nt %d remap %u two %d rows %d waves %d (%.4f ms)", best_chunk,
+                  (int)best_nt, best_remap, (int)best_two, brows, bwaves, best);
     rep += line;
     if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
     // the history buffer was overwritten by the trial sweeps: restart from phi0

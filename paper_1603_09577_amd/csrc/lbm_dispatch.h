@@ -72,13 +72,13 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
 template <typename TS>
 constexpr int two_step_rows() { return sizeof(TS) == 8 ? 6 : 14; }
 
-template <typename TS, typename TC, int TH>
-hipError_t sweep2_rows(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                       const void *pin, void *pout, int *flag, hipStream_t st) {
+template <typename TS, typename TC, int TH, int NW>
+hipError_t sweep2_shape(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                        const void *pin, void *pout, int *flag, hipStream_t st) {
     using TP = typename HistType<TS>::T;
     const auto *cf = (const Coefs<TC> *)coefs;
     const uint32_t tiles_x = (g.nx + 61) / 62, tiles_y = (g.ny + TH - 1) / TH;
-    const dim3 grid(tiles_x * tiles_y), block(kBlock);
+    const dim3 grid(tiles_x * tiles_y), block(64 * NW);
     const TS *fi = (const TS *)fin;
     TS *fo = (TS *)fout;
     const TP *pi = (const TP *)pin;
@@ -86,10 +86,10 @@ hipError_t sweep2_rows(const Dims &dm, const Geom &g, const void *coefs, const v
     const int code = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.deg3 ? 8 : (dm.lowdeg ? 1 : 0));
 #define LBM_SW2(S, K, NP, TAG)                                                                       \
     case (S * 4 + K * 2 + TAG):                                                                      \
-        hipLaunchKernelGGL((k_sweep2<TS, TC, S, K, NP, TH>), grid, block, 0, st, g, cf, fi, fo, pi, po, tiles_x, \
-                           flag);                                                                    \
+        hipLaunchKernelGGL((k_sweep2<TS, TC, S, K, NP, TH, NW>), grid, block, 0, st, g, cf, fi, fo, pi, po, \
+                           tiles_x, flag);                                                           \
         break;
-    if constexpr (TH == two_step_rows<TS>()) {
+    if constexpr (TH == two_step_rows<TS>() && NW == kBlock / 64) {
         switch (code) {
             LBM_SW2(0, 0, 9, 0) LBM_SW2(0, 1, 9, 0) LBM_SW2(1, 0, 9, 0) LBM_SW2(1, 1, 9, 0)
             LBM_SW2(0, 0, 4, 1) LBM_SW2(0, 1, 4, 1) LBM_SW2(1, 0, 4, 1) LBM_SW2(1, 1, 4, 1)
@@ -97,7 +97,7 @@ hipError_t sweep2_rows(const Dims &dm, const Geom &g, const void *coefs, const v
             default: return hipErrorInvalidValue;
         }
     } else {
-        // other tile heights: the 3-term kernels only
+        // the other tile shapes: 3-term kernels only
         switch (code) {
             LBM_SW2(0, 0, 3, 8) LBM_SW2(0, 1, 3, 8) LBM_SW2(1, 0, 3, 8) LBM_SW2(1, 1, 3, 8)
             default: return hipErrorInvalidValue;
@@ -107,26 +107,37 @@ hipError_t sweep2_rows(const Dims &dm, const Geom &g, const void *coefs, const v
     return hipGetLastError();
 }
 
-// Tile heights a two-step pass may use: the default by storage size, and for
-// 4- and 2-byte storage with 3-term polynomials also 10 and 6 rows (smaller
-// tiles: more workgroups per CU, more halo work).
+// Tile shapes of a two-step pass, (rows, waves per workgroup).  Shape 0 is the
+// default for the storage size; the others (3-term polynomials only) trade
+// halo work against waves per CU: phase 1 gives each wave (rows + 2) / waves
+// rows, and fewer rows per wave need fewer registers.
 template <typename TS>
-constexpr bool two_step_rows_ok(int rows, bool deg3) {
-    return rows == two_step_rows<TS>() || (sizeof(TS) < 8 && deg3 && (rows == 10 || rows == 6));
+constexpr int two_step_shape_count() { return sizeof(TS) == 8 ? 3 : 4; }
+
+template <typename TS>
+constexpr bool two_step_shape(int id, int &rows, int &waves) {
+    constexpr int r8[3][2] = {{6, 4}, {6, 8}, {14, 16}};
+    constexpr int r4[4][2] = {{14, 4}, {14, 8}, {10, 6}, {6, 4}};
+    if (id < 0 || id >= two_step_shape_count<TS>()) return false;
+    rows = sizeof(TS) == 8 ? r8[id][0] : r4[id][0];
+    waves = sizeof(TS) == 8 ? r8[id][1] : r4[id][1];
+    return true;
 }
 
 template <int Q, typename TS, typename TC>
 hipError_t sweep2_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                        const void *pin, void *pout, int *flag, int rows, hipStream_t st) {
+                        const void *pin, void *pout, int *flag, int shape, hipStream_t st) {
     if (Q != 9 || !dm.eqr || dm.wall) return hipErrorNotSupported;
-    if (rows == 0) rows = two_step_rows<TS>();
-    if (!two_step_rows_ok<TS>(rows, dm.deg3)) return hipErrorInvalidValue;
+    if (shape < 0 || shape >= two_step_shape_count<TS>() || (shape > 0 && !dm.deg3)) return hipErrorInvalidValue;
     if constexpr (sizeof(TS) == 8) {
-        return sweep2_rows<TS, TC, 6>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+        if (shape == 1) return sweep2_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+        if (shape == 2) return sweep2_shape<TS, TC, 14, 16>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+        return sweep2_shape<TS, TC, 6, 4>(dm, g, coefs, fin, fout, pin, pout, flag, st);
     } else {
-        if (rows == 10) return sweep2_rows<TS, TC, 10>(dm, g, coefs, fin, fout, pin, pout, flag, st);
-        if (rows == 6) return sweep2_rows<TS, TC, 6>(dm, g, coefs, fin, fout, pin, pout, flag, st);
-        return sweep2_rows<TS, TC, 14>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+        if (shape == 1) return sweep2_shape<TS, TC, 14, 8>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+        if (shape == 2) return sweep2_shape<TS, TC, 10, 6>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+        if (shape == 3) return sweep2_shape<TS, TC, 6, 4>(dm, g, coefs, fin, fout, pin, pout, flag, st);
+        return sweep2_shape<TS, TC, 14, 4>(dm, g, coefs, fin, fout, pin, pout, flag, st);
     }
 }
 

@@ -632,17 +632,18 @@ k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f
 // result equals two single sweeps bit for bit; the state is read and written
 // once per two steps.  The phi history is read at halo nodes, which another
 // tile may already have advanced, so it is read from `pin` and written to
-// `pout` (two history buffers, alternating).
+// `pout` (two history buffers, alternating).  NW waves per workgroup share
+// the TH + 2 rows of phase 1 (more waves: fewer rows and registers per wave).
 // ---------------------------------------------------------------------------
-template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH>
-__global__ void __launch_bounds__(kBlock)
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW = kBlock / 64>
+__global__ void __launch_bounds__(64 * NW)
 k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
          const typename HistType<TS>::T *__restrict__ pin, typename HistType<TS>::T *__restrict__ pout,
          uint32_t tiles_x, int *flag) {
     using L = Lattice<9>;
     using TP = typename HistType<TS>::T;
     constexpr int TX = 64, TR = TH + 2;
-    static_assert(TR % (kBlock / 64) == 0, "tile rows must split evenly over the waves");
+    static_assert(TR % NW == 0, "tile rows must split evenly over the waves");
     __shared__ TS lf[9][TR][TX];
     __shared__ TP lp[TR][TX];
     const uint32_t tile = block_index(blockIdx.x, gridDim.x, g.remap);
@@ -655,8 +656,8 @@ k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ 
     int xg = x0 - 1 + lane;
     xg = xg < 0 ? xg + nx : (xg >= nx ? xg - nx : xg);
 #pragma unroll
-    for (int i = 0; i < TR / (kBlock / 64); ++i) {
-        const int r = wv + i * (kBlock / 64);
+    for (int i = 0; i < TR / NW; ++i) {
+        const int r = wv + i * NW;
         int yg = y0 - 1 + r;   // in [-1, ny + TH - 1], ny >= TH + 2: one wrap
         yg = yg < 0 ? yg + ny : (yg >= ny ? yg - ny : yg);
         const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
@@ -675,7 +676,7 @@ k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ 
     // phase 2: interior lanes 1..62, rows 1..TH
     if (lane >= 1 && lane <= TX - 2) {
         const int x = x0 + lane - 1;
-        for (int r = 1 + wv; r <= TH; r += kBlock / 64) {
+        for (int r = 1 + wv; r <= TH; r += NW) {
             const int y = y0 + r - 1;
             TC h[9];
 #pragma unroll

@@ -59,12 +59,15 @@ hipError_t launch_set_wall_q9(const Dims &dm, void *coefs, const double *ewp, hi
 
 
 hipError_t launch_sweep2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                            const void *pin, void *pout, int *flag, int rows, hipStream_t st) {
-    LBM_BY_PREC(sweep2_typed, dm, g, coefs, fin, fout, pin, pout, flag, rows, st)
+                            const void *pin, void *pout, int *flag, int shape, hipStream_t st) {
+    LBM_BY_PREC(sweep2_typed, dm, g, coefs, fin, fout, pin, pout, flag, shape, st)
 }
 
-bool two_step_rows_allowed(int prec, int rows, bool deg3) {
-    return prec == 0 ? two_step_rows_ok<double>(rows, deg3) : two_step_rows_ok<float>(rows, deg3);
+bool two_step_shape_of(int prec, int shape, int *rows, int *waves) {
+    int r = 0, w = 0;
+    const bool ok = prec == 0 ? two_step_shape<double>(shape, r, w) : two_step_shape<float>(shape, r, w);
+    if (ok) { *rows = r; *waves = w; }
+    return ok;
 }
 
 hipError_t launch_adjoint2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,

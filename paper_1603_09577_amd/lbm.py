@@ -33,7 +33,7 @@ EXPORTS = [
     "lbm_batch_step", "lbm_batch_get_phi", "lbm_batch_tune", "lbm_batch_set_shape",
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
     "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields", "lbm_set_phi_wall",
-    "lbm_set_two_step", "lbm_adjoint_step2", "lbm_adjoint_pair_ok",
+    "lbm_set_two_step", "lbm_two_step_shape", "lbm_adjoint_step2", "lbm_adjoint_pair_ok",
 ]
 
 
@@ -126,6 +126,8 @@ def load():
         "lbm_set_fields": ([_VP, _VP, _VP], ctypes.c_int),
         "lbm_set_phi_wall": ([_VP, ctypes.c_double, ctypes.c_double, _VP], ctypes.c_int),
         "lbm_set_two_step": ([_VP, ctypes.c_int], ctypes.c_int),
+        "lbm_two_step_shape": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                               ctypes.c_int),
         "lbm_adjoint_step2": ([_VP] * 10, ctypes.c_int),
         "lbm_adjoint_pair_ok": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     }
@@ -286,11 +288,19 @@ class Lbm:
         _check(self.lib.lbm_tune(self.ctx, int(reps), _stream(stream), buf, len(buf)))
         return buf.value.decode()
 
-    def set_two_step(self, on):
-        """Two time steps per pass inside step() (D2Q9 periodic equal-rate runs):
-        False/True, or a tile height (lbm_set_two_step)."""
-        mode = int(on) if (isinstance(on, int) and not isinstance(on, bool)) else int(bool(on))
-        _check(self.lib.lbm_set_two_step(self.ctx, mode))
+    def set_two_step(self, on, shape=0):
+        """Two time steps per pass inside step() (D2Q9 periodic equal-rate
+        runs), with tile shape `shape` (lbm_set_two_step, two_step_shapes)."""
+        _check(self.lib.lbm_set_two_step(self.ctx, 1 + int(shape) if on else 0))
+
+    def two_step_shapes(self):
+        """[(rows, waves per workgroup)] of the two-step tile shapes."""
+        out, i = [], 0
+        r, w = ctypes.c_int(), ctypes.c_int()
+        while self.lib.lbm_two_step_shape(self.ctx, i, ctypes.byref(r), ctypes.byref(w)) == 0:
+            out.append((r.value, w.value))
+            i += 1
+        return out
 
     def set_check(self, every):
         _check(self.lib.lbm_set_check(self.ctx, int(every)))

@@ -256,25 +256,26 @@ def test_launch_variants_identical():
         assert torch.equal(s.phi(), want)
 
 
-@pytest.mark.parametrize("nx,ny,prec,source,rows", [(100, 37, "f32", True, 1), (190, 23, "f64", True, 1),
-                                                    (130, 50, "f16", True, 1), (64, 16, "f32", False, 1),
-                                                    (257, 91, "f64", False, 1), (100, 37, "f32", True, 10),
-                                                    (131, 29, "f32", True, 6), (130, 50, "f16", True, 10),
-                                                    (64, 16, "f16", False, 6)])
-def test_two_step_passes_bit_identical(nx, ny, prec, source, rows):
+@pytest.mark.parametrize("nx,ny,prec,source,shape", [(100, 37, "f32", True, 0), (190, 23, "f64", True, 0),
+                                                     (130, 50, "f16", True, 0), (64, 16, "f32", False, 0),
+                                                     (257, 91, "f64", False, 0), (100, 37, "f32", True, 1),
+                                                     (131, 29, "f32", True, 2), (130, 50, "f16", True, 3),
+                                                     (64, 16, "f16", False, 1), (190, 23, "f64", True, 1),
+                                                     (70, 16, "f32", True, 3), (130, 29, "f64", True, 2)])
+def test_two_step_passes_bit_identical(nx, ny, prec, source, shape):
     """Two time steps per pass (LDS tiles of 62 x 14, 10 or 6 nodes with a
-    one-node halo) against single sweeps: the same arithmetic on the same
+    one-node halo, 4, 6 or 8 waves per workgroup) against single sweeps: the same arithmetic on the same
     inputs, so phi, the stored state and the phi history agree bit for bit,
     across graph replays, passes in pairs and single-sweep remainders; and the
     result matches the oracle."""
     lbm = _lbm()
     spec = W.spec_nonlinear_2d(nx, ny, source=source, precision=prec)
     phi0 = W.noise_field((ny, nx), 71)
-    say(f"[gpu] two-step passes {nx}x{ny} {prec} source={source} rows={rows}")
+    say(f"[gpu] two-step passes {nx}x{ny} {prec} source={source} shape={shape}")
     a = lbm.Lbm(spec).init(phi0)
     a.set_two_step(False)
     b = lbm.Lbm(spec).init(phi0)
-    b.set_two_step(rows)
+    b.set_two_step(True, shape)
     t = 0
     for s in (4, 8, 37, 70):
         a.step(s - t)
@@ -300,11 +301,16 @@ def test_two_step_refused_where_it_does_not_apply():
         with pytest.raises(lbm.LbmError) as ei:
             s.set_two_step(True)
         assert ei.value.code == lbm.LBM_E_UNSUPPORTED
-    # tile heights other than the default: 3-term polynomials, 4- and 2-byte storage only
-    for spec, rows in ((W.spec_nonlinear_2d(100, 37, precision="f64"), 10),
-                       (W.spec_nonlinear_2d(100, 37, precision="f32"), 12),
-                       (W.spec_nonlinear_2d(100, 37, precision="f32", bcoef=0.0) | {"b": [[0, 0, 0, 0.1]] * 2}, 10)):
+    # tile shapes: 4 for 4- and 2-byte storage, 2 for FP64; the non-default
+    # ones need 3-term polynomials
+    assert lbm.Lbm(W.spec_nonlinear_2d(100, 37, precision="f32")).two_step_shapes() == \
+        [(14, 4), (14, 8), (10, 6), (6, 4)]
+    assert lbm.Lbm(W.spec_nonlinear_2d(100, 37, precision="f64")).two_step_shapes() == [(6, 4), (6, 8), (14, 16)]
+    for spec, shape in ((W.spec_nonlinear_2d(100, 37, precision="f64"), 3),
+                        (W.spec_nonlinear_2d(100, 37, precision="f32"), 4),
+                        (W.spec_nonlinear_2d(100, 15, precision="f64"), 2),     # 14 rows need ny >= 16
+                        (W.spec_nonlinear_2d(100, 37, precision="f32", bcoef=0.0) | {"b": [[0, 0, 0, 0.1]] * 2}, 1)):
         s = lbm.Lbm(spec)
         with pytest.raises(lbm.LbmError) as ei:
-            s.set_two_step(rows)
+            s.set_two_step(True, shape)
         assert ei.value.code == lbm.LBM_E_INVALID
