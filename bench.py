@@ -278,7 +278,13 @@ PROFILE_COMMANDS = {
              "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19",
     "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write --output-format csv -- "
              "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19",
+    "valu": "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVES -d gpurun_out/pmc_valu -o valu "
+            "--output-format csv -- python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint",
 }
+# vector-ALU issue peak without packed FP32: each SIMD issues one 64-lane
+# instruction every 4 clocks (16 lanes per clock), 4 SIMDs per CU, so one
+# wave-instruction per CU per clock: 256 CUs x 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 2.4e9
 
 # workload label -> (kernel name prefix in the trace, algorithmic bytes per launch)
 PROFILED = {
@@ -404,6 +410,46 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
                   f"{float(r['Percentage']):.1f} |")
     with open(os.path.join(pdir, "sweep_kernels_kernel_trace.md"), "w") as fh:
         fh.write("\n".join(tl) + "\n")
+
+    vpath = os.path.join(gdir, "pmc_valu", "valu_counter_collection.csv")
+    if os.path.exists(vpath):
+        vals = {}
+        for r in csv.DictReader(open(vpath)):
+            vals.setdefault(kname(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+        vl = ["# Instruction issue of the sweep and adjoint kernels (rocprofv3 counters)", "",
+              "From the repository root with `TMPDIR=/tmp`:", "", "    " + PROFILE_COMMANDS["valu"], "",
+              "Summarised by `python3 bench.py --summarize-profiles gpurun_out`. Medians per dispatch of "
+              "the variant with the most dispatches. The issue fraction is SQ_INSTS_VALU (wave-instructions "
+              "per dispatch) over the trace median time of the same workload times the vector issue peak: "
+              "with packed FP32 off, each SIMD issues one 64-lane instruction every 4 clocks, so a CU issues "
+              "one wave-instruction per clock, 256 x 2.4e9 = 6.14e11 per second. Lane-instructions per "
+              "update = SQ_INSTS_VALU x 64 / node updates per dispatch.", "",
+              "| workload | kernel | waves | VALU | SALU | LDS | VALU lane-instructions per update | "
+              "trace median us | VALU issue fraction |", "|---|---|---|---|---|---|---|---|---|"]
+        for label, (prefix, alg) in PROFILED.items():
+            hits = sorted((k for k in vals if prefix in k and "SQ_INSTS_VALU" in vals[k]),
+                          key=lambda k: -len(vals[k]["SQ_INSTS_VALU"]))
+            if not hits:
+                continue
+            k = hits[0]
+            m = {c: stats.median(v) for c, v in vals[k].items()}
+            w = out["workloads"].get(label, {})
+            tr = w.get("trace_median_us")
+            nodes = {"nonlinear2d-1024": 1024 * 1024, "adjoint2d-512": 512 * 512,
+                     "d3q19-256": 256 ** 3}[label.split(" ")[0]]
+            upd = nodes * (2 if "two-step" in label else 1)
+            frac = m["SQ_INSTS_VALU"] / (tr * 1e-6 * VALU_ISSUE_PEAK) if tr else None
+            w.update({"sq_insts_valu": m["SQ_INSTS_VALU"], "valu_issue_fraction": frac})
+            vl.append(f"| {label} | `{k.replace('lbm::', '')}` | {m.get('SQ_WAVES', 0):.0f} | "
+                      f"{m['SQ_INSTS_VALU']:.0f} | {m.get('SQ_INSTS_SALU', 0):.0f} | {m.get('SQ_INSTS_LDS', 0):.0f} | "
+                      f"{m['SQ_INSTS_VALU'] * 64 / upd:.0f} | {'-' if tr is None else f'{tr:.2f}'} | "
+                      f"{'-' if frac is None else f'{frac:.2f}'} |")
+        vl += ["", f"Kernel-source hash `{out['kernel_hash']}`."]
+        with open(os.path.join(pdir, "sweep_kernels_valu_issue.md"), "w") as fh:
+            fh.write("\n".join(vl) + "\n")
+        with open(os.path.join(pdir, "pmc_traffic.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
     return out
 
 
