@@ -17,8 +17,8 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
     auto *fo = (TS *)fout;
     auto *pp = (TP *)p;
     const dim3 grid((g.nblocks + g.chunk - 1) / g.chunk), block(kBlock);
-    // D2Q9 with every polynomial of degree <= 2: 3-term kernels (32-bit offsets)
-    if constexpr (Q == 9) {
+    // every polynomial of degree <= 2: 3-term kernels (32-bit offsets)
+    {
         if (dm.eqr && dm.deg3 && dm.o32) {
             const int c3 = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) | (dm.nt ? 8 : 0);
 #define LBM_SWEEP3(S, K, W, NT)                                                                       \
@@ -215,7 +215,7 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
     const auto *pn = (const TC *)psi_next;
     auto *po = (TC *)psi_out;
     const dim3 grid(g.nblocks), block(kBlock);
-    if constexpr (Q == 9) {
+    {
         if (dm.eqr && dm.deg3 && dm.o32) {
             const int c3 = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
 #define LBM_ADJ3(S, K, W)                                                                               \
