@@ -216,10 +216,13 @@ def run_batch(torch, lbm, W, steps):
     N = b.total_nodes
     bpn = bytes_per_node(9, "f32", False)
     fin = torch.isfinite(b.phi()).all().item()
+    shape = b.get_shape()
+    two = shape["npt"] < 0        # two time steps per launch: the state crosses HBM once per two steps
+    launch_gbs = bpn * N / ((2 if two else 1) * per) / 1e9
     return {"instances": len(items), "nodes": N, "steps": steps, "ms_per_step": per * 1e3,
-            "mlups": N / per / 1e6, "bytes_per_node": bpn, "achieved_gbs": bpn * N / per / 1e9,
-            "hbm_frac": bpn * N / per / 1e9 / PEAK_HBM_GBS, "shape": b.get_shape(),
-            "tuner": rep.splitlines()[-1], "finite": bool(fin)}
+            "mlups": N / per / 1e6, "bytes_per_node": bpn, "two_step": two, "achieved_gbs": launch_gbs,
+            "hbm_frac": launch_gbs / PEAK_HBM_GBS, "per_update_hbm_frac": bpn * N / per / 1e9 / PEAK_HBM_GBS,
+            "shape": shape, "tuner": rep.splitlines()[-1], "finite": bool(fin)}
 
 
 def copy_probe(torch, lbm, nbytes=1 << 30, reps=20):

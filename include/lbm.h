@@ -188,8 +188,8 @@ int lbm_set_nontemporal(lbm_ctx *ctx, int on);
 int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_len);
 
 /* Two time steps per pass inside lbm_step (D2Q9, periodic axes, equal
- * non-flux rates, nx >= 64, ny >= 16 (FP64: 8)).  A workgroup runs step t on a
- * tile with a one-node halo, keeps the post-collision populations in LDS
+ * non-flux rates, any grid size: tiles wrap periodically).  A workgroup runs
+ * step t on a tile with a one-node halo, keeps the post-collision populations in LDS
  * (rounded to the storage type as a store would round them), runs step t + 1
  * on the tile and stores only that result: every update is the single-sweep
  * arithmetic on the same inputs, so results equal single sweeps bit for bit,
@@ -311,8 +311,8 @@ int lbm_adjoint_step(lbm_ctx *ctx, const void *f_s, const void *p_s, const void 
  * sweeps.  psi and pi equal those of two lbm_adjoint_step calls bit for bit;
  * the K0 sums agree up to the order of FP64 additions.  The intermediate
  * (psi_s, pi_s) lives in workgroup memory only.  Applies to D2Q9 with
- * periodic axes and equal non-flux rates, nx >= 64 and ny >= 16 (F32) or 8
- * (F64) (lbm_adjoint_pair_ok tells in advance; elsewhere LBM_E_UNSUPPORTED).
+ * periodic axes and equal non-flux rates (lbm_adjoint_pair_ok tells in
+ * advance; elsewhere LBM_E_UNSUPPORTED).
  * psi_out must differ from psi_next and pi_out from pi_next (LBM_E_INVALID):
  * neighbouring tiles read pi_{s+1} during the launch. */
 int lbm_adjoint_step2(lbm_ctx *ctx, const void *f_s, const void *p_s, const void *f_sm1, const void *p_sm1,
@@ -382,7 +382,15 @@ int lbm_batch_tune(lbm_batch *b, int reps, int use_cache, void *stream, char *re
 
 /* Force / read the launch shape: shape index 0..3 = (256 threads, 1 node per
  * thread), (256, 2), (128, 1), (512, 1); grid 0 = one workgroup per tile,
- * otherwise persistent workgroups over contiguous chunks of the list. */
+ * otherwise persistent workgroups over contiguous chunks of the list.
+ * Batches without a source whose polynomials all have degree <= 2 also offer
+ * two time steps per launch (the two-step pass of lbm_set_two_step, one
+ * workgroup per 62 x rows tile of an instance, bit-identical to single
+ * sweeps): shape 4 = 14 rows x 8 waves and shape 5 = 6 rows x 4 waves for 4-
+ * and 2-byte storage, shape 4 = 6 rows x 8 waves for FP64; the grid argument
+ * is ignored for them, an odd remaining step runs shape 0, and get_shape
+ * reports wg = 64 x waves and npt = -rows.  lbm_batch_tune times them with the
+ * others.  LBM_E_INVALID for a shape the batch does not offer. */
 int lbm_batch_set_shape(lbm_batch *b, int shape, unsigned grid, int remap);
 int lbm_batch_get_shape(const lbm_batch *b, int *shape, unsigned *grid, int *remap, int *wg, int *npt);
 

@@ -501,17 +501,16 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
     TC gk[6] = {TC(0), TC(0), TC(0), TC(0), TC(0), TC(0)};
     // a lane owns column x0 + lane - 1 when it is an interior lane inside the grid
     const bool xown = lane >= 1 && lane <= TX - 2 && x0 + lane - 1 < nx;
-    // phase 1 (x0 - 1 + lane lies in [-1, nx + 61] and nx >= 64: one wrap)
-    int xg = x0 - 1 + lane;
-    xg = xg < 0 ? xg + nx : (xg >= nx ? xg - nx : xg);
+    // phase 1: the tile and its halo (coordinates wrapped periodically; narrow
+    // or low grids repeat nodes in the halo, which only the owner counts)
+    const int xg = wrap_coord(x0 - 1 + lane, nx);
     // FP32 unrolls the rows (all loads in flight); FP64 takes them one by one
     // (about 165 registers per lane as it is: 3 waves per SIMD)
     constexpr int kUnroll = sizeof(TC) == 4 ? TR / (kBlock / 64) : 1;
 #pragma unroll kUnroll
     for (int i = 0; i < TR / (kBlock / 64); ++i) {
         const int r = wv + i * (kBlock / 64);
-        int yg = y0 - 1 + r;   // in [-1, ny + TH - 1], ny >= TH + 2: one wrap
-        yg = yg < 0 ? yg + ny : (yg >= ny ? yg - ny : yg);
+        const int yg = wrap_coord(y0 - 1 + r, ny);
         const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
         const NodeGeo ng = node_geometry<9, false>(g, n);
         TC h[9], lam[9], out[9];

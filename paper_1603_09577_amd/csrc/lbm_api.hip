@@ -462,7 +462,7 @@ int advance(lbm_ctx *c, int nsteps, hipStream_t st) {
 namespace lbm {
 
 // Validation and packed constants of one description (used by the batch API).
-int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, bool *lowdeg,
+int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, bool *lowdeg, bool *deg3,
                  void *coefs_out, size_t *coef_bytes) {
     Dims dm;
     const int rc = validate(d, dm);
@@ -485,6 +485,7 @@ int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar,
     *src = dm.src;
     *kvar = dm.kvar;
     *lowdeg = dm.lowdeg;
+    *deg3 = dm.deg3;
     return LBM_OK;
 }
 
@@ -528,8 +529,7 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     // every array a kernel indexes (planes of f and psi, p, pi: at most 8-byte
     // elements, at most `plane` of them) spans < 4 GiB: 32-bit byte offsets
     c->dm.o32 = (uint64_t)g.plane * 8u < (1ull << 32);
-    c->two_ok = dm.q == 9 && !dm.wall && dm.eqr && c->dm.o32 && desc->nx >= 64 &&
-                desc->ny >= two_step_rows_of(dm.prec) + 2;
+    c->two_ok = dm.q == 9 && !dm.wall && dm.eqr && c->dm.o32;
     c->two = c->two_ok;   // on by default where it applies (bit-identical; lbm_tune re-decides)
     {
         const uint32_t th = (uint32_t)adjoint_pair_rows(dm.prec, g.nx, g.ny);
@@ -641,11 +641,11 @@ int lbm_recenter(lbm_ctx *c, void *stream) {
 }
 
 // a tile shape usable here: in the table, 3-term polynomials for the
-// non-default shapes, and rows + 2 <= ny
+// non-default shapes (tiles wrap periodically, so any grid size will do)
 static bool two_shape_usable(const lbm_ctx *c, int shape) {
     int rows = 0, waves = 0;
     if (!two_step_shape_of(c->dm.prec, shape, &rows, &waves)) return false;
-    return (shape == 0 || c->dm.deg3) && (uint32_t)rows + 2 <= c->g.ny;
+    return shape == 0 || c->dm.deg3;
 }
 
 int lbm_two_step_shape(const lbm_ctx *c, int shape, int *rows, int *waves) {
@@ -658,11 +658,10 @@ int lbm_set_two_step(lbm_ctx *c, int mode) {
     if (!c) return fail(LBM_E_INVALID, "null context");
     if (mode < 0) return fail(LBM_E_INVALID, "mode must be 0 (off) or 1 + a tile shape");
     if (mode && !c->two_ok)
-        return fail(LBM_E_UNSUPPORTED, "two steps per pass need D2Q9, periodic axes, equal non-flux rates and a grid "
-                                       "of at least 64 x (tile rows + 2)");
+        return fail(LBM_E_UNSUPPORTED, "two steps per pass need D2Q9, periodic axes and equal non-flux rates");
     const int shape = mode > 0 ? mode - 1 : 0;
     if (mode && !two_shape_usable(c, shape))
-        return fail(LBM_E_INVALID, "tile shape not available for this storage type, polynomial length or grid");
+        return fail(LBM_E_INVALID, "tile shape not available for this storage type or polynomial length");
     drop_graphs(c);
     c->two = mode != 0;
     c->two_shape = shape;
@@ -836,8 +835,7 @@ int lbm_adjoint_step2(lbm_ctx *c, const void *f_s, const void *p_s, const void *
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     if (!adjoint_pair_applies(c))
         return fail(LBM_E_UNSUPPORTED,
-                    "two reversed sweeps per launch need D2Q9, periodic axes, equal rates and nx >= 64, "
-                    "ny >= tile rows + 2");
+                    "two reversed sweeps per launch need D2Q9, periodic axes and equal rates");
     hipError_t e = launch_adjoint2_q9(c->dm, c->g, c->d_coefs, f_s, p_s, f_sm1, p_sm1, psi_next, pi_next, psi_out,
                                       pi_out, c->d_adj_part, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint pair kernel");

@@ -9,7 +9,10 @@
 // XCD-aware so that each XCD sweeps a contiguous run of instances.  Runs of
 // sweeps are replayed from captured HIP graphs.  An autotuner times the
 // candidate (WG, NPT, grid) shapes on the real batch and keeps the fastest;
-// results are cached in a small text file.
+// results are cached in a small text file.  Batches without a source whose
+// polynomials have degree <= 2 may instead advance two time steps per launch:
+// a second work list holds one entry per (instance, 62 x TH tile), and each
+// workgroup runs the two-step tile of the single-instance pass on it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,6 +45,15 @@ struct TileShape {
 constexpr TileShape kShapes[] = {{256, 1}, {256, 2}, {128, 1}, {512, 1}};
 constexpr int kNumShapes = 4;
 
+// two-step shapes (tile rows, waves per workgroup), batch shape indices
+// kNumShapes + i: 4- and 2-byte storage, and FP64
+struct TwoShape {
+    int rows, waves;
+};
+constexpr TwoShape kTwo4[] = {{14, 8}, {6, 4}};
+constexpr TwoShape kTwo8[] = {{6, 8}};
+constexpr int kMaxTwo = 2;
+
 template <typename TS, typename TC, bool SRC, bool KVAR, int WG, int NPT, int NP>
 __global__ void __launch_bounds__(WG)
 k_batch_sweep(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ coefs,
@@ -63,6 +75,20 @@ k_batch_sweep(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ 
                                                                p + I.p_off, flag, n);
         }
     }
+}
+
+// Two time steps per launch (no source, so no phi history): one workgroup per
+// entry (instance, tx | ty << 16) of the two-step work list.
+template <typename TS, typename TC, bool KVAR, int TH, int NW>
+__global__ void __launch_bounds__(64 * NW)
+k_batch_sweep2(const BatchInst *__restrict__ inst, const Coefs<TC> *__restrict__ coefs,
+               const uint2 *__restrict__ tiles, int remap, const TS *__restrict__ fin, TS *__restrict__ fout,
+               int *flag) {
+    const uint2 e = tiles[block_index(blockIdx.x, gridDim.x, remap)];
+    const BatchInst &I = inst[e.x];
+    const Geom g = I.g;
+    sweep2_tile<TS, TC, false, KVAR, 3, TH, NW>(g, coefs + e.x, fin + I.f_off, fout + I.f_off, nullptr, nullptr,
+                                               e.y & 0xffffu, e.y >> 16, flag);
 }
 
 template <typename TS, typename TC, int NP>
@@ -127,7 +153,7 @@ using namespace lbm;
 
 namespace lbm {
 // coefficient derivation shared with the single-instance API (lbm_api.hip)
-int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, bool *lowdeg,
+int derive_coefs(const lbm_desc *d, int *prec, bool *eqr, bool *src, bool *kvar, bool *lowdeg, bool *deg3,
                  void *coefs_out, size_t *coef_bytes);
 const char *api_error_message();
 int api_fail(int code, const char *msg);
@@ -136,7 +162,7 @@ int api_fail(int code, const char *msg);
 struct lbm_batch {
     int count = 0;
     int prec = 0;
-    bool src = false, kvar = false, lowdeg = true;
+    bool src = false, kvar = false, lowdeg = true, deg3 = true;
     size_t coef_stride = 0;
     std::vector<BatchInst> inst;
     std::vector<int> nx, ny;
@@ -146,8 +172,12 @@ struct lbm_batch {
     // one tile list per shape (tile size differs)
     uint2 *d_tiles[kNumShapes] = {nullptr, nullptr, nullptr, nullptr};
     uint32_t ntiles[kNumShapes] = {0, 0, 0, 0};
+    // two-step work lists, one per two-step shape (tile rows differ)
+    uint2 *d_tiles2[kMaxTwo] = {nullptr, nullptr};
+    uint32_t ntiles2[kMaxTwo] = {0, 0};
+    int ntwo = 0;           // two-step shapes available (0: no source-free 3-term batch)
     int *d_flag = nullptr;
-    int shape = 0;          // index into kShapes
+    int shape = 0;          // index into kShapes, or kNumShapes + a two-step shape
     uint32_t grid = 0;      // workgroups per sweep (0 = one per tile)
     int remap = 1;
     void *f[2] = {nullptr, nullptr};
@@ -169,13 +199,19 @@ size_t ssize(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 size_t hsize(int prec) { return prec == 0 ? 8 : 4; }
 size_t r256(size_t v) { return (v + 255) & ~size_t(255); }
 
-hipError_t batch_sweep_launch(lbm_batch *b, const void *fin, void *fout, hipStream_t st) {
-    const TileShape sh = kShapes[b->shape];
-    const uint32_t nt = b->ntiles[b->shape];
-    const uint32_t grid = (b->grid == 0 || b->grid > nt) ? nt : b->grid;
+TwoShape two_shape(const lbm_batch *b, int i) { return b->prec == 0 ? kTwo8[i] : kTwo4[i]; }
+
+bool is_two(const lbm_batch *b) { return b->shape >= kNumShapes; }
+
+// one sweep; single-sweep shape `shape` (a two-step batch uses shape 0 for
+// an odd remaining step)
+hipError_t batch_sweep_launch(lbm_batch *b, const void *fin, void *fout, hipStream_t st, int shape) {
+    const TileShape sh = kShapes[shape];
+    const uint32_t nt = b->ntiles[shape];
+    const uint32_t grid = (shape != b->shape || b->grid == 0 || b->grid > nt) ? nt : b->grid;
     const uint32_t chunk = (nt + grid - 1) / grid;
     const uint32_t nblk = (nt + chunk - 1) / chunk;
-    const uint2 *tl = b->d_tiles[b->shape];
+    const uint2 *tl = b->d_tiles[shape];
 #define LBM_BL(TS, TC, S, K, WG, NPT)                                                                   \
     if (b->lowdeg) LBM_BL_NP(TS, TC, S, K, WG, NPT, 4) else LBM_BL_NP(TS, TC, S, K, WG, NPT, 9)
 #define LBM_BL_NP(TS, TC, S, K, WG, NPT, NP)                                                            \
@@ -183,7 +219,7 @@ hipError_t batch_sweep_launch(lbm_batch *b, const void *fin, void *fout, hipStre
                        b->d_inst, (const Coefs<TC> *)b->d_coefs, tl, nt, chunk, b->remap,               \
                        (const TS *)fin, (TS *)fout, (typename HistType<TS>::T *)b->p, b->d_flag);
 #define LBM_BL_SHAPE(TS, TC, S, K)                                                                      \
-    switch (b->shape) {                                                                                 \
+    switch (shape) {                                                                                    \
         case 0: LBM_BL(TS, TC, S, K, 256, 1); break;                                                    \
         case 1: LBM_BL(TS, TC, S, K, 256, 2); break;                                                    \
         case 2: LBM_BL(TS, TC, S, K, 128, 1); break;                                                    \
@@ -205,6 +241,57 @@ hipError_t batch_sweep_launch(lbm_batch *b, const void *fin, void *fout, hipStre
     return hipGetLastError();
 }
 
+// two time steps, two-step shape b->shape - kNumShapes
+hipError_t batch_sweep2_launch(lbm_batch *b, const void *fin, void *fout, hipStream_t st) {
+    const int i = b->shape - kNumShapes;
+    const TwoShape sh = two_shape(b, i);
+    const dim3 grid(b->ntiles2[i]);
+    const uint2 *tl = b->d_tiles2[i];
+#define LBM_B2(TS, TC, K, TH, NW)                                                                       \
+    hipLaunchKernelGGL((k_batch_sweep2<TS, TC, K, TH, NW>), grid, dim3(64 * NW), 0, st, b->d_inst,      \
+                       (const Coefs<TC> *)b->d_coefs, tl, b->remap, (const TS *)fin, (TS *)fout, b->d_flag)
+#define LBM_B2_SHAPE(TS, TC, K)                                                                         \
+    if (sh.rows == 14) LBM_B2(TS, TC, K, 14, 8);                                                        \
+    else LBM_B2(TS, TC, K, 6, 4);
+    if (b->prec == 0) {
+        if (b->kvar) LBM_B2(double, double, true, 6, 8);
+        else LBM_B2(double, double, false, 6, 8);
+    } else if (b->prec == 1) {
+        if (b->kvar) { LBM_B2_SHAPE(float, float, true) }
+        else { LBM_B2_SHAPE(float, float, false) }
+    } else {
+        if (b->kvar) { LBM_B2_SHAPE(_Float16, float, true) }
+        else { LBM_B2_SHAPE(_Float16, float, false) }
+    }
+#undef LBM_B2_SHAPE
+#undef LBM_B2
+    return hipGetLastError();
+}
+
+// `steps` time steps from f[start]: pairs in two-step launches (the odd step,
+// if any, a single sweep); the state ends in f[start ^ (launches & 1)]
+hipError_t batch_advance(lbm_batch *b, int start, int steps, hipStream_t st, int *end) {
+    hipError_t e = hipSuccess;
+    int cur = start;
+    if (is_two(b)) {
+        for (int i = 0; i + 1 < steps && e == hipSuccess; i += 2) {
+            e = batch_sweep2_launch(b, b->f[cur], b->f[cur ^ 1], st);
+            cur ^= 1;
+        }
+        if ((steps & 1) && e == hipSuccess) {
+            e = batch_sweep_launch(b, b->f[cur], b->f[cur ^ 1], st, 0);
+            cur ^= 1;
+        }
+    } else {
+        for (int i = 0; i < steps && e == hipSuccess; ++i) {
+            e = batch_sweep_launch(b, b->f[cur], b->f[cur ^ 1], st, b->shape);
+            cur ^= 1;
+        }
+    }
+    *end = cur;
+    return e;
+}
+
 void drop_graphs(lbm_batch *b) {
     for (int i = 0; i < 2; ++i)
         if (b->gexec[i]) { (void)hipGraphExecDestroy(b->gexec[i]); b->gexec[i] = nullptr; }
@@ -216,12 +303,8 @@ hipError_t make_graph(lbm_batch *b, int start) {
     if (e != hipSuccess) return e;
     e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    int cur = start;
-    hipError_t le = hipSuccess;
-    for (int i = 0; i < kBatchGraphSteps && le == hipSuccess; ++i) {
-        le = batch_sweep_launch(b, b->f[cur], b->f[cur ^ 1], b->cap);
-        cur ^= 1;
-    }
+    int end = start;
+    const hipError_t le = batch_advance(b, start, kBatchGraphSteps, b->cap, &end);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(b->cap, &graph);
     if (le != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return le; }
@@ -274,7 +357,7 @@ bool cache_lookup(const std::string &key, int &shape, uint32_t &grid, int &remap
     int s, r;
     unsigned g;
     while (in >> k >> s >> g >> r)
-        if (k == key && s >= 0 && s < kNumShapes) { shape = s; grid = g; remap = r; return true; }
+        if (k == key && s >= 0 && s < kNumShapes + kMaxTwo) { shape = s; grid = g; remap = r; return true; }
     return false;
 }
 
@@ -310,10 +393,10 @@ int lbm_batch_create(const lbm_desc *descs, int count, lbm_batch **out) {
             return api_fail(LBM_E_UNSUPPORTED, "batched instances must be periodic");
         }
         int prec = 0;
-        bool eqr = false, src = false, kvar = false, low = false;
+        bool eqr = false, src = false, kvar = false, low = false, d3 = false;
         size_t cb = 0;
         std::vector<unsigned char> tmp(sizeof(Coefs<double>));
-        const int rc = derive_coefs(&d, &prec, &eqr, &src, &kvar, &low, tmp.data(), &cb);
+        const int rc = derive_coefs(&d, &prec, &eqr, &src, &kvar, &low, &d3, tmp.data(), &cb);
         if (rc != LBM_OK) { delete b; return rc; }
         if (!eqr) { delete b; return api_fail(LBM_E_UNSUPPORTED, "batched instances need equal non-flux rates"); }
         if (d.flags & LBM_FLAG_REMARK3) {
@@ -329,6 +412,7 @@ int lbm_batch_create(const lbm_desc *descs, int count, lbm_batch **out) {
         b->src = b->src || src;
         b->kvar = b->kvar || kvar;
         b->lowdeg = b->lowdeg && low;
+        b->deg3 = b->deg3 && d3;
         coefs.insert(coefs.end(), tmp.begin(), tmp.begin() + cb);
         BatchInst I;
         std::memset(&I, 0, sizeof(I));
@@ -378,6 +462,26 @@ int lbm_batch_create(const lbm_desc *descs, int count, lbm_batch **out) {
         e = hipMalloc((void **)&b->d_tiles[s], sizeof(uint2) * tl.size());
         if (e == hipSuccess) e = hipMemcpy(b->d_tiles[s], tl.data(), sizeof(uint2) * tl.size(), hipMemcpyHostToDevice);
     }
+    // two-step work lists: source-free batches with 3-term polynomials, every
+    // instance below 65536 tiles per axis (16-bit tile coordinates) and with
+    // planes below 4 GiB (32-bit byte offsets)
+    bool fits = true;
+    for (int i = 0; i < count; ++i)
+        fits = fits && (b->inst[i].g.nx + 61) / 62 < 65536u && b->inst[i].g.ny < 65536u * 6u &&
+               (uint64_t)b->inst[i].g.plane * 8u < (1ull << 32);
+    b->ntwo = (!b->src && b->deg3 && fits) ? (b->prec == 0 ? 1 : 2) : 0;
+    for (int s = 0; s < b->ntwo && e == hipSuccess; ++s) {
+        const uint32_t th = (uint32_t)two_shape(b, s).rows;
+        std::vector<uint2> tl;
+        for (int i = 0; i < count; ++i) {
+            const uint32_t tx = (b->inst[i].g.nx + 61) / 62, ty = (b->inst[i].g.ny + th - 1) / th;
+            for (uint32_t y = 0; y < ty; ++y)
+                for (uint32_t x = 0; x < tx; ++x) tl.push_back(make_uint2((unsigned)i, x | (y << 16)));
+        }
+        b->ntiles2[s] = (uint32_t)tl.size();
+        e = hipMalloc((void **)&b->d_tiles2[s], sizeof(uint2) * tl.size());
+        if (e == hipSuccess) e = hipMemcpy(b->d_tiles2[s], tl.data(), sizeof(uint2) * tl.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         lbm_batch_destroy(b);
         std::string m = std::string("batch setup: ") + hipGetErrorString(e);
@@ -396,6 +500,8 @@ void lbm_batch_destroy(lbm_batch *b) {
     if (b->d_flag) (void)hipFree(b->d_flag);
     for (int s = 0; s < kNumShapes; ++s)
         if (b->d_tiles[s]) (void)hipFree(b->d_tiles[s]);
+    for (int s = 0; s < kMaxTwo; ++s)
+        if (b->d_tiles2[s]) (void)hipFree(b->d_tiles2[s]);
     delete b;
 }
 
@@ -430,7 +536,8 @@ int lbm_batch_init(lbm_batch *b, const double *phi0, void *f_a, void *f_b, void 
 }
 
 int lbm_batch_set_shape(lbm_batch *b, int shape, unsigned grid, int remap) {
-    if (!b || shape < 0 || shape >= kNumShapes) return api_fail(LBM_E_INVALID, "bad shape index");
+    if (!b || shape < 0 || shape >= kNumShapes + (b ? b->ntwo : 0))
+        return api_fail(LBM_E_INVALID, "bad shape index");
     b->shape = shape;
     b->grid = grid;
     b->remap = remap ? 1 : 0;
@@ -443,8 +550,14 @@ int lbm_batch_get_shape(const lbm_batch *b, int *shape, unsigned *grid, int *rem
     if (shape) *shape = b->shape;
     if (grid) *grid = b->grid;
     if (remap) *remap = b->remap;
-    if (wg) *wg = kShapes[b->shape].wg;
-    if (npt) *npt = kShapes[b->shape].npt;
+    if (is_two(b)) {
+        const TwoShape t = two_shape(b, b->shape - kNumShapes);
+        if (wg) *wg = 64 * t.waves;
+        if (npt) *npt = -t.rows;    // minus the tile rows: two steps per launch
+    } else {
+        if (wg) *wg = kShapes[b->shape].wg;
+        if (npt) *npt = kShapes[b->shape].npt;
+    }
     return LBM_OK;
 }
 
@@ -460,14 +573,16 @@ int lbm_batch_step(lbm_batch *b, int nsteps, void *stream) {
         }
         hipError_t e = hipGraphLaunch(b->gexec[b->cur], st);
         if (e != hipSuccess) return api_fail(LBM_E_HIP, hipGetErrorString(e));
+        // 32 single sweeps or 16 two-step launches: an even number of buffer swaps
         b->t += kBatchGraphSteps;
         nsteps -= kBatchGraphSteps;
     }
-    for (int i = 0; i < nsteps; ++i) {
-        hipError_t e = batch_sweep_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st);
+    if (nsteps > 0) {
+        int end = b->cur;
+        hipError_t e = batch_advance(b, b->cur, nsteps, st, &end);
         if (e != hipSuccess) return api_fail(LBM_E_HIP, hipGetErrorString(e));
-        b->cur ^= 1;
-        ++b->t;
+        b->cur = end;
+        b->t += nsteps;
     }
     return LBM_OK;
 }
@@ -501,7 +616,7 @@ int lbm_batch_tune(lbm_batch *b, int reps, int use_cache, void *stream, char *re
     std::ostringstream rep;
     int shape = 0, remap = 1;
     uint32_t grid = 0;
-    if (use_cache && cache_lookup(b->key, shape, grid, remap)) {
+    if (use_cache && cache_lookup(b->key, shape, grid, remap) && shape < kNumShapes + b->ntwo) {
         lbm_batch_set_shape(b, shape, grid, remap);
         rep << "cached " << b->key << " shape " << shape << " grid " << grid << " remap " << remap;
     } else {
@@ -521,10 +636,10 @@ int lbm_batch_tune(lbm_batch *b, int reps, int use_cache, void *stream, char *re
                 for (int rm = 0; rm < 2; ++rm) {
                     b->shape = s; b->grid = gr; b->remap = rm;
                     // sweeps read the current state and write the other buffer only
-                    hipError_t e = batch_sweep_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st);
+                    hipError_t e = batch_sweep_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st, s);
                     if (e == hipSuccess) e = hipEventRecord(e0, st);
                     for (int r = 0; r < reps && e == hipSuccess; ++r)
-                        e = batch_sweep_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st);
+                        e = batch_sweep_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st, s);
                     if (e == hipSuccess) e = hipEventRecord(e1, st);
                     if (e == hipSuccess) e = hipEventSynchronize(e1);
                     float ms = 0.f;
@@ -538,6 +653,28 @@ int lbm_batch_tune(lbm_batch *b, int reps, int use_cache, void *stream, char *re
                         << ": " << ms << " ms\n";
                     if (ms < best) { best = ms; shape = s; grid = gr; remap = rm; }
                 }
+        // two steps per launch: time per step
+        for (int i = 0; i < b->ntwo; ++i)
+            for (int rm = 0; rm < 2; ++rm) {
+                b->shape = kNumShapes + i; b->grid = 0; b->remap = rm;
+                hipError_t e = batch_sweep2_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st);
+                if (e == hipSuccess) e = hipEventRecord(e0, st);
+                for (int r = 0; r < reps && e == hipSuccess; ++r)
+                    e = batch_sweep2_launch(b, b->f[b->cur], b->f[b->cur ^ 1], st);
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+                    return api_fail(LBM_E_HIP, hipGetErrorString(e));
+                }
+                ms /= 2 * reps;
+                const TwoShape t = two_shape(b, i);
+                rep << "two steps per launch rows " << t.rows << " waves " << t.waves << " remap " << rm << ": "
+                    << ms << " ms per step\n";
+                if (ms < best) { best = ms; shape = kNumShapes + i; grid = 0; remap = rm; }
+            }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         lbm_batch_set_shape(b, shape, grid, remap);

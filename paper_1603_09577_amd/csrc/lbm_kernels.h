@@ -635,31 +635,41 @@ k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f
 // `pout` (two history buffers, alternating).  NW waves per workgroup share
 // the TH + 2 rows of phase 1 (more waves: fewer rows and registers per wave).
 // ---------------------------------------------------------------------------
-template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW = kBlock / 64>
-__global__ void __launch_bounds__(64 * NW)
-k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
-         const typename HistType<TS>::T *__restrict__ pin, typename HistType<TS>::T *__restrict__ pout,
-         uint32_t tiles_x, int *flag) {
+// Periodic image of a tile coordinate v >= -1 on an axis of n >= 1 nodes
+// (v exceeds n by at most the tile span, so the loop runs a bounded number of
+// times; once at most when n is at least the tile span).
+__device__ __forceinline__ int wrap_coord(int v, int n) {
+    if (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
+// One tile of a two-step pass (tile (tx, ty) of 62 x TH nodes of the grid g;
+// NW waves of the workgroup).  Grids narrower or lower than a tile are fine:
+// halo lanes and rows then repeat nodes (computed identically) and only the
+// tile's own nodes inside the grid are stored.
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW>
+__device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__restrict__ cf,
+                                            const TS *__restrict__ fin, TS *__restrict__ fout,
+                                            const typename HistType<TS>::T *__restrict__ pin,
+                                            typename HistType<TS>::T *__restrict__ pout, uint32_t tx, uint32_t ty,
+                                            int *flag) {
     using L = Lattice<9>;
     using TP = typename HistType<TS>::T;
     constexpr int TX = 64, TR = TH + 2;
     static_assert(TR % NW == 0, "tile rows must split evenly over the waves");
     __shared__ TS lf[9][TR][TX];
     __shared__ TP lp[TR][TX];
-    const uint32_t tile = block_index(blockIdx.x, gridDim.x, g.remap);
-    const uint32_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
     const int x0 = (int)(tx * (TX - 2)), y0 = (int)(ty * TH);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nx = (int)g.nx, ny = (int)g.ny;
     bool bad = false;
-    // phase 1 (x0 - 1 + lane lies in [-1, nx + 61] and nx >= 64: one wrap)
-    int xg = x0 - 1 + lane;
-    xg = xg < 0 ? xg + nx : (xg >= nx ? xg - nx : xg);
+    // phase 1: the tile and its halo, coordinates x0 - 1 + lane and y0 - 1 + r
+    const int xg = wrap_coord(x0 - 1 + lane, nx);
 #pragma unroll
     for (int i = 0; i < TR / NW; ++i) {
         const int r = wv + i * NW;
-        int yg = y0 - 1 + r;   // in [-1, ny + TH - 1], ny >= TH + 2: one wrap
-        yg = yg < 0 ? yg + ny : (yg >= ny ? yg - ny : yg);
+        const int yg = wrap_coord(y0 - 1 + r, ny);
         const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
         const NodeGeo ng = node_geometry<9, false>(g, n);
         TC h[9];
@@ -694,6 +704,16 @@ k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ 
         }
     }
     if (bad) *flag = 1;
+}
+
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW = kBlock / 64>
+__global__ void __launch_bounds__(64 * NW)
+k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
+         const typename HistType<TS>::T *__restrict__ pin, typename HistType<TS>::T *__restrict__ pout,
+         uint32_t tiles_x, int *flag) {
+    const uint32_t tile = block_index(blockIdx.x, gridDim.x, g.remap);
+    const uint32_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    sweep2_tile<TS, TC, SRC, KVAR, NP, TH, NW>(g, cf, fin, fout, pin, pout, tx, ty, flag);
 }
 
 // The general sweep: Scheme B and/or per-node fields.  Polynomials of any

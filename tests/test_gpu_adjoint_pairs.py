@@ -51,6 +51,7 @@ CASES = [
     ("f64", 100, 37, True), ("f64", 128, 64, True), ("f64", 100, 37, False),
     ("f32", 100, 37, True), ("f32", 64, 16, True), ("f32", 190, 45, False),
     ("f32", 1024, 848, True),    # 1037 tiles of 14 rows (smaller grids take 6-row tiles)
+    ("f64", 40, 30, True), ("f32", 33, 5, True),     # grids narrower and lower than a tile
 ]
 
 
@@ -154,9 +155,8 @@ def test_pair_refused_where_it_does_not_apply():
     with pytest.raises(lbm.LbmError) as ei:
         sim.adjoint_step2(fb, pb, fa, pa, psi, pi, psi2, pi)
     assert ei.value.code == lbm.LBM_E_INVALID
-    # narrow grid, walls, D3Q19
-    for s in (W.spec_nonlinear_2d(40, 37),
-              dict(W.spec_nonlinear_2d(100, 37), bc=["periodic", "abb", "periodic"],
+    # walls, D3Q19
+    for s in (dict(W.spec_nonlinear_2d(100, 37), bc=["periodic", "abb", "periodic"],
                    phi_wall=[[0, 0], [0.3, 0.7], [0, 0]]),
               W.spec_d3q19_aniso((16, 16, 16), phi_wall=0.3)):
         sim = lbm.Lbm(s)

@@ -4,7 +4,9 @@
   (same kernel arithmetic: bit-identical), for every launch shape;
 * instances against the CPU oracle (FP64 <= 1e-12, FP32 <= 1e-5);
 * the 512-instance workload: autotuned shape, every instance against its
-  single-instance GPU run, a seeded subset of 32 against the oracle.
+  single-instance GPU run, a seeded subset of 32 against the oracle;
+* two time steps per launch (source-free batches): bit-identical to the
+  instances run alone, for every two-step shape.
 """
 import sys
 
@@ -99,3 +101,44 @@ def test_batch_workload_512_instances():
         o, _ = orc.run(orc.params_from_spec(sp), phis[i], 64)
         e = float(np.linalg.norm(got[i].cpu().numpy() - o) / np.linalg.norm(o))
         assert e <= 1e-5, (i, e)
+
+
+def sourcefree_batch(prec, count=10, seed=33):
+    rng = np.random.default_rng(seed)
+    specs, phis = [], []
+    for i in range(count):
+        nx, ny = int(rng.integers(5, 150)), int(rng.integers(3, 60))
+        k = np.diag(rng.uniform(0.005, 0.05, 2))
+        specs.append(W.spec_nonlinear_2d(nx, ny, bcoef=float(rng.uniform(0, 1)), k0=k, source=False,
+                                         precision=prec))
+        phis.append(W.noise_field((ny, nx), 2000 + i))
+    return specs, phis
+
+
+@pytest.mark.parametrize("prec,shape", [("f32", 4), ("f32", 5), ("f16", 4), ("f64", 4)])
+@pytest.mark.parametrize("remap", [1, 0])
+def test_two_step_batch_identical(prec, shape, remap):
+    """Two time steps per launch over a ragged source-free batch (instances
+    narrower and lower than a tile included) against each instance run alone:
+    bit-identical after an odd number of steps, with graph replays."""
+    from paper_1603_09577_amd import lbm
+    specs, phis = sourcefree_batch(prec)
+    say(f"[gpu batch] two steps per launch, {prec} shape {shape} remap {remap}")
+    b = lbm.Batch(specs).init(phis)
+    b.set_shape(shape, 0, remap)
+    sh = b.get_shape()
+    assert sh["npt"] < 0 and sh["wg"] % 64 == 0
+    b.step(71)
+    got = b.unpack(b.phi())
+    ref = single_runs(specs, phis, 71)
+    for i, (g, r) in enumerate(zip(got, ref)):
+        assert torch.equal(g, r), (i, specs[i]["shape"])
+
+
+def test_two_step_batch_refused_with_a_source():
+    from paper_1603_09577_amd import lbm
+    specs, phis = small_batch("f32", 3, seed=34)
+    b = lbm.Batch(specs)
+    with pytest.raises(lbm.LbmError) as ei:
+        b.set_shape(4, 0, 1)
+    assert ei.value.code == lbm.LBM_E_INVALID

@@ -261,7 +261,10 @@ def test_launch_variants_identical():
                                                      (257, 91, "f64", False, 0), (100, 37, "f32", True, 1),
                                                      (131, 29, "f32", True, 2), (130, 50, "f16", True, 3),
                                                      (64, 16, "f16", False, 1), (190, 23, "f64", True, 1),
-                                                     (70, 16, "f32", True, 3), (130, 29, "f64", True, 2)])
+                                                     (70, 16, "f32", True, 3), (130, 29, "f64", True, 2),
+                                                     (40, 30, "f32", True, 1), (33, 7, "f64", True, 0),
+                                                     (20, 5, "f16", True, 3), (61, 13, "f64", False, 2),
+                                                     (3, 2, "f32", True, 0)])
 def test_two_step_passes_bit_identical(nx, ny, prec, source, shape):
     """Two time steps per pass (LDS tiles of 62 x 14, 10 or 6 nodes with a
     one-node halo, 4, 6 or 8 waves per workgroup) against single sweeps: the same arithmetic on the same
@@ -296,7 +299,8 @@ def test_two_step_passes_bit_identical(nx, ny, prec, source, shape):
 
 def test_two_step_refused_where_it_does_not_apply():
     lbm = _lbm()
-    for spec in (W.d3q19_walls((20, 18, 22))[0], W.spec_nonlinear_2d(40, 30)):
+    walls = dict(W.spec_nonlinear_2d(70, 30), bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]])
+    for spec in (W.d3q19_walls((20, 18, 22))[0], walls):
         s = lbm.Lbm(spec)
         with pytest.raises(lbm.LbmError) as ei:
             s.set_two_step(True)
@@ -308,7 +312,6 @@ def test_two_step_refused_where_it_does_not_apply():
     assert lbm.Lbm(W.spec_nonlinear_2d(100, 37, precision="f64")).two_step_shapes() == [(6, 4), (6, 8), (14, 16)]
     for spec, shape in ((W.spec_nonlinear_2d(100, 37, precision="f64"), 3),
                         (W.spec_nonlinear_2d(100, 37, precision="f32"), 4),
-                        (W.spec_nonlinear_2d(100, 15, precision="f64"), 2),     # 14 rows need ny >= 16
                         (W.spec_nonlinear_2d(100, 37, precision="f32", bcoef=0.0) | {"b": [[0, 0, 0, 0.1]] * 2}, 1)):
         s = lbm.Lbm(spec)
         with pytest.raises(lbm.LbmError) as ei:
