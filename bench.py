@@ -89,14 +89,28 @@ def time_steps(torch, sim, steps, warmup):
     return e0.elapsed_time(e1) / 1e3 / steps, wall
 
 
+# tile shape forced on two-step runs after tuning, with the XCD-aware order
+# (--two-step-shape; None: the tuner's choices)
+TWO_STEP_SHAPE = None
+
+
 def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_step=None):
     """Time `steps` sweeps.  With tune, the launch shape is the autotuner's
-    (which may pick two time steps per pass); two_step forces that choice."""
+    (which may pick two time steps per pass); two_step forces that choice,
+    TWO_STEP_SHAPE the tile shape of a two-step run."""
     sim = lbm.Lbm(spec).init(phi0)
     rep = sim.tune(reps=20).splitlines()[-1] if tune else "untuned"
     if two_step is not None:
         sim.set_two_step(two_step)
         rep += f"; two steps per pass forced {'on' if two_step else 'off'}"
+    if TWO_STEP_SHAPE is not None and (" two 1" in rep if two_step is None else two_step):
+        shapes = sim.two_step_shapes()
+        if TWO_STEP_SHAPE < len(shapes):
+            sim.set_two_step(True, TWO_STEP_SHAPE)
+            sim.set_remap(True)
+            r, w = shapes[TWO_STEP_SHAPE]
+            rep = re.sub(r" rows \d+ waves \d+", f" rows {r} waves {w}", rep)
+            rep = re.sub(r" remap \d", " remap 1", rep) + f"; shape {r} x {w} and XCD order forced"
     two = (" two 1" in rep) if two_step is None else bool(two_step)
     m = re.search(r" rows (\d+) waves (\d+)", rep)
     rows = f"{m.group(1)} rows x {m.group(2)} waves" if (two and m) else None
@@ -276,18 +290,22 @@ def cpu_baseline(spec, phi0, target_s=12.0):
 
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 1000 --warmup 50",
+             "python3 bench.py --no-cpu --steps 1000 --warmup 50 --two-step-shape 1",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19",
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1",
     "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19",
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1",
     "valu": "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVES -d gpurun_out/pmc_valu -o valu "
-            "--output-format csv -- python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint",
+            "--output-format csv -- python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint "
+            "--two-step-shape 1",
 }
 # vector-ALU issue peak without packed FP32: each SIMD issues one 64-lane
 # instruction every 4 clocks (16 lanes per clock), 4 SIMDs per CU, so one
 # wave-instruction per CU per clock: 256 CUs x 2.4 GHz
 VALU_ISSUE_PEAK = 256 * 2.4e9
+
+# nodes of the 512-instance batch workload (sides 32..512, seed 4)
+BATCH_NODES = 44439067
 
 # workload label -> (kernel name prefix in the trace, algorithmic bytes per launch)
 PROFILED = {
@@ -299,10 +317,11 @@ PROFILED = {
                              bytes_per_node(9, "f32", True) * 1024 * 1024),
     "nonlinear2d-1024 f64": ("k_sweep<9, double, double, true, true, true, false, 3, false, ",
                              bytes_per_node(9, "f64", True) * 1024 * 1024),
-    "d3q19-256 f32": ("k_sweep<19, float, float, true, false, false, true, 4, true, ",
+    "d3q19-256 f32": ("k_sweep<19, float, float, true, false, false, true, ",
                       bytes_per_node(19, "f32", False) * 256 ** 3),
-    "d3q19-256 f64": ("k_sweep<19, double, double, true, false, false, true, 4, true, ",
+    "d3q19-256 f64": ("k_sweep<19, double, double, true, false, false, true, ",
                       bytes_per_node(19, "f64", False) * 256 ** 3),
+    "batch-512 f32 two-step": ("k_batch_sweep2<float, float, ", bytes_per_node(9, "f32", False) * BATCH_NODES),
     "adjoint2d-512 f64": ("k_adjoint<9, double, double, true, true, true, false, 3, ",
                           adjoint_bytes_per_node(9, "f64", True) * 512 * 512),
     "adjoint2d-512 f32": ("k_adjoint<9, float, float, true, true, true, false, 3, ",
@@ -350,21 +369,22 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
            "commands": PROFILE_COMMANDS, "workloads": {}}
     rows = []
     for label, (kn, alg) in PROFILED.items():
-        # the variant with the most dispatches: the timed run, not the tuner's trials
-        hits = sorted((k for k in fetch if kn in k and k in write), key=lambda k: -len(fetch[k]))
+        # the variant with the most dispatches (the timed run, not the tuners'
+        # trials); the profiled runs pin the two-step tile shape, so the
+        # trace and the counter runs time the same kernel
+        prefix = kn
+        hits = sorted((k for k in fetch if prefix in k and k in write), key=lambda k: -len(fetch[k]))
         if not hits:
             continue
         k = hits[0]
-        prefix, kn = kn, k.replace("lbm::", "")
+        kn = k.replace("lbm::", "")
         fv, wv = stats.median(fetch[k]), stats.median(write[k])
         t = fv * 1024 * fscale + wv * 1024 * wscale
-        # trace time: the same variant if the trace run timed it most, else the
-        # most-dispatched variant there (traffic does not depend on the tile shape)
         tk = sorted((n for n in durs if prefix in n), key=lambda n: -len(durs[n]))
         tr = med_us.get(tk[0]) if tk else None
         if tr is None:
             tr = next((v for n, v in avg_us.items() if kn in n), None)
-        if tk and kn not in tk[0]:
+        if tk and tk[0] != k:
             kn = f"{kn} (counters); {tk[0].replace('lbm::', '')} (trace)"
         out["workloads"][label] = {"kernel": kn, "fetch_kib": fv, "write_kib": wv,
                                    "traffic_bytes_per_launch": t, "algorithmic_bytes_per_launch": alg,
@@ -431,16 +451,17 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
               "| workload | kernel | waves | VALU | SALU | LDS | VALU lane-instructions per update | "
               "trace median us | VALU issue fraction |", "|---|---|---|---|---|---|---|---|---|"]
         for label, (prefix, alg) in PROFILED.items():
+            want = "lbm::" + out["workloads"].get(label, {}).get("kernel", "")
             hits = sorted((k for k in vals if prefix in k and "SQ_INSTS_VALU" in vals[k]),
                           key=lambda k: -len(vals[k]["SQ_INSTS_VALU"]))
             if not hits:
                 continue
-            k = hits[0]
+            k = want if want in vals and "SQ_INSTS_VALU" in vals[want] else hits[0]
             m = {c: stats.median(v) for c, v in vals[k].items()}
             w = out["workloads"].get(label, {})
             tr = w.get("trace_median_us")
             nodes = {"nonlinear2d-1024": 1024 * 1024, "adjoint2d-512": 512 * 512,
-                     "d3q19-256": 256 ** 3}[label.split(" ")[0]]
+                     "d3q19-256": 256 ** 3, "batch-512": BATCH_NODES}[label.split(" ")[0]]
             upd = nodes * (2 if "two-step" in label else 1)
             frac = m["SQ_INSTS_VALU"] / (tr * 1e-6 * VALU_ISSUE_PEAK) if tr else None
             w.update({"sq_insts_valu": m["SQ_INSTS_VALU"], "valu_issue_fraction": frac})
@@ -467,6 +488,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain copy (practical bandwidth, counter calibration)")
+    ap.add_argument("--two-step-shape", type=int, default=None,
+                    help="after tuning, run two-step passes with this tile shape (lbm_two_step_shape index) "
+                         "and the XCD-aware order; the profiles pin 1 with that order, the tuner's usual choice, "
+                         "so that every profiled run times the same kernel")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write the profiles/ summaries from rocprofv3 output under DIR and exit (no GPU)")
     args = ap.parse_args()
@@ -475,6 +500,8 @@ def main():
         print(json.dumps({k: v["traffic_bytes_per_launch"] / v["algorithmic_bytes_per_launch"]
                           for k, v in out["workloads"].items()}))
         return
+    global TWO_STEP_SHAPE
+    TWO_STEP_SHAPE = args.two_step_shape
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)

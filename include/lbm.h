@@ -171,6 +171,12 @@ int lbm_set_current(lbm_ctx *ctx, int which, long long t);
  * (1 = one block per workgroup, the default). */
 int lbm_set_chunk(lbm_ctx *ctx, int chunk);
 
+/* Workgroup order: on = one contiguous run of the domain per XCD (the
+ * default unless the state exceeds the Infinity Cache or
+ * LBM_FLAG_NO_XCD_REMAP is set), off = the hardware's round-robin order.
+ * lbm_tune sets it too. */
+int lbm_set_remap(lbm_ctx *ctx, int on);
+
 /* Non-temporal (streaming) loads and stores of the distributions in the
  * equal-rate sweep (default: on when the state exceeds 256 MB, the size of
  * the Infinity Cache, where they raise HBM throughput; off otherwise, where

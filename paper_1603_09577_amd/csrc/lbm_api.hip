@@ -878,6 +878,13 @@ int lbm_set_nontemporal(lbm_ctx *c, int on) {
     return LBM_OK;
 }
 
+int lbm_set_remap(lbm_ctx *c, int on) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    c->g.remap = on ? 1u : 0u;
+    drop_graphs(c);
+    return LBM_OK;
+}
+
 int lbm_set_chunk(lbm_ctx *c, int chunk) {
     if (!c || chunk < 1) return fail(LBM_E_INVALID, "chunk must be >= 1");
     c->g.chunk = (uint32_t)chunk;

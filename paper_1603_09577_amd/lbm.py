@@ -33,7 +33,7 @@ EXPORTS = [
     "lbm_batch_step", "lbm_batch_get_phi", "lbm_batch_tune", "lbm_batch_set_shape",
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
     "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields", "lbm_set_phi_wall",
-    "lbm_set_two_step", "lbm_two_step_shape", "lbm_adjoint_step2", "lbm_adjoint_pair_ok",
+    "lbm_set_two_step", "lbm_two_step_shape", "lbm_adjoint_step2", "lbm_adjoint_pair_ok", "lbm_set_remap",
 ]
 
 
@@ -126,6 +126,7 @@ def load():
         "lbm_set_fields": ([_VP, _VP, _VP], ctypes.c_int),
         "lbm_set_phi_wall": ([_VP, ctypes.c_double, ctypes.c_double, _VP], ctypes.c_int),
         "lbm_set_two_step": ([_VP, ctypes.c_int], ctypes.c_int),
+        "lbm_set_remap": ([_VP, ctypes.c_int], ctypes.c_int),
         "lbm_two_step_shape": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
                                ctypes.c_int),
         "lbm_adjoint_step2": ([_VP] * 10, ctypes.c_int),
@@ -281,6 +282,10 @@ class Lbm:
 
     def set_chunk(self, chunk):
         _check(self.lib.lbm_set_chunk(self.ctx, int(chunk)))
+
+    def set_remap(self, on):
+        """XCD-aware workgroup order on or off (lbm_set_remap)."""
+        _check(self.lib.lbm_set_remap(self.ctx, int(bool(on))))
 
     def tune(self, reps=5, stream=None):
         """Autotune the launch shape; restarts from the phi0 given to init."""

@@ -111,6 +111,7 @@ def test_null_arguments(L):
     assert L.lbm_adjoint_step2(*([None] * 10)) == lbm.LBM_E_INVALID
     assert L.lbm_adjoint_pair_ok(None, None) == lbm.LBM_E_INVALID
     assert L.lbm_two_step_shape(None, 0, None, None) == lbm.LBM_E_INVALID
+    assert L.lbm_set_remap(None, 1) == lbm.LBM_E_INVALID
     assert L.lbm_recenter(None, None) == lbm.LBM_E_INVALID
     assert L.lbm_set_recenter(None, 5) == lbm.LBM_E_INVALID
     assert L.lbm_set_check(None, 5) == lbm.LBM_E_INVALID
