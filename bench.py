@@ -59,9 +59,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_key):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on different kernel sources."""
+def profile_entry(kernel_key, kernel=None):
+    """The committed rocprofv3 summary of a workload (HBM traffic per launch,
+    VALU issue fraction), or None when it is missing, was taken on different
+    kernel sources, or (with `kernel`) profiled another kernel variant."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     try:
         d = json.load(open(path))
@@ -70,7 +71,9 @@ def traffic_from_profiles(kernel_key):
     if d.get("kernel_hash") != kernel_hash():
         return None
     v = d.get("workloads", {}).get(kernel_key)
-    return None if v is None else v.get("traffic_bytes_per_launch")
+    if v is None or (kernel is not None and not v.get("kernel", "").startswith(kernel)):
+        return None
+    return v
 
 
 def time_steps(torch, sim, steps, warmup):
@@ -576,7 +579,13 @@ def main():
         extra["rel_l2_vs_oracle"] = {"steps": ncpu, **errs}
 
     per = head["ms_per_step"] / 1e3
-    traffic = traffic_from_profiles("nonlinear2d-1024 f32 two-step" if head["two_step"] else "nonlinear2d-1024 f32")
+    if head["two_step"]:
+        m = re.match(r"(\d+) rows x (\d+) waves", head["tile_rows"] or "")
+        prof = profile_entry("nonlinear2d-1024 f32 two-step",
+                             f"k_sweep2<float, float, true, true, 3, {m.group(1)}, {m.group(2)}>" if m else "?")
+    else:
+        prof = profile_entry("nonlinear2d-1024 f32")
+    traffic = prof.get("traffic_bytes_per_launch") if prof else None
     line = {
         "metric": METRIC,
         "value": head["mlups"],
@@ -605,6 +614,10 @@ def main():
             "bytes_per_node": head["bytes_per_node"], "nodes_per_launch": head["nodes"],
             "steps_per_launch": 2 if head["two_step"] else 1,
             "per_update_frac": head["per_update_hbm_frac"],
+            # measured vector-instruction issue of the same kernel (rocprofv3
+            # SQ_INSTS_VALU over its trace time) against 6.14e11 wave-instructions/s
+            # (256 CUs x 2.4 GHz, one 64-lane instruction per CU per clock without packed FP32)
+            "valu_issue_frac": prof.get("valu_issue_fraction") if prof else None,
         },
         "single_step": {"mlups": single32["mlups"], "ms_per_step": single32["ms_per_step"],
                         "achieved_gbs": single32["achieved_gbs"], "hbm_frac": single32["hbm_frac"]},
