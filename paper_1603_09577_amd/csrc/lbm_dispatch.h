@@ -67,8 +67,8 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
     return hipGetLastError();
 }
 
-// Two steps per pass (D2Q9, periodic, equal rates): tile height by storage
-// size (the LDS tile is 9 x (TH + 2) x 64 values).
+// Default tile height of a two-step pass by storage size (the LDS tile is
+// 9 x (TH + 2) x 64 values; 40 KB with 4-byte and 8-byte storage).
 template <typename TS>
 constexpr int two_step_rows() { return sizeof(TS) == 8 ? 6 : 14; }
 

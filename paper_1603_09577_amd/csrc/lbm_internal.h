@@ -123,12 +123,11 @@ LBM_LAUNCHERS(q19)
 
 hipError_t launch_zero(double *p, uint32_t n, hipStream_t st);
 
-// Two time steps per pass, D2Q9 only (sweep_d2q9.hip); rows per tile by precision.
+// Two time steps per pass, D2Q9 only (sweep_d2q9.hip), with tile shape `shape`.
 hipError_t launch_sweep2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
                             const void *pin, void *pout, int *flag, int shape, hipStream_t st);
 // tile shape `shape` of two-step passes (rows, waves per workgroup); false past the last
 bool two_step_shape_of(int prec, int shape, int *rows, int *waves);
-int two_step_rows_of(int prec);
 int adjoint_pair_rows(int prec, uint32_t nx, uint32_t ny);
 // Two reversed sweeps per pass (sweep s, then s - 1), D2Q9 only; tile rows
 // by compute type and grid size (adjoint_pair_rows).

@@ -79,6 +79,5 @@ hipError_t launch_adjoint2_q9(const Dims &dm, const Geom &g, const void *coefs, 
 
 int adjoint_pair_rows(int prec, uint32_t nx, uint32_t ny) { return adjoint_pair_rows_for(prec, nx, ny); }
 
-int two_step_rows_of(int prec) { return prec == 0 ? two_step_rows<double>() : two_step_rows<float>(); }
 
 }  // namespace lbm
