@@ -250,6 +250,11 @@ def test_launch_variants_identical():
             s.set_chunk(chunk)
             s.step(70)
             assert torch.equal(s.phi(), want), (nt, chunk, fl)
+        for remap in (0, 1):
+            s = lbm.Lbm(spec).init(phi0)
+            s.set_remap(remap)
+            s.step(70)
+            assert torch.equal(s.phi(), want), remap
         s = lbm.Lbm(spec).init(phi0)
         s.tune(reps=2)
         s.step(70)
