@@ -27,6 +27,10 @@
 #include <string>
 #include <vector>
 
+#include <cerrno>
+#include <sys/stat.h>
+#include <sys/types.h>
+
 #include "../../include/lbm.h"
 #include "lbm_kernels.h"
 
@@ -361,14 +365,25 @@ bool cache_lookup(const std::string &key, int &shape, uint32_t &grid, int &remap
     return false;
 }
 
+// create every missing directory of `dir` (no shell involved)
+bool make_dirs(const std::string &dir) {
+    for (size_t i = 1; i <= dir.size(); ++i) {
+        if (i < dir.size() && dir[i] != '/') continue;
+        const std::string part = dir.substr(0, i);
+        struct stat st;
+        if (stat(part.c_str(), &st) == 0) {
+            if (!S_ISDIR(st.st_mode)) return false;
+        } else if (mkdir(part.c_str(), 0755) != 0 && errno != EEXIST) {
+            return false;
+        }
+    }
+    return true;
+}
+
 void cache_store(const std::string &key, int shape, uint32_t grid, int remap) {
     const std::string path = cache_path();
     const size_t slash = path.find_last_of('/');
-    if (slash != std::string::npos) {
-        std::string dir = path.substr(0, slash);
-        std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
-        if (std::system(cmd.c_str()) != 0) return;
-    }
+    if (slash != std::string::npos && slash > 0 && !make_dirs(path.substr(0, slash))) return;
     std::ofstream out(path, std::ios::app);
     if (out) out << key << " " << shape << " " << grid << " " << remap << "\n";
 }

@@ -142,3 +142,20 @@ def test_two_step_batch_refused_with_a_source():
     with pytest.raises(lbm.LbmError) as ei:
         b.set_shape(4, 0, 1)
     assert ei.value.code == lbm.LBM_E_INVALID
+
+
+def test_tuner_cache_roundtrip(tmp_path, monkeypatch):
+    """The batch tuner's decision is appended to $LBM_TUNE_CACHE (missing
+    directories created) and read back by the next tune of the same batch."""
+    from paper_1603_09577_amd import lbm
+    path = tmp_path / "a" / "b" / "tune.txt"
+    monkeypatch.setenv("LBM_TUNE_CACHE", str(path))
+    specs, phis = sourcefree_batch("f32", 4, seed=35)
+    b = lbm.Batch(specs).init(phis)
+    first = b.tune(reps=1, use_cache=True)
+    assert path.exists() and "chosen" in first.splitlines()[-1]
+    shape = b.get_shape()
+    b2 = lbm.Batch(specs).init(phis)
+    second = b2.tune(reps=1, use_cache=True)
+    assert second.startswith("cached")
+    assert b2.get_shape() == shape
