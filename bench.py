@@ -487,7 +487,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--quick", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--only", default="",
-                    help="comma list of secondary workloads to run: adjoint,d3q19,batch (default: all)")
+                    help="comma list of secondary workloads to run: adjoint,d3q19,batch,hbm (default: all)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30,
                     help="size of the plain copy (practical bandwidth, counter calibration)")
@@ -533,7 +533,7 @@ def main():
     print(f"# nonlinear2d-1024 f16: {f16['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
     extra = {}
-    only = set(w for w in args.only.split(",") if w) or {"adjoint", "d3q19", "batch"}
+    only = set(w for w in args.only.split(",") if w) or {"adjoint", "d3q19", "batch", "hbm"}
     if args.quick:
         only = set()
     if "adjoint" in only:
@@ -562,6 +562,23 @@ def main():
         torch.cuda.empty_cache()
     if "batch" in only:
         extra["batch_f32"] = run_batch(torch, lbm, W, 1000 if args.steps >= 1000 else args.steps)
+    if "hbm" in only:
+        # the headline grid's state (79 MB) fits in the 256 MB Infinity Cache;
+        # the same workload at 4096^2 (1.2 GB) is bound by HBM proper
+        spec4, _, _ = W.nonlinear_2d(4096, precision="f32")
+        p4 = W.noise_field((4096, 4096), 2)
+        big, sb, _ = run_forward(torch, lbm, spec4, p4, 200, 64, "nonlinear2d-4096 f32")
+        del sb
+        one, s1, _ = run_forward(torch, lbm, spec4, p4, 200, 64, "nonlinear2d-4096 f32 single", two_step=False)
+        del s1
+        extra["hbm_resident_4096_f32"] = {
+            "mlups": big["mlups"], "two_step": big["two_step"], "tile_rows": big["tile_rows"],
+            "per_update_hbm_frac": big["per_update_hbm_frac"], "hbm_frac": big["hbm_frac"],
+            "single_sweep_mlups": one["mlups"], "single_sweep_hbm_frac": one["hbm_frac"],
+            "state_bytes": 2 * 9 * 4 * 4096 * 4096 + 4 * 4096 * 4096}
+        print(f"# nonlinear2d-4096 f32: {big['mlups']:.0f} MLUPS (single sweep {one['mlups']:.0f})",
+              file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
         print(f"# batch {extra['batch_f32']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     extra["copy_probe"] = copy_probe(torch, lbm, args.copy_bytes)
