@@ -96,7 +96,8 @@ __device__ __forceinline__ TC gbar_scatter(const Coefs<TC> *__restrict__ cf, TC 
 
 // lambda_k(x) = psi_{s+1,k}(x + c_k): the transposed streaming of the pull
 // gather (across a wall, -psi_{s+1,kbar}(x), the transposed anti-bounce-back).
-template <int Q, bool WALL, bool O32 = false, typename TC>
+// NT: streaming (non-temporal) loads, for states far larger than the caches.
+template <int Q, bool WALL, bool O32 = false, bool NT = false, typename TC>
 __device__ __forceinline__ void gather_adjoint(const Geom &g, const TC *__restrict__ psi_next, const NodeGeo &ng,
                                                TC *lam) {
     using L = Lattice<Q>;
@@ -111,9 +112,9 @@ __device__ __forceinline__ void gather_adjoint(const Geom &g, const TC *__restri
         }
         const int cl = L::c(k, D - 1);
         if (WALL && ((cl == 1 && ng.hi) || (cl == -1 && ng.lo)))
-            lam[k] = -*at<O32>(psi_next + (uint64_t)L::opp(k) * g.plane, ng.n);
+            lam[k] = -load_s<TC, NT>(at<O32>(psi_next + (uint64_t)L::opp(k) * g.plane, ng.n));
         else
-            lam[k] = *at<O32>(psi_next + (uint64_t)k * g.plane, (uint32_t)((int)ng.n + off));
+            lam[k] = load_s<TC, NT>(at<O32>(psi_next + (uint64_t)k * g.plane, (uint32_t)((int)ng.n + off)));
     }
 }
 
@@ -437,7 +438,8 @@ __device__ __forceinline__ void k0_partials(const Coefs<TC> *__restrict__ cf, co
 // Occupancy: D2Q9 is held at 4 waves per SIMD (it fits 128 registers without
 // spills); D3Q19 keeps 19 populations, their adjoints and the outputs live and
 // is allowed down to 2.
-template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool O32 = false>
+template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool O32 = false,
+          bool NT = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Q == 9 ? 4 : 2, 8)))
 k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fs,
           const typename HistType<TS>::T *__restrict__ ps, const TC *__restrict__ psi_next,
@@ -450,18 +452,18 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
         const NodeGeo ng = node_geometry<Q, WALL>(g, n);
         // ---- forward recomputation ----
         TC h[Q];
-        gather<Q, WALL, false, O32>(g, cf, fs, ng, h);
+        gather<Q, WALL, NT, O32>(g, cf, fs, ng, h);
         const TC pp_off = SRC ? (TC)*at<O32>(ps, n) : TC(0);
         const TC pin = (TC)*at<O32>(pi_next, n);   // p_{s+1} = phi - phi_ref
 
         // ---- lambda = dL/d(out) by transposed streaming ----
         TC lam[Q];
-        gather_adjoint<Q, WALL, O32>(g, psi_next, ng, lam);
+        gather_adjoint<Q, WALL, O32, NT>(g, psi_next, ng, lam);
 
         TC out[Q];
         const TC pb = adjoint_node<Q, TC, EQR, SRC, KVAR, NP>(cf, h, pp_off, lam, pin, out, gk);
 #pragma unroll
-        for (int k = 0; k < Q; ++k) *at<O32>(psi_out + (uint64_t)k * g.plane, n) = out[k];
+        for (int k = 0; k < Q; ++k) store_s<NT>(at<O32>(psi_out + (uint64_t)k * g.plane, n), out[k]);
         *at<O32>(pi_out, n) = (double)pb;
     }
     __shared__ double sh[6][kBlock / 64];

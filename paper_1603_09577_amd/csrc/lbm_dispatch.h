@@ -217,15 +217,18 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
     const dim3 grid(g.nblocks), block(kBlock);
     {
         if (dm.eqr && dm.deg3 && dm.o32) {
-            const int c3 = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
-#define LBM_ADJ3(S, K, W)                                                                               \
-    case (S * 4 + K * 2 + W):                                                                           \
-        hipLaunchKernelGGL((k_adjoint<Q, TS, TC, true, S, K, W, 3, true>), grid, block, 0, st, g, cf, fs, ps, pn, \
-                           pi_next, po, pi_out, gk_part);                                               \
+            // streaming accesses when the state exceeds the Infinity Cache (dm.nt)
+            const int c3 = (dm.nt ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
+#define LBM_ADJ3(S, K, W, NT)                                                                           \
+    case (NT * 8 + S * 4 + K * 2 + W):                                                                  \
+        hipLaunchKernelGGL((k_adjoint<Q, TS, TC, true, S, K, W, 3, true, NT>), grid, block, 0, st, g, cf, fs, ps, \
+                           pn, pi_next, po, pi_out, gk_part);                                           \
         break;
             switch (c3) {
-                LBM_ADJ3(0, 0, 0) LBM_ADJ3(0, 0, 1) LBM_ADJ3(0, 1, 0) LBM_ADJ3(0, 1, 1)
-                LBM_ADJ3(1, 0, 0) LBM_ADJ3(1, 0, 1) LBM_ADJ3(1, 1, 0) LBM_ADJ3(1, 1, 1)
+                LBM_ADJ3(0, 0, 0, 0) LBM_ADJ3(0, 0, 1, 0) LBM_ADJ3(0, 1, 0, 0) LBM_ADJ3(0, 1, 1, 0)
+                LBM_ADJ3(1, 0, 0, 0) LBM_ADJ3(1, 0, 1, 0) LBM_ADJ3(1, 1, 0, 0) LBM_ADJ3(1, 1, 1, 0)
+                LBM_ADJ3(0, 0, 0, 1) LBM_ADJ3(0, 0, 1, 1) LBM_ADJ3(0, 1, 0, 1) LBM_ADJ3(0, 1, 1, 1)
+                LBM_ADJ3(1, 0, 0, 1) LBM_ADJ3(1, 0, 1, 1) LBM_ADJ3(1, 1, 0, 1) LBM_ADJ3(1, 1, 1, 1)
                 default: return hipErrorInvalidValue;
             }
 #undef LBM_ADJ3

@@ -169,3 +169,34 @@ def test_pair_refused_where_it_does_not_apply():
         with pytest.raises(lbm.LbmError) as ei:
             sim.adjoint_step2(sim.f[which], sim.p, sim.f[which], sim.p, psi, pi, psi2, pi2)
         assert ei.value.code == lbm.LBM_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("lattice,prec", [(19, "f32"), (19, "f64"), (9, "f32")])
+def test_adjoint_streaming_accesses_identical(lattice, prec):
+    """Non-temporal (streaming) accesses, which the library turns on for states
+    larger than the Infinity Cache, change only how memory is accessed: a
+    reversed sweep gives the same psi, pi and K0 sums with them on and off."""
+    from paper_1603_09577_amd import lbm
+    if lattice == 19:
+        spec, phi0, _ = W.d3q19_walls((20, 18, 22), precision=prec)
+    else:
+        spec = W.spec_nonlinear_2d(70, 33, precision=prec)
+        phi0 = W.noise_field((33, 70), 38)
+    say(f"[gpu adjoint] streaming accesses D{2 if lattice == 9 else 3}Q{lattice} {prec}")
+    res = []
+    for nt in (False, True):
+        sim = lbm.Lbm(spec).init(phi0)
+        sim.set_nontemporal(nt)
+        sim.step(5)
+        which, _ = sim.current()
+        g = torch.tensor(np.random.default_rng(39).standard_normal(sim.shape), dtype=torch.float64, device="cuda")
+        a, pa = sim.adjoint_buffers()
+        b, pb = sim.adjoint_buffers()
+        sim.adjoint_seed(g, a, pa)
+        for _ in range(3):
+            sim.adjoint_step(sim.f[which], sim.p, a, pa, b, pa)
+            a, b = b, a
+        torch.cuda.synchronize()
+        res.append((planes(sim, a).clone(), pa.clone(), sim.adjoint_grad_k0()))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+    assert res[0][2] == res[1][2]
