@@ -348,11 +348,14 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
     avg_us = {kname(r["Name"]): float(r["AverageNs"]) / 1e3 for r in trace}
     # per-dispatch durations: the median is not moved by the autotuner's trials
     durs = {}
+    by_grid = {}   # (kernel, launch grid in threads) -> durations: one kernel may run on several grids
     tpath = os.path.join(gdir, "prof_trace", "trace_kernel_trace.csv")
     if os.path.exists(tpath):
         for r in csv.DictReader(open(tpath)):
-            durs.setdefault(kname(r["Kernel_Name"]), []).append(
-                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            durs.setdefault(kname(r["Kernel_Name"]), []).append(d)
+            grid = tuple(int(r.get(f"Grid_Size_{a}", 1) or 1) for a in "XYZ")
+            by_grid.setdefault((kname(r["Kernel_Name"]), grid), []).append(d)
     med_us = {k: stats.median(v) for k, v in durs.items()}
 
     def counters(sub, stem, cname):
@@ -434,6 +437,43 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
                   f"{'-' if med is None else f'{med:.2f}'} | "
                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                   f"{float(r['Percentage']):.1f} |")
+    # one kernel instantiation can serve several workloads (the two-step pass
+    # runs the 1024^2 and the 4096^2 grids), so the per-workload figures take
+    # the dispatches of the workload's kernel on its most frequent launch grid
+    tl += ["", "## Per workload", "",
+           "Dispatches of each workload's kernel on its own launch grid (the grid with the most dispatches "
+           "of that kernel; tuner trials of the same kernel on the same grid are the same work and are "
+           "included). GB/s = algorithmic bytes per launch over the average duration.", "",
+           "| workload | kernel | launch grid (threads) | dispatches | avg us | median us | "
+           "algorithmic MB per launch | GB/s (avg) | fraction of 8 TB/s |", "|---|---|---|---|---|---|---|---|---|"]
+    per_wl = {}
+    for label, (prefix, alg) in PROFILED.items():
+        groups = sorted(((k, g) for (k, g) in by_grid if prefix in k), key=lambda kg: -len(by_grid[kg]))
+        if not groups:
+            continue
+        k, grid = groups[0]
+        v = by_grid[(k, grid)]
+        avg, med = stats.mean(v), stats.median(v)
+        per_wl[label] = {"kernel": k.replace("lbm::", ""), "grid": grid, "dispatches": len(v),
+                         "avg_us": avg, "median_us": med, "gbs_avg": alg / (avg * 1e-6) / 1e9}
+        gx = " x ".join(str(x) for x in grid if x > 1) or "1"
+        tl.append(f"| {label} | `{k.replace('lbm::', '')}` | {gx} | {len(v)} | {avg:.2f} | {med:.2f} | "
+                  f"{alg / 1e6:.2f} | {alg / (avg * 1e-6) / 1e9:.0f} | {alg / (avg * 1e-6) / 8e12:.3f} |")
+    # the profiled run's own bench line: its roofline figure for the headline
+    # kernel comes from HIP events around the timed region of the same run
+    blog = os.path.join(gdir, "trace.log")
+    head = "nonlinear2d-1024 f32 two-step"
+    if os.path.exists(blog) and head in per_wl:
+        line = next((ln for ln in open(blog) if ln.startswith('{"metric"')), None)
+        if line:
+            rf = json.loads(line)["roofline"]
+            per_launch_us = rf["bytes_per_node"] * rf["nodes_per_launch"] / (rf["achieved"] * 1e9) * 1e6
+            w = per_wl[head]
+            tl += ["", f"The bench line of this profiled run reports `roofline.achieved` = {rf['achieved']:.0f} GB/s "
+                   f"for `{rf['kernel']}`, i.e. {per_launch_us:.2f} us per launch (HIP events over the timed "
+                   f"region); the trace gives {w['avg_us']:.2f} us average and {w['median_us']:.2f} us median "
+                   f"per dispatch of that kernel on the same grid ({w['gbs_avg']:.0f} GB/s)."]
+    out["trace_per_workload"] = per_wl
     with open(os.path.join(pdir, "sweep_kernels_kernel_trace.md"), "w") as fh:
         fh.write("\n".join(tl) + "\n")
 
