@@ -462,8 +462,12 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
 
         TC out[Q];
         const TC pb = adjoint_node<Q, TC, EQR, SRC, KVAR, NP>(cf, h, pp_off, lam, pin, out, gk);
+        if constexpr (O32) {
+            store_planes<Q, NT>(psi_out, g.plane, n, out);
+        } else {
 #pragma unroll
-        for (int k = 0; k < Q; ++k) store_s<NT>(at<O32>(psi_out + (uint64_t)k * g.plane, n), out[k]);
+            for (int k = 0; k < Q; ++k) store_s<NT>(psi_out + (uint64_t)k * g.plane + n, out[k]);
+        }
         *at<O32>(pi_out, n) = (double)pb;
     }
     __shared__ double sh[6][kBlock / 64];

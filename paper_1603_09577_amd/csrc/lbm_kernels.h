@@ -64,6 +64,23 @@ __device__ __forceinline__ T *at(T *base, uint32_t idx) {
     }
 }
 
+// Stores of the q direction planes at one node, with 32-bit offsets (every
+// array the kernel indexes spans less than 4 GiB).  The byte offset passes
+// through an empty asm before each store, so each store sees its own opaque
+// offset and takes the scalar-base form (plane base in scalar registers,
+// offset in one vector register).  Without it the compiler forms one 64-bit
+// vector address for the node and adds each plane's offset to it with a
+// 64-bit vector instruction per store.
+template <int Q, bool NT, typename TS, typename TC>
+__device__ __forceinline__ void store_planes(TS *__restrict__ base, uint64_t plane, uint32_t n, const TC *out) {
+    uint32_t off = n * (uint32_t)sizeof(TS);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        asm("" : "+v"(off));
+        store_s<NT>(reinterpret_cast<TS *>(reinterpret_cast<char *>(base + (uint64_t)k * plane) + off), out[k]);
+    }
+}
+
 // sum_{p < N} c[p] x^p by Horner over a compile-time length: no branches;
 // the host picks the short length whenever every polynomial fits in it (the
 // coefficients beyond a polynomial's degree are zero).
@@ -601,8 +618,12 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
     const TC phio = collide_node<Q, TC, EQR, SRC, KVAR, NP, SB, KF>(cf, h, pp_off, n, kfield, rfield, rem3, out);
     if (SRC || rem3) *at<O32>(p, n) = (typename HistType<TS>::T)phio;
 
+    if constexpr (O32) {
+        store_planes<Q, NT>(fout, g.plane, n, out);
+    } else {
 #pragma unroll
-    for (int k = 0; k < Q; ++k) store_s<NT>(at<O32>(fout + (uint64_t)k * g.plane, n), out[k]);
+        for (int k = 0; k < Q; ++k) store_s<NT>(fout + (uint64_t)k * g.plane + n, out[k]);
+    }
 
     if (!__builtin_isfinite(phio)) *flag = 1;
 }
@@ -697,8 +718,7 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
             bad |= !__builtin_isfinite(phio);
             if (x < nx && y < ny) {
                 const uint32_t m = (uint32_t)y * g.nx + (uint32_t)x;
-#pragma unroll
-                for (int k = 0; k < 9; ++k) store_s(at<true>(fout + (uint64_t)k * g.plane, m), out[k]);
+                store_planes<9, false>(fout, g.plane, m, out);
                 if (SRC) *at<true>(pout, m) = (TP)phio;
             }
         }
