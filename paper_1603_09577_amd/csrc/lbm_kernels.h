@@ -883,14 +883,26 @@ __device__ __forceinline__ float lane_f32(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Sum over the 64 lanes of a wave, the same in every lane (same pattern in
-// both precisions).
+// DPP move restricted to the rows in ROWS; lanes of the other rows read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_rows_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+
+// Sum over the 64 lanes of a wave, the same in every lane.  The four row
+// sums r0..r3 are combined with the row broadcasts of the DPP unit: rows 1
+// and 3 add lane 15 of the row before (r1 + r0, r3 + r2), then row 3 adds
+// lane 31 ((r3 + r2) + (r1 + r0)); one read of lane 63.  IEEE addition is
+// commutative, so this equals (r0 + r1) + (r2 + r3), the order of the FP64
+// form below, bit for bit.
 __device__ __forceinline__ float wave_total(float v) {
-    v += dpp_f32<0xB1>(v);
-    v += dpp_f32<0x4E>(v);
-    v += dpp_f32<0x141>(v);
-    v += dpp_f32<0x140>(v);
-    return (lane_f32(v, 0) + lane_f32(v, 16)) + (lane_f32(v, 32) + lane_f32(v, 48));
+    v += dpp_f32<0xB1>(v);                 // quad_perm (1, 0, 3, 2)
+    v += dpp_f32<0x4E>(v);                 // quad_perm (2, 3, 0, 1)
+    v += dpp_f32<0x141>(v);                // row_half_mirror
+    v += dpp_f32<0x140>(v);                // row_mirror: every lane holds its row's sum
+    v += dpp_rows_f32<0x142, 0xA>(v);      // row_bcast:15 into rows 1 and 3
+    v += dpp_rows_f32<0x143, 0xC>(v);      // row_bcast:31 into rows 2 and 3
+    return lane_f32(v, 63);
 }
 
 __device__ __forceinline__ double wave_total(double v) {

@@ -373,11 +373,14 @@ class Lbm:
         _check(self.lib.lbm_adjoint_pair_ok(self.ctx, ctypes.byref(ok)))
         return bool(ok.value)
 
-    def adjoint_pairs_faster(self, reps=4):
+    def adjoint_pairs_faster(self, reps=8, trials=3):
         """Whether two reversed sweeps per launch beat two one-sweep launches
-        here: both are timed once on scratch buffers (zero adjoint variables,
-        the current forward state) and the answer is kept.  The trial adds to
-        the K0 sums, so call it before lbm_adjoint_seed, which clears them."""
+        here: both are timed `trials` times, alternately, on scratch buffers
+        (zero adjoint variables, the current forward state), and pairs are
+        taken only when their best time per sweep is at least 2% below the
+        one-sweep kernel's best, so that near-ties resolve the same way in
+        every run.  The answer is kept.  The trial adds to the K0 sums, so
+        call it before lbm_adjoint_seed, which clears them."""
         import torch
         if getattr(self, "_adj_pairs", None) is not None:
             return self._adj_pairs
@@ -401,13 +404,15 @@ class Lbm:
                 self.adjoint_step2(f, p, f, p, b, pb, a, pa)
 
         singles(); pairs()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        ev[0].record(); singles(); ev[1].record()
-        ev[2].record(); pairs(); ev[3].record()
-        torch.cuda.synchronize()
-        per_single = ev[0].elapsed_time(ev[1]) / (2 * reps)
-        per_pair = ev[2].elapsed_time(ev[3]) / (4 * reps)
-        self._adj_pairs = per_pair < per_single
+        per_single, per_pair = float("inf"), float("inf")
+        for _ in range(trials):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record(); singles(); ev[1].record()
+            ev[2].record(); pairs(); ev[3].record()
+            torch.cuda.synchronize()
+            per_single = min(per_single, ev[0].elapsed_time(ev[1]) / (2 * reps))
+            per_pair = min(per_pair, ev[2].elapsed_time(ev[3]) / (4 * reps))
+        self._adj_pairs = per_pair < 0.98 * per_single
         return self._adj_pairs
 
     def adjoint_step2(self, f_s, p_s, f_sm1, p_sm1, psi_next, pi_next, psi_out, pi_out, stream=None):
