@@ -682,19 +682,39 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
     __shared__ TS lf[9][TR][TX];
     __shared__ TP lp[TR][TX];
     const int x0 = (int)(tx * (TX - 2)), y0 = (int)(ty * TH);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // the wave index is the same in every lane; taken into a scalar register,
+    // it makes the row arithmetic of both phases scalar
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nx = (int)g.nx, ny = (int)g.ny;
     bool bad = false;
-    // phase 1: the tile and its halo, coordinates x0 - 1 + lane and y0 - 1 + r
+    // phase 1: the tile and its halo, coordinates x0 - 1 + lane and y0 - 1 + r.
+    // A population with velocity c comes from column x - c_x of row y - c_y
+    // (periodic).  The three source columns are byte offsets fixed per lane;
+    // the source rows are wave-uniform, so every load is a scalar row base
+    // plus one of the three offsets (each passed through an empty asm so that
+    // the load keeps that form instead of a 64-bit vector address per load).
     const int xg = wrap_coord(x0 - 1 + lane, nx);
+    uint32_t cb[3] = {(uint32_t)(xg == 0 ? nx - 1 : xg - 1) * (uint32_t)sizeof(TS),   // c_x = 1
+                      (uint32_t)xg * (uint32_t)sizeof(TS),                              // c_x = 0
+                      (uint32_t)(xg == nx - 1 ? 0 : xg + 1) * (uint32_t)sizeof(TS)};   // c_x = -1
+    const uint32_t row_bytes = g.nx * (uint32_t)sizeof(TS);
 #pragma unroll
     for (int i = 0; i < TR / NW; ++i) {
         const int r = wv + i * NW;
         const int yg = wrap_coord(y0 - 1 + r, ny);
+        const int ym = yg == 0 ? ny - 1 : yg - 1, yp = yg == ny - 1 ? 0 : yg + 1;
         const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
-        const NodeGeo ng = node_geometry<9, false>(g, n);
         TC h[9];
-        gather<9, false, false, true>(g, cf, fin, ng, h);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int cy = L::cy(k);
+            const uint32_t row = (uint32_t)(cy == 1 ? ym : (cy == -1 ? yp : yg));
+            const char *rb = reinterpret_cast<const char *>(fin + (uint64_t)k * g.plane) + row * row_bytes;
+            uint32_t &c = cb[1 - L::cx(k)];
+            asm("" : "+v"(c));
+            h[k] = (TC)*reinterpret_cast<const TS *>(rb + c);
+        }
         const TC pp_off = SRC ? (TC)*at<true>(pin, n) : TC(0);
         TC out[9];
         const TC phio = collide_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, n, nullptr, nullptr, false, out);
