@@ -118,6 +118,76 @@ __device__ __forceinline__ void gather_adjoint(const Geom &g, const TC *__restri
     }
 }
 
+// Source offsets of a wave that lies within one grid row (2-D, nx a multiple
+// of 64, so the 64 consecutive nodes of a wave share their row): the rows
+// y - 1, y, y + 1 (periodic) are wave-uniform, their byte offsets scalar; the
+// columns x - 1, x, x + 1 are byte offsets per lane.  The gathers below take
+// a scalar row base plus one column offset per load, with no per-node
+// division or neighbour selects.
+struct RowWave {
+    uint32_t n;          // this lane's node
+    uint32_t rowb[3];    // byte offsets of rows y - 1, y, y + 1
+    uint32_t colb[3];    // byte offsets of columns x - 1, x, x + 1
+    bool lo, hi;         // the row next to the low / high wall
+};
+
+template <typename T, bool WALL>
+__device__ __forceinline__ RowWave row_wave(const Geom &g, uint32_t n) {
+    RowWave w;
+    w.n = n;
+    const uint32_t nw = __builtin_amdgcn_readfirstlane(n & ~63u);   // first node of the wave
+    const uint32_t y = g.fx.div(nw), x = n - y * g.nx;
+    const uint32_t nx = g.nx, ny = g.ny, rb = nx * (uint32_t)sizeof(T);
+    w.rowb[0] = (y == 0 ? ny - 1 : y - 1) * rb;
+    w.rowb[1] = y * rb;
+    w.rowb[2] = (y == ny - 1 ? 0 : y + 1) * rb;
+    w.colb[0] = (x == 0 ? nx - 1 : x - 1) * (uint32_t)sizeof(T);
+    w.colb[1] = x * (uint32_t)sizeof(T);
+    w.colb[2] = (x == nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(T);
+    w.lo = WALL && y == 0;
+    w.hi = WALL && y == ny - 1;
+    return w;
+}
+
+// Element at row offset rb and column offset c of plane base p; the column
+// offset passes through an empty asm so that each load keeps the
+// scalar-base form.
+template <typename T>
+__device__ __forceinline__ const T *row_elem(const T *p, uint32_t rb, uint32_t &c) {
+    asm("" : "+v"(c));
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + rb + c);
+}
+
+// gather (pull: row y - c_y, column x - c_x) and gather_adjoint (row y + c_y,
+// column x + c_x) for a row wave, D2Q9.
+template <bool WALL, bool NT, typename TS, typename TC>
+__device__ __forceinline__ void gather_rw(const Geom &g, const Coefs<TC> *__restrict__ cf,
+                                          const TS *__restrict__ fin, RowWave &w, TC *h) {
+    using L = Lattice<9>;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = L::cx(k), cy = L::cy(k);
+        if (WALL && ((cy == 1 && w.lo) || (cy == -1 && w.hi)))
+            h[k] = -load_s<TC, NT>(at<true>(fin + (uint64_t)L::opp(k) * g.plane, w.n)) + cf->ew[cy == 1 ? 0 : 1][k];
+        else
+            h[k] = load_s<TC, NT>(row_elem(fin + (uint64_t)k * g.plane, w.rowb[1 - cy], w.colb[1 - cx]));
+    }
+}
+
+template <bool WALL, bool NT, typename TC>
+__device__ __forceinline__ void gather_adjoint_rw(const Geom &g, const TC *__restrict__ psi_next, RowWave &w,
+                                                  TC *lam) {
+    using L = Lattice<9>;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = L::cx(k), cy = L::cy(k);
+        if (WALL && ((cy == 1 && w.hi) || (cy == -1 && w.lo)))
+            lam[k] = -load_s<TC, NT>(at<true>(psi_next + (uint64_t)L::opp(k) * g.plane, w.n));
+        else
+            lam[k] = load_s<TC, NT>(row_elem(psi_next + (uint64_t)k * g.plane, w.rowb[1 + cy], w.colb[1 + cx]));
+    }
+}
+
 // The reversed map at one node, shared by the one-sweep and two-sweep
 // kernels: from the gathered forward populations h (offset form), the history
 // pp_off = p_s(x), lam_k = psi_{s+1,k}(x + c_k) and pin = pi_{s+1}(x), writes
@@ -438,8 +508,10 @@ __device__ __forceinline__ void k0_partials(const Coefs<TC> *__restrict__ cf, co
 // Occupancy: D2Q9 is held at 4 waves per SIMD (it fits 128 registers without
 // spills); D3Q19 keeps 19 populations, their adjoints and the outputs live and
 // is allowed down to 2.
+// RW: every wave lies within one grid row (D2Q9 with nx a multiple of 64;
+// the host checks), and the loads take the row-wave form above.
 template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool O32 = false,
-          bool NT = false>
+          bool NT = false, bool RW = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Q == 9 ? 4 : 2, 8)))
 k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fs,
           const typename HistType<TS>::T *__restrict__ ps, const TC *__restrict__ psi_next,
@@ -449,16 +521,24 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
     const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
     TC gk[6] = {TC(0), TC(0), TC(0), TC(0), TC(0), TC(0)};
     if (n < g.N) {
-        const NodeGeo ng = node_geometry<Q, WALL>(g, n);
-        // ---- forward recomputation ----
-        TC h[Q];
-        gather<Q, WALL, NT, O32>(g, cf, fs, ng, h);
-        const TC pp_off = SRC ? (TC)*at<O32>(ps, n) : TC(0);
-        const TC pin = (TC)*at<O32>(pi_next, n);   // p_{s+1} = phi - phi_ref
-
-        // ---- lambda = dL/d(out) by transposed streaming ----
-        TC lam[Q];
-        gather_adjoint<Q, WALL, O32, NT>(g, psi_next, ng, lam);
+        TC h[Q], lam[Q];
+        TC pp_off, pin;
+        if constexpr (RW) {
+            static_assert(Q == 9 && O32, "row waves: D2Q9 with 32-bit offsets");
+            RowWave w = row_wave<TS, WALL>(g, n);
+            // ---- forward recomputation ----
+            gather_rw<WALL, NT>(g, cf, fs, w, h);
+            pp_off = SRC ? (TC)*at<true>(ps, n) : TC(0);
+            pin = (TC)*at<true>(pi_next, n);   // p_{s+1} = phi - phi_ref
+            // ---- lambda = dL/d(out) by transposed streaming ----
+            gather_adjoint_rw<WALL, NT>(g, psi_next, w, lam);
+        } else {
+            const NodeGeo ng = node_geometry<Q, WALL>(g, n);
+            gather<Q, WALL, NT, O32>(g, cf, fs, ng, h);
+            pp_off = SRC ? (TC)*at<O32>(ps, n) : TC(0);
+            pin = (TC)*at<O32>(pi_next, n);
+            gather_adjoint<Q, WALL, O32, NT>(g, psi_next, ng, lam);
+        }
 
         TC out[Q];
         const TC pb = adjoint_node<Q, TC, EQR, SRC, KVAR, NP>(cf, h, pp_off, lam, pin, out, gk);

@@ -224,6 +224,26 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
         hipLaunchKernelGGL((k_adjoint<Q, TS, TC, true, S, K, W, 3, true, NT>), grid, block, 0, st, g, cf, fs, ps, \
                            pn, pi_next, po, pi_out, gk_part);                                           \
         break;
+            if constexpr (Q == 9) {
+                if (sizeof(TS) == 8 && !dm.nt && g.nx % 64 == 0) {
+                    // every wave within one row: the row-wave loads (k_adjoint
+                    // RW).  FP64 only: in FP32 they measured slower on the
+                    // 512^2 grid (6.35 against 6.27 us per sweep), in FP64
+                    // faster (10.3 against 10.4-10.8)
+#define LBM_ADJ3R(S, K, W)                                                                              \
+    case (S * 4 + K * 2 + W):                                                                           \
+        hipLaunchKernelGGL((k_adjoint<Q, TS, TC, true, S, K, W, 3, true, false, true>), grid, block, 0, st, g, cf, \
+                           fs, ps, pn, pi_next, po, pi_out, gk_part);                                   \
+        break;
+                    switch (c3) {
+                        LBM_ADJ3R(0, 0, 0) LBM_ADJ3R(0, 0, 1) LBM_ADJ3R(0, 1, 0) LBM_ADJ3R(0, 1, 1)
+                        LBM_ADJ3R(1, 0, 0) LBM_ADJ3R(1, 0, 1) LBM_ADJ3R(1, 1, 0) LBM_ADJ3R(1, 1, 1)
+                        default: return hipErrorInvalidValue;
+                    }
+#undef LBM_ADJ3R
+                    return hipGetLastError();
+                }
+            }
             switch (c3) {
                 LBM_ADJ3(0, 0, 0, 0) LBM_ADJ3(0, 0, 1, 0) LBM_ADJ3(0, 1, 0, 0) LBM_ADJ3(0, 1, 1, 0)
                 LBM_ADJ3(1, 0, 0, 0) LBM_ADJ3(1, 0, 1, 0) LBM_ADJ3(1, 1, 0, 0) LBM_ADJ3(1, 1, 1, 0)

@@ -46,10 +46,12 @@ def k0_matrix(spec, kent):
     return km
 
 
-def gpu_gradient(spec, phi0, target, T, seg=None, flags=0):
+def gpu_gradient(spec, phi0, target, T, seg=None, flags=0, singles=False):
     from paper_1603_09577_amd import lbm
     from paper_1603_09577_amd.rollout import rollout
     sim = lbm.Lbm(spec, flags=flags)
+    if singles:
+        sim._adj_pairs = False   # one reversed sweep per launch, whatever the timing trial would pick
     p0 = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
     k0 = torch.tensor(k0_entries(spec), dtype=torch.float64, requires_grad=True)
     tgt = torch.tensor(target, dtype=torch.float64, device="cuda")
@@ -87,6 +89,26 @@ def test_adjoint_matches_oracle_nonlinear(flags):
     assert abs(lg - lo) <= 1e-12 * abs(lo)
     assert rel(gg, go) <= 1e-10
     assert rel(kg, ko) <= 1e-10
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_adjoint_row_waves_match_oracle(walls):
+    """Widths that are multiples of 64 put every wave within one grid row, and
+    the one-sweep FP64 adjoint then takes its row-wave loads (scalar row
+    offsets, per-lane columns); periodic and with walls."""
+    spec = W.spec_nonlinear_2d(64, 7)
+    if walls:
+        spec["bc"] = ["periodic", "abb", "periodic"]
+        spec["phi_wall"] = [[0, 0], [0.35, 0.7], [0, 0]]
+    rng = np.random.default_rng(25)
+    phi0 = W.noise_field((7, 64), 26)
+    target = 0.5 + 0.1 * rng.uniform(-1, 1, (7, 64))
+    T = 13
+    say(f"[gpu adjoint] row waves 64x7 walls={walls} T={T}")
+    lg, gg, kg = gpu_gradient(spec, phi0, target, T, seg=4, singles=True)
+    lo, go, ko = oracle_gradient(spec, phi0, target, T)
+    say(f"    dphi0 {rel(gg, go):.2e}  dK0 {rel(kg, ko):.2e}")
+    assert rel(gg, go) <= 1e-10 and rel(kg, ko) <= 1e-10
 
 
 def test_adjoint_matches_oracle_walls_general_rates():
