@@ -501,7 +501,13 @@ __device__ __forceinline__ void k0_partials(const Coefs<TC> *__restrict__ cf, co
         double v = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) v += sh[j][w];
-        gk_part[(size_t)slot * 6 + i] += v;
+        // An atomic add without return instead of a load, an add and a
+        // store: the workgroup's last wave no longer waits for a global load
+        // before it can finish.  The slot belongs to this workgroup and the
+        // sweeps that add to it are successive launches, so no two adds to
+        // it are ever in flight together: the sum is formed in the same
+        // order, one FP64 addition per sweep, as before.
+        unsafeAtomicAdd(gk_part + (size_t)slot * 6 + i, v);
     }
 }
 
