@@ -329,6 +329,8 @@ PROFILED = {
                           adjoint_bytes_per_node(9, "f64", True) * 512 * 512),
     "adjoint2d-512 f32": ("k_adjoint<9, float, float, true, true, true, false, 3, ",
                           adjoint_bytes_per_node(9, "f32", True) * 512 * 512),
+    "adjoint2d-512 f32 pairs": ("k_adjoint2<float, float, true, true, 3, ",
+                                adjoint_pair_bytes_per_node(9, "f32", True) * 512 * 512),
 }
 
 
@@ -505,7 +507,7 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
             tr = w.get("trace_median_us")
             nodes = {"nonlinear2d-1024": 1024 * 1024, "adjoint2d-512": 512 * 512,
                      "d3q19-256": 256 ** 3, "batch-512": BATCH_NODES}[label.split(" ")[0]]
-            upd = nodes * (2 if "two-step" in label else 1)
+            upd = nodes * (2 if ("two-step" in label or "pairs" in label) else 1)
             frac = m["SQ_INSTS_VALU"] / (tr * 1e-6 * VALU_ISSUE_PEAK) if tr else None
             w.update({"sq_insts_valu": m["SQ_INSTS_VALU"], "valu_issue_fraction": frac})
             vl.append(f"| {label} | `{k.replace('lbm::', '')}` | {m.get('SQ_WAVES', 0):.0f} | "

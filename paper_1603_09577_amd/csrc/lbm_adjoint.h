@@ -588,7 +588,9 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
     const uint32_t tile = block_index(blockIdx.x, gridDim.x, g.remap);
     const uint32_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
     const int x0 = (int)(tx * (TX - 2)), y0 = (int)(ty * TH);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // wave index in a scalar register: the rows of both phases are wave-uniform
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int nx = (int)g.nx, ny = (int)g.ny;
     TC gk[6] = {TC(0), TC(0), TC(0), TC(0), TC(0), TC(0)};
     // a lane owns column x0 + lane - 1 when it is an interior lane inside the grid
@@ -596,6 +598,16 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
     // phase 1: the tile and its halo (coordinates wrapped periodically; narrow
     // or low grids repeat nodes in the halo, which only the owner counts)
     const int xg = wrap_coord(x0 - 1 + lane, nx);
+    // byte offsets of the columns x - 1, x, x + 1 (periodic), fixed per lane;
+    // rows are wave-uniform, so every load is a scalar row base plus one of
+    // them (the same for an owner's node in phase 2, where x = xg)
+    static_assert(sizeof(TS) == sizeof(TC), "adjoint state and psi share the element size");
+    RowWave w;
+    w.colb[0] = (uint32_t)(xg == 0 ? nx - 1 : xg - 1) * (uint32_t)sizeof(TS);
+    w.colb[1] = (uint32_t)xg * (uint32_t)sizeof(TS);
+    w.colb[2] = (uint32_t)(xg == nx - 1 ? 0 : xg + 1) * (uint32_t)sizeof(TS);
+    w.lo = w.hi = false;
+    const uint32_t rowb = g.nx * (uint32_t)sizeof(TS);
     // FP32 unrolls the rows (all loads in flight); FP64 takes them one by one
     // (about 165 registers per lane as it is: 3 waves per SIMD)
     constexpr int kUnroll = sizeof(TC) == 4 ? TR / (kBlock / 64) : 1;
@@ -604,10 +616,13 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
         const int r = wv + i * (kBlock / 64);
         const int yg = wrap_coord(y0 - 1 + r, ny);
         const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
-        const NodeGeo ng = node_geometry<9, false>(g, n);
+        w.n = n;
+        w.rowb[0] = (uint32_t)(yg == 0 ? ny - 1 : yg - 1) * rowb;
+        w.rowb[1] = (uint32_t)yg * rowb;
+        w.rowb[2] = (uint32_t)(yg == ny - 1 ? 0 : yg + 1) * rowb;
         TC h[9], lam[9], out[9];
-        gather<9, false, false, true>(g, cf, f1, ng, h);
-        gather_adjoint<9, false, true>(g, psi_next, ng, lam);
+        gather_rw<false, false>(g, cf, f1, w, h);
+        gather_adjoint_rw<false, false>(g, psi_next, w, lam);
         const TC pp_off = SRC ? (TC)*at<true>(p1, n) : TC(0);
         const TC pin = (TC)*at<true>(pi_next, n);
         TC gkn[6] = {TC(0), TC(0), TC(0), TC(0), TC(0), TC(0)};
@@ -625,16 +640,19 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
     if (xown) {
         const uint32_t x = (uint32_t)(x0 + lane - 1);
         for (int r = 1 + wv; r <= TH && y0 + r - 1 < ny; r += kBlock / 64) {
-            const uint32_t n = (uint32_t)(y0 + r - 1) * g.nx + x;
-            const NodeGeo ng = node_geometry<9, false>(g, n);
+            const int y = y0 + r - 1;
+            const uint32_t n = (uint32_t)y * g.nx + x;
+            w.n = n;
+            w.rowb[0] = (uint32_t)(y == 0 ? ny - 1 : y - 1) * rowb;
+            w.rowb[1] = (uint32_t)y * rowb;
+            w.rowb[2] = (uint32_t)(y == ny - 1 ? 0 : y + 1) * rowb;
             TC h[9], lam[9], out[9];
-            gather<9, false, false, true>(g, cf, f0, ng, h);
+            gather_rw<false, false>(g, cf, f0, w, h);
 #pragma unroll
             for (int k = 0; k < 9; ++k) lam[k] = lpsi[k][r + L::cy(k)][lane + L::cx(k)];
             const TC pp_off = SRC ? (TC)*at<true>(p0, n) : TC(0);
             const TC pb = adjoint_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, lam, lpi[r][lane], out, gk);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) *at<true>(psi_out + (uint64_t)k * g.plane, n) = out[k];
+            store_planes<9, false>(psi_out, g.plane, n, out);
             *at<true>(pi_out, n) = (double)pb;
         }
     }
