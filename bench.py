@@ -329,6 +329,8 @@ PROFILED = {
                           adjoint_bytes_per_node(9, "f64", True) * 512 * 512),
     "adjoint2d-512 f32": ("k_adjoint<9, float, float, true, true, true, false, 3, ",
                           adjoint_bytes_per_node(9, "f32", True) * 512 * 512),
+    "adjoint2d-512 f64 pairs": ("k_adjoint2<double, double, true, true, 3, ",
+                                adjoint_pair_bytes_per_node(9, "f64", True) * 512 * 512),
     "adjoint2d-512 f32 pairs": ("k_adjoint2<float, float, true, true, 3, ",
                                 adjoint_pair_bytes_per_node(9, "f32", True) * 512 * 512),
 }

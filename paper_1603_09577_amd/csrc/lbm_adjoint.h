@@ -572,8 +572,12 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
 // count only the tile's own nodes (the halo belongs to the neighbours).
 // pi_out must differ from pi_next: neighbouring tiles still read pi_{s+1} at
 // their halo.
+// FP64 with short polynomials is held to 3 waves per SIMD (168 registers),
+// what the workgroup memory of its 6-row tiles allows anyway (3 workgroups of
+// 4 waves per CU); with 9-term polynomials that limit would spill.
 template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH>
 __global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(TC) == 8 && NP <= 4 ? 3 : 1, 8)))
 k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f1,
            const typename HistType<TS>::T *__restrict__ p1, const TS *__restrict__ f0,
            const typename HistType<TS>::T *__restrict__ p0, const TC *__restrict__ psi_next,
