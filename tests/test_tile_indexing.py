@@ -1,0 +1,125 @@
+"""CPU check of the source indices that the scalar-row and row-wave gathers
+form (D2Q9), against the general node geometry of the one-node-per-thread
+kernels, before any of them runs on a GPU.
+
+The general form (node_geometry + gather): node n = y nx + x, neighbour
+offsets om/op per axis with periodic wrap, source index n + sum of the
+offsets for the components of c_k (pull: x - c_k; transposed: x + c_k).
+The scalar-row forms: source row y -/+ c_y chosen from three wave-uniform
+rows, source column x -/+ c_x from three per-lane columns.  Every index
+must be equal and inside the grid, for every tile shape, tile, lane and row,
+on grids from 1 x 1 up (narrower and lower than a tile included).
+"""
+import pytest
+
+CX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+CY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+TILE_W = 62   # interior columns of a 64-lane tile
+
+
+def wrap(v, n):
+    if v < 0:
+        v += n
+    while v >= n:
+        v -= n
+    return v
+
+
+def general_index(n, nx, ny, k, sign):
+    """Source index of population k at node n by the node geometry: sign = -1
+    for the pull gather (x - c_k), +1 for the transposed gather (x + c_k)."""
+    y = n // nx
+    x = n - y * nx
+    om = [nx - 1 if x == 0 else -1, (ny - 1) * nx if y == 0 else -nx]
+    op = [-(nx - 1) if x == nx - 1 else 1, -(ny - 1) * nx if y == ny - 1 else nx]
+    off = 0
+    for a, c in enumerate((CX[k], CY[k])):
+        c = -c if sign > 0 else c   # x + c is the pull form of -c
+        off += om[a] if c == 1 else (op[a] if c == -1 else 0)
+    return n + off
+
+
+def three(v, n):
+    """Periodic v - 1, v, v + 1, indexed by d + 1 for the coordinate v + d."""
+    return [n - 1 if v == 0 else v - 1, v, 0 if v == n - 1 else v + 1]
+
+
+def row_form_index(x, y, nx, ny, k, sign):
+    cols, rows = three(x, nx), three(y, ny)
+    return rows[1 + sign * CY[k]] * nx + cols[1 + sign * CX[k]]
+
+
+SIZES = [(a, b) for a in (1, 2, 3, 61, 62, 63, 64, 65) for b in (1, 2, 3, 7, 14, 15, 17)] + [(130, 33)]
+
+
+@pytest.mark.parametrize("th,nw", [(14, 8), (14, 4), (10, 6), (6, 4), (6, 8), (14, 16)])
+def test_two_step_phase1_rows(th, nw):
+    """Phase 1 of a two-step tile (64 lanes x th + 2 rows from (x0 - 1, y0 - 1),
+    coordinates wrapped), pull gather."""
+    tr = th + 2
+    for nx, ny in SIZES:
+        for ty in range((ny + th - 1) // th):
+            for tx in range((nx + TILE_W - 1) // TILE_W):
+                x0, y0 = tx * TILE_W, ty * th
+                for lane in range(64):
+                    xg = wrap(x0 - 1 + lane, nx)
+                    for wv in range(nw):
+                        for i in range(tr // nw):
+                            yg = wrap(y0 - 1 + wv + i * nw, ny)
+                            n = yg * nx + xg
+                            for k in range(9):
+                                got = row_form_index(xg, yg, nx, ny, k, -1)
+                                assert got == general_index(n, nx, ny, k, -1)
+                                assert 0 <= got < nx * ny
+
+
+@pytest.mark.parametrize("th", [6, 14])
+def test_two_sweep_adjoint_rows(th):
+    """Both phases of the two-sweep adjoint tile (4 waves): phase 1 gathers the
+    forward state (pull) and psi (transposed) on the tile and halo; phase 2
+    gathers the forward state at the tile's own nodes."""
+    tr, nw = th + 2, 4
+    for nx, ny in SIZES:
+        for ty in range((ny + th - 1) // th):
+            for tx in range((nx + TILE_W - 1) // TILE_W):
+                x0, y0 = tx * TILE_W, ty * th
+                for lane in range(64):
+                    xg = wrap(x0 - 1 + lane, nx)
+                    own = 1 <= lane <= TILE_W and x0 + lane - 1 < nx
+                    for wv in range(nw):
+                        for i in range(tr // nw):
+                            yg = wrap(y0 - 1 + wv + i * nw, ny)
+                            n = yg * nx + xg
+                            for k in range(9):
+                                for sign in (-1, 1):
+                                    got = row_form_index(xg, yg, nx, ny, k, sign)
+                                    assert got == general_index(n, nx, ny, k, sign)
+                                    assert 0 <= got < nx * ny
+                        if own:
+                            assert x0 + lane - 1 == xg
+                            r = 1 + wv
+                            while r <= th and y0 + r - 1 < ny:
+                                y = y0 + r - 1
+                                n = y * nx + xg
+                                for k in range(9):
+                                    got = row_form_index(xg, y, nx, ny, k, -1)
+                                    assert got == general_index(n, nx, ny, k, -1)
+                                    assert 0 <= got < nx * ny
+                                r += nw
+
+
+@pytest.mark.parametrize("nx", [64, 128, 192])
+def test_adjoint_row_waves(nx):
+    """One-sweep adjoint on widths that are multiples of 64: the 64 nodes of a
+    wave share their row (taken from the wave's first node), both gathers."""
+    for ny in (1, 2, 3, 5, 9):
+        for n in range(nx * ny):
+            nw = n & ~63
+            y = nw // nx
+            x = n - y * nx
+            assert y == n // nx   # the wave's first node is in the lane's row
+            for k in range(9):
+                for sign in (-1, 1):
+                    got = row_form_index(x, y, nx, ny, k, sign)
+                    assert got == general_index(n, nx, ny, k, sign)
+                    assert 0 <= got < nx * ny
