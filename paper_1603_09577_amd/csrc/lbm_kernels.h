@@ -734,29 +734,29 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
         }
     } else {
 #pragma unroll
-    for (int i = 0; i < TR / NW; ++i) {
-        const int r = wv + i * NW;
-        const int yg = wrap_coord(y0 - 1 + r, ny);
-        const int ym = yg == 0 ? ny - 1 : yg - 1, yp = yg == ny - 1 ? 0 : yg + 1;
-        const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
-        TC h[9];
+        for (int i = 0; i < TR / NW; ++i) {
+            const int r = wv + i * NW;
+            const int yg = wrap_coord(y0 - 1 + r, ny);
+            const int ym = yg == 0 ? ny - 1 : yg - 1, yp = yg == ny - 1 ? 0 : yg + 1;
+            const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
+            TC h[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const int cy = L::cy(k);
-            const uint32_t row = (uint32_t)(cy == 1 ? ym : (cy == -1 ? yp : yg));
-            const char *rb = reinterpret_cast<const char *>(fin + (uint64_t)k * g.plane) + row * row_bytes;
-            uint32_t &c = cb[1 - L::cx(k)];
-            asm("" : "+v"(c));
-            h[k] = (TC)*reinterpret_cast<const TS *>(rb + c);
+            for (int k = 0; k < 9; ++k) {
+                const int cy = L::cy(k);
+                const uint32_t row = (uint32_t)(cy == 1 ? ym : (cy == -1 ? yp : yg));
+                const char *rb = reinterpret_cast<const char *>(fin + (uint64_t)k * g.plane) + row * row_bytes;
+                uint32_t &c = cb[1 - L::cx(k)];
+                asm("" : "+v"(c));
+                h[k] = (TC)*reinterpret_cast<const TS *>(rb + c);
+            }
+            const TC pp_off = SRC ? (TC)*at<true>(pin, n) : TC(0);
+            TC out[9];
+            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, n, nullptr, nullptr, false, out);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
+            lp[r][lane] = (TP)phio;
+            bad |= !__builtin_isfinite(phio);
         }
-        const TC pp_off = SRC ? (TC)*at<true>(pin, n) : TC(0);
-        TC out[9];
-        const TC phio = collide_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, n, nullptr, nullptr, false, out);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
-        lp[r][lane] = (TP)phio;
-        bad |= !__builtin_isfinite(phio);
-    }
     }
     __syncthreads();
     // phase 2: interior lanes 1..62, rows 1..TH
