@@ -118,62 +118,7 @@ __device__ __forceinline__ void gather_adjoint(const Geom &g, const TC *__restri
     }
 }
 
-// Source offsets of a wave that lies within one grid row (2-D, nx a multiple
-// of 64, so the 64 consecutive nodes of a wave share their row): the rows
-// y - 1, y, y + 1 (periodic) are wave-uniform, their byte offsets scalar; the
-// columns x - 1, x, x + 1 are byte offsets per lane.  The gathers below take
-// a scalar row base plus one column offset per load, with no per-node
-// division or neighbour selects.
-struct RowWave {
-    uint32_t n;          // this lane's node
-    uint32_t rowb[3];    // byte offsets of rows y - 1, y, y + 1
-    uint32_t colb[3];    // byte offsets of columns x - 1, x, x + 1
-    bool lo, hi;         // the row next to the low / high wall
-};
-
-template <typename T, bool WALL>
-__device__ __forceinline__ RowWave row_wave(const Geom &g, uint32_t n) {
-    RowWave w;
-    w.n = n;
-    const uint32_t nw = __builtin_amdgcn_readfirstlane(n & ~63u);   // first node of the wave
-    const uint32_t y = g.fx.div(nw), x = n - y * g.nx;
-    const uint32_t nx = g.nx, ny = g.ny, rb = nx * (uint32_t)sizeof(T);
-    w.rowb[0] = (y == 0 ? ny - 1 : y - 1) * rb;
-    w.rowb[1] = y * rb;
-    w.rowb[2] = (y == ny - 1 ? 0 : y + 1) * rb;
-    w.colb[0] = (x == 0 ? nx - 1 : x - 1) * (uint32_t)sizeof(T);
-    w.colb[1] = x * (uint32_t)sizeof(T);
-    w.colb[2] = (x == nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(T);
-    w.lo = WALL && y == 0;
-    w.hi = WALL && y == ny - 1;
-    return w;
-}
-
-// Element at row offset rb and column offset c of plane base p; the column
-// offset passes through an empty asm so that each load keeps the
-// scalar-base form.
-template <typename T>
-__device__ __forceinline__ const T *row_elem(const T *p, uint32_t rb, uint32_t &c) {
-    asm("" : "+v"(c));
-    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + rb + c);
-}
-
-// gather (pull: row y - c_y, column x - c_x) and gather_adjoint (row y + c_y,
-// column x + c_x) for a row wave, D2Q9.
-template <bool WALL, bool NT, typename TS, typename TC>
-__device__ __forceinline__ void gather_rw(const Geom &g, const Coefs<TC> *__restrict__ cf,
-                                          const TS *__restrict__ fin, RowWave &w, TC *h) {
-    using L = Lattice<9>;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int cx = L::cx(k), cy = L::cy(k);
-        if (WALL && ((cy == 1 && w.lo) || (cy == -1 && w.hi)))
-            h[k] = -load_s<TC, NT>(at<true>(fin + (uint64_t)L::opp(k) * g.plane, w.n)) + cf->ew[cy == 1 ? 0 : 1][k];
-        else
-            h[k] = load_s<TC, NT>(row_elem(fin + (uint64_t)k * g.plane, w.rowb[1 - cy], w.colb[1 - cx]));
-    }
-}
-
+// gather_adjoint (row y + c_y, column x + c_x) for a row wave (RowWave), D2Q9.
 template <bool WALL, bool NT, typename TC>
 __device__ __forceinline__ void gather_adjoint_rw(const Geom &g, const TC *__restrict__ psi_next, RowWave &w,
                                                   TC *lam) {

@@ -21,6 +21,25 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
     {
         if (dm.eqr && dm.deg3 && dm.o32) {
             const int c3 = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) | (dm.nt ? 8 : 0);
+            if constexpr (Q == 9) {
+                if (dm.wall && g.nx % 64 == 0) {
+                    // every wave within one row: the row-wave gathers (k_sweep
+                    // RW).  With walls only: there they measured 2.9% faster on
+                    // 1024^2 FP32; on periodic grids 1.8% slower
+#define LBM_SWEEP3R(S, K, NT)                                                                         \
+    case (NT * 8 + S * 4 + K * 2 + 1):                                                                \
+        hipLaunchKernelGGL((k_sweep<Q, TS, TC, true, S, K, true, 3, NT, true, true>), grid, block, 0, st, g, cf, fi, fo, \
+                           pp, flag);                                                                 \
+        break;
+                    switch (c3) {
+                        LBM_SWEEP3R(0, 0, 0) LBM_SWEEP3R(0, 1, 0) LBM_SWEEP3R(1, 0, 0) LBM_SWEEP3R(1, 1, 0)
+                        LBM_SWEEP3R(0, 0, 1) LBM_SWEEP3R(0, 1, 1) LBM_SWEEP3R(1, 0, 1) LBM_SWEEP3R(1, 1, 1)
+                        default: return hipErrorInvalidValue;
+                    }
+#undef LBM_SWEEP3R
+                    return hipGetLastError();
+                }
+            }
 #define LBM_SWEEP3(S, K, W, NT)                                                                       \
     case (NT * 8 + S * 4 + K * 2 + W):                                                                \
         hipLaunchKernelGGL((k_sweep<Q, TS, TC, true, S, K, W, 3, NT, true>), grid, block, 0, st, g, cf, fi, fo, pp, flag); \

@@ -108,6 +108,29 @@ def test_channel_walls_fp64():
     compare(spec, phi0, (1, 20, 200), 1e-12, name="channel-general-rates")
 
 
+@pytest.mark.parametrize("walls,prec,tol", [(False, "f64", 1e-12), (True, "f64", 1e-12), (True, "f32", 1e-5)])
+def test_row_wave_sweeps(walls, prec, tol):
+    """Widths that are multiples of 64 put every wave within one grid row; with
+    walls the one-sweep kernel then takes its row-wave gathers (scalar row
+    offsets, per-lane columns).  The periodic case (two steps per pass off)
+    runs the general gathers on the same grid."""
+    lbm = _lbm()
+    spec = W.spec_nonlinear_2d(128, 11, source=True, precision=prec)
+    if walls:
+        spec["bc"] = ["periodic", "abb", "periodic"]
+        spec["phi_wall"] = [[0, 0], [0.3, 0.8], [0, 0]]
+    phi0 = W.noise_field((11, 128), 15)
+    say(f"[gpu parity] row waves 128x11 walls={walls} {prec}")
+    sim = lbm.Lbm(spec).init(phi0)
+    if not walls:
+        sim.set_two_step(False)
+    sim.step(40)
+    ref = oracle_run(dict(spec, precision="f64"), phi0, (40,))[40]
+    err = rel_l2(sim.phi().cpu().numpy(), ref)
+    say(f"    rel L2 {err:.2e}")
+    assert err <= tol
+
+
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 2e-2)])
 def test_nonlinear_reduced_storage(prec, tol):
     """FP32 / FP16 offset storage against the FP64 oracle."""
