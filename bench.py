@@ -149,6 +149,26 @@ def adjoint_pair_bytes_per_node(q, prec, src):
     return adjoint_bytes_per_node(q, prec, src) + q * s + (h if src else 0)
 
 
+def time_diagnostics(torch, sim, head_ms_per_step, every=100, reps=50):
+    """Cost of the FP64 diagnostics on a forward state: phi in FP64
+    (lbm_get_phi) and the FP64 sums, min/max and non-finite count
+    (lbm_reduce, which returns its results to the host), per call, and as a
+    fraction of the sweeps when taken every `every` steps."""
+    import time
+    phi = sim.phi()
+    for _ in range(5):
+        sim.reduce(sim.phi(out=phi))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.reduce(sim.phi(out=phi))
+    per = (time.perf_counter() - t0) / reps
+    return {"ms_per_call": per * 1e3, "every_steps": every,
+            "fraction_of_sweep_time": per * 1e3 / (every * head_ms_per_step),
+            "what": "phi to FP64 plus FP64 sum, sum of squares, min, max and non-finite count, "
+                    "synchronous (results on the host)"}
+
+
 def run_adjoint(torch, lbm, spec, phi0, steps, warmup, label, pairs=True):
     """Time the reversed sweep on a fixed forward state: `steps` sweeps
     captured in a HIP graph (through torch's graph capture, which records the
@@ -575,6 +595,7 @@ def main():
     err16 = float(torch.linalg.norm(phi16 - phi64) / torch.linalg.norm(phi64))
     del sim16, phi16
     print(f"# nonlinear2d-1024 f16: {f16['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    diag = time_diagnostics(torch, sim32, head["ms_per_step"])
 
     extra = {}
     only = set(w for w in args.only.split(",") if w) or {"adjoint", "d3q19", "batch", "hbm"}
@@ -694,6 +715,7 @@ def main():
                  "hbm_frac": f16["hbm_frac"], "rel_l2_vs_fp64_after_run": err16,
                  "storage": "f16 offsets, re-centred every 256 steps"},
         "nonfinite": head["nonfinite"] + f64["nonfinite"] + f16["nonfinite"],
+        "diagnostics_fp64": diag,
         **extra,
     }
     print(json.dumps(line))
