@@ -163,10 +163,21 @@ def time_diagnostics(torch, sim, head_ms_per_step, every=100, reps=50):
     for _ in range(reps):
         sim.reduce(sim.phi(out=phi))
     per = (time.perf_counter() - t0) / reps
+    # the same work without waiting (lbm_reduce_async: results stay on the device)
+    out = torch.empty(8, dtype=torch.float64, device=phi.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sim.reduce_async(sim.phi(out=phi), out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    per_async = e0.elapsed_time(e1) / 1e3 / reps
     return {"ms_per_call": per * 1e3, "every_steps": every,
             "fraction_of_sweep_time": per * 1e3 / (every * head_ms_per_step),
-            "what": "phi to FP64 plus FP64 sum, sum of squares, min, max and non-finite count, "
-                    "synchronous (results on the host)"}
+            "ms_per_call_async": per_async * 1e3,
+            "fraction_of_sweep_time_async": per_async * 1e3 / (every * head_ms_per_step),
+            "what": "phi to FP64 plus FP64 sum, sum of squares, min, max and non-finite count; "
+                    "synchronous (lbm_reduce, results on the host) and without waiting (lbm_reduce_async)"}
 
 
 def run_adjoint(torch, lbm, spec, phi0, steps, warmup, label, pairs=True):

@@ -286,6 +286,14 @@ int lbm_set_k0(lbm_ctx *ctx, const double k0[9]);
 int lbm_reduce(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev, double out[8],
                void *stream);
 
+/* The same reductions without waiting: the 8 values of lbm_reduce are
+ * written, in the same order and bit for bit the same, to out_dev (8 doubles
+ * of caller device memory) on the stream; nothing returns to the host.  Calls
+ * on one context share its partial-sum scratch, so two reductions of the
+ * same context (this call or lbm_reduce) must not run on different streams
+ * at the same time.  Errors: LBM_E_INVALID (null argument), LBM_E_HIP. */
+int lbm_reduce_async(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev, double *out_dev, void *stream);
+
 /* ---- discrete adjoint (D2Q9 and D3Q19, F64 and F32) ---------------------- *
  * Sweep s maps the state X_s = (f_s, p_s) to X_{s+1}: it gathers g_s from f_s,
  * collides with history p_s and stores f_{s+1}; p_{s+1} = sum_k g_s,k.

@@ -777,6 +777,15 @@ int lbm_reduce(lbm_ctx *c, const double *phi, const double *ref, double out[8], 
     return LBM_OK;
 }
 
+int lbm_reduce_async(lbm_ctx *c, const double *phi, const double *ref, double *out_dev, void *stream) {
+    if (!c || !phi || !out_dev) return fail(LBM_E_INVALID, "null argument");
+    int parts = (int)std::min<uint32_t>(kRedParts, (c->g.N + kBlock - 1) / kBlock);
+    if (parts < 1) parts = 1;
+    const hipError_t e = launch_reduce(phi, ref, c->g.N, c->d_red_part, parts, out_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "reduction");
+    return LBM_OK;
+}
+
 int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void *stream) {
     if (!c || !gphi || !psi || !pi) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");

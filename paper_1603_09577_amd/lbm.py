@@ -34,6 +34,7 @@ EXPORTS = [
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
     "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields", "lbm_set_phi_wall",
     "lbm_set_two_step", "lbm_two_step_shape", "lbm_adjoint_step2", "lbm_adjoint_pair_ok", "lbm_set_remap",
+    "lbm_reduce_async",
 ]
 
 
@@ -131,6 +132,7 @@ def load():
                                ctypes.c_int),
         "lbm_adjoint_step2": ([_VP] * 10, ctypes.c_int),
         "lbm_adjoint_pair_ok": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "lbm_reduce_async": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -348,6 +350,15 @@ class Lbm:
         _check(self.lib.lbm_reduce(self.ctx, _ptr(phi), _ptr(ref), out, _stream(stream)))
         keys = ("sum", "sumsq", "sum_d2", "sum_ref2", "min", "max", "nonfinite", "sum_absd")
         return dict(zip(keys, list(out)))
+
+    def reduce_async(self, phi, ref=None, out=None, stream=None):
+        """The reductions of reduce() into a device tensor of 8 FP64 values
+        (same order), enqueued on the stream without waiting."""
+        import torch
+        if out is None:
+            out = torch.empty(8, dtype=torch.float64, device=self.device)
+        _check(self.lib.lbm_reduce_async(self.ctx, _ptr(phi), _ptr(ref), _ptr(out), _stream(stream)))
+        return out
 
     # -- adjoint -------------------------------------------------------------
     def adjoint_buffers(self):

@@ -207,6 +207,35 @@ def test_conservation_reduction_fp64():
     assert abs(s0 - phi0.sum()) <= 1e-13 * abs(s0)
 
 
+def test_reduce_async_equals_reduce():
+    """lbm_reduce_async writes the 8 values of lbm_reduce, bit for bit, to
+    device memory; several in flight on the stream before one read, with and
+    without a reference field; values checked against numpy in FP64."""
+    lbm = _lbm()
+    spec = W.spec_nonlinear_2d(200, 130)
+    phi0 = W.noise_field((130, 200), 18)
+    say("[gpu] reduce_async 200x130")
+    sim = lbm.Lbm(spec).init(phi0)
+    sim.step(7)
+    phi = sim.phi()
+    ref = torch.tensor(W.noise_field((130, 200), 19), dtype=torch.float64, device="cuda")
+    outs = [sim.reduce_async(phi), sim.reduce_async(phi, ref)]
+    sim.step(3)
+    phi2 = sim.phi()
+    outs.append(sim.reduce_async(phi2, ref))
+    torch.cuda.synchronize()
+    keys = ("sum", "sumsq", "sum_d2", "sum_ref2", "min", "max", "nonfinite", "sum_absd")
+    for o, (p, r) in zip(outs, ((phi, None), (phi, ref), (phi2, ref))):
+        want = sim.reduce(p, r)
+        got = o.cpu().numpy()
+        assert [got[i] for i in range(8)] == [want[k] for k in keys]
+    p, r = phi2.cpu().numpy(), ref.cpu().numpy()
+    got = outs[2].cpu().numpy()
+    assert abs(got[0] - p.sum()) <= 1e-13 * abs(p.sum())
+    assert abs(got[2] - ((p - r) ** 2).sum()) <= 1e-12 * ((p - r) ** 2).sum()
+    assert got[4] == p.min() and got[5] == p.max() and got[6] == 0
+
+
 def test_every_node_written():
     """Poison the destination with NaN: one sweep must overwrite every value."""
     lbm = _lbm()
