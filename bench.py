@@ -172,12 +172,22 @@ def time_diagnostics(torch, sim, head_ms_per_step, every=100, reps=50):
     e1.record()
     torch.cuda.synchronize()
     per_async = e0.elapsed_time(e1) / 1e3 / reps
+    # phi formed inside the reduction (lbm_reduce_state: one pass over the state)
+    e0.record()
+    for _ in range(reps):
+        sim.reduce_state(out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    per_state = e0.elapsed_time(e1) / 1e3 / reps
     return {"ms_per_call": per * 1e3, "every_steps": every,
+            "ms_per_call_state": per_state * 1e3,
+            "fraction_of_sweep_time_state": per_state * 1e3 / (every * head_ms_per_step),
             "fraction_of_sweep_time": per * 1e3 / (every * head_ms_per_step),
             "ms_per_call_async": per_async * 1e3,
             "fraction_of_sweep_time_async": per_async * 1e3 / (every * head_ms_per_step),
             "what": "phi to FP64 plus FP64 sum, sum of squares, min, max and non-finite count; "
-                    "synchronous (lbm_reduce, results on the host) and without waiting (lbm_reduce_async)"}
+                    "synchronous (lbm_reduce, results on the host), without waiting (lbm_reduce_async), "
+                    "and in one pass over the state without a phi field (lbm_reduce_state)"}
 
 
 def run_adjoint(torch, lbm, spec, phi0, steps, warmup, label, pairs=True):

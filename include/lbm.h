@@ -294,6 +294,15 @@ int lbm_reduce(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev, doubl
  * at the same time.  Errors: LBM_E_INVALID (null argument), LBM_E_HIP. */
 int lbm_reduce_async(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev, double *out_dev, void *stream);
 
+/* The reductions of lbm_reduce over the phi of the current state (the one
+ * lbm_get_phi would write), formed on the fly from the stored populations in
+ * one pass: no phi field is written or read.  The 8 values, bit for bit those
+ * of lbm_reduce over lbm_get_phi's field, go to out_dev (8 doubles of caller
+ * device memory) on the stream, without waiting.  Shares the context's
+ * partial-sum scratch like lbm_reduce_async.  Errors: LBM_E_INVALID (null
+ * argument), LBM_E_STATE (before lbm_init), LBM_E_HIP. */
+int lbm_reduce_state(lbm_ctx *ctx, const double *ref_dev, double *out_dev, void *stream);
+
 /* ---- discrete adjoint (D2Q9 and D3Q19, F64 and F32) ---------------------- *
  * Sweep s maps the state X_s = (f_s, p_s) to X_{s+1}: it gathers g_s from f_s,
  * collides with history p_s and stores f_{s+1}; p_{s+1} = sum_k g_s,k.

@@ -786,6 +786,22 @@ int lbm_reduce_async(lbm_ctx *c, const double *phi, const double *ref, double *o
     return LBM_OK;
 }
 
+int lbm_reduce_state(lbm_ctx *c, const double *ref, double *out_dev, void *stream) {
+    if (!c || !out_dev) return fail(LBM_E_INVALID, "null argument");
+    if (!c->bound) return fail(LBM_E_STATE, "lbm_init has not been called");
+    int parts = (int)std::min<uint32_t>(kRedParts, (c->g.N + kBlock - 1) / kBlock);
+    if (parts < 1) parts = 1;
+    const Dims d = eff_dims(c);
+    const hipStream_t st = (hipStream_t)stream;
+    const hipError_t e =
+        c->dm.q == 9
+            ? launch_phi_reduce_q9(d, c->g, c->d_coefs, c->f[c->cur], ref, c->rfield, c->d_red_part, parts, out_dev, st)
+            : launch_phi_reduce_q19(d, c->g, c->d_coefs, c->f[c->cur], ref, c->rfield, c->d_red_part, parts, out_dev,
+                                    st);
+    if (e != hipSuccess) return hip_fail(e, "state reduction");
+    return LBM_OK;
+}
+
 int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void *stream) {
     if (!c || !gphi || !psi || !pi) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");

@@ -223,6 +223,26 @@ hipError_t phi_typed(const Dims &dm, const Geom &g, const void *coefs, const voi
     return hipGetLastError();
 }
 
+// Reductions over phi formed from the state (k_phi_reduce), then the fold.
+template <int Q, typename TS, typename TC>
+hipError_t phi_reduce_typed(const Dims &dm, const Geom &g, const void *coefs, const void *f, const double *ref,
+                            const double *rfield, double *part, int nparts, double *out, hipStream_t st) {
+    const auto *cf = (const Coefs<TC> *)coefs;
+    const dim3 grid(nparts), block(kBlock);
+    const TS *fs = (const TS *)f;
+    if (dm.wall && dm.sb)
+        hipLaunchKernelGGL((k_phi_reduce<Q, TS, TC, true, true>), grid, block, 0, st, g, cf, fs, ref, rfield, part);
+    else if (dm.wall)
+        hipLaunchKernelGGL((k_phi_reduce<Q, TS, TC, true, false>), grid, block, 0, st, g, cf, fs, ref, rfield, part);
+    else if (dm.sb)
+        hipLaunchKernelGGL((k_phi_reduce<Q, TS, TC, false, true>), grid, block, 0, st, g, cf, fs, ref, rfield, part);
+    else
+        hipLaunchKernelGGL((k_phi_reduce<Q, TS, TC, false, false>), grid, block, 0, st, g, cf, fs, ref, rfield, part);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_reduce_final(part, nparts, out, st);
+}
+
 template <int Q, typename TS, typename TC>
 hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const void *f, const void *p,
                          const void *psi_next, const double *pi_next, void *psi_out, double *pi_out,

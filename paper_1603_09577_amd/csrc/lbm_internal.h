@@ -106,6 +106,9 @@ inline uint64_t plane_stride(uint64_t n, int q, size_t elem, int pad_req) {
                                  void *f, void *p, const double *rfield, hipStream_t st);               \
     hipError_t launch_phi_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *f,       \
                                 double *phi, const double *rfield, hipStream_t st);                     \
+    hipError_t launch_phi_reduce_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *f,\
+                                       const double *ref, const double *rfield, double *part,          \
+                                       int nparts, double *out, hipStream_t st);                        \
     hipError_t launch_recenter_##SFX(const Dims &dm, const Geom &g, void *coefs, void *f, void *p,     \
                                      double *part, int nparts, double *shift, hipStream_t st);          \
     hipError_t launch_adjoint_##SFX(const Dims &dm, const Geom &g, const void *coefs, const void *f,   \
@@ -122,6 +125,8 @@ LBM_LAUNCHERS(q19)
 #undef LBM_LAUNCHERS
 
 hipError_t launch_zero(double *p, uint32_t n, hipStream_t st);
+// fold of per-workgroup reduction partials (lbm_reduce.hip)
+hipError_t launch_reduce_final(const double *part, int nparts, double *out, hipStream_t st);
 
 // Two time steps per pass, D2Q9 only (sweep_d2q9.hip), with tile shape `shape`.
 hipError_t launch_sweep2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,

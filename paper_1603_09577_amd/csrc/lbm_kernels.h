@@ -21,6 +21,7 @@
 
 #include "lbm_internal.h"
 #include "lbm_lattice.h"
+#include "lbm_reduce.h"   // before the contraction pragma below: the same rounding as lbm_reduce.hip
 
 // Multiply-adds fuse only within one source expression (as the language
 // allows), never across statements: the rounding of a node update is then
@@ -933,12 +934,10 @@ k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict_
 }
 
 // phi = phi_ref + sum_k g_k (Scheme B: + R / 2, Eq. 35), accumulated in FP64.
-template <int Q, typename TS, typename TC, bool WALL, bool SB = false>
-__global__ void __launch_bounds__(kBlock)
-k_phi(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
-      double *__restrict__ phi, const double *rfield = nullptr) {
-    const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
-    if (n >= g.N) return;
+// phi at node n of a state (Eq. 10a; Scheme B Eq. 35), in FP64.
+template <int Q, typename TS, typename TC, bool WALL, bool SB>
+__device__ __forceinline__ double phi_at(const Geom &g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
+                                         uint32_t n, const double *rfield) {
     const NodeGeo ng = node_geometry<Q, WALL>(g, n);
     TC h[Q];
     gather<Q, WALL>(g, cf, f, ng, h);
@@ -946,7 +945,30 @@ k_phi(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
 #pragma unroll
     for (int k = 0; k < Q; ++k) acc += (double)h[k];
     if (SB) acc += 0.5 * ((double)cf->r[0] + (rfield ? rfield[n] : 0.0));
-    phi[n] = (double)cf->phi_ref + acc;
+    return (double)cf->phi_ref + acc;
+}
+
+template <int Q, typename TS, typename TC, bool WALL, bool SB>
+__global__ void __launch_bounds__(kBlock)
+k_phi(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
+      double *__restrict__ phi, const double *rfield = nullptr) {
+    const uint32_t n = block_index(blockIdx.x, gridDim.x, g.remap) * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    phi[n] = phi_at<Q, TS, TC, WALL, SB>(g, cf, f, n, rfield);
+}
+
+// The FP64 reductions of lbm_reduce over phi formed from the state on the
+// fly (no phi field written or read): per-workgroup partials in the same
+// per-thread order as the reduction over a stored phi field.
+template <int Q, typename TS, typename TC, bool WALL, bool SB>
+__global__ void __launch_bounds__(kBlock)
+k_phi_reduce(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f,
+             const double *__restrict__ ref, const double *rfield, double *__restrict__ part) {
+    double acc[kRed];
+    red_init(acc);
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < g.N; i += gridDim.x * kBlock)
+        red_add(acc, phi_at<Q, TS, TC, WALL, SB>(g, cf, f, i, rfield), ref ? ref[i] : 0.0);
+    red_block_fold(acc, part + (size_t)blockIdx.x * kRed);
 }
 
 // ---------------------------------------------------------------------------

@@ -4,73 +4,33 @@
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.h"
+#include "lbm_reduce.h"
 
 namespace lbm {
 
 namespace {
 
-constexpr int kRed = 8;  // sum, sumsq, sum d^2, sum ref^2, min, max, nonfinite, sum |d|
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ void block_fold(double *acc, double *out) {
-    __shared__ double sh[kRed][kBlock / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < kRed; ++i) {
-        double v = acc[i];
-        v = (i == 4) ? wave_min(v) : ((i == 5) ? wave_max(v) : wave_sum(v));
-        if (lane == 0) sh[i][wv] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < kRed) {
-        const int i = threadIdx.x;
-        double v = sh[i][0];
-        for (int w = 1; w < kBlock / 64; ++w)
-            v = (i == 4) ? fmin(v, sh[i][w]) : ((i == 5) ? fmax(v, sh[i][w]) : v + sh[i][w]);
-        out[i] = v;
-    }
-}
-
 __global__ void __launch_bounds__(kBlock)
 k_reduce_part(const double *__restrict__ phi, const double *__restrict__ ref, uint32_t n,
               double *__restrict__ part) {
-    double acc[kRed] = {0.0, 0.0, 0.0, 0.0, __builtin_inf(), -__builtin_inf(), 0.0, 0.0};
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const double v = phi[i];
-        const double r = ref ? ref[i] : 0.0;
-        if (!__builtin_isfinite(v)) { acc[6] += 1.0; continue; }
-        const double d = v - r;
-        acc[0] += v; acc[1] += v * v; acc[2] += d * d; acc[3] += r * r;
-        acc[4] = fmin(acc[4], v); acc[5] = fmax(acc[5], v); acc[7] += fabs(d);
-    }
-    block_fold(acc, part + (size_t)blockIdx.x * kRed);
+    double acc[kRed];
+    red_init(acc);
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        red_add(acc, phi[i], ref ? ref[i] : 0.0);
+    red_block_fold(acc, part + (size_t)blockIdx.x * kRed);
 }
 
 __global__ void __launch_bounds__(kBlock)
 k_reduce_final(const double *__restrict__ part, int nparts, double *__restrict__ out) {
-    double acc[kRed] = {0.0, 0.0, 0.0, 0.0, __builtin_inf(), -__builtin_inf(), 0.0, 0.0};
+    double acc[kRed];
+    red_init(acc);
     for (int b = threadIdx.x; b < nparts; b += kBlock) {
         const double *q = part + (size_t)b * kRed;
 #pragma unroll
         for (int i = 0; i < kRed; ++i)
             acc[i] = (i == 4) ? fmin(acc[i], q[i]) : ((i == 5) ? fmax(acc[i], q[i]) : acc[i] + q[i]);
     }
-    block_fold(acc, out);
+    red_block_fold(acc, out);
 }
 
 // acc[j] += sum_b part[b * width + j]
@@ -121,6 +81,11 @@ hipError_t launch_copy16(const void *src, void *dst, size_t n16, int grid, hipSt
 hipError_t launch_reduce(const double *phi, const double *ref, uint32_t n, double *part, int nparts,
                          double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce_part, dim3(nparts), dim3(kBlock), 0, st, phi, ref, n, part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, part, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_final(const double *part, int nparts, double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, st, part, nparts, out);
     return hipGetLastError();
 }

@@ -19,6 +19,11 @@ hipError_t launch_phi_q9(const Dims &dm, const Geom &g, const void *coefs, const
     LBM_BY_PREC(phi_typed, dm, g, coefs, f, phi, rfield, st)
 }
 
+hipError_t launch_phi_reduce_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f, const double *ref,
+                               const double *rfield, double *part, int nparts, double *out, hipStream_t st) {
+    LBM_BY_PREC(phi_reduce_typed, dm, g, coefs, f, ref, rfield, part, nparts, out, st)
+}
+
 hipError_t launch_sweep_gen_q9(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
                                void *p, int *flag, const double *kfield, const double *rfield, bool remark3,
                                hipStream_t st) {

@@ -34,7 +34,7 @@ EXPORTS = [
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
     "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields", "lbm_set_phi_wall",
     "lbm_set_two_step", "lbm_two_step_shape", "lbm_adjoint_step2", "lbm_adjoint_pair_ok", "lbm_set_remap",
-    "lbm_reduce_async",
+    "lbm_reduce_async", "lbm_reduce_state",
 ]
 
 
@@ -133,6 +133,7 @@ def load():
         "lbm_adjoint_step2": ([_VP] * 10, ctypes.c_int),
         "lbm_adjoint_pair_ok": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "lbm_reduce_async": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_reduce_state": ([_VP, _VP, _VP, _VP], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -358,6 +359,16 @@ class Lbm:
         if out is None:
             out = torch.empty(8, dtype=torch.float64, device=self.device)
         _check(self.lib.lbm_reduce_async(self.ctx, _ptr(phi), _ptr(ref), _ptr(out), _stream(stream)))
+        return out
+
+    def reduce_state(self, ref=None, out=None, stream=None):
+        """The reductions of reduce() over phi of the current state, formed
+        from the populations in one pass (no phi field), into a device tensor
+        of 8 FP64 values, enqueued without waiting."""
+        import torch
+        if out is None:
+            out = torch.empty(8, dtype=torch.float64, device=self.device)
+        _check(self.lib.lbm_reduce_state(self.ctx, _ptr(ref), _ptr(out), _stream(stream)))
         return out
 
     # -- adjoint -------------------------------------------------------------

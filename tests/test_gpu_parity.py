@@ -236,6 +236,32 @@ def test_reduce_async_equals_reduce():
     assert got[4] == p.min() and got[5] == p.max() and got[6] == 0
 
 
+@pytest.mark.parametrize("case", ["periodic-f32", "walls-f64", "d3q19-f32", "d3q19-f16"])
+def test_reduce_state_equals_reduce_of_phi(case):
+    """lbm_reduce_state forms phi from the stored populations inside the
+    reduction; its 8 values equal, bit for bit, those of lbm_reduce over the
+    field lbm_get_phi writes, with and without a reference field."""
+    lbm = _lbm()
+    if case == "periodic-f32":
+        spec = W.spec_nonlinear_2d(200, 130, precision="f32")
+    elif case == "walls-f64":
+        spec = dict(W.spec_nonlinear_2d(130, 70), bc=["periodic", "abb", "periodic"],
+                    phi_wall=[[0, 0], [0.3, 0.8], [0, 0]])
+    else:
+        spec = W.d3q19_walls((20, 18, 22), precision=case[-3:])[0]
+    sim = lbm.Lbm(spec)
+    phi0 = W.noise_field(tuple(sim.shape), 20)
+    say(f"[gpu] reduce_state {case} {sim.shape}")
+    sim.init(phi0)
+    sim.step(9)
+    ref = torch.tensor(W.noise_field(tuple(sim.shape), 21), dtype=torch.float64, device="cuda")
+    keys = ("sum", "sumsq", "sum_d2", "sum_ref2", "min", "max", "nonfinite", "sum_absd")
+    for r in (None, ref):
+        got = sim.reduce_state(r).cpu().numpy()
+        want = sim.reduce(sim.phi(), r)
+        assert [got[i] for i in range(8)] == [want[k] for k in keys], (case, r is None)
+
+
 def test_every_node_written():
     """Poison the destination with NaN: one sweep must overwrite every value."""
     lbm = _lbm()
