@@ -11,9 +11,13 @@
  *  - Lattice units: c = dx = dt = 1, cs^2 = 1/3 (Eq. 5/6 and the text after
  *    them).  A problem stated with other dx, dt is rewritten by the caller
  *    (B dt/dx, K dt/dx^2, R dt).
- *  - Every device pointer is owned by the caller (the library never allocates
- *    or frees caller buffers); the context owns only its parameter tables and
- *    a small device scratch area for flags and reduction partials.
+ *  - Every buffer that grows with the grid is owned by the caller: both
+ *    distribution buffers, the phi history and, for two steps per pass with a
+ *    source, a second history (sizes from lbm_state_bytes).  The library
+ *    never allocates or frees caller buffers.  A context owns only its
+ *    parameter table and a fixed device scratch area (divergence flag,
+ *    reduction partials, adjoint K0 partials: about 3.1 MiB whatever the
+ *    grid size); a batch owns its per-instance tables and tile work lists.
  *  - Calls are asynchronous on the caller's HIP stream (a hipStream_t passed
  *    as void*, NULL = the default stream) unless stated otherwise.
  *  - Every call returns LBM_OK (0) or a negative error code; lbm_last_error()
@@ -121,23 +125,35 @@ typedef struct lbm_ctx lbm_ctx;
  * (LBM_E_INVALID): unknown lattice, sizes < 1 or more than 2^31 nodes,
  * d <= 0, a used rate outside (0, 2), k0 not symmetric positive definite,
  * dten not symmetric.  LBM_E_UNSUPPORTED: walls on an axis other than the
- * last, Scheme B with a source.  Allocates a few KB of device scratch on the
- * current device.  *out is set only on success. */
+ * last, Scheme B with a source.  Allocates the context's coefficient table and
+ * its fixed scratch (about 3.1 MiB, independent of the grid) on the current
+ * device, nothing that scales with the grid.  *out is set only on success. */
 int lbm_create(const lbm_desc *desc, lbm_ctx **out);
 
-/* Bytes of one distribution buffer (f_bytes) and of the phi-history buffer
- * (p_bytes) that the caller must provide; both multiples of 256. */
-int lbm_state_bytes(const lbm_ctx *ctx, size_t *f_bytes, size_t *p_bytes);
+/* Bytes of the buffers the caller provides, each a multiple of 256 (any
+ * output pointer may be NULL):
+ *  f_bytes  one distribution buffer (two are needed);
+ *  p_bytes  the phi-history buffer (phi of the last step: Scheme A's
+ *           R_k(t - 1), Remark II);
+ *  p2_bytes a second history buffer, used only by two time steps per pass on
+ *           runs that keep a history (D2Q9, periodic, equal non-flux rates,
+ *           with a source); 0 when no pass would read it.  Without it such a
+ *           run uses one sweep per step. */
+int lbm_state_bytes(const lbm_ctx *ctx, size_t *f_bytes, size_t *p_bytes, size_t *p2_bytes);
 
 /* Bytes of one adjoint-variable buffer psi (same plane layout as the
  * distribution buffers, in the compute type: FP64 or FP32). */
 int lbm_adjoint_bytes(const lbm_ctx *ctx, size_t *psi_bytes);
 
-/* Bind two distribution buffers and the phi-history buffer, and initialise
- * with the equilibrium of phi0 (Eq. 40; the history is set to phi0, the
- * reading of the first Scheme-A step).  phi0_dev: FP64 [nz][ny][nx] on the
- * device.  Buffers must be 256-byte aligned and of lbm_state_bytes sizes. */
-int lbm_init(lbm_ctx *ctx, const double *phi0_dev, void *f_a, void *f_b, void *p,
+/* Bind two distribution buffers, the phi-history buffer and the optional
+ * second history p2, and initialise with the equilibrium of phi0 (Eq. 40; the
+ * history is set to phi0, the reading of the first Scheme-A step).  phi0_dev:
+ * FP64 [nz][ny][nx] on the device, kept by pointer for lbm_tune.  Buffers
+ * must be 256-byte aligned and of lbm_state_bytes sizes.  p2 may be NULL: it
+ * is ignored when lbm_state_bytes reports p2_bytes = 0, and otherwise its
+ * absence turns two steps per pass off for this binding.  p2 must differ from
+ * the other buffers (LBM_E_INVALID). */
+int lbm_init(lbm_ctx *ctx, const double *phi0_dev, void *f_a, void *f_b, void *p, void *p2,
              void *stream);
 
 /* Advance nsteps time steps (Eq. 2 with the Scheme-A source, anti-bounce-back
@@ -200,17 +216,19 @@ int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_l
  * on the tile and stores only that result: every update is the single-sweep
  * arithmetic on the same inputs, so results equal single sweeps bit for bit,
  * while the state crosses HBM once per two steps.  Passes run in pairs (four
- * steps) through a second phi history buffer owned by the context, so state
- * and history end in the same buffers as after single sweeps; remaining steps
- * use single sweeps.  On by default where it applies (lbm_tune times it
+ * steps); with a source they alternate the history between p and the
+ * caller's p2 (lbm_init), so state and history end in the same buffers as
+ * after single sweeps; remaining steps use single sweeps.  On by default
+ * where it applies and, with a source, p2 is bound (lbm_tune times it
  * against single sweeps); not used with a divergence check, Scheme B sources,
  * per-node fields or Remark III.
  * mode: 0 off; k >= 1 on with tile shape k - 1 (lbm_two_step_shape; shape 0,
  * the default, is 14 rows x 4 waves for 4- and 2-byte storage and 6 x 4 for
  * FP64).  The other shapes need every polynomial of degree <= 2; lbm_tune
  * times them all.
- * Errors: LBM_E_UNSUPPORTED when the run does not qualify; LBM_E_INVALID for a
- * shape that is not available here. */
+ * Errors: LBM_E_UNSUPPORTED when the run does not qualify; LBM_E_STATE when a
+ * run with a source was bound without p2; LBM_E_INVALID for a shape that is
+ * not available here. */
 int lbm_set_two_step(lbm_ctx *ctx, int mode);
 
 /* Tile shape `shape` of two-step passes for this context's storage type: tile
@@ -279,10 +297,19 @@ int lbm_set_fields(lbm_ctx *ctx, const double *k0_field, const double *r_field);
 /* Replace K0 (keeps every other parameter); same validation as lbm_create. */
 int lbm_set_k0(lbm_ctx *ctx, const double k0[9]);
 
-/* FP64 reductions over a phi field (synchronous).  out[0] = sum phi,
- * out[1] = sum phi^2, out[2] = sum (phi - ref)^2, out[3] = sum ref^2,
- * out[4] = min phi, out[5] = max phi, out[6] = number of non-finite values,
- * out[7] = sum |phi - ref|.  ref_dev may be NULL (then ref = 0). */
+/* FP64 reductions over a phi field (synchronous), the quantities the method
+ * is checked with: the total of phi, whose change over a step is the source
+ * total because phi = sum_k f_k (Eq. 10a) and streaming permutes the
+ * populations; and the error norms against a reference field, out[7] /
+ * sum |ref| being the global relative error of Eq. 39 and
+ * sqrt(out[2] / out[3]) the relative L2 error.  The field is N FP64 values
+ * (the node count of the context), ref_dev N values or NULL (then ref = 0).
+ *   out[0] = sum phi,  out[1] = sum phi^2,  out[2] = sum (phi - ref)^2,
+ *   out[3] = sum ref^2,  out[4] = min phi,  out[5] = max phi,
+ *   out[6] = number of non-finite values (left out of every other entry),
+ *   out[7] = sum |phi - ref|.
+ * Partials are folded in a fixed order, so results do not vary between runs.
+ * Errors: LBM_E_INVALID (null argument), LBM_E_HIP. */
 int lbm_reduce(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev, double out[8],
                void *stream);
 

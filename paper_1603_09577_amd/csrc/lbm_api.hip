@@ -60,8 +60,9 @@ struct lbm_ctx {
     bool recentered = false;  // phi_ref on the device differs from the description's
     // per-node fields (caller-owned, FP64): K0(x) and the external source R(x, t)
     const double *kfield = nullptr, *rfield = nullptr;
-    // two time steps per pass (D2Q9 periodic equal-rate runs): a second phi
-    // history buffer owned by the context, and whether the path is on
+    // two time steps per pass (D2Q9 periodic equal-rate runs): the caller's
+    // second phi history buffer (needed only when the run keeps a history),
+    // and whether the path is on
     void *p2 = nullptr;
     bool two_ok = false, two = false;
     int two_shape = 0;        // tile shape of two-step passes (two_step_shape_of; 0: the default)
@@ -346,16 +347,27 @@ bool remark3(const lbm_ctx *c) { return (c->desc.flags & LBM_FLAG_REMARK3) != 0;
 
 bool general_path(const lbm_ctx *c) { return c->kfield || eff_dims(c).sb || remark3(c); }
 
-bool two_active(const lbm_ctx *c) { return c->two && c->two_ok && !general_path(c) && c->check_every == 0; }
+// Two-step passes can run: the run qualifies and, when it keeps a phi history
+// (a Scheme-A source), the caller bound the second history buffer.
+bool two_ready(const lbm_ctx *c) { return c->two_ok && (!c->dm.src || c->p2 != nullptr); }
+
+bool two_active(const lbm_ctx *c) { return c->two && two_ready(c) && !general_path(c) && c->check_every == 0; }
+
+// Bytes of the second history buffer (0 when two-step passes never read one).
+size_t hist2_bytes(const lbm_ctx *c) {
+    return (c->two_ok && c->dm.src) ? round256((size_t)c->g.N * hist_size(c->dm.prec)) : 0;
+}
 
 // Four steps as two passes of two steps each: f[start] -> f[start ^ 1] with the
 // history p -> p2, then back; state and history end where four single sweeps
 // would leave them.
+// Without a source the kernels touch no history, and p stands in for p2.
 hipError_t sweep_pair(lbm_ctx *c, int start, hipStream_t st) {
-    hipError_t e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, c->p2, c->d_flag,
+    void *p2 = c->dm.src ? c->p2 : c->p;
+    hipError_t e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, p2, c->d_flag,
                                     c->two_shape, st);
     if (e == hipSuccess)
-        e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], c->p2, c->p, c->d_flag,
+        e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], p2, c->p, c->d_flag,
                              c->two_shape, st);
     return e;
 }
@@ -553,10 +565,6 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     c->recenter_every = (dm.prec == 2 && dm.src) ? kRecenterF16 : 0;
     e = hipMemset(c->d_scratch, 0, scratch);
     if (e != hipSuccess) { lbm_destroy(c); return hip_fail(e, "hipMemset(scratch)"); }
-    if (c->two_ok) {
-        e = hipMalloc(&c->p2, round256((size_t)g.N * hist_size(dm.prec)));
-        if (e != hipSuccess) { lbm_destroy(c); return hip_fail(e, "hipMalloc(second history)"); }
-    }
     rc = upload_coefs(c);
     if (rc != LBM_OK) { lbm_destroy(c); return rc; }
     *out = c;
@@ -569,14 +577,14 @@ void lbm_destroy(lbm_ctx *c) {
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->d_coefs) (void)hipFree(c->d_coefs);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
-    if (c->p2) (void)hipFree(c->p2);
     delete c;
 }
 
-int lbm_state_bytes(const lbm_ctx *c, size_t *f_bytes, size_t *p_bytes) {
+int lbm_state_bytes(const lbm_ctx *c, size_t *f_bytes, size_t *p_bytes, size_t *p2_bytes) {
     if (!c) return fail(LBM_E_INVALID, "null context");
     if (f_bytes) *f_bytes = round256((size_t)c->dm.q * c->g.plane * storage_size(c->dm.prec));
     if (p_bytes) *p_bytes = round256((size_t)c->g.N * hist_size(c->dm.prec));
+    if (p2_bytes) *p2_bytes = hist2_bytes(c);
     return LBM_OK;
 }
 
@@ -586,12 +594,16 @@ int lbm_adjoint_bytes(const lbm_ctx *c, size_t *psi_bytes) {
     return LBM_OK;
 }
 
-int lbm_init(lbm_ctx *c, const double *phi0, void *f_a, void *f_b, void *p, void *stream) {
+int lbm_init(lbm_ctx *c, const double *phi0, void *f_a, void *f_b, void *p, void *p2, void *stream) {
     if (!c || !phi0 || !f_a || !f_b || !p) return fail(LBM_E_INVALID, "null argument");
     if (f_a == f_b) return fail(LBM_E_INVALID, "the two distribution buffers must differ");
-    if (((uintptr_t)f_a | (uintptr_t)f_b | (uintptr_t)p) & 255) return fail(LBM_E_INVALID, "buffers must be 256-byte aligned");
-    if (c->f[0] != f_a || c->f[1] != f_b || c->p != p) drop_graphs(c);
-    c->f[0] = f_a; c->f[1] = f_b; c->p = p; c->phi0 = phi0;
+    if (((uintptr_t)f_a | (uintptr_t)f_b | (uintptr_t)p | (uintptr_t)p2) & 255)
+        return fail(LBM_E_INVALID, "buffers must be 256-byte aligned");
+    if (p2 && (p2 == p || p2 == f_a || p2 == f_b))
+        return fail(LBM_E_INVALID, "the second history buffer must differ from the other buffers");
+    if (hist2_bytes(c) == 0) p2 = nullptr;   // never read: keep no pointer to it
+    if (c->f[0] != f_a || c->f[1] != f_b || c->p != p || c->p2 != p2) drop_graphs(c);
+    c->f[0] = f_a; c->f[1] = f_b; c->p = p; c->p2 = p2; c->phi0 = phi0;
     c->cur = 0; c->t = 0; c->bound = true;
     hipStream_t st = (hipStream_t)stream;
     if (c->recentered) {
@@ -604,8 +616,9 @@ int lbm_init(lbm_ctx *c, const double *phi0, void *f_a, void *f_b, void *p, void
     hipError_t e = (c->dm.q == 9) ? launch_init_q9(d, c->g, c->d_coefs, phi0, f_a, p, c->rfield, st)
                                   : launch_init_q19(d, c->g, c->d_coefs, phi0, f_a, p, c->rfield, st);
     if (e != hipSuccess) return hip_fail(e, "init kernel");
-    e = hipMemsetAsync(c->d_flag, 0, sizeof(int), st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(flag)");
+    // a fill kernel, not a memset node, in case the caller captures this call
+    e = launch_zero((double *)c->d_flag, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "flag reset");
     return LBM_OK;
 }
 
@@ -659,6 +672,8 @@ int lbm_set_two_step(lbm_ctx *c, int mode) {
     if (mode < 0) return fail(LBM_E_INVALID, "mode must be 0 (off) or 1 + a tile shape");
     if (mode && !c->two_ok)
         return fail(LBM_E_UNSUPPORTED, "two steps per pass need D2Q9, periodic axes and equal non-flux rates");
+    if (mode && c->bound && !two_ready(c))
+        return fail(LBM_E_STATE, "two steps per pass with a source need the second history buffer (lbm_init p2)");
     const int shape = mode > 0 ? mode - 1 : 0;
     if (mode && !two_shape_usable(c, shape))
         return fail(LBM_E_INVALID, "tile shape not available for this storage type or polynomial length");
@@ -964,7 +979,7 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
     int best_shape = 0;
     c->g.chunk = (uint32_t)best_chunk;
     c->dm.nt = best_nt;
-    if (c->two_ok && !general_path(c)) {
+    if (two_ready(c) && !general_path(c)) {
         // four steps per pair; twice the steps of a single-sweep trial, as the
         // shapes differ by a few per cent
         const int pair_reps = std::max(2, reps / 2);
@@ -1035,7 +1050,7 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
     rep += line;
     if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
     // the history buffer was overwritten by the trial sweeps: restart from phi0
-    return lbm_init(c, c->phi0, c->f[0], c->f[1], c->p, stream);
+    return lbm_init(c, c->phi0, c->f[0], c->f[1], c->p, c->p2, stream);
 }
 
 int lbm_probe_copy(const void *src, void *dst, size_t bytes, int grid, void *stream) {

@@ -86,9 +86,10 @@ def load():
     L = ctypes.CDLL(LIB_PATH)
     sig = {
         "lbm_create": ([ctypes.POINTER(LbmDesc), ctypes.POINTER(_VP)], ctypes.c_int),
-        "lbm_state_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_state_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                             ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_adjoint_bytes": ([_VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
-        "lbm_init": ([_VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_init": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
         "lbm_step": ([_VP, ctypes.c_int, _VP], ctypes.c_int),
         "lbm_sweep": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
         "lbm_get_phi": ([_VP, _VP, _VP], ctypes.c_int),
@@ -209,8 +210,9 @@ def _ptr(t):
 class Lbm:
     """One MRT lattice Boltzmann instance on the current GPU.
 
-    Owns two distribution buffers and the phi-history buffer as torch tensors
-    (uint8 storage, sizes from lbm_state_bytes) and the library context.
+    Owns two distribution buffers, the phi-history buffer and, where two
+    steps per pass read one, the second history buffer as torch tensors (uint8
+    storage, sizes from lbm_state_bytes), and the library context.
     """
 
     def __init__(self, spec, device="cuda", flags=0):
@@ -221,9 +223,9 @@ class Lbm:
         ctx = _VP()
         _check(self.lib.lbm_create(ctypes.byref(self.desc), ctypes.byref(ctx)))
         self.ctx = ctx
-        fb, pb = ctypes.c_size_t(), ctypes.c_size_t()
-        _check(self.lib.lbm_state_bytes(self.ctx, ctypes.byref(fb), ctypes.byref(pb)))
-        self.f_bytes, self.p_bytes = fb.value, pb.value
+        fb, pb, p2b = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(self.lib.lbm_state_bytes(self.ctx, ctypes.byref(fb), ctypes.byref(pb), ctypes.byref(p2b)))
+        self.f_bytes, self.p_bytes, self.p2_bytes = fb.value, pb.value, p2b.value
         self.device = torch.device(device)
         self.shape = (self.desc.nz, self.desc.ny, self.desc.nx) if self.desc.lattice == 19 \
             else (self.desc.ny, self.desc.nx)
@@ -231,6 +233,7 @@ class Lbm:
         self.N = int(np.prod(self.shape))
         self.f = [torch.empty(self.f_bytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
         self.p = torch.empty(self.p_bytes, dtype=torch.uint8, device=self.device)
+        self.p2 = torch.empty(self.p2_bytes, dtype=torch.uint8, device=self.device) if self.p2_bytes else None
         self.compute_dtype = torch.float64 if self.desc.precision == 0 else torch.float32
 
     def __del__(self):
@@ -248,7 +251,7 @@ class Lbm:
         assert phi0.numel() == self.N
         self._phi0 = phi0
         _check(self.lib.lbm_init(self.ctx, _ptr(phi0), _ptr(self.f[0]), _ptr(self.f[1]), _ptr(self.p),
-                                 _stream(stream)))
+                                 _ptr(self.p2), _stream(stream)))
         return self
 
     def step(self, n=1, stream=None):
