@@ -8,9 +8,13 @@ K = K0 (1 + phi^2), R = 0.1 phi (1 - phi), phi0 = 0.5 + 0.1 U[-1, 1) seed 2),
 distributions stored as FP32 offsets.  One step = one time step of every
 node: one fused sweep, or half of a pass that runs two time steps (the
 autotuner's choice where it is faster; the results are bit-identical).  The
-roofline object describes the kernel launched, with that kernel's algorithmic
-bytes (a two-step pass reads and writes the state once for two updates);
-single sweeps are reported beside it.  The same run in FP64 storage, the
+value is the median of 5 timed regions of --steps steps each.  The roofline
+object describes the kernel launched: algorithmic bytes per node update (one
+read and one write of every population and of the phi history) times the
+updates one launch performs, over the launch time; a two-step pass performs
+two updates per node while moving the state once, so its fraction can exceed
+1 (its fraction on its own bytes is reported beside it), and single sweeps
+are reported beside it too.  The same run in FP64 storage, the
 reversed (adjoint) sweep on the
 512 x 512 adjoint workload, the D3Q19 sweep on 256^3 with walls, a plain copy
 kernel (practical HBM ceiling) and the CPU oracle on a bounded sample are
@@ -76,20 +80,38 @@ def profile_entry(kernel_key, kernel=None):
     return v
 
 
-def time_steps(torch, sim, steps, warmup):
-    """Average time of one sweep over `steps` sweeps (HIP events on the
-    stream the kernels run on), after `warmup` untimed sweeps."""
+SAMPLES = 5          # timed samples of `steps` steps each; the median is reported
+PREROLL_CYCLES = 2_000_000
+
+
+def time_steps(torch, sim, steps, warmup, samples=SAMPLES):
+    """Time per step: the median over `samples` timed regions of `steps`
+    steps each (HIP events on the stream the kernels run on), after `warmup`
+    untimed steps.  Before each region a spin kernel holds the GPU for about
+    a millisecond while the host enqueues the region's launches, so that a
+    short region measures the sweeps back to back rather than the host's
+    launch latency; the device synchronises before and after each region.
+    Returns (median seconds per step, details)."""
+    import statistics
     sim.step(warmup)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(st)
-    sim.step(steps)
-    e1.record(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / 1e3 / steps, wall
+    per, walls = [], []
+    for _ in range(samples):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(PREROLL_CYCLES)
+        t0 = time.perf_counter()
+        e0.record(st)
+        sim.step(steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        per.append(e0.elapsed_time(e1) / 1e3 / steps)
+    med = statistics.median(per)
+    return med, {"samples": samples, "ms_per_step_samples": [round(v * 1e3, 6) for v in per],
+                 "ms_per_step_min": min(per) * 1e3, "ms_per_step_max": max(per) * 1e3,
+                 "wall_s": sum(walls)}
 
 
 # tile shape forced on two-step runs after tuning, with the XCD-aware order
@@ -117,7 +139,7 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_ste
     two = (" two 1" in rep) if two_step is None else bool(two_step)
     m = re.search(r" rows (\d+) waves (\d+)", rep)
     rows = f"{m.group(1)} rows x {m.group(2)} waves" if (two and m) else None
-    per, wall = time_steps(torch, sim, steps, warmup)
+    per, tinfo = time_steps(torch, sim, steps, warmup)
     N = sim.N
     prec = spec.get("precision", "f64")
     src = bool(spec.get("rpoly"))
@@ -125,7 +147,7 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_ste
     out = {
         "label": label, "nodes": N, "steps": steps, "ms_per_step": per * 1e3,
         "mlups": N / per / 1e6, "bytes_per_node": bpn, "two_step": two, "tile_rows": rows,
-        "wall_s": wall, "tuner": rep,
+        "timing": tinfo, "tuner": rep,
     }
     # algorithmic bytes of the launched kernel: a single sweep reads and writes
     # the state once per step; a two-step pass once per two steps
@@ -263,14 +285,7 @@ def run_batch(torch, lbm, W, steps):
     items = W.batch_specs()
     b = lbm.Batch([s for s, _ in items]).init([p for _, p in items])
     rep = b.tune(reps=3)
-    b.step(32)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    b.step(steps)
-    e1.record()
-    torch.cuda.synchronize()
-    per = e0.elapsed_time(e1) / 1e3 / steps
+    per, tinfo = time_steps(torch, b, steps, 32, samples=3)
     N = b.total_nodes
     bpn = bytes_per_node(9, "f32", False)
     fin = torch.isfinite(b.phi()).all().item()
@@ -280,7 +295,7 @@ def run_batch(torch, lbm, W, steps):
     return {"instances": len(items), "nodes": N, "steps": steps, "ms_per_step": per * 1e3,
             "mlups": N / per / 1e6, "bytes_per_node": bpn, "two_step": two, "achieved_gbs": launch_gbs,
             "hbm_frac": launch_gbs / PEAK_HBM_GBS, "per_update_hbm_frac": bpn * N / per / 1e9 / PEAK_HBM_GBS,
-            "shape": shape, "tuner": rep.splitlines()[-1], "finite": bool(fin)}
+            "shape": shape, "tuner": rep.splitlines()[-1], "finite": bool(fin), "timing": tinfo}
 
 
 def copy_probe(torch, lbm, nbytes=1 << 30, reps=20):
@@ -306,9 +321,20 @@ def copy_probe(torch, lbm, nbytes=1 << 30, reps=20):
     return out
 
 
-def cpu_baseline(spec, phi0, target_s=12.0):
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(spec, phi0, target_s=12.0, single_s=6.0):
     """The oracle as it stands, on the host cores, on a bounded number of
-    steps of the same workload; MLUPS over the timed steps."""
+    steps of the same workload; MLUPS over the timed steps, with OpenMP on
+    every thread the box grants (OMP_NUM_THREADS) and on one thread."""
     import oracle as orc
     p = orc.params_from_spec(dict(spec, precision="f64"))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -322,9 +348,22 @@ def cpu_baseline(spec, phi0, target_s=12.0):
         orc.step(p, f, pp, nthreads=threads)
     dt = time.perf_counter() - t0
     N = orc.nodes(p)
+    phi_after = orc.phi(p, f)
+    # one thread, continuing from the same state (a separate sample)
+    t0 = time.perf_counter()
+    orc.step(p, f, pp, nthreads=1)
+    one1 = time.perf_counter() - t0
+    n1 = max(1, min(50, int(single_s / max(one1, 1e-3))))
+    t0 = time.perf_counter()
+    for _ in range(n1):
+        orc.step(p, f, pp, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "single_thread_mlups": N * n1 / dt1 / 1e6, "cpu_model": cpu_model(),
+            "host_threads_visible": os.cpu_count(),
             "sample": f"{n + 1} steps of the 1024x1024 D2Q9 headline workload in FP64 "
-                      f"(first step untimed), OpenMP over nodes"}, orc.phi(p, f), n + 1
+                      f"(first step untimed), OpenMP over nodes on {threads} threads; then "
+                      f"{n1 + 1} steps on one thread (first untimed)"}, phi_after, n + 1
 
 
 # ---------------------------------------------------------------------------
@@ -512,12 +551,14 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
         line = next((ln for ln in open(blog) if ln.startswith('{"metric"')), None)
         if line:
             rf = json.loads(line)["roofline"]
-            per_launch_us = rf["bytes_per_node"] * rf["nodes_per_launch"] / (rf["achieved"] * 1e9) * 1e6
+            per_launch_us = rf["launch_us"]
             w = per_wl[head]
-            tl += ["", f"The bench line of this profiled run reports `roofline.achieved` = {rf['achieved']:.0f} GB/s "
-                   f"for `{rf['kernel']}`, i.e. {per_launch_us:.2f} us per launch (HIP events over the timed "
-                   f"region); the trace gives {w['avg_us']:.2f} us average and {w['median_us']:.2f} us median "
-                   f"per dispatch of that kernel on the same grid ({w['gbs_avg']:.0f} GB/s)."]
+            tl += ["", f"The bench line of this profiled run reports `roofline.launch_us` = {per_launch_us:.2f} us "
+                   f"per launch of `{rf['kernel']}` (HIP events over the timed region, median of the samples; "
+                   f"`roofline.achieved` = {rf['achieved']:.0f} GB/s at {rf['bytes_per_node']} B per node "
+                   f"update x {rf['steps_per_launch']} updates of {rf['nodes_per_launch']} nodes per launch); "
+                   f"the trace gives {w['avg_us']:.2f} us average and {w['median_us']:.2f} us median "
+                   f"per dispatch of that kernel on the same grid."]
     out["trace_per_workload"] = per_wl
     with open(os.path.join(pdir, "sweep_kernels_kernel_trace.md"), "w") as fh:
         fh.write("\n".join(tl) + "\n")
@@ -709,14 +750,26 @@ def main():
             "scheme": "A", "grid_spacing": W.NONLINEAR_DX, "time_step": W.NONLINEAR_DT,
         },
         "roofline": {
-            "bound": "hbm", "achieved": head["achieved_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": head["hbm_frac"], "traffic": traffic,
+            # algorithmic bytes per launch = bytes per node update (one read and
+            # one write of every population plus the phi history) x the node
+            # updates one launch performs (2 N for a two-step pass), over the
+            # launch time
+            "bound": "hbm", "achieved": head["per_update_hbm_frac"] * PEAK_HBM_GBS, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": head["per_update_hbm_frac"], "traffic": traffic,
+            "frac_own_bytes": head["hbm_frac"],
+            "note": ("frac counts the bytes one sweep per step would move; a two-step pass moves the "
+                     "state through HBM once per two updates (frac_own_bytes: its own bytes over its time), "
+                     "and the 79 MB state also fits the 256 MB Infinity Cache, so frac can exceed 1. "
+                     "HBM-resident evidence: hbm_resident_4096_f32 and d3q19_f32/f64"
+                     if head["two_step"] else
+                     "the 79 MB state fits the 256 MB Infinity Cache; HBM-resident evidence: "
+                     "hbm_resident_4096_f32 and d3q19_f32/f64"),
             "kernel": (f"k_sweep2<float, float, SRC, KVAR, 3-term polynomials, {head['tile_rows']}> "
                        "(two steps per pass)"
                        if head["two_step"] else "k_sweep<9, float, float, EQR, SRC, KVAR, !WALL, 3-term polynomials>"),
             "bytes_per_node": head["bytes_per_node"], "nodes_per_launch": head["nodes"],
             "steps_per_launch": 2 if head["two_step"] else 1,
-            "per_update_frac": head["per_update_hbm_frac"],
+            "launch_us": head["ms_per_step"] * (2 if head["two_step"] else 1) * 1e3,
             # measured vector-instruction issue of the same kernel (rocprofv3
             # SQ_INSTS_VALU over its trace time) against 6.14e11 wave-instructions/s
             # (256 CUs x 2.4 GHz, one 64-lane instruction per CU per clock without packed FP32)
@@ -726,6 +779,7 @@ def main():
                         "achieved_gbs": single32["achieved_gbs"], "hbm_frac": single32["hbm_frac"]},
         "cpu_baseline": cpu,
         "tuner": head["tuner"],
+        "timing": head["timing"],
         "fp64": {"mlups": f64["mlups"], "ms_per_step": f64["ms_per_step"], "two_step": f64["two_step"],
                  "tile_rows": f64["tile_rows"], "achieved_gbs": f64["achieved_gbs"], "hbm_frac": f64["hbm_frac"],
                  "per_update_hbm_frac": f64["per_update_hbm_frac"]},

@@ -132,7 +132,7 @@ def test_rollout_with_pairs_matches_oracle():
     p0 = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
     k0 = torch.tensor([spec["k0"][0][0], spec["k0"][0][1], spec["k0"][1][1]], dtype=torch.float64,
                       requires_grad=True)
-    phiT = rollout(sim, p0, k0, T, 4)
+    phiT = rollout(sim, p0, k0, T, 4, pairs=True)    # the two-sweep kernel, whatever a timing trial says
     loss = 0.5 * ((phiT - torch.tensor(target, device="cuda")) ** 2).sum()
     loss.backward()
     torch.cuda.synchronize()
