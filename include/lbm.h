@@ -330,6 +330,30 @@ int lbm_reduce_async(lbm_ctx *ctx, const double *phi_dev, const double *ref_dev,
  * argument), LBM_E_STATE (before lbm_init), LBM_E_HIP. */
 int lbm_reduce_state(lbm_ctx *ctx, const double *ref_dev, double *out_dev, void *stream);
 
+/* The reductions of lbm_reduce_async over any FP64 field of n values, with no
+ * context and no allocation: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The per-workgroup partial sums live in a fixed device array of
+ * the library (64 KiB: 1024 rows of 8 FP64 values), one copy per GPU, held
+ * until the process ends; its address is resolved on the first call on each
+ * device, with that device current.  The call launches two kernels and makes
+ * no allocating call (no hipMalloc, hipFree or library allocation) and no
+ * memset: every partial row the fold reads is written by the same call first,
+ * so nothing needs clearing between calls.  Results equal, bit for bit,
+ * those of lbm_reduce_async on a context of n nodes over the same fields
+ * (same partial rows, same fixed folding order).
+ *   phi_dev  n FP64 values on the current device;
+ *   ref_dev  n FP64 values or NULL (ref = 0);
+ *   out_dev  8 FP64 values of caller device memory, the order of lbm_reduce
+ *            (n = 0 gives 0, 0, 0, 0, +inf, -inf, 0, 0).
+ * Asynchronous on `stream`, which must belong to the current device.  All
+ * calls on one GPU share its array: calls that overlap in time on one GPU
+ * (different streams, or host threads) race and must be serialised by the
+ * caller.  Errors: LBM_E_INVALID (null phi or out, n above
+ * LBM_NOALLOC_MAX_NODES), LBM_E_HIP. */
+#define LBM_NOALLOC_MAX_NODES 2147483647
+int lbm_reduce_noalloc(const double *phi_dev, const double *ref_dev, size_t n, double *out_dev, void *stream);
+
 /* ---- discrete adjoint (D2Q9 and D3Q19, F64 and F32) ---------------------- *
  * Sweep s maps the state X_s = (f_s, p_s) to X_{s+1}: it gathers g_s from f_s,
  * collides with history p_s and stores f_{s+1}; p_{s+1} = sum_k g_s,k.

@@ -29,7 +29,6 @@ int hip_fail(hipError_t e, const char *where) {
     return LBM_E_HIP;
 }
 
-constexpr int kRedParts = 1024;       // partial rows of the phi reductions
 constexpr int kAdjWidth = 6;          // K0 gradient entries per adjoint partial
 constexpr int kMaxAdjParts = 65536;   // workgroups covered by the adjoint partials
 constexpr int kGraphSteps = 32;       // sweeps per captured graph (even: ends on the start buffer)

@@ -11,6 +11,7 @@ constexpr int kBlock = 256;     // threads per workgroup (4 wave64)
 constexpr int kMaxP = 9;        // coefficients of B, D, K, R polynomials
 constexpr int kMaxC = 16;       // coefficients of the C-bar polynomials
 constexpr int kNumXcd = 8;      // accelerator complex dies on MI355X
+constexpr int kRedParts = 1024; // most workgroups of the phi reductions (one partial row each)
 
 // n / d for n < 2^31 via one high multiply (Granlund-Montgomery).
 struct FastDiv {

@@ -3,10 +3,17 @@
 // partials, then one workgroup folds them in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+#include <string>
+
+#include "../../include/lbm.h"
 #include "lbm_internal.h"
 #include "lbm_reduce.h"
 
 namespace lbm {
+
+int api_fail(int code, const char *msg);
 
 namespace {
 
@@ -96,3 +103,59 @@ hipError_t launch_sum_partials(const double *part, int nparts, int width, double
 }
 
 }  // namespace lbm
+
+// ---- lbm_reduce_noalloc: the reductions with library-held partials --------
+//
+// The partial rows live in one file-scope device array instead of memory the
+// library allocates.  Each device that runs the call holds its own copy of
+// the array at its own address, found once per device with
+// hipGetSymbolAddress; host code uses only that address (the array's name in
+// host code is a stand-in, not a device pointer).
+
+static __device__ __align__(256) double scratch[lbm::kRedParts * lbm::kRed];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// The address of this device's copy of `scratch` (nullptr and a message on
+// failure).  The first call on a device resolves it, with that device current.
+double *device_scratch(std::string *err) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { *err = std::string("hipGetDevice: ") + hipGetErrorString(e); return nullptr; }
+    if (dev < 0 || dev >= kMaxDevices) { *err = "device index beyond the supported 64"; return nullptr; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_dev[dev] = (double *)ptr;
+    }
+    return g_scratch_dev[dev];
+}
+
+}  // namespace
+
+extern "C" int lbm_reduce_noalloc(const double *phi_dev, const double *ref_dev, size_t n, double *out_dev,
+                                  void *stream) {
+    using namespace lbm;
+    if (!phi_dev || !out_dev) return api_fail(LBM_E_INVALID, "null argument");
+    if (n > (size_t)LBM_NOALLOC_MAX_NODES)
+        return api_fail(LBM_E_INVALID, "lbm_reduce_noalloc: more than 2^31 - 1 values");
+    std::string err;
+    double *part = device_scratch(&err);
+    if (!part) return api_fail(LBM_E_HIP, err.c_str());
+    // the partial-row count of lbm_reduce_async on a context of n nodes, so
+    // that both add in the same order
+    int parts = (int)std::min<size_t>(kRedParts, (n + kBlock - 1) / kBlock);
+    if (parts < 1) parts = 1;
+    const hipError_t e = launch_reduce(phi_dev, ref_dev, (uint32_t)n, part, parts, out_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return api_fail(LBM_E_HIP, (std::string("reduction: ") + hipGetErrorString(e)).c_str());
+    return LBM_OK;
+}

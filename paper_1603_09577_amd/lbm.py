@@ -34,7 +34,7 @@ EXPORTS = [
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
     "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields", "lbm_set_phi_wall",
     "lbm_set_two_step", "lbm_two_step_shape", "lbm_adjoint_step2", "lbm_adjoint_pair_ok", "lbm_set_remap",
-    "lbm_reduce_async", "lbm_reduce_state",
+    "lbm_reduce_async", "lbm_reduce_state", "lbm_reduce_noalloc",
 ]
 
 
@@ -135,6 +135,7 @@ def load():
         "lbm_adjoint_pair_ok": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "lbm_reduce_async": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
         "lbm_reduce_state": ([_VP, _VP, _VP, _VP], ctypes.c_int),
+        "lbm_reduce_noalloc": ([_VP, _VP, ctypes.c_size_t, _VP, _VP], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -479,6 +480,19 @@ class Lbm:
         _check(self.lib.lbm_adjoint_bytes(self.ctx, ctypes.byref(nb)))
         # psi uses the same plane stride in the compute type
         return nb.value // (8 if self.desc.precision == 0 else 4) // self.q
+
+
+def reduce_noalloc(phi, ref=None, out=None, n=None, stream=None):
+    """The 8 FP64 reductions of Lbm.reduce_async over the first n values of a
+    float64 device tensor (default: all), with no context and no allocation
+    in the library (lbm_reduce_noalloc); `out` (8 float64 values on the
+    device) is allocated here by torch when not given."""
+    import torch
+    if out is None:
+        out = torch.empty(8, dtype=torch.float64, device=phi.device)
+    n = phi.numel() if n is None else int(n)
+    _check(load().lbm_reduce_noalloc(_ptr(phi), _ptr(ref), ctypes.c_size_t(n), _ptr(out), _stream(stream)))
+    return out
 
 
 def probe_copy(src, dst, grid=0, stream=None):
