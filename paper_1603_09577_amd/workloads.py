@@ -16,6 +16,7 @@ __all__ = [
     "spec_linear_gaussian", "spec_nonlinear_2d", "spec_d3q19_aniso",
     "gaussian_hill", "noise_field", "gaussians_3d", "random_spd3",
     "hill_linear_64", "nonlinear_2d", "d3q19_walls", "adjoint_2d", "adjoint_2d_sourcefree", "batch_specs",
+    "burgers_fisher_wave", "spec_burgers_fisher",
 ]
 
 
@@ -98,6 +99,41 @@ def spec_d3q19_aniso(n=(256, 256, 256), K=None, u=(0.03, 0.0, 0.01), phi_wall=0.
         k0=np.asarray(K).tolist(), kpoly=[1.0], rpoly=[],
         precision=precision, phi_ref=phi_ref,
     )
+
+
+def burgers_fisher_wave(y, t, a=4.0, b=1.0, kappa=0.4, delta=1.0, y0=0.0):
+    """Travelling-wave solution of the Burgers-Fisher equation (Sec. 3.2,
+    Eq. 46) reduced to one dimension along y,
+        d_t phi + a phi^delta d_y phi = kappa d_yy phi + b phi (1 - phi^delta),
+    phi = {1/2 + 1/2 tanh[A (y - y0 - omega t)]}^(1/delta) with
+        A = -a delta / (2 kappa (delta + 1)),
+        omega = (a^2 + b kappa (delta + 1)^2) / (a (delta + 1)),
+    obtained by substituting the form of Eq. 47 into the one-dimensional
+    equation (Eq. 48 is the same with x + y, whose diffusivity is 2 kappa; the
+    tests check this form by substitution)."""
+    A = -a * delta / (2.0 * kappa * (delta + 1.0))
+    om = (a * a + b * kappa * (delta + 1.0) ** 2) / (a * (delta + 1.0))
+    return (0.5 + 0.5 * np.tanh(A * (np.asarray(y, dtype=np.float64) - y0 - om * t))) ** (1.0 / delta)
+
+
+def spec_burgers_fisher(n, nx=2, a=4.0, b=1.0, kappa=0.4, length=3.0, klat=0.1, precision="f64",
+                        scheme="A"):
+    """D2Q9 problem of the Burgers-Fisher wave along y (delta = 1): B = (0,
+    a/2 phi^2) (Eq. 49 turned onto y), K = kappa I, D = phi I (Eq. 51),
+    R = b phi (1 - phi) (Eq. 46), anti-bounce-back walls half a link beyond
+    the first and last of n nodes on an axis of `length`, periodic in x (nx
+    nodes; the solution does not depend on x).  Diffusive scaling: the lattice
+    diffusivity is klat on every grid, dx = length / n, dt = klat dx^2 / kappa.
+    Returns (spec in lattice units, dx, dt); the wall values are set from
+    burgers_fisher_wave by the caller, per step."""
+    dx = length / n
+    dt = klat * dx * dx / kappa
+    spec = dict(lattice=9, shape=(nx, n), bc=["periodic", "abb", "periodic"],
+                phi_wall=[[0.0, 0.0], [0.0, 0.0], [0.0, 0.0]], scheme=scheme, d=1.0, s=_rates(9, 1.0),
+                b=[[0.0], [0.0, 0.0, 0.5 * a * dt / dx]], dpoly=[0.0, 1.0], dten=np.eye(3).tolist(),
+                k0=(klat * np.eye(3)).tolist(), kpoly=[1.0], rpoly=[0.0, b * dt, -b * dt],
+                precision=precision, phi_ref=0.5)
+    return spec, dx, dt
 
 
 # ----------------------------------------------------------------------------

@@ -217,6 +217,69 @@ def test_source_moments_eq10_eq30(scheme):
     assert np.abs(c[:, :2].T @ Rk - lam * Bp * R).max() < 1e-15
 
 
+def test_source_previous_level_eq28():
+    """Scheme A (Remark II): the explicit time difference of R_k uses R_k of
+    the previous level with its own Btilde, i.e. (I - A/2) B' at phi(t - 1),
+    A from K(phi(t - 1)) (Eq. 26, 28 with gamma = 0).  A node in equilibrium
+    at phi with history phi_prev receives 3/2 R_k(phi) - 1/2 R_k(phi_prev);
+    its moments (Eq. 10) are checked with Btilde from the diagonal form of
+    Eq. 30a, lambda = (s - 2)/(-2) with s = 1/(3 K(phi) + 1/2) at each level."""
+    k0 = [0.01, 0.04]
+    kpoly = [1.0, 0.6, 0.5]
+    spec = base_spec(k0=np.diag(k0 + [0.0]).tolist(), b=[[0.0, 0.1, 0.3], [0.0, -0.2, 0.1, 0.05]],
+                     rpoly=[0.02, 0.05, -0.03], kpoly=kpoly)
+    p = orc.params_from_spec(spec)
+    c, w, M, Minv = orc.tables(p)
+
+    def moments(x):
+        R = np.polyval(spec["rpoly"][::-1], x)
+        Bp = np.array([np.polyval(np.polyder(np.asarray(spec["b"][a][::-1])), x) for a in range(2)])
+        kx = np.polyval(kpoly[::-1], x)
+        s = np.array([1.0 / (3 * k0[0] * kx + 0.5), 1.0 / (3 * k0[1] * kx + 0.5)])
+        return R, (s - 2) / -2.0 * Bp * R
+
+    for phi, prev in ((0.7, 0.2), (0.3, 0.9), (0.55, 0.55)):
+        fe = orc.feq(p, phi)
+        out, _ = orc.collide(p, fe, prev)
+        d = out - fe
+        (R1, F1), (R0, F0) = moments(phi), moments(prev)
+        assert abs(d.sum() - (1.5 * R1 - 0.5 * R0)) < 1e-15
+        assert np.abs(c[:, :2].T @ d - (1.5 * F1 - 0.5 * F0)).max() < 1e-15
+
+
+@pytest.mark.parametrize("case", ["A-periodic-d2q9", "B-walls-d2q9", "A-walls-d3q19", "remark3"])
+def test_c0_shift_invariance(case):
+    """Reading R3: the integration constant of Eq. 7 does not change phi.  A
+    constant tensor E added to C-bar = C + d cs^2 D shifts every equilibrium by
+    the same zero-sum vector delta_k = w_k E:(c_k c_k - cs^2 I)/(2 cs^4),
+    even in c_k; then f + delta is the solution of the shifted scheme (the
+    collision only sees f - feq, streaming moves a uniform delta onto itself,
+    and an anti-bounce-back wall returns -(f*_k + delta_k) + 2(e+_k + delta_k)
+    = f_kbar + delta_kbar).  Shifting C(0) by E is the same as adding the
+    constant (3/d) E / Dten to D, i.e. changing dpoly[0] with dten fixed:
+    phi must not change, for any rates, nonlinear B, K(phi), sources and walls."""
+    if case == "A-periodic-d2q9":
+        spec = nonlinear_spec(9, (9, 7))
+    elif case == "B-walls-d2q9":
+        spec = nonlinear_spec(9, (9, 7), scheme="B", rpoly=[0.003], bc=["periodic", "abb", "periodic"],
+                              phi_wall=[[0, 0], [0.2, 0.8], [0, 0]])
+    elif case == "A-walls-d3q19":
+        spec = nonlinear_spec(19, (5, 4, 6), bc=["periodic", "periodic", "abb"],
+                              phi_wall=[[0, 0], [0, 0], [0.3, 0.6]])
+    else:
+        spec = nonlinear_spec(9, (9, 7), variant="remark3")
+    rng = np.random.default_rng(5)
+    shape = (6, 4, 5) if spec["lattice"] == 19 else (7, 9)
+    phi0 = 0.5 + 0.1 * rng.uniform(-1, 1, shape)
+    out = []
+    for c0 in (0.1, 0.1 + 0.35, 0.1 - 0.2):
+        sp = dict(spec, dpoly=[c0] + list(spec["dpoly"][1:]))
+        out.append(orc.run(orc.params_from_spec(sp), phi0, 25)[0])
+    assert np.abs(out[0] - phi0).max() > 1e-3
+    for o in out[1:]:
+        assert np.abs(o - out[0]).max() < 1e-14, np.abs(o - out[0]).max()
+
+
 # ---------------------------------------------------------------------------
 # collision special cases
 # ---------------------------------------------------------------------------
@@ -391,13 +454,15 @@ def _gre(num, ana):
     return np.abs(ana - num).sum() / np.abs(ana).sum()
 
 
-def _hill_run(n, K, u, sigma0, T, q=9, rates=1.0, variant="standard", dten=None):
+def _hill_run(n, K, u, sigma0, T, q=9, rates=1.0, variant="standard", dten=None, s_over=None):
     dim = 2 if q == 9 else 3
     shape = (n,) * dim
     k0 = np.zeros((3, 3))
     k0[:dim, :dim] = K
     bl = [[0.0, u[a]] for a in range(dim)]
     s = [0.0] + [rates] * (q - 1)
+    for i, v in (s_over or {}).items():
+        s[i] = v
     spec = dict(lattice=q, shape=shape, bc=["periodic"] * 3, scheme="A", d=1.0, s=s, b=bl,
                 dpoly=[0, 1], dten=(np.eye(3) if dten is None else dten).tolist(), k0=k0.tolist(),
                 kpoly=[1.0], rpoly=[], variant=variant)
@@ -420,6 +485,24 @@ def test_gaussian_hill_c1_accuracy_and_order():
         gres.append(_hill_run(32 * r, K, (0.05 / r, 0.02 / r), 3.0 * r, 125 * r * r))
     order = [math.log2(gres[i] / gres[i + 1]) for i in range(2)]
     assert gres[-1] < 2e-3
+    assert all(1.8 < o < 2.2 for o in order), (gres, order)
+
+
+def test_gaussian_hill_c1_own_rates():
+    """The linear Gaussian-hill workload as stated (64 x 64, s1 = s2 = 1.2,
+    u = (0.05, 0.02), kappa = 0.01, 1000 steps) against Eq. 60 summed over
+    periodic images, and second order under diffusive refinement with those
+    rates (Sec. 3.4 Fig. 11 slope 2)."""
+    spec, phi0, T = W.hill_linear_64()
+    p = orc.params_from_spec(spec)
+    phiT, _ = orc.run(p, phi0, T)
+    ana = _gaussian_closed_form((64, 64), (32.0, 32.0), (0.05, 0.02), 0.01 * np.eye(2), 6.0, float(T)).T
+    gre = _gre(phiT, ana)
+    assert gre < 1e-2, gre          # 5.7e-3: the hill travels (50, 20) nodes over the run
+    K = 0.01 * np.eye(2)
+    gres = [_hill_run(32 * r, K, (0.05 / r, 0.02 / r), 3.0 * r, 125 * r * r, s_over={1: 1.2, 2: 1.2})
+            for r in (1, 2, 4)]
+    order = [math.log2(gres[i] / gres[i + 1]) for i in range(2)]
     assert all(1.8 < o < 2.2 for o in order), (gres, order)
 
 
