@@ -63,9 +63,11 @@ extern "C" {
                                  of the source, needs phi of the last step   */
 #define LBM_SCHEME_B 1        /* Remark II, gamma = 1: Btilde = B', stored
                                  fbar = f - R_k/2 (Eq. 33), Eq. 34, phi from
-                                 Eq. 35; R must not depend on phi (constant
-                                 rpoly[0] plus an optional field, see
-                                 lbm_set_fields)                              */
+                                 Eq. 35.  R = rpoly(phi) of degree <= 2 plus
+                                 an optional field (lbm_set_fields); when R
+                                 depends on phi, Eq. 35 is a quadratic in phi
+                                 solved in closed form at every node (the
+                                 root that tends to sum fbar + R/2 as R -> 0) */
 
 #define LBM_FLAG_MOMENT_PATH 1 /* always use the moment-space collision even
                                   when all non-flux rates are equal          */
@@ -125,7 +127,7 @@ typedef struct lbm_ctx lbm_ctx;
  * (LBM_E_INVALID): unknown lattice, sizes < 1 or more than 2^31 nodes,
  * d <= 0, a used rate outside (0, 2), k0 not symmetric positive definite,
  * dten not symmetric.  LBM_E_UNSUPPORTED: walls on an axis other than the
- * last, Scheme B with a source.  Allocates the context's coefficient table and
+ * last, Scheme B with rpoly of degree > 2.  Allocates the context's coefficient table and
  * its fixed scratch (about 3.1 MiB, independent of the grid) on the current
  * device, nothing that scales with the grid.  *out is set only on success. */
 int lbm_create(const lbm_desc *desc, lbm_ctx **out);
@@ -283,8 +285,8 @@ int lbm_set_phi_wall(lbm_ctx *ctx, double phi_lo, double phi_hi, void *stream);
  *    tensor of Sec. 3.5).  Each K0(x) must be symmetric positive definite; it
  *    is not checked (a non-finite phi shows in lbm_set_check).
  *  - r_field: FP64 [nz][ny][nx], an external source added to R: R(x, t) =
- *    rpoly[0] + r_field(x) (Eq. 1; Scheme B only, where Eq. 35 is then
- *    explicit).  Its contents are R at the current time: a sweep from t to
+ *    rpoly(phi) + r_field(x) (Eq. 1; Scheme B only).  Its contents are R at
+ *    the current time: a sweep from t to
  *    t + 1 reads R(x, t), and lbm_get_phi reads it as R(x, t) of the state it
  *    converts, so a time-dependent source is rewritten between steps (on the
  *    same stream).

@@ -257,8 +257,6 @@ int orc_check(const orc_params *p)
     if (p->q == 9 && p->bc[2] != 0) return -1;
     if (p->scheme != 0 && p->scheme != 1) return -1;
     if (p->variant != 0 && p->variant != 1) return -1;
-    if (p->scheme == 1)
-        for (int i = 1; i < ORC_MAXP; ++i) if (p->rpoly[i] != 0.0) return -2; /* Eq. 35 implicit */
     return 0;
 }
 
@@ -425,7 +423,7 @@ void orc_phi(const orc_params *p, const double *f, const double *rext, double *p
     for (long n = 0; n < N; ++n) {
         double s = 0.0;
         for (int k = 0; k < p->q; ++k) s += f[(long)k * N + n];
-        if (p->scheme == 1) s += 0.5 * (p->rpoly[0] + (rext ? rext[n] : 0.0));
+        if (p->scheme == 1) s = phi_scheme_b_r(p, s, rext ? rext[n] : 0.0);   /* Eq. 35 */
         phi[n] = s;
     }
 }

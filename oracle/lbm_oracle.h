@@ -78,7 +78,8 @@ int orc_step(const orc_params *p, double *f, double *pprev,
              const double *rext, const double *rext_prev, const double *kfield,
              int nthreads);
 
-/* Macroscopic phi (Eq. 10a; Scheme B: Eq. 35 with R explicit). */
+/* Macroscopic phi (Eq. 10a; Scheme B: Eq. 35, solved by Newton's method
+ * when R depends on phi). */
 void orc_phi(const orc_params *p, const double *f, const double *rext, double *phi);
 
 /* Reverse step of the discrete adjoint, from complex-step local Jacobians.

@@ -274,10 +274,10 @@ int validate(const lbm_desc *d, Dims &dm) {
     }
     if (!(d->kpoly[0] > 0.0)) return fail(LBM_E_INVALID, "kpoly[0] must be positive (K(0) positive definite)");
     if (d->scheme == LBM_SCHEME_B)
-        for (int p = 1; p < LBM_MAXP; ++p)
+        for (int p = 3; p < LBM_MAXP; ++p)
             if (d->rpoly[p] != 0.0)
                 return fail(LBM_E_UNSUPPORTED,
-                            "Scheme B with R depending on phi (Eq. 35 implicit) is not built on the GPU");
+                            "Scheme B solves Eq. 35 in closed form for R of degree <= 2 in phi");
     {
         int nb = 0;
         for (int a = 0; a < dim; ++a) nb = std::max(nb, top_count(d->b[a], LBM_MAXP));

@@ -355,11 +355,38 @@ __device__ __forceinline__ void gather_rw(const Geom &g, const Coefs<TC> *__rest
     }
 }
 
+// Scheme B, Eq. 35: phi = sum_k fbar_k + R(phi) / 2, for x = phi - phi_ref
+// given x0 = sum_k fbar_k - phi_ref (the sum of the stored offsets) and the
+// external source rext at the node.  R = r0 + r1 phi + r2 phi^2 + rext (the
+// host admits degree <= 2 in Scheme B).  A source that does not depend on phi
+// makes Eq. 35 explicit: x = x0 + R / 2.  Otherwise, expanded about phi_ref,
+// Eq. 35 is the quadratic  a x^2 + b x + c = 0  with a = r2 / 2,
+// b = R'(phi_ref) / 2 - 1, c = x0 + R(phi_ref) / 2, and the root that tends to
+// x0 + R / 2 as R -> 0 is x = 2 c / (sqrt(b^2 - 4 a c) - b): with b close to
+// -1 the denominator is close to 2, so no digits cancel.  Returns x and sets
+// *R = R(phi_ref + x).
+template <typename T, typename TC>
+__device__ __forceinline__ T phi_scheme_b(const Coefs<TC> *__restrict__ cf, T x0, T rext, T *R) {
+    if (cf->nr <= 1) {
+        *R = (T)cf->r[0] + rext;
+        return x0 + T(0.5) * *R;
+    }
+    const T pr = (T)cf->phi_ref, r0 = (T)cf->r[0] + rext, r1 = (T)cf->r[1], r2 = (T)cf->r[2];
+    const T a = T(0.5) * r2;
+    const T b = T(0.5) * (r1 + T(2) * r2 * pr) - T(1);
+    const T c = x0 + T(0.5) * (r0 + pr * (r1 + pr * r2));
+    const T x = T(2) * c / (sqrt(b * b - T(4) * a * c) - b);
+    const T phi = pr + x;
+    *R = r0 + phi * (r1 + phi * r2);
+    return x;
+}
+
 // One node of the sweep (shared by the single-instance and batched kernels).
 //
 // SB: Scheme B (Eq. 33-35): the stored variable is fbar = f - R_k / 2, phi =
-// sum fbar + R / 2 with R = R0 + an external field R(x, t) (explicit in phi),
-// Btilde = B', and the source enters as M^-1 (I - S/2) M R_k (Eq. 34).  SRC
+// sum fbar + R / 2 with R = R(phi) + an external field R(x, t) (Eq. 35,
+// solved by phi_scheme_b), Btilde = B', and the source enters as
+// M^-1 (I - S/2) M R_k (Eq. 34).  SRC
 // then stays false (it is the Scheme-A source with its phi history).
 // KF: K0 per node from `kfield` (A per node by Eq. 26).
 // rem3 (uniform across a launch): Remark III, Eq. 36-38.  The equilibrium has
@@ -378,13 +405,12 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
     TC g0n[6];
     const bool kfon = KF && kfield != nullptr;   // uniform across the launch
     if (kfon) g0_of_field<D>(cf, kfield, n, g0n);
-    // Scheme B: R at this node and time (explicit in phi), Eq. 35
-    const TC Rx = SB ? cf->r[0] + (rfield ? (TC)rfield[n] : TC(0)) : TC(0);
-
     TC phio = TC(0);
 #pragma unroll
     for (int k = 0; k < Q; ++k) phio += h[k];
-    if (SB) phio += TC(0.5) * Rx;
+    // Scheme B: phi from Eq. 35 and R at this node and time
+    TC Rx = TC(0);
+    if (SB) phio = phi_scheme_b<TC>(cf, phio, rfield ? (TC)rfield[n] : TC(0), &Rx);
     const TC phi = cf->phi_ref + phio;
 
     TC A[6];
@@ -914,7 +940,7 @@ k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict_
             const TC ph = (TC)phi0[n];
             TC e = feq_one<Q, NP>(cf, ph, L::opp(k));
             // Scheme B stores fbar = feq - R_k / 2 (Eq. 33)
-            if (SB) e -= half_source_one<Q, NP>(cf, ph, cf->r[0] + (rfield ? (TC)rfield[n] : TC(0)), L::opp(k));
+            if (SB) e -= half_source_one<Q, NP>(cf, ph, poly<NP>(cf->r, ph) + (rfield ? (TC)rfield[n] : TC(0)), L::opp(k));
             v = cf->ew[cl == 1 ? 1 : 0][k] - e;
         } else {
             int off = 0;
@@ -926,7 +952,7 @@ k_init(const Geom g, const Coefs<TC> *__restrict__ cf, const double *__restrict_
             const uint32_t src = (uint32_t)((int)n + off);
             const TC ph = (TC)phi0[src];
             v = feq_one<Q, NP>(cf, ph, k);
-            if (SB) v -= half_source_one<Q, NP>(cf, ph, cf->r[0] + (rfield ? (TC)rfield[src] : TC(0)), k);
+            if (SB) v -= half_source_one<Q, NP>(cf, ph, poly<NP>(cf->r, ph) + (rfield ? (TC)rfield[src] : TC(0)), k);
         }
         store_s(f + (uint64_t)k * g.plane + n, v);
     }
@@ -944,7 +970,10 @@ __device__ __forceinline__ double phi_at(const Geom &g, const Coefs<TC> *__restr
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k) acc += (double)h[k];
-    if (SB) acc += 0.5 * ((double)cf->r[0] + (rfield ? rfield[n] : 0.0));
+    if (SB) {
+        double R;
+        acc = phi_scheme_b<double>(cf, acc, rfield ? rfield[n] : 0.0, &R);
+    }
     return (double)cf->phi_ref + acc;
 }
 

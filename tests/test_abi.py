@@ -87,8 +87,9 @@ def test_unsupported_combinations(L):
     assert _create(L, sp)[0] == lbm.LBM_E_UNSUPPORTED
     sp = dict(spec)
     sp["scheme"] = "B"
-    assert _create(L, sp)[0] == lbm.LBM_E_UNSUPPORTED        # Scheme B with R(phi): Eq. 35 implicit
-    for rp in ([], [1e-3]):                                     # no source, constant source
+    sp["rpoly"] = [0.0, 0.1, 0.0, -0.1]
+    assert _create(L, sp)[0] == lbm.LBM_E_UNSUPPORTED        # Scheme B: Eq. 35 in closed form up to degree 2
+    for rp in ([], [1e-3], [0.0, 0.1, -0.1]):                   # no source, constant, quadratic R(phi)
         sp["rpoly"] = rp
         rc, msg = _create(L, sp)
         assert rc in (lbm.LBM_OK, lbm.LBM_E_HIP), msg           # valid; needs a GPU

@@ -1,12 +1,14 @@
 """Scheme B (Eq. 33-35) and per-node fields on the GPU, against the oracle.
 
 Scheme B stores fbar = f - R_k / 2, evolves it by Eq. 34 with Btilde = B'
-and recovers phi by Eq. 35; R may be a constant plus an external field
-R(x, t) (explicit in phi).  A per-node K0(x) field gives A per node by Eq. 26
+and recovers phi by Eq. 35; R may be a polynomial of degree <= 2 in phi
+(Eq. 35 then implicit, solved in closed form on the GPU and by Newton's
+method in the oracle) plus an external field R(x, t).  A per-node K0(x) field gives A per node by Eq. 26
 (Sec. 3.5).  Cases: equal-rate and moment-space collisions, walls, D3Q19, the
 time-dependent source of Sec. 3.1 (rewritten on the device between steps),
 the variable diffusion tensor of Sec. 3.5, and reduced-precision storage.
-    FP64 <= 1e-12 relative L2 against the oracle, FP32 <= 1e-5.
+    FP64 <= 1e-12 against the oracle, FP32 <= 1e-5 (relative L2 and
+    max |d| / max |phi|).
 """
 import math
 import sys
@@ -78,8 +80,11 @@ def compare(name, spec, phi0, snapshots, tol, **kw):
     got = gpu_run(spec, phi0, snapshots, flags=flags, **kw)
     ref = oracle_snaps(spec, phi0, snapshots, **kw)
     errs = {s: rel(got[s], ref[s]) for s in snapshots}
-    say("    " + "  ".join(f"{s}: {e:.2e}" for s, e in errs.items()))
+    pts = {s: float(np.abs(got[s] - ref[s]).max() / np.abs(ref[s]).max()) for s in snapshots}
+    say("    rel L2 " + "  ".join(f"{s}: {e:.2e}" for s, e in errs.items()))
+    say("    max |d| / max |phi| " + "  ".join(f"{s}: {e:.2e}" for s, e in pts.items()))
     assert max(errs.values()) <= tol, errs
+    assert max(pts.values()) <= tol, pts
 
 
 def _nonlinear_b(nx, ny, precision="f64"):
@@ -119,6 +124,53 @@ def test_scheme_b_d3q19_walls_source_field_kfield():
     rfield = 1e-4 * rng.uniform(-1, 1, n[::-1])
     compare("d3q19 walls, K0 field, source field", spec, phi0, (1, 5, 40), 1e-12, kfield=kf,
             source=lambda t: rfield)
+
+
+# ---------------------------------------------------------------------------
+# Scheme B with R depending on phi (Eq. 35 solved at every node)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("flags,prec,tol", [(0, "f64", 1e-12), (1, "f64", 1e-12), (0, "f32", 1e-5),
+                                            (1, "f32", 1e-5)])
+def test_scheme_b_implicit_source_nonlinear(flags, prec, tol):
+    """The nonlinear 2-D workload's physics (B = 0.5 phi^2 (1, 1), K = K0 (1 +
+    phi^2), R = 0.1 phi (1 - phi) in its grid units) in Scheme B: the closed-
+    form root of Eq. 35 on the GPU against the oracle's Newton solve;
+    equal-rate (flags 0) and moment-space (flags 1) collisions."""
+    spec = W.spec_nonlinear_2d(37, 29, precision=prec)
+    spec["scheme"] = "B"
+    compare(f"implicit R(phi) flags={flags}", spec, W.noise_field((29, 37), 34), (1, 7, 60, 300), tol,
+            flags=flags)
+
+
+def test_scheme_b_implicit_walls_field_d2q9():
+    """R(phi) plus an external field, walls with unequal rates."""
+    spec = W.spec_nonlinear_2d(23, 31)
+    spec.update(scheme="B", bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.65], [0, 0]],
+                s=[0.0, 1.3, 1.1, 1.0, 1.4, 1.0, 0.9, 1.2, 1.05], rpoly=[1e-4, 2e-3, -3e-3])
+    rng = np.random.default_rng(35)
+    rfield = 1e-4 * rng.uniform(-1, 1, (31, 23))
+    compare("implicit R(phi) + field, walls", spec, W.noise_field((31, 23), 36), (1, 9, 120), 1e-12,
+            source=lambda t: rfield)
+
+
+def test_scheme_b_implicit_d3q19():
+    n = (13, 11, 15)
+    spec = W.spec_d3q19_aniso(n, phi_wall=0.2)
+    spec.update(scheme="B", rpoly=[0.0, 0.01, -0.01], phi_ref=0.3)
+    spec["s"] = [0.0] + [1.0 + 0.04 * i for i in range(18)]
+    compare("d3q19 implicit R(phi), unequal rates", spec, W.gaussians_3d(n, 8), (1, 5, 40), 1e-12)
+    spec32 = dict(spec, precision="f32", s=[0.0] + [1.0] * 18)
+    compare("d3q19 implicit R(phi) f32", spec32, W.gaussians_3d(n, 8), (1, 40), 1e-5)
+
+
+def test_scheme_b_implicit_full_size():
+    """The 1024 x 1024 nonlinear workload in Scheme B, a few steps at full size."""
+    spec, phi0, _ = W.nonlinear_2d(1024)
+    spec["scheme"] = "B"
+    compare("nonlinear2d-1024 scheme B", spec, phi0, (1, 4), 1e-12)
+    spec32 = dict(spec, precision="f32")
+    compare("nonlinear2d-1024 scheme B f32", spec32, phi0, (4,), 1e-5)
 
 
 def _channel_spec(N, s1, s3, ux, precision="f64"):
@@ -265,9 +317,16 @@ def test_refusals():
     with pytest.raises(lbm.LbmError) as ei:
         sim.adjoint_seed(torch.ones(sim.shape, dtype=torch.float64, device="cuda"), psi, pi)
     assert ei.value.code == lbm.LBM_E_UNSUPPORTED
-    # Scheme B with R depending on phi stays unsupported (Eq. 35 implicit)
+    # Scheme B solves Eq. 35 in closed form for R of degree <= 2 only
     spec_b = _nonlinear_b(16, 12)
-    spec_b["rpoly"] = [0.0, 1e-3]
+    spec_b["rpoly"] = [0.0, 1e-3, 0.0, -1e-3]
     with pytest.raises(lbm.LbmError) as ei:
         lbm.Lbm(spec_b)
+    assert ei.value.code == lbm.LBM_E_UNSUPPORTED
+    # and the adjoint refuses Scheme B sources, also R(phi)
+    spec_b["rpoly"] = [0.0, 1e-3, -1e-3]
+    sim = lbm.Lbm(spec_b).init(W.noise_field((12, 16), 38))
+    psi, pi = sim.adjoint_buffers()
+    with pytest.raises(lbm.LbmError) as ei:
+        sim.adjoint_seed(torch.ones(sim.shape, dtype=torch.float64, device="cuda"), psi, pi)
     assert ei.value.code == lbm.LBM_E_UNSUPPORTED

@@ -90,3 +90,17 @@ def test_burgers_fisher_second_order(kappa, ns):
     print(f"Burgers-Fisher kappa={kappa}: GRE {gres}, orders {order}")
     assert gres[-1] < 2e-3
     assert all(1.7 <= o <= 2.3 for o in order), (gres, order)
+
+
+def test_burgers_fisher_scheme_b_second_order():
+    """The paper's default scheme on the same wave: Scheme B, whose Eq. 35 is
+    implicit for R = b phi (1 - phi) (solved by the oracle's Newton step).
+    Second order, and close to the Scheme-A errors."""
+    gres = []
+    for n in (48, 96, 192):
+        ph, ex, _ = run_wave(n, 0.4, 0.5, scheme="B")
+        gres.append(gre(ph, ex))
+    order = [math.log2(gres[i] / gres[i + 1]) for i in range(2)]
+    print(f"Burgers-Fisher Scheme B: GRE {gres}, orders {order}")
+    assert gres[-1] < 2e-3
+    assert all(1.7 <= o <= 2.3 for o in order), (gres, order)

@@ -789,3 +789,64 @@ def test_remark3_second_order():
     gres = [_hill_run(32 * r, K, (0.04 / r, -0.03 / r), 3.0 * r, 100 * r * r, variant="remark3") for r in (1, 2, 4)]
     order = [math.log2(gres[i] / gres[i + 1]) for i in range(2)]
     assert all(1.7 < o < 2.3 for o in order), (gres, order)
+
+
+# ---------------------------------------------------------------------------
+# Scheme B with a source that depends on phi (Eq. 35 implicit)
+# ---------------------------------------------------------------------------
+
+def test_scheme_b_implicit_uniform_field_is_trapezoidal():
+    """Remark II, Scheme B with R(phi): on a uniform field streaming changes
+    nothing, sum fbar grows by R(phi(t)) each step (Eq. 34: the relaxation
+    leaves the density row, (I - S/2) adds R with s0 = 0) and Eq. 35 gives
+    phi = sum fbar + R(phi)/2, so phi follows the implicit trapezoidal rule
+    phi' = phi + (R(phi) + R(phi'))/2.  Each step of the rule is solved here
+    by bracketing (scipy's brentq), independently of the oracle's Newton
+    solve; both the logistic source and a cubic one, with s0 = 0 and 0.8."""
+    from scipy.optimize import brentq
+    for rpoly, phi in (([0.0, 0.1, -0.1], 0.2), ([0.01, 0.05, 0.02, -0.04], 0.7)):
+        for s0 in (0.0, 0.8):
+            spec = nonlinear_spec(9, (3, 3), scheme="B", rpoly=rpoly)
+            spec["s"][0] = s0
+            p = orc.params_from_spec(spec)
+            R = lambda x: np.polyval(rpoly[::-1], x)
+            f, pp = orc.init(p, np.full((3, 3), phi))
+            assert np.abs(orc.phi(p, f) - phi).max() < 1e-15       # Eq. 33/35 at t = 0
+            for _ in range(50):
+                orc.step(p, f, pp)
+                phi = brentq(lambda y: y - phi - 0.5 * (R(phi) + R(y)), phi - 1.0, phi + 1.0, xtol=1e-17,
+                             rtol=8.9e-16)
+                got = orc.phi(p, f)
+                assert np.abs(got - phi).max() < 2e-15, (rpoly, s0, got.max(), phi)
+
+
+def test_scheme_b_implicit_mass_balance():
+    """Periodic grid, Scheme B with R(phi) and nonlinear B, K: summing Eq. 34
+    over directions and nodes, sum_x [phi(t+1) - R(phi(t+1))/2] =
+    sum_x [phi(t) + R(phi(t))/2]."""
+    spec = nonlinear_spec(9, (10, 8), scheme="B", rpoly=[0.002, 0.03, -0.05])
+    p = orc.params_from_spec(spec)
+    rng = np.random.default_rng(8)
+    phi0 = 0.5 + 0.1 * rng.uniform(-1, 1, (8, 10))
+    R = lambda x: np.polyval(spec["rpoly"][::-1], x)
+    f, pp = orc.init(p, phi0)
+    cur = phi0
+    for _ in range(20):
+        orc.step(p, f, pp)
+        nxt = orc.phi(p, f)
+        lhs, rhs = (nxt - 0.5 * R(nxt)).sum(), (cur + 0.5 * R(cur)).sum()
+        assert abs(lhs - rhs) < 1e-13 * abs(rhs)
+        cur = nxt
+
+
+def test_scheme_b_explicit_case_unchanged():
+    """A source that does not depend on phi takes one Newton step, which is
+    the explicit Eq. 35 exactly: phi = sum fbar + R/2."""
+    spec = nonlinear_spec(9, (6, 5), scheme="B", rpoly=[0.004])
+    p = orc.params_from_spec(spec)
+    rng = np.random.default_rng(9)
+    f, pp = orc.init(p, 0.5 + 0.1 * rng.uniform(-1, 1, (5, 6)))
+    for _ in range(7):
+        orc.step(p, f, pp)
+    want = f.reshape(9, -1).sum(axis=0) + 0.002
+    assert np.array_equal(orc.phi(p, f).reshape(-1), want)
