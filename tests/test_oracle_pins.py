@@ -850,3 +850,36 @@ def test_scheme_b_explicit_case_unchanged():
         orc.step(p, f, pp)
     want = f.reshape(9, -1).sum(axis=0) + 0.002
     assert np.array_equal(orc.phi(p, f).reshape(-1), want)
+
+
+# ---------------------------------------------------------------------------
+# reading R32: the nonlinear 2-D workload read in lattice units diverges
+# ---------------------------------------------------------------------------
+
+def _nonlinear_in_units(dx, dt, n=64):
+    spec = W.spec_nonlinear_2d(n, n, dx=dx, dt=dt)
+    return spec, W.noise_field((n, n), 2)
+
+
+def test_nonlinear_workload_lattice_units_diverge():
+    """With dx = dt = 1 the stated coefficients (|B'| up to about 1 against
+    K0 of 0.01-0.02) put the grid Peclet number near 150 and the scheme is
+    linearly unstable: the oracle's phi turns non-finite within 200 steps on
+    64 x 64.  With the grid units the workloads use (dx = 1/32, dt = dx / 10)
+    the same 200 steps stay bounded, with phi rising under the logistic
+    source."""
+    spec, phi0 = _nonlinear_in_units(1.0, 1.0)
+    p = orc.params_from_spec(spec)
+    f, pp = orc.init(p, phi0)
+    bad = None
+    for t in range(200):
+        orc.step(p, f, pp)
+        ph = orc.phi(p, f)
+        if not np.isfinite(ph).all() or np.abs(ph).max() > 1e6:
+            bad = t + 1
+            break
+    print(f"lattice units: phi non-finite or beyond 1e6 at step {bad}")
+    assert bad is not None and bad < 200
+    spec, phi0 = _nonlinear_in_units(W.NONLINEAR_DX, W.NONLINEAR_DT)
+    ph, _ = orc.run(orc.params_from_spec(spec), phi0, 200)
+    assert np.isfinite(ph).all() and 0.4 < ph.min() and ph.max() < 0.7 and ph.mean() > phi0.mean()
