@@ -344,17 +344,32 @@ Dims eff_dims(const lbm_ctx *c) {
 
 bool remark3(const lbm_ctx *c) { return (c->desc.flags & LBM_FLAG_REMARK3) != 0; }
 
-bool general_path(const lbm_ctx *c) { return c->kfield || eff_dims(c).sb || remark3(c); }
+// The sweep needs the general kernel: per-node fields, Remark III, or Scheme B
+// with a source outside the 3-term equal-rate kernels.
+bool general_path(const lbm_ctx *c) {
+    if (c->kfield || c->rfield || remark3(c)) return true;
+    return eff_dims(c).sb && !(c->dm.eqr && c->dm.deg3 && c->dm.o32);
+}
 
-// Two-step passes can run: the run qualifies and, when it keeps a phi history
-// (a Scheme-A source), the caller bound the second history buffer.
-bool two_ready(const lbm_ctx *c) { return c->two_ok && (!c->dm.src || c->p2 != nullptr); }
+// The sweep reads and writes the phi history: a Scheme-A source (Remark III
+// takes the general kernel and never runs two-step passes).
+bool keeps_history(const lbm_ctx *c) { return c->dm.src && !c->dm.sb; }
+
+// Calls the adjoint does not cover: Scheme B sources, fields, Remark III.
+bool adjoint_refused(const lbm_ctx *c) { return eff_dims(c).sb || c->kfield || c->rfield || remark3(c); }
+
+// Two-step passes can run: the run qualifies (Scheme B sources with 3-term
+// polynomials) and, when it keeps a phi history, the caller bound the second
+// history buffer.
+bool two_ready(const lbm_ctx *c) {
+    return c->two_ok && (!eff_dims(c).sb || c->dm.deg3) && (!keeps_history(c) || c->p2 != nullptr);
+}
 
 bool two_active(const lbm_ctx *c) { return c->two && two_ready(c) && !general_path(c) && c->check_every == 0; }
 
 // Bytes of the second history buffer (0 when two-step passes never read one).
 size_t hist2_bytes(const lbm_ctx *c) {
-    return (c->two_ok && c->dm.src) ? round256((size_t)c->g.N * hist_size(c->dm.prec)) : 0;
+    return (c->two_ok && keeps_history(c)) ? round256((size_t)c->g.N * hist_size(c->dm.prec)) : 0;
 }
 
 // Four steps as two passes of two steps each: f[start] -> f[start ^ 1] with the
@@ -362,11 +377,12 @@ size_t hist2_bytes(const lbm_ctx *c) {
 // would leave them.
 // Without a source the kernels touch no history, and p stands in for p2.
 hipError_t sweep_pair(lbm_ctx *c, int start, hipStream_t st) {
-    void *p2 = c->dm.src ? c->p2 : c->p;
-    hipError_t e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, p2, c->d_flag,
+    void *p2 = keeps_history(c) ? c->p2 : c->p;
+    const Dims d = eff_dims(c);
+    hipError_t e = launch_sweep2_q9(d, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, p2, c->d_flag,
                                     c->two_shape, st);
     if (e == hipSuccess)
-        e = launch_sweep2_q9(c->dm, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], p2, c->p, c->d_flag,
+        e = launch_sweep2_q9(d, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], p2, c->p, c->d_flag,
                              c->two_shape, st);
     return e;
 }
@@ -378,8 +394,8 @@ hipError_t sweep(lbm_ctx *c, const void *fin, void *fout, void *p, hipStream_t s
                                                   remark3(c), st)
                             : launch_sweep_gen_q19(d, c->g, c->d_coefs, fin, fout, p, c->d_flag, c->kfield, c->rfield,
                                                    remark3(c), st);
-    return c->dm.q == 9 ? launch_sweep_q9(c->dm, c->g, c->d_coefs, fin, fout, p, c->d_flag, st)
-                        : launch_sweep_q19(c->dm, c->g, c->d_coefs, fin, fout, p, c->d_flag, st);
+    return c->dm.q == 9 ? launch_sweep_q9(d, c->g, c->d_coefs, fin, fout, p, c->d_flag, st)
+                        : launch_sweep_q19(d, c->g, c->d_coefs, fin, fout, p, c->d_flag, st);
 }
 
 void drop_graphs(lbm_ctx *c) {
@@ -671,7 +687,9 @@ int lbm_set_two_step(lbm_ctx *c, int mode) {
     if (mode < 0) return fail(LBM_E_INVALID, "mode must be 0 (off) or 1 + a tile shape");
     if (mode && !c->two_ok)
         return fail(LBM_E_UNSUPPORTED, "two steps per pass need D2Q9, periodic axes and equal non-flux rates");
-    if (mode && c->bound && !two_ready(c))
+    if (mode && eff_dims(c).sb && !c->dm.deg3)
+        return fail(LBM_E_UNSUPPORTED, "two steps per pass with a Scheme-B source need polynomials of degree <= 2");
+    if (mode && c->bound && keeps_history(c) && !c->p2)
         return fail(LBM_E_STATE, "two steps per pass with a source need the second history buffer (lbm_init p2)");
     const int shape = mode > 0 ? mode - 1 : 0;
     if (mode && !two_shape_usable(c, shape))
@@ -819,7 +837,7 @@ int lbm_reduce_state(lbm_ctx *c, const double *ref, double *out_dev, void *strea
 int lbm_adjoint_seed(lbm_ctx *c, const double *gphi, void *psi, double *pi, void *stream) {
     if (!c || !gphi || !psi || !pi) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
-    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
+    if (adjoint_refused(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipStream_t st = (hipStream_t)stream;
@@ -837,7 +855,7 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
         return fail(LBM_E_INVALID, "null argument");
     if (psi_next == psi_out) return fail(LBM_E_INVALID, "psi_next and psi_out must differ");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
-    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
+    if (adjoint_refused(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     if (c->adj_slots > (uint32_t)kMaxAdjParts) return fail(LBM_E_UNSUPPORTED, "grid too large for the adjoint partials");
@@ -857,7 +875,7 @@ static bool adjoint_pair_applies(const lbm_ctx *c) {
 
 int lbm_adjoint_pair_ok(const lbm_ctx *c, int *ok) {
     if (!c || !ok) return fail(LBM_E_INVALID, "null argument");
-    *ok = adjoint_pair_applies(c) && !general_path(c) ? 1 : 0;
+    *ok = adjoint_pair_applies(c) && !adjoint_refused(c) ? 1 : 0;
     return LBM_OK;
 }
 
@@ -869,7 +887,7 @@ int lbm_adjoint_step2(lbm_ctx *c, const void *f_s, const void *p_s, const void *
     if ((const void *)pi_next == (const void *)pi_out)
         return fail(LBM_E_INVALID, "pi_next and pi_out must differ for two sweeps per launch");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
-    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
+    if (adjoint_refused(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     if (!adjoint_pair_applies(c))
@@ -885,7 +903,7 @@ int lbm_adjoint_init(lbm_ctx *c, const double *phi0, const void *psi0, const dou
                      void *stream) {
     if (!c || !phi0 || !psi0 || !pi0 || !gphi0) return fail(LBM_E_INVALID, "null argument");
     if (c->dm.prec == 2) return fail(LBM_E_UNSUPPORTED, "no adjoint for FP16 storage");
-    if (general_path(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
+    if (adjoint_refused(c)) return fail(LBM_E_UNSUPPORTED, "no adjoint for Scheme B sources, per-node fields or Remark III");
     if (c->recentered)
         return fail(LBM_E_STATE, "offsets were re-centred during the forward run; the adjoint needs a fixed phi_ref");
     hipError_t e = c->dm.q == 9

@@ -17,10 +17,28 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
     auto *fo = (TS *)fout;
     auto *pp = (TP *)p;
     const dim3 grid((g.nblocks + g.chunk - 1) / g.chunk), block(kBlock);
+    // Scheme B with a source (dm.sb) keeps no history: the Scheme-A flag is off
+    const bool sa = dm.src && !dm.sb;
     // every polynomial of degree <= 2: 3-term kernels (32-bit offsets)
     {
         if (dm.eqr && dm.deg3 && dm.o32) {
-            const int c3 = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) | (dm.nt ? 8 : 0);
+            if (dm.sb) {
+                // Scheme B with R(phi): 3-term kernels only (no row-wave variant)
+                const int cb = (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) | (dm.nt ? 8 : 0);
+#define LBM_SWEEP3B(K, W, NT)                                                                         \
+    case (NT * 8 + K * 2 + W):                                                                        \
+        hipLaunchKernelGGL((k_sweep<Q, TS, TC, true, false, K, W, 3, NT, true, false, true>), grid, block, 0, st, g, \
+                           cf, fi, fo, pp, flag);                                                     \
+        break;
+                switch (cb) {
+                    LBM_SWEEP3B(0, 0, 0) LBM_SWEEP3B(0, 1, 0) LBM_SWEEP3B(1, 0, 0) LBM_SWEEP3B(1, 1, 0)
+                    LBM_SWEEP3B(0, 0, 1) LBM_SWEEP3B(0, 1, 1) LBM_SWEEP3B(1, 0, 1) LBM_SWEEP3B(1, 1, 1)
+                    default: return hipErrorInvalidValue;
+                }
+#undef LBM_SWEEP3B
+                return hipGetLastError();
+            }
+            const int c3 = (sa ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) | (dm.nt ? 8 : 0);
             if constexpr (Q == 9) {
                 if (dm.wall && g.nx % 64 == 0) {
                     // every wave within one row: the row-wave gathers (k_sweep
@@ -55,6 +73,8 @@ hipError_t sweep_typed(const Dims &dm, const Geom &g, const void *coefs, const v
             return hipGetLastError();
         }
     }
+    // Scheme B sources elsewhere run k_sweep_gen (the host routes them there)
+    if (dm.sb) return hipErrorInvalidValue;
     // short polynomials (all degrees <= 3) get the branch-free 4-term kernels
     // non-temporal accesses: equal-rate short-polynomial kernels only
     const int code = (dm.eqr ? 8 : 0) | (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0) |
@@ -102,6 +122,17 @@ hipError_t sweep2_shape(const Dims &dm, const Geom &g, const void *coefs, const 
     TS *fo = (TS *)fout;
     const TP *pi = (const TP *)pin;
     TP *po = (TP *)pout;
+    if (dm.sb) {
+        // Scheme B with R(phi), 3-term polynomials: no history
+        if (!dm.deg3) return hipErrorInvalidValue;
+        if (dm.kvar)
+            hipLaunchKernelGGL((k_sweep2<TS, TC, false, true, 3, TH, NW, true>), grid, block, 0, st, g, cf, fi, fo,
+                               pi, po, tiles_x, flag);
+        else
+            hipLaunchKernelGGL((k_sweep2<TS, TC, false, false, 3, TH, NW, true>), grid, block, 0, st, g, cf, fi, fo,
+                               pi, po, tiles_x, flag);
+        return hipGetLastError();
+    }
     const int code = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.deg3 ? 8 : (dm.lowdeg ? 1 : 0));
 #define LBM_SW2(S, K, NP, TAG)                                                                       \
     case (S * 4 + K * 2 + TAG):                                                                      \

@@ -717,8 +717,9 @@ __device__ __forceinline__ void sweep_node(const Geom &g, const Coefs<TC> *__res
 
 // RW: every wave lies within one grid row (D2Q9 with nx a multiple of 64;
 // the host checks), and the gathers take the row-wave form.
+// SB: Scheme B with R(phi) and no fields (the fields take k_sweep_gen).
 template <int Q, typename TS, typename TC, bool EQR, bool SRC, bool KVAR, bool WALL, int NP, bool NT, bool O32 = false,
-          bool RW = false>
+          bool RW = false, bool SB = false>
 __global__ void __launch_bounds__(kBlock)
 k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin,
         TS *__restrict__ fout, typename HistType<TS>::T *p, int *flag) {
@@ -728,7 +729,7 @@ k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f
     for (uint32_t i = 0; i < g.chunk; ++i) {
         const uint32_t n = (first + i) * kBlock + threadIdx.x;
         if (n >= g.N) return;
-        sweep_node<Q, TS, TC, EQR, SRC, KVAR, WALL, NP, NT, false, false, O32, RW>(g, cf, fin, fout, p, flag, n);
+        sweep_node<Q, TS, TC, EQR, SRC, KVAR, WALL, NP, NT, SB, false, O32, RW>(g, cf, fin, fout, p, flag, n);
     }
 }
 
@@ -758,8 +759,9 @@ __device__ __forceinline__ int wrap_coord(int v, int n) {
 // One tile of a two-step pass (tile (tx, ty) of 62 x TH nodes of the grid g;
 // NW waves of the workgroup).  Grids narrower or lower than a tile are fine:
 // halo lanes and rows then repeat nodes (computed identically) and only the
-// tile's own nodes inside the grid are stored.
-template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW>
+// tile's own nodes inside the grid are stored.  SB: Scheme B with R(phi) (no
+// history; phi from Eq. 35 at every node of both phases).
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW, bool SB = false>
 __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__restrict__ cf,
                                             const TS *__restrict__ fin, TS *__restrict__ fout,
                                             const typename HistType<TS>::T *__restrict__ pin,
@@ -816,7 +818,7 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
         for (int i = 0; i < NR; ++i) {
             const int r = wv + i * NW;
             TC out[9];
-            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP>(cf, hs[i], ps[i], 0u, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP, SB>(cf, hs[i], ps[i], 0u, nullptr, nullptr, false, out);
 #pragma unroll
             for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
             lp[r][lane] = (TP)phio;
@@ -841,7 +843,7 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
             }
             const TC pp_off = SRC ? (TC)*at<true>(pin, n) : TC(0);
             TC out[9];
-            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, n, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP, SB>(cf, h, pp_off, n, nullptr, nullptr, false, out);
 #pragma unroll
             for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
             lp[r][lane] = (TP)phio;
@@ -859,7 +861,7 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
             for (int k = 0; k < 9; ++k) h[k] = (TC)lf[k][r - L::cy(k)][lane - L::cx(k)];
             const TC pp_off = SRC ? (TC)lp[r][lane] : TC(0);
             TC out[9];
-            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP>(cf, h, pp_off, 0u, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr, false, out);
             bad |= !__builtin_isfinite(phio);
             if (x < nx && y < ny) {
                 const uint32_t m = (uint32_t)y * g.nx + (uint32_t)x;
@@ -871,14 +873,14 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
     if (bad) *flag = 1;
 }
 
-template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW = kBlock / 64>
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW = kBlock / 64, bool SB = false>
 __global__ void __launch_bounds__(64 * NW)
 k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
          const typename HistType<TS>::T *__restrict__ pin, typename HistType<TS>::T *__restrict__ pout,
          uint32_t tiles_x, int *flag) {
     const uint32_t tile = block_index(blockIdx.x, gridDim.x, g.remap);
     const uint32_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    sweep2_tile<TS, TC, SRC, KVAR, NP, TH, NW>(g, cf, fin, fout, pin, pout, tx, ty, flag);
+    sweep2_tile<TS, TC, SRC, KVAR, NP, TH, NW, SB>(g, cf, fin, fout, pin, pout, tx, ty, flag);
 }
 
 // The general sweep: Scheme B and/or per-node fields.  Polynomials of any

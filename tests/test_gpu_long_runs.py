@@ -12,10 +12,13 @@ graph-replayed), and the same summaries are compared:
     FP16 offsets   reported, with loose per-workload bounds (see TOL)
 
 Workloads: the nonlinear anisotropic D2Q9 case with the Scheme-A source at
-its full 1024 x 1024 size and 5000 steps; the D3Q19 case with walls, at the
-full 2000 steps on a 64^3 grid (the full-length 256^3 oracle run is out of
-reach of the host; the 256^3 size is covered for two steps elementwise in
-test_gpu_parity.py).
+its full 1024 x 1024 size and 5000 steps, and the same in Scheme B (Eq. 35
+implicit in phi); the D3Q19 case with walls, at the full 2000 steps on 64^3
+and 128^3 grids (the full-length 256^3 oracle run is out of reach of the
+host; the 256^3 size is covered for two steps elementwise in
+test_gpu_parity.py).  Beside the relative L2 of the samples, the largest
+sample difference relative to the largest |phi| of the samples is bounded by
+the same tolerance.
 """
 import json
 import os
@@ -34,7 +37,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lon
 # is re-centred (it has a source) and ends near 5e-4; the D3Q19 field keeps
 # O(1) structure on a zero background, so its stored values cannot be made
 # small and 10-bit rounding accumulates to about 4e-3 over 2000 steps.
-TOL = {"f64": 1e-12, "f32": 1e-5, ("nonlinear2d-1024", "f16"): 2e-3, ("d3q19-walls-64", "f16"): 1e-2}
+TOL = {"f64": 1e-12, "f32": 1e-5, ("nonlinear2d-1024", "f16"): 2e-3, ("d3q19-walls-64", "f16"): 1e-2,
+       ("d3q19-walls-128", "f16"): 1e-2, ("nonlinear2d-1024-scheme-b", "f16"): 2e-3}
 
 
 def say(msg):
@@ -51,8 +55,13 @@ def load():
 def workload(name, precision):
     if name == "nonlinear2d-1024":
         spec, phi0, _ = W.nonlinear_2d(1024, precision=precision)
+    elif name == "nonlinear2d-1024-scheme-b":
+        spec, phi0, _ = W.nonlinear_2d(1024, precision=precision)
+        spec["scheme"] = "B"
     elif name == "d3q19-walls-64":
         spec, phi0, _ = W.d3q19_walls((64, 64, 64), precision=precision)
+    elif name == "d3q19-walls-128":
+        spec, phi0, _ = W.d3q19_walls((128, 128, 128), precision=precision)
     else:
         raise KeyError(name)
     return spec, phi0
@@ -75,10 +84,13 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32", "f16"])
-@pytest.mark.parametrize("name", ["nonlinear2d-1024", "d3q19-walls-64"])
+@pytest.mark.parametrize("name", ["nonlinear2d-1024", "d3q19-walls-64", "d3q19-walls-128",
+                                  "nonlinear2d-1024-scheme-b"])
 def test_full_length_against_oracle(name, precision):
     from paper_1603_09577_amd import lbm
-    g = load()[name]
+    g = load().get(name)
+    if g is None:
+        pytest.fail(f"{name} missing from {GOLDEN}: run tests/golden/make_long_runs.py --cases {name}")
     spec, phi0 = workload(name, precision)
     assert list(phi0.shape) == g["shape"]
     sim = lbm.Lbm(spec).init(phi0)
@@ -92,10 +104,11 @@ def test_full_length_against_oracle(name, precision):
         ref = g["snapshots"][str(s)]
         gs, gq, gb, gv = summaries(sim.phi(), g["block_edge"], g["idx"])
         e_vals = rel(gv, ref["vals"])
+        e_pt = float(np.abs(np.asarray(gv) - np.asarray(ref["vals"])).max() / np.abs(np.asarray(ref["vals"])).max())
         e_blk = rel(gb, ref["blocks"])
         e_sum = abs(gs - ref["sum"]) / abs(ref["sum"])
         e_sq = abs(gq - ref["sumsq"]) / abs(ref["sumsq"])
-        say(f"[gpu long run] {name} {precision} step {s}: samples {e_vals:.2e} blocks {e_blk:.2e} "
-            f"sum {e_sum:.2e} sumsq {e_sq:.2e}")
-        worst = max(worst, e_vals, e_blk, e_sum, e_sq)
+        say(f"[gpu long run] {name} {precision} step {s}: samples {e_vals:.2e} (pointwise {e_pt:.2e}) "
+            f"blocks {e_blk:.2e} sum {e_sum:.2e} sumsq {e_sq:.2e}")
+        worst = max(worst, e_vals, e_pt, e_blk, e_sum, e_sq)
     assert worst <= tol, f"{name} {precision}: {worst:.3e} > {tol}"
