@@ -1,0 +1,174 @@
+"""The paper's convergence studies on the GPU at its printed resolutions
+(Sec. 3.1 Fig. 1-2, Sec. 3.4 Fig. 11, Sec. 3.5 Fig. 14), FP64.
+
+Reading R36: the figures report second order in space over the printed
+lattice spacings, which holds only if the relaxation rates stay fixed while
+the grid is refined, i.e. under diffusive scaling (dt proportional to dx^2).
+The runs here take c = dx / dt = 1 on the coarsest printed grid (reading R23)
+and refine diffusively from there.  With c = 1 on every grid the error of
+the Pe = 100 problems stops falling (the lattice diffusivity grows with the
+resolution); `test_fixed_lattice_speed_stalls` records that.  Printed
+"N x N" periodic lattices have N - 1 distinct nodes (reading R23).
+
+    Fig. 1 (Sec. 3.1, 201^2, T = 3, Pe = 100 and 1000): GRE reported, < 5e-4.
+    Fig. 2 (Sec. 3.1, dx = L/100 ... L/500, T = 3): fitted order 2 +- 0.2.
+    Fig. 11 (Sec. 3.4, dx = L/200 ... L/800, T = 10, isotropic and fully
+      anisotropic K): order 2 +- 0.2.
+    Fig. 14 (Sec. 3.5, dx = L/200 ... L/800, T = 3, Pe = 100 and 1000):
+      order 2 +- 0.2.
+GRE is Eq. 39.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gre(num, ana):
+    return float(np.abs(ana - num).sum() / np.abs(ana).sum())
+
+
+def fitted_order(ns, errs):
+    """Least-squares slope of log GRE against log of the lattice spacing."""
+    return float(-np.polyfit(np.log(ns), np.log(errs), 1)[0])
+
+
+def time_step(L, n, n0, c0=1.0):
+    """dt on an n-node grid: lattice speed c0 on the coarsest grid (n0 nodes),
+    diffusive refinement from there (dt proportional to dx^2)."""
+    dx, dx0 = L / n, L / n0
+    return dx0 / c0 * (dx / dx0) ** 2
+
+
+def run_with_source(spec, phi0, nst, dt, body, g, kfield=None):
+    """Scheme B with R(x, t) = exp(g t) body (lattice units: times dt), the
+    field rewritten on the device after every step (R at the new time level)."""
+    from paper_1603_09577_amd import lbm
+    rf = (dt * body).contiguous()
+    sim = lbm.Lbm(spec)
+    sim.set_fields(kfield, rf)
+    sim.init(phi0)
+    for t in range(nst):
+        sim.step(1)
+        rf.copy_(dt * math.exp(g * (t + 1) * dt) * body)
+    return sim.phi().cpu().numpy()
+
+
+def _spec(n, dt, dx, u, kl):
+    return dict(lattice=9, shape=(n, n), bc=["periodic"] * 3, scheme="B", d=1.0, s=[0.0] + [1.0] * 8,
+                b=[[0.0, u[0] * dt / dx], [0.0, u[1] * dt / dx]], dpoly=[0, 1], dten=np.eye(3).tolist(),
+                k0=kl.tolist(), kpoly=[1.0], rpoly=[])
+
+
+def sine_wave(n, kappa, dt, T=3.0, L=2.0, u=0.1):
+    """Sec. 3.1 (Eq. 42-45) on [0, 2]^2, u = (0.1, 0.1), Pe = L u / kappa."""
+    dx = L / n
+    kl = kappa * dt / dx ** 2
+    x = np.arange(n) * dx
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    g = 1 - 2 * math.pi ** 2 * kappa
+    body = torch.tensor(np.sin(math.pi * (X + Y)) + math.pi * 2 * u * np.cos(math.pi * (X + Y)), device="cuda")
+    nst = int(round(T / dt))
+    ph = run_with_source(_spec(n, dt, dx, (u, u), kl * np.eye(3)), np.sin(math.pi * (X + Y)), nst, dt, body, g)
+    return gre(ph, math.exp(g * nst * dt) * np.sin(math.pi * (X + Y)))
+
+
+def gaussian_hill(n, K, dt, T=10.0, L=2.0, u=(0.01, 0.01), s0=0.01):
+    """Sec. 3.4 (Eq. 58-61, first approach) on [-1, 1]^2, sigma0 = 0.01."""
+    from paper_1603_09577_amd import lbm
+    dx = L / n
+    kl = np.asarray(K) * dt / dx ** 2
+    k3 = np.eye(3) * kl[0, 0]
+    k3[:2, :2] = kl
+    x = -1 + np.arange(n) * dx
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    sim = lbm.Lbm(_spec(n, dt, dx, u, k3)).init(np.exp(-(X * X + Y * Y) / (2 * s0 * s0)))
+    nst = int(round(T / dt))
+    sim.step(nst)
+    t = nst * dt
+    sig = s0 * s0 * np.eye(2) + 2 * np.asarray(K) * t
+    si = np.linalg.inv(sig)
+    ana = np.zeros_like(X)
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            ddx, ddy = X - u[0] * t - i * L, Y - u[1] * t - j * L
+            ana += np.exp(-(si[0, 0] * ddx * ddx + 2 * si[0, 1] * ddx * ddy + si[1, 1] * ddy * ddy) / 2)
+    ana *= s0 * s0 / math.sqrt(abs(np.linalg.det(sig)))
+    return gre(sim.phi().cpu().numpy(), ana)
+
+
+def variable_k(n, kappa, dt, T=3.0, u=0.1):
+    """Sec. 3.5 (Eq. 64-68) on [0, 1]^2: K(x) as a per-node field."""
+    dx = 1.0 / n
+    kl = kappa * dt / dx ** 2
+    x = np.arange(n) * dx
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    sxy = np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+    kf = torch.tensor(np.stack([kl * (2 - sxy), np.full_like(sxy, kl), np.zeros_like(sxy)], axis=-1),
+                      device="cuda").contiguous()
+    g = 1 - 12 * np.pi ** 2 * kappa
+    body = torch.tensor(sxy + 4 * kappa * np.pi ** 2 * np.cos(4 * np.pi * X) * np.sin(2 * np.pi * Y) ** 2
+                        + 2 * np.pi * (u * np.cos(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+                                       + u * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)), device="cuda")
+    nst = int(round(T / dt))
+    ph = run_with_source(_spec(n, dt, dx, (u, u), kl * np.eye(3)), sxy, nst, dt, body, g, kf)
+    return gre(ph, math.exp(g * nst * dt) * sxy)
+
+
+@pytest.mark.parametrize("pe", [100, 1000])
+def test_fig1_sine_wave_201(pe):
+    kappa = 2.0 * 0.1 / pe
+    e = sine_wave(200, kappa, 2.0 / 200)
+    say(f"[paper] Sec. 3.1 Fig. 1, 201^2, Pe = {pe}, c = 1, T = 3: GRE {e:.3e}")
+    assert e < 5e-4
+
+
+@pytest.mark.parametrize("pe", [100, 1000])
+def test_fig2_sine_wave_order(pe):
+    kappa = 2.0 * 0.1 / pe
+    ns = (100, 200, 300, 400, 500)
+    errs = [sine_wave(n, kappa, time_step(2.0, n, ns[0])) for n in ns]
+    o = fitted_order(ns, errs)
+    say(f"[paper] Sec. 3.1 Fig. 2, Pe = {pe}, dx = L/100 ... L/500: GRE {[f'{v:.3e}' for v in errs]}, order {o:.3f}")
+    assert abs(o - 2.0) <= 0.2
+
+
+@pytest.mark.parametrize("name", ["isotropic", "full"])
+def test_fig11_gaussian_hill_order(name):
+    K = (np.eye(2) if name == "isotropic" else np.array([[1.0, 1.0], [1.0, 2.0]])) * 1e-3
+    ns = (200, 300, 400, 500, 600, 800)
+    errs = [gaussian_hill(n, K, time_step(2.0, n, ns[0])) for n in ns]
+    o = fitted_order(ns, errs)
+    say(f"[paper] Sec. 3.4 Fig. 11, {name} K, dx = L/200 ... L/800: GRE {[f'{v:.3e}' for v in errs]}, order {o:.3f}")
+    assert abs(o - 2.0) <= 0.2
+
+
+@pytest.mark.parametrize("kappa", [1e-3, 1e-4])
+def test_fig14_variable_k_order(kappa):
+    ns = (200, 300, 400, 500, 600, 800)
+    errs = [variable_k(n, kappa, time_step(1.0, n, ns[0])) for n in ns]
+    o = fitted_order(ns, errs)
+    say(f"[paper] Sec. 3.5 Fig. 14, kappa = {kappa:g}, dx = L/200 ... L/800: GRE {[f'{v:.3e}' for v in errs]}, "
+        f"order {o:.3f}")
+    assert abs(o - 2.0) <= 0.2
+
+
+def test_fixed_lattice_speed_stalls():
+    """Evidence for reading R36: with c = 1 on every grid the Pe = 100 sine
+    wave's GRE stops falling between dx = L/200 and L/500 (the lattice
+    diffusivity rises from 0.2 to 0.5), far from second order."""
+    kappa = 0.002
+    ns = (200, 300, 400, 500)
+    errs = [sine_wave(n, kappa, 2.0 / n) for n in ns]
+    o = fitted_order(ns, errs)
+    say(f"[paper] Sec. 3.1 with c = 1 on every grid: GRE {[f'{v:.3e}' for v in errs]}, order {o:.3f}")
+    assert o < 1.0
