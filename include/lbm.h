@@ -81,8 +81,9 @@ extern "C" {
                                  (Eq. 38) plus the source G_k of Eq. 37, dB/dt
                                  as the difference over the last step (from
                                  the phi history); for a B whose C of Eq. 7 is
-                                 not wanted.  General kernel; no adjoint, no
-                                 batches                                      */
+                                 not wanted or has no closed form, such as a
+                                 rational B (lbm_desc.bden).  General kernel;
+                                 no adjoint, no batches                       */
 
 #define LBM_MAXP 9            /* polynomial coefficients per function        */
 
@@ -119,6 +120,13 @@ typedef struct lbm_desc {
                                  0 = library choice (spreads the planes over
                                  the L2 sets and memory channels), > 0 exact,
                                  < 0 none                                      */
+    double bden[LBM_MAXP];    /* denominator Q(phi) of a rational flux
+                                 B_a = (sum_p b[a][p] phi^p) / Q(phi), e.g. the
+                                 Buckley-Leverett flux of Sec. 3.3 (Eq. 54),
+                                 whose C of Eq. 7 has no polynomial form; all
+                                 zero (or Q = 1) for a polynomial B.  A rational
+                                 B needs LBM_FLAG_REMARK3 (C = 0, Eq. 38) and
+                                 Q(phi) != 0 on the range phi takes          */
 } lbm_desc;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -127,7 +135,8 @@ typedef struct lbm_ctx lbm_ctx;
  * (LBM_E_INVALID): unknown lattice, sizes < 1 or more than 2^31 nodes,
  * d <= 0, a used rate outside (0, 2), k0 not symmetric positive definite,
  * dten not symmetric.  LBM_E_UNSUPPORTED: walls on an axis other than the
- * last, Scheme B with rpoly of degree > 2.  Allocates the context's coefficient table and
+ * last, Scheme B with rpoly of degree > 2, a rational B (bden) without
+ * LBM_FLAG_REMARK3.  Allocates the context's coefficient table and
  * its fixed scratch (about 3.1 MiB, independent of the grid) on the current
  * device, nothing that scales with the grid.  *out is set only on success. */
 int lbm_create(const lbm_desc *desc, lbm_ctx **out);

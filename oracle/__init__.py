@@ -35,6 +35,7 @@ class Params(ctypes.Structure):
         ("kpoly", ctypes.c_double * MAXP),
         ("rpoly", ctypes.c_double * MAXP),
         ("variant", ctypes.c_int),
+        ("bden", ctypes.c_double * MAXP),
     ]
 
 
@@ -91,7 +92,8 @@ def params_from_spec(spec, basis=0):
     Keys: lattice (9 | 19), shape (nx, ny[, nz]), bc (per axis "periodic" |
     "abb"), phi_wall ([[lo, hi]] * 3), scheme ("A" | "B"), d, s (rates in
     moment-row order), b (per axis polynomial coefficients of B), dpoly, dten,
-    k0, kpoly, rpoly, variant ("standard" | "remark3": Eq. 36-38).
+    k0, kpoly, rpoly, variant ("standard" | "remark3": Eq. 36-38), bden
+    (denominator of a rational B = b / bden, Remark III only; default 1).
     """
     p = Params()
     q = int(spec["lattice"])
@@ -122,6 +124,9 @@ def params_from_spec(spec, basis=0):
         arr = getattr(p, name)
         for i in range(MAXP):
             arr[i] = row[i]
+    row = _pad(spec.get("bden", []))
+    for i in range(MAXP):
+        p.bden[i] = row[i]
     dten = np.asarray(spec.get("dten", np.eye(3)), dtype=np.float64)
     k0 = np.asarray(spec["k0"], dtype=np.float64)
     for a in range(3):

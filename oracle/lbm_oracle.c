@@ -257,6 +257,11 @@ int orc_check(const orc_params *p)
     if (p->q == 9 && p->bc[2] != 0) return -1;
     if (p->scheme != 0 && p->scheme != 1) return -1;
     if (p->variant != 0 && p->variant != 1) return -1;
+    {
+        int rational = p->bden[0] != 0.0 && p->bden[0] != 1.0;
+        for (int i = 1; i < ORC_MAXP; ++i) if (p->bden[i] != 0.0) rational = 1;
+        if (rational && p->variant != 1) return -2;   /* C of Eq. 7 for a rational B: Remark III */
+    }
     return 0;
 }
 

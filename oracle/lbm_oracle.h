@@ -41,6 +41,10 @@ typedef struct orc_params {
     int variant;               /* 0: equilibrium of Eq. 3; 1: Remark III (Eq. 36-38):
                                   C = 0 in the equilibrium and the source G_k of
                                   Eq. 37 with an explicit time difference of B    */
+    double bden[ORC_MAXP];     /* B_a = bpoly_a(phi) / bden(phi), a rational flux
+                                  such as the Buckley-Leverett one (Sec. 3.3, Eq.
+                                  54); all zero: bden = 1.  A non-constant bden
+                                  needs variant 1 (C of Eq. 7 is not integrated) */
 } orc_params;
 
 /* 0 on success, negative on an invalid parameter set. */

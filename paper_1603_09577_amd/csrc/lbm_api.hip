@@ -121,9 +121,18 @@ void sym_inv_host(const double *G, double *A, int dim) {
 
 struct HostModel {
     double b[3][kMaxP], bp[3][kMaxP], bpp[3][kMaxP], cb[6][kMaxC], cbd[6][kMaxC], g0[6], kp[kMaxP],
-        kdp[kMaxP], a[6], r[kMaxP], rp[kMaxP], ew[2][19], ewp[2][19], s[19], phi_ref, srate, k0scale;
-    int nb, ncb, nk, nr;
+        kdp[kMaxP], a[6], r[kMaxP], rp[kMaxP], ew[2][19], ewp[2][19], s[19], phi_ref, srate, k0scale,
+        bq[kMaxP], bqp[kMaxP];
+    int nb, ncb, nk, nr, nq;
 };
+
+// A rational B: a denominator other than 0 (unset) or the constant 1.
+bool rational_flux(const lbm_desc &d) {
+    if (d.bden[0] != 0.0 && d.bden[0] != 1.0) return true;
+    for (int p = 1; p < LBM_MAXP; ++p)
+        if (d.bden[p] != 0.0) return true;
+    return false;
+}
 
 double polyval(const double *c, int n, double x) {
     double acc = 0.0;
@@ -210,6 +219,13 @@ void derive(const lbm_desc &d, const Dims &dm, HostModel &m) {
     for (int i = 0; i < 19; ++i) m.s[i] = (i < dm.q) ? d.s[i] : 0.0;
     m.srate = d.s[1];
     m.phi_ref = d.phi_ref;
+    // rational flux (Remark III): the denominator and its derivative
+    m.nq = 0;
+    if (rational_flux(d)) {
+        for (int p = 0; p < kMaxP; ++p) m.bq[p] = d.bden[p];
+        for (int p = 0; p + 1 < kMaxP; ++p) m.bqp[p] = (p + 1) * d.bden[p + 1];
+        m.nq = std::max(1, top_count(d.bden, kMaxP));
+    }
 }
 
 template <typename TC>
@@ -232,6 +248,8 @@ void pack(const HostModel &m, Coefs<TC> &c) {
     c.srate = (TC)m.srate;
     c.k0scale = (TC)m.k0scale;
     c.nb = m.nb; c.ncb = m.ncb; c.nk = m.nk; c.nr = m.nr;
+    for (int p = 0; p < kMaxP; ++p) { c.bq[p] = (TC)m.bq[p]; c.bqp[p] = (TC)m.bqp[p]; }
+    c.nq = m.nq;
 }
 
 int validate(const lbm_desc *d, Dims &dm) {
@@ -278,6 +296,11 @@ int validate(const lbm_desc *d, Dims &dm) {
             if (d->rpoly[p] != 0.0)
                 return fail(LBM_E_UNSUPPORTED,
                             "Scheme B solves Eq. 35 in closed form for R of degree <= 2 in phi");
+    for (int p = 0; p < LBM_MAXP; ++p)
+        if (!std::isfinite(d->bden[p])) return fail(LBM_E_INVALID, "non-finite polynomial coefficient");
+    const bool rat = rational_flux(*d);
+    if (rat && !(d->flags & LBM_FLAG_REMARK3))
+        return fail(LBM_E_UNSUPPORTED, "a rational B needs LBM_FLAG_REMARK3 (its C of Eq. 7 is not integrated)");
     {
         int nb = 0;
         for (int a = 0; a < dim; ++a) nb = std::max(nb, top_count(d->b[a], LBM_MAXP));
@@ -287,7 +310,10 @@ int validate(const lbm_desc *d, Dims &dm) {
                     top_count(d->rpoly, LBM_MAXP) <= 4;
         dm.deg3 = nb <= 3 && ncb <= 4 && top_count(d->kpoly, LBM_MAXP) <= 3 &&
                   top_count(d->rpoly, LBM_MAXP) <= 3;
+        // a rational B is evaluated by the 9-term kernels only
+        if (rat) dm.lowdeg = dm.deg3 = false;
     }
+    dm.rat = rat;
     dm.nt = false;
     dm.q = q;
     dm.prec = d->precision;

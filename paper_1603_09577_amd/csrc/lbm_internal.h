@@ -61,6 +61,11 @@ struct Coefs {
     TC srate;             // common non-flux rate (equal-rate path)
     TC k0scale;           // 3 / d = dG / d(K0 k)
     int nb, ncb, nk, nr;  // used coefficient counts
+    // rational flux B_a = (sum b[a] phi^p) / Q(phi) (Remark III only): Q and Q',
+    // nq = 0 for a polynomial B
+    TC bq[kMaxP];
+    TC bqp[kMaxP];
+    int nq;
 };
 
 struct Dims {
@@ -75,6 +80,7 @@ struct Dims {
     bool o32 = false;     // every indexed array spans < 4 GiB: 32-bit byte offsets (the 3-term and two-step kernels)
     bool nt;              // non-temporal distribution accesses
     bool sb;              // Scheme B (Eq. 33-35): stored fbar, explicit source
+    bool rat = false;     // rational B (Remark III): the 9-term kernels evaluate P / Q
 };
 
 // Elements between consecutive direction planes.  A plane stride that is a

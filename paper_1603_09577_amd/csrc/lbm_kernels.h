@@ -104,6 +104,32 @@ struct PolyLen {
     static constexpr int NCD = NC > 1 ? NC - 1 : 1;      // C-bar'
 };
 
+// B_a(phi) of Eq. 1 and B'_a(phi).  A rational flux B_a = P_a / Q (Remark III,
+// cf->nq > 0) is evaluated only by the 9-term kernels, which the host selects
+// for it; the shorter kernels evaluate the polynomial P_a alone.  B' by the
+// quotient rule, (P'_a - B_a Q') / Q.
+template <int NP, typename TC>
+__device__ __forceinline__ TC flux_b(const Coefs<TC> *__restrict__ cf, int a, TC phi) {
+    const TC num = poly<NP>(cf->b[a], phi);
+    if constexpr (NP == kMaxP) {
+        if (cf->nq) return num / poly<NP>(cf->bq, phi);
+    }
+    return num;
+}
+
+template <int NP, typename TC>
+__device__ __forceinline__ TC flux_bp(const Coefs<TC> *__restrict__ cf, int a, TC phi) {
+    const TC dnum = poly<PolyLen<NP>::ND>(cf->bp[a], phi);
+    if constexpr (NP == kMaxP) {
+        if (cf->nq) {
+            const TC q = poly<NP>(cf->bq, phi);
+            const TC b = poly<NP>(cf->b[a], phi) / q;
+            return (dnum - b * poly<PolyLen<NP>::ND>(cf->bqp, phi)) / q;
+        }
+    }
+    return dnum;
+}
+
 // Workgroup order that gives each XCD one contiguous run of the domain, so
 // the neighbouring rows and planes a workgroup reads sit in its own L2.
 __device__ __forceinline__ uint32_t block_index(uint32_t b, uint32_t nb, int remap) {
@@ -193,7 +219,7 @@ __device__ __forceinline__ void equilibrium(const Coefs<TC> *__restrict__ cf, TC
     constexpr int D = L::dim;
     TC B[3], E[6];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) B[a] = (a < D) ? poly<NP>(cf->b[a], phi) : TC(0);
+    for (int a = 0; a < 3; ++a) B[a] = (a < D) ? flux_b<NP>(cf, a, phi) : TC(0);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         const bool used = (D == 3) || (i == 0 || i == 1 || i == 3);
@@ -227,7 +253,7 @@ __device__ __forceinline__ void source_terms(const Coefs<TC> *__restrict__ cf, T
                                              TC *Bt, TC &R) {
     TC Bp[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Bp[a] = (a < DIM) ? poly<PolyLen<NP>::ND>(cf->bp[a], phi) : TC(0);
+    for (int a = 0; a < 3; ++a) Bp[a] = (a < DIM) ? flux_bp<NP>(cf, a, phi) : TC(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         TC acc = Bp[a];
@@ -435,7 +461,7 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
         const TC s = cf->srate;
         TC B[3], E[6];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) B[a] = (a < D) ? poly<NP>(cf->b[a], phi) : TC(0);
+        for (int a = 0; a < 3; ++a) B[a] = (a < D) ? flux_b<NP>(cf, a, phi) : TC(0);
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             const bool used = (D == 3) || (i == 0 || i == 1 || i == 3);
@@ -463,7 +489,7 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
             const TC hs = (TC(1) - TC(0.5) * s) * Rx;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const TC bp = poly<PolyLen<NP>::ND>(cf->bp[a], phi);
+                const TC bp = flux_bp<NP>(cf, a, phi);
                 Vo[a] = TC(3) * hs * bp;
                 jsh[a] = TC(0.5) * Rx * bp;
             }
@@ -473,7 +499,7 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
             const TC pp = cf->phi_ref + pp_off;
             TC dB[3] = {TC(0), TC(0), TC(0)};
 #pragma unroll
-            for (int a = 0; a < D; ++a) dB[a] = poly<NP>(cf->b[a], phi) - poly<NP>(cf->b[a], pp);
+            for (int a = 0; a < D; ++a) dB[a] = flux_b<NP>(cf, a, phi) - flux_b<NP>(cf, a, pp);
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 TC acc = dB[a];
@@ -568,7 +594,7 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
             // r -= (I - S/2) M R_k, R_k = w_k R (1 + 3 c_k . B') (Eq. 9, Btilde = B')
             TC Bp[3] = {TC(0), TC(0), TC(0)};
 #pragma unroll
-            for (int a = 0; a < D; ++a) Bp[a] = poly<PolyLen<NP>::ND>(cf->bp[a], phi);
+            for (int a = 0; a < D; ++a) Bp[a] = flux_bp<NP>(cf, a, phi);
             TC Rk[Q], mR[Q], sR[Q];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
@@ -648,7 +674,7 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
         const TC pp = cf->phi_ref + pp_off;
         TC dB[3] = {TC(0), TC(0), TC(0)}, gq[3] = {TC(0), TC(0), TC(0)};
 #pragma unroll
-        for (int a = 0; a < D; ++a) dB[a] = poly<NP>(cf->b[a], phi) - poly<NP>(cf->b[a], pp);
+        for (int a = 0; a < D; ++a) dB[a] = flux_b<NP>(cf, a, phi) - flux_b<NP>(cf, a, pp);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             TC acc = dB[a];
@@ -918,7 +944,7 @@ __device__ __forceinline__ TC half_source_one(const Coefs<TC> *__restrict__ cf, 
 #pragma unroll
     for (int a = 0; a < L::dim; ++a) {
         const int c = L::c(kk, a);
-        if (c) cb += TC(c) * poly<PolyLen<NP>::ND>(cf->bp[a], phi);
+        if (c) cb += TC(c) * flux_bp<NP>(cf, a, phi);
     }
     return TC(0.5) * TC(L::w(kk)) * R * (TC(1) + TC(3) * cb);
 }

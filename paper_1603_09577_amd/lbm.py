@@ -67,6 +67,7 @@ class LbmDesc(ctypes.Structure):
         ("rpoly", ctypes.c_double * MAXP),
         ("flags", ctypes.c_int),
         ("plane_pad", ctypes.c_int),
+        ("bden", ctypes.c_double * MAXP),
     ]
 
 
@@ -194,6 +195,9 @@ def desc_from_spec(spec, flags=0):
             d.k0[a][c] = k0[a, c] if a < k0.shape[0] and c < k0.shape[1] else 0.0
     d.flags = int(flags | spec.get("flags", 0) | (FLAG_REMARK3 if spec.get("variant") == "remark3" else 0))
     d.plane_pad = int(spec.get("plane_pad", 0))
+    row = _pad(spec.get("bden", []))
+    for i in range(MAXP):
+        d.bden[i] = row[i]
     return d
 
 

@@ -118,3 +118,15 @@ def test_null_arguments(L):
     assert L.lbm_set_check(None, 5) == lbm.LBM_E_INVALID
     assert L.lbm_tune(None, 1, None, None, 0) == lbm.LBM_E_INVALID
     assert L.lbm_batch_step(None, 1, None) == lbm.LBM_E_INVALID
+
+
+def test_rational_flux_needs_remark3(L):
+    spec = W.spec_nonlinear_2d(16)
+    spec["bden"] = [1.0, -2.0, 2.0]
+    rc, msg = _create(L, spec)
+    assert rc == lbm.LBM_E_UNSUPPORTED and "REMARK3" in msg
+    spec["flags"] = lbm.FLAG_REMARK3
+    rc, msg = _create(L, spec)
+    assert rc in (lbm.LBM_OK, lbm.LBM_E_HIP), msg
+    spec["bden"] = [1.0, float("nan")]
+    assert _create(L, spec)[0] == lbm.LBM_E_INVALID
