@@ -114,9 +114,12 @@ def time_steps(torch, sim, steps, warmup, samples=SAMPLES):
                  "wall_s": sum(walls)}
 
 
-# tile shape forced on two-step runs after tuning, with the XCD-aware order
-# (--two-step-shape; None: the tuner's choices)
+# tile shape forced on D2Q9 two-step runs after tuning, with the XCD-aware
+# order (--two-step-shape; None: the tuner's choices)
 TWO_STEP_SHAPE = None
+# (rows, waves) of the two-step pass forced on D3Q19 runs (--two-step-3d;
+# None: the tuner's choice between single sweeps and each shape)
+TWO_STEP_3D = None
 
 
 def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_step=None):
@@ -128,7 +131,14 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_ste
     if two_step is not None:
         sim.set_two_step(two_step)
         rep += f"; two steps per pass forced {'on' if two_step else 'off'}"
-    if TWO_STEP_SHAPE is not None and (" two 1" in rep if two_step is None else two_step):
+    if TWO_STEP_3D is not None and sim.q == 19 and two_step is None:
+        shapes = sim.two_step_shapes()
+        if TWO_STEP_3D in shapes:
+            sim.set_two_step(True, shapes.index(TWO_STEP_3D))
+            r, w = TWO_STEP_3D
+            rep = re.sub(r" two \d rows \d+ waves \d+", f" two 1 rows {r} waves {w}", rep)
+            rep += f"; two steps per pass with shape {r} x {w} forced"
+    elif TWO_STEP_SHAPE is not None and (" two 1" in rep if two_step is None else two_step):
         shapes = sim.two_step_shapes()
         if TWO_STEP_SHAPE < len(shapes):
             sim.set_two_step(True, TWO_STEP_SHAPE)
@@ -373,14 +383,21 @@ def cpu_baseline(spec, phi0, target_s=12.0, single_s=6.0):
 
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 1000 --warmup 50 --two-step-shape 1",
+             "python3 bench.py --no-cpu --steps 1000 --warmup 50 --two-step-shape 1 --two-step-3d 6x8",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1",
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 6x8",
     "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1",
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 6x8",
     "valu": "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVES -d gpurun_out/pmc_valu -o valu "
-            "--output-format csv -- python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint "
-            "--two-step-shape 1",
+            "--output-format csv -- python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19 "
+            "--two-step-shape 1 --two-step-3d 6x8",
+    "stall": "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
+             "SQ_WAIT_INST_LDS -d gpurun_out/pmc_stall -o stall --output-format csv -- "
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19 --two-step-shape 1 "
+             "--two-step-3d 6x8",
+    "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -d gpurun_out/pmc_l2 -o l2 --output-format csv -- "
+          "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19 --two-step-shape 1 "
+          "--two-step-3d 6x8",
 }
 # vector-ALU issue peak without packed FP32: each SIMD issues one 64-lane
 # instruction every 4 clocks (16 lanes per clock), 4 SIMDs per CU, so one
@@ -404,6 +421,8 @@ PROFILED = {
                       bytes_per_node(19, "f32", False) * 256 ** 3),
     "d3q19-256 f64": ("k_sweep<19, double, double, true, false, false, true, ",
                       bytes_per_node(19, "f64", False) * 256 ** 3),
+    "d3q19-256 f32 two-step": ("k_sweep2_3d<float, float, ", bytes_per_node(19, "f32", False) * 256 ** 3),
+    "d3q19-256 f64 two-step": ("k_sweep2_3d<double, double, ", bytes_per_node(19, "f64", False) * 256 ** 3),
     "batch-512 f32 two-step": ("k_batch_sweep2<float, float, ", bytes_per_node(9, "f32", False) * BATCH_NODES),
     "adjoint2d-512 f64": ("k_adjoint<9, double, double, true, true, true, false, 3, ",
                           adjoint_bytes_per_node(9, "f64", True) * 512 * 512),
@@ -601,6 +620,60 @@ def summarize_profiles(gdir, copy_bytes=1 << 30):
         vl += ["", f"Kernel-source hash `{out['kernel_hash']}`."]
         with open(os.path.join(pdir, "sweep_kernels_valu_issue.md"), "w") as fh:
             fh.write("\n".join(vl) + "\n")
+
+    def per_kernel(sub, stem):
+        path = os.path.join(gdir, sub, f"{stem}_counter_collection.csv")
+        if not os.path.exists(path):
+            return None
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            vals.setdefault(kname(r["Kernel_Name"]), {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+        return vals
+
+    stall, l2 = per_kernel("pmc_stall", "stall"), per_kernel("pmc_l2", "l2")
+    if stall:
+        sl = ["# Where the waves of the sweep and adjoint kernels wait (rocprofv3 counters)", "",
+              "From the repository root with `TMPDIR=/tmp`:", "", "    " + PROFILE_COMMANDS["stall"]]
+        if l2:
+            sl += ["    " + PROFILE_COMMANDS["l2"]]
+        sl += ["", "Summarised by `python3 bench.py --summarize-profiles gpurun_out`. Medians per dispatch of "
+               "the variant with the most dispatches (the profiled runs pin the tile shapes, so this is the "
+               "timed kernel). The counters are taken as the hardware reports them, summed over the waves "
+               "of a dispatch; the ratios compare kernels with each other and are not calibrated shares of "
+               "time. `wait` = SQ_WAIT_ANY / SQ_WAVE_CYCLES (waves held at a wait on memory, LDS or a "
+               "barrier counter), `issue wait` = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (waves ready but not "
+               "issued), `LDS wait` = SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES; `cycles per wave` = "
+               "SQ_WAVE_CYCLES / SQ_WAVES. L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS), summed over the L2 "
+               "channels.", "",
+               "| workload | kernel | waves | cycles per wave | wait | issue wait | LDS wait | L2 hit |",
+               "|---|---|---|---|---|---|---|---|"]
+        for label, (prefix, alg) in PROFILED.items():
+            want = "lbm::" + out["workloads"].get(label, {}).get("kernel", "")
+            hits = sorted((k for k in stall if prefix in k and "SQ_WAVE_CYCLES" in stall[k]),
+                          key=lambda k: -len(stall[k]["SQ_WAVE_CYCLES"]))
+            if not hits:
+                continue
+            k = want if want in stall and "SQ_WAVE_CYCLES" in stall[want] else hits[0]
+            m = {c: stats.median(v) for c, v in stall[k].items()}
+            wc = m["SQ_WAVE_CYCLES"] or 1.0
+            hit = None
+            if l2 and k in l2 and "TCC_HIT_sum" in l2[k]:
+                h, ms = stats.median(l2[k]["TCC_HIT_sum"]), stats.median(l2[k].get("TCC_MISS_sum", [0.0]))
+                hit = h / (h + ms) if h + ms else None
+            w = out["workloads"].setdefault(label, {})
+            w.update({"wait_ratio": m.get("SQ_WAIT_ANY", 0) / wc, "issue_wait_ratio": m.get("SQ_WAIT_INST_ANY", 0) / wc,
+                      "lds_wait_ratio": m.get("SQ_WAIT_INST_LDS", 0) / wc, "l2_hit": hit})
+            waves = m.get("SQ_WAVES", 0)
+            sl.append(f"| {label} | `{k.replace('lbm::', '')}` | {waves:.0f} | "
+                      f"{'-' if not waves else f'{wc / waves:.0f}'} | {m.get('SQ_WAIT_ANY', 0) / wc:.2f} | "
+                      f"{m.get('SQ_WAIT_INST_ANY', 0) / wc:.2f} | {m.get('SQ_WAIT_INST_LDS', 0) / wc:.2f} | "
+                      f"{'-' if hit is None else f'{hit:.2f}'} |")
+        sl += ["", f"Kernel-source hash `{out['kernel_hash']}`."]
+        with open(os.path.join(pdir, "sweep_kernels_stalls.md"), "w") as fh:
+            fh.write("\n".join(sl) + "\n")
+        with open(os.path.join(pdir, "pmc_traffic.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
         with open(os.path.join(pdir, "pmc_traffic.json"), "w") as fh:
             json.dump(out, fh, indent=1)
     return out
@@ -621,6 +694,9 @@ def main():
                     help="after tuning, run two-step passes with this tile shape (lbm_two_step_shape index) "
                          "and the XCD-aware order; the profiles pin 1 with that order, the tuner's usual choice, "
                          "so that every profiled run times the same kernel")
+    ap.add_argument("--two-step-3d", metavar="ROWSxWAVES", default=None,
+                    help="run the D3Q19 legs with two steps per pass in this tile shape (6x8 exists in every "
+                         "precision), so that the profiled runs time one kernel whatever the tuner picks")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write the profiles/ summaries from rocprofv3 output under DIR and exit (no GPU)")
     args = ap.parse_args()
@@ -629,8 +705,10 @@ def main():
         print(json.dumps({k: v["traffic_bytes_per_launch"] / v["algorithmic_bytes_per_launch"]
                           for k, v in out["workloads"].items()}))
         return
-    global TWO_STEP_SHAPE
+    global TWO_STEP_SHAPE, TWO_STEP_3D
     TWO_STEP_SHAPE = args.two_step_shape
+    if args.two_step_3d:
+        TWO_STEP_3D = tuple(int(v) for v in args.two_step_3d.lower().split("x"))
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
@@ -802,8 +880,9 @@ def main():
                  "storage": "f16 offsets, re-centred every 256 steps"},
         "nonfinite": head["nonfinite"] + f64["nonfinite"] + f16["nonfinite"],
         "diagnostics_fp64": diag,
-        "scheme_b": dict(schemeb, note="Scheme B (no phi history: bytes per node without it); the general "
-                                       "kernel with the closed-form root of Eq. 35 per node"),
+        "scheme_b": dict(schemeb, note="Scheme B (no phi history: bytes per node without it); the tuned "
+                                       "3-term kernels with the closed-form root of Eq. 35 per node; "
+                                       "hbm_frac is per launch (a two-step pass: its own bytes)"),
         **extra,
     }
     print(json.dumps(line))

@@ -220,34 +220,41 @@ int lbm_set_nontemporal(lbm_ctx *ctx, int on);
  * back to 0; phi0 must still be valid). */
 int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_len);
 
-/* Two time steps per pass inside lbm_step (D2Q9, periodic axes, equal
- * non-flux rates, any grid size: tiles wrap periodically).  A workgroup runs
- * step t on a tile with a one-node halo, keeps the post-collision populations in LDS
- * (rounded to the storage type as a store would round them), runs step t + 1
- * on the tile and stores only that result: every update is the single-sweep
- * arithmetic on the same inputs, so results equal single sweeps bit for bit,
- * while the state crosses HBM once per two steps.  Passes run in pairs (four
- * steps); with a source they alternate the history between p and the
- * caller's p2 (lbm_init), so state and history end in the same buffers as
- * after single sweeps; remaining steps use single sweeps.  On by default
- * where it applies and, with a source, p2 is bound (lbm_tune times it
- * against single sweeps); not used with a divergence check, Scheme B sources,
- * per-node fields or Remark III.
- * mode: 0 off; k >= 1 on with tile shape k - 1 (lbm_two_step_shape; shape 0,
- * the default, is 14 rows x 4 waves for 4- and 2-byte storage and 6 x 4 for
- * FP64).  The other shapes need every polynomial of degree <= 2; lbm_tune
- * times them all.
+/* Two time steps per pass inside lbm_step.  Every node update is the
+ * single-sweep arithmetic on the same inputs (post-collision values kept in
+ * LDS are rounded to the storage type as a store would round them), so
+ * results equal single sweeps bit for bit, while the state crosses HBM once
+ * per two steps.
+ *  - D2Q9, periodic axes, equal non-flux rates (any grid size: tiles wrap
+ *    periodically): a workgroup runs step t on a 62 x rows tile with a
+ *    one-node halo and step t + 1 on the tile.  Passes run in pairs (four
+ *    steps); with a Scheme-A source they alternate the history between p and
+ *    the caller's p2 (lbm_init).  Scheme-B sources need polynomials of
+ *    degree <= 2.
+ *  - D3Q19, equal non-flux rates, polynomials of degree <= 2, no source, walls
+ *    on z or periodic: a workgroup owns a column of 62 x rows nodes and a
+ *    chunk of z planes and marches up it, phase 1 (step t, with a one-node
+ *    halo in x and y) feeding a ring of three planes in LDS that phase 2
+ *    (step t + 1) reads one plane behind.
+ * Remaining steps use single sweeps.  On by default where it applies (with a
+ * Scheme-A source: where p2 is bound); lbm_tune times it against single
+ * sweeps.  Not used with a divergence check, per-node fields or Remark III.
+ * mode: 0 off; k >= 1 on with tile shape k - 1 (lbm_two_step_shape; shape 0
+ * is the default).  The non-default D2Q9 shapes need every polynomial of
+ * degree <= 2.
  * Errors: LBM_E_UNSUPPORTED when the run does not qualify; LBM_E_STATE when a
- * run with a source was bound without p2; LBM_E_INVALID for a shape that is
- * not available here. */
+ * run with a Scheme-A source was bound without p2; LBM_E_INVALID for a shape
+ * that is not available here. */
 int lbm_set_two_step(lbm_ctx *ctx, int mode);
 
-/* Tile shape `shape` of two-step passes for this context's storage type: tile
- * rows (the tile is 62 x rows nodes, the workgroup's LDS holds 64 x (rows + 2))
- * and waves per workgroup.  4- and 2-byte storage: 14 x 4, 14 x 8, 10 x 6,
- * 6 x 4; FP64: 6 x 4, 6 x 8, 14 x 16.  More waves per workgroup
- * (fewer rows each) fit more waves per CU; fewer rows per tile cost more halo
- * work.  LBM_E_INVALID past the last shape. */
+/* Tile shape `shape` of two-step passes for this context's lattice and
+ * storage type: tile rows (the tile is 62 x rows nodes, phase 1 covers
+ * 64 x (rows + 2)) and waves per workgroup.  D2Q9, 4- and 2-byte storage:
+ * 14 x 4, 14 x 8, 10 x 6, 6 x 4; FP64: 6 x 4, 6 x 8, 14 x 16.  D3Q19 (one
+ * phase-1 row per wave): 4- and 2-byte storage 14 x 16, 6 x 8, 2 x 4; FP64
+ * 6 x 8, 2 x 4.  More waves per workgroup (fewer rows each) fit more waves per
+ * CU; fewer rows per tile cost more halo work.  LBM_E_INVALID past the last
+ * shape. */
 int lbm_two_step_shape(const lbm_ctx *ctx, int shape, int *rows, int *waves);
 
 /* Divergence check every `every` steps inside lbm_step (0 = off). */

@@ -401,8 +401,31 @@ size_t hist2_bytes(const lbm_ctx *c) {
 // Four steps as two passes of two steps each: f[start] -> f[start ^ 1] with the
 // history p -> p2, then back; state and history end where four single sweeps
 // would leave them.
+// Planes per z chunk of the D3Q19 two-step pass: enough chunks that the
+// launch has at least 1024 workgroups (four per CU), each chunk computing two
+// planes beyond its own in phase 1.
+uint32_t zchunk(const lbm_ctx *c) {
+    int rows = 0, waves = 0;
+    if (!two_step3_shape_of(c->dm.prec, c->two_shape, &rows, &waves)) return c->g.nz;
+    const uint32_t tiles_xy = ((c->g.nx + 61) / 62) * ((c->g.ny + (uint32_t)rows - 1) / (uint32_t)rows);
+    uint32_t tiles_z = (1024 + tiles_xy - 1) / tiles_xy;
+    if (tiles_z > c->g.nz) tiles_z = c->g.nz;
+    if (tiles_z < 1) tiles_z = 1;
+    return (c->g.nz + tiles_z - 1) / tiles_z;
+}
+
 // Without a source the kernels touch no history, and p stands in for p2.
 hipError_t sweep_pair(lbm_ctx *c, int start, hipStream_t st) {
+    if (c->dm.q == 19) {
+        const uint32_t zc = zchunk(c);
+        const Dims d = eff_dims(c);
+        hipError_t e = launch_sweep2_q19(d, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->d_flag,
+                                         c->two_shape, zc, st);
+        if (e == hipSuccess)
+            e = launch_sweep2_q19(d, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], c->d_flag, c->two_shape, zc,
+                                  st);
+        return e;
+    }
     void *p2 = keeps_history(c) ? c->p2 : c->p;
     const Dims d = eff_dims(c);
     hipError_t e = launch_sweep2_q9(d, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, p2, c->d_flag,
@@ -582,12 +605,15 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     // every array a kernel indexes (planes of f and psi, p, pi: at most 8-byte
     // elements, at most `plane` of them) spans < 4 GiB: 32-bit byte offsets
     c->dm.o32 = (uint64_t)g.plane * 8u < (1ull << 32);
-    c->two_ok = dm.q == 9 && !dm.wall && dm.eqr && c->dm.o32;
+    // two steps per pass: D2Q9 periodic equal-rate runs; D3Q19 equal-rate runs
+    // with 3-term polynomials and no source (walls on z allowed)
+    c->two_ok = (dm.q == 9 && !dm.wall && dm.eqr && c->dm.o32) ||
+                (dm.q == 19 && dm.eqr && dm.deg3 && !dm.src && c->dm.o32);
     c->two = c->two_ok;   // on by default where it applies (bit-identical; lbm_tune re-decides)
     {
         const uint32_t th = (uint32_t)adjoint_pair_rows(dm.prec, g.nx, g.ny);
         const uint32_t tiles = ((g.nx + 61) / 62) * ((g.ny + th - 1) / th);
-        c->adj_slots = c->two_ok && tiles > g.nblocks ? tiles : g.nblocks;
+        c->adj_slots = dm.q == 9 && c->two_ok && tiles > g.nblocks ? tiles : g.nblocks;
     }
     hipError_t e = hipMalloc(&c->d_coefs, sizeof(Coefs<double>));
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipMalloc(coefficients)"); }
@@ -696,15 +722,20 @@ int lbm_recenter(lbm_ctx *c, void *stream) {
 
 // a tile shape usable here: in the table, 3-term polynomials for the
 // non-default shapes (tiles wrap periodically, so any grid size will do)
+static bool shape_of(const lbm_ctx *c, int shape, int *rows, int *waves) {
+    return c->dm.q == 9 ? two_step_shape_of(c->dm.prec, shape, rows, waves)
+                        : two_step3_shape_of(c->dm.prec, shape, rows, waves);
+}
+
 static bool two_shape_usable(const lbm_ctx *c, int shape) {
     int rows = 0, waves = 0;
-    if (!two_step_shape_of(c->dm.prec, shape, &rows, &waves)) return false;
+    if (!shape_of(c, shape, &rows, &waves)) return false;
     return shape == 0 || c->dm.deg3;
 }
 
 int lbm_two_step_shape(const lbm_ctx *c, int shape, int *rows, int *waves) {
     if (!c || !rows || !waves) return fail(LBM_E_INVALID, "null argument");
-    if (!two_step_shape_of(c->dm.prec, shape, rows, waves)) return fail(LBM_E_INVALID, "no such tile shape");
+    if (!shape_of(c, shape, rows, waves)) return fail(LBM_E_INVALID, "no such tile shape");
     return LBM_OK;
 }
 
@@ -712,7 +743,9 @@ int lbm_set_two_step(lbm_ctx *c, int mode) {
     if (!c) return fail(LBM_E_INVALID, "null context");
     if (mode < 0) return fail(LBM_E_INVALID, "mode must be 0 (off) or 1 + a tile shape");
     if (mode && !c->two_ok)
-        return fail(LBM_E_UNSUPPORTED, "two steps per pass need D2Q9, periodic axes and equal non-flux rates");
+        return fail(LBM_E_UNSUPPORTED,
+                    "two steps per pass need equal non-flux rates and D2Q9 with periodic axes, or D3Q19 without a "
+                    "source and with polynomials of degree <= 2");
     if (mode && eff_dims(c).sb && !c->dm.deg3)
         return fail(LBM_E_UNSUPPORTED, "two steps per pass with a Scheme-B source need polynomials of degree <= 2");
     if (mode && c->bound && keeps_history(c) && !c->p2)
@@ -896,7 +929,7 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
 
 // Two reversed sweeps per launch: the forward pass's tile conditions.
 static bool adjoint_pair_applies(const lbm_ctx *c) {
-    return c->two_ok && c->dm.prec != 2 && c->adj_slots <= (uint32_t)kMaxAdjParts;
+    return c->dm.q == 9 && c->two_ok && c->dm.prec != 2 && c->adj_slots <= (uint32_t)kMaxAdjParts;
 }
 
 int lbm_adjoint_pair_ok(const lbm_ctx *c, int *ok) {
@@ -1034,13 +1067,14 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
         // FP64 14 x 16 (lbm_set_two_step shape 2) is left out: it won short
         // trials on some boxes and then ran 12% slower than 6 x 4 over 5000
         // steps (61.5 against 70 GLUPS on 1024^2).
-        static const int order4[4] = {1, 3, 0, 2}, order8[2] = {0, 1};
-        const int nshape = c->dm.prec == 0 ? 2 : 4;
+        static const int order4[4] = {1, 3, 0, 2}, order8[2] = {0, 1}, order3[3] = {0, 1, 2};
+        const int *order = c->dm.q == 19 ? order3 : (c->dm.prec == 0 ? order8 : order4);
+        const int nshape = c->dm.q == 19 ? (c->dm.prec == 0 ? 2 : 3) : (c->dm.prec == 0 ? 2 : 4);
         float tms[4][2];
         for (int ri = 0; ri < remaps * nshape; ++ri) tms[ri / remaps][ri % remaps] = -1.f;
         for (int pass = 0; pass < 2; ++pass) {
             for (int ri = 0; ri < remaps * nshape; ++ri) {
-                const int shape = c->dm.prec == 0 ? order8[ri / remaps] : order4[ri / remaps];
+                const int shape = order[ri / remaps];
                 if (!two_shape_usable(c, shape)) continue;
                 c->two_shape = shape;
                 c->g.remap = (remaps == 2 && ri % remaps == 0) ? 1u : 0u;
@@ -1062,12 +1096,12 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
         }
         float best_two_ms = 1e30f;
         for (int ri = 0; ri < remaps * nshape; ++ri) {
-            const int shape = c->dm.prec == 0 ? order8[ri / remaps] : order4[ri / remaps];
+            const int shape = order[ri / remaps];
             const float ms = tms[ri / remaps][ri % remaps];
             if (ms < 0.f) continue;
             const uint32_t remap = (remaps == 2 && ri % remaps == 0) ? 1u : 0u;
             int rows = 0, waves = 0;
-            two_step_shape_of(c->dm.prec, shape, &rows, &waves);
+            shape_of(c, shape, &rows, &waves);
             char line[112];
             std::snprintf(line, sizeof(line), "two steps per pass rows %d waves %d remap %u: %.4f ms per step\n",
                           rows, waves, remap, ms);
@@ -1086,7 +1120,7 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
     c->two_shape = best_shape;
     drop_graphs(c);
     int brows = 0, bwaves = 0;
-    if (best_two) two_step_shape_of(c->dm.prec, best_shape, &brows, &bwaves);
+    if (best_two) shape_of(c, best_shape, &brows, &bwaves);
     char line[160];
     std::snprintf(line, sizeof(line), "chosen chunk %d nt %d remap %u two %d rows %d waves %d (%.4f ms)", best_chunk,
                   (int)best_nt, best_remap, (int)best_two, brows, bwaves, best);

@@ -191,6 +191,67 @@ hipError_t sweep2_typed(const Dims &dm, const Geom &g, const void *coefs, const 
     }
 }
 
+// Tile shapes of the D3Q19 two-step pass, (rows TY, waves per workgroup), one
+// phase-1 row per wave.  The LDS ring holds 38 planes of 64 x (TY + 2)
+// values: FP32 156 KB at TY = 14 (one workgroup of 16 waves per CU), 78 KB at
+// TY = 6 (two of 8 waves), 39 KB at TY = 2; FP64 156 KB at TY = 6, 78 KB at
+// TY = 2.  Shape 0 measured fastest on 256^3 with walls.
+template <typename TS>
+constexpr int two_step3_shape_count() { return sizeof(TS) == 8 ? 2 : 3; }
+
+template <typename TS>
+constexpr bool two_step3_shape(int id, int &rows, int &waves) {
+    constexpr int r8[2][2] = {{6, 8}, {2, 4}};
+    constexpr int r4[3][2] = {{14, 16}, {6, 8}, {2, 4}};
+    if (id < 0 || id >= two_step3_shape_count<TS>()) return false;
+    rows = sizeof(TS) == 8 ? r8[id][0] : r4[id][0];
+    waves = sizeof(TS) == 8 ? r8[id][1] : r4[id][1];
+    return true;
+}
+
+template <typename TS, typename TC, int TY, int NW>
+hipError_t sweep2_3d_shape(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                           int *flag, uint32_t zc, hipStream_t st) {
+    const auto *cf = (const Coefs<TC> *)coefs;
+    const uint32_t tiles_x = (g.nx + 61) / 62, tiles_y = (g.ny + TY - 1) / TY, tiles_z = (g.nz + zc - 1) / zc;
+    const dim3 grid(tiles_x * tiles_y * tiles_z), block(64 * NW);
+    const TS *fi = (const TS *)fin;
+    TS *fo = (TS *)fout;
+    const int code = (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
+#define LBM_SW3(K, W)                                                                                \
+    case (K * 2 + W):                                                                                \
+        hipLaunchKernelGGL((k_sweep2_3d<TS, TC, K, W, 3, TY, NW>), grid, block, 0, st, g, cf, fi, fo, tiles_x, \
+                           tiles_y, zc, flag);                                                       \
+        break;
+    switch (code) {
+        LBM_SW3(0, 0) LBM_SW3(0, 1) LBM_SW3(1, 0) LBM_SW3(1, 1)
+        default: return hipErrorInvalidValue;
+    }
+#undef LBM_SW3
+    return hipGetLastError();
+}
+
+// D3Q19 two steps per pass: equal non-flux rates, 3-term polynomials, no source
+// (no phi history), walls on z or periodic; chunks of zc planes.
+template <int Q, typename TS, typename TC>
+hipError_t sweep2_3d_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout, int *flag,
+                           int shape, uint32_t zc, hipStream_t st) {
+    if constexpr (Q == 19) {
+        if (!dm.eqr || !dm.deg3 || !dm.o32 || dm.src || dm.sb || zc < 1) return hipErrorNotSupported;
+        if constexpr (sizeof(TS) == 8) {
+            if (shape == 0) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, flag, zc, st);
+            if (shape == 1) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, flag, zc, st);
+        } else {
+            if (shape == 0) return sweep2_3d_shape<TS, TC, 14, 16>(dm, g, coefs, fin, fout, flag, zc, st);
+            if (shape == 1) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, flag, zc, st);
+            if (shape == 2) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, flag, zc, st);
+        }
+        return hipErrorInvalidValue;
+    } else {
+        return hipErrorNotSupported;
+    }
+}
+
 // Scheme B and/or per-node fields: the general kernel (any polynomial length).
 template <int Q, typename TS, typename TC>
 hipError_t sweep_gen_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,

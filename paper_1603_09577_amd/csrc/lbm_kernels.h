@@ -389,8 +389,10 @@ __device__ __forceinline__ void gather_rw(const Geom &g, const Coefs<TC> *__rest
 // Eq. 35 is the quadratic  a x^2 + b x + c = 0  with a = r2 / 2,
 // b = R'(phi_ref) / 2 - 1, c = x0 + R(phi_ref) / 2, and the root that tends to
 // x0 + R / 2 as R -> 0 is x = 2 c / (sqrt(b^2 - 4 a c) - b): with b close to
-// -1 the denominator is close to 2, so no digits cancel.  Returns x and sets
-// *R = R(phi_ref + x).
+// -1 the denominator is close to 2, so no digits cancel.  Sets *R = R at that
+// root and returns x0 + R / 2 (Eq. 35 itself, equal to the root up to
+// rounding): the sweep then writes exactly the stored mass plus R, whereas the
+// root's own rounding error, biased in FP32, would add to the mass every step.
 template <typename T, typename TC>
 __device__ __forceinline__ T phi_scheme_b(const Coefs<TC> *__restrict__ cf, T x0, T rext, T *R) {
     if (cf->nr <= 1) {
@@ -404,7 +406,7 @@ __device__ __forceinline__ T phi_scheme_b(const Coefs<TC> *__restrict__ cf, T x0
     const T x = T(2) * c / (sqrt(b * b - T(4) * a * c) - b);
     const T phi = pr + x;
     *R = r0 + phi * (r1 + phi * r2);
-    return x;
+    return x0 + T(0.5) * *R;
 }
 
 // One node of the sweep (shared by the single-instance and batched kernels).
@@ -911,6 +913,185 @@ k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ 
 
 // The general sweep: Scheme B and/or per-node fields.  Polynomials of any
 // length, K(phi) evaluated per node, Scheme-A history kept when SB is off.
+// ---------------------------------------------------------------------------
+// Two time steps per pass for D3Q19 (equal non-flux rates, no source, any
+// walls on z).  A workgroup owns a column of 62 x TY nodes in x and y and a
+// chunk of zc planes in z, and marches up the chunk.  At logical plane i
+// (z = z0 - 1 + i) phase 1 runs step t on the column plus a one-node halo in
+// x and y and keeps the post-collision populations in LDS, rounded to the
+// storage type as a store would round them; phase 2 then runs step t + 1 on
+// plane i - 1 of the column's own nodes, gathering from LDS, and stores only
+// that result.  The ring is split by the z component of the velocity:
+// c_z = +1 populations are read one plane up (two slots by plane parity,
+// written after phase 2 since slot i & 1 still holds plane i - 2 then),
+// c_z = 0 on their own plane (two slots) and c_z = -1 one plane down (two
+// slots: at the low wall a node also reads its own c_z = -1 populations).
+// Every node update is the one-sweep arithmetic on the same inputs, so the
+// result equals two single sweeps bit for bit; the state crosses HBM once
+// per two steps.  Planes beyond a wall are not computed: the gather there is
+// the anti-bounce-back form, -f*_opp(k) of the node itself plus the wall term.
+// ---------------------------------------------------------------------------
+struct Zc3 {
+    // the populations of Eq. 6 by the z component of their velocity
+    static constexpr int p[5] = {5, 11, 13, 15, 18};                 // c_z = +1
+    static constexpr int z[9] = {0, 1, 2, 3, 4, 7, 8, 9, 10};        // c_z = 0
+    static constexpr int m[5] = {6, 12, 14, 16, 17};                 // c_z = -1
+    // position of population k within its class
+    static constexpr int pos(int k) {
+        for (int i = 0; i < 5; ++i) if (p[i] == k || m[i] == k) return i;
+        for (int i = 0; i < 9; ++i) if (z[i] == k) return i;
+        return -1;
+    }
+};
+
+// Phase 1 reads each population from a wave-uniform source row (plane
+// z - c_z and row y - c_y, periodic, a 32-bit byte offset) plus one of three
+// per-lane column offsets (x - c_x, periodic), and the loads of the next
+// plane are issued before the current plane's arithmetic, so that their
+// latency overlaps phase 1, phase 2 and both barriers.
+template <typename TS, typename TC, bool KVAR, bool WALL, int NP, int TY, int NW>
+__global__ void __launch_bounds__(64 * NW)
+k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
+            uint32_t tiles_x, uint32_t tiles_y, uint32_t zc, int *flag) {
+    using L = Lattice<19>;
+    constexpr int TX = 64, TR = TY + 2;
+    constexpr int PR = (TR + NW - 1) / NW;          // phase-1 rows per wave
+    __shared__ TS rp[2][5][TR][TX];
+    __shared__ TS r0[2][9][TR][TX];
+    __shared__ TS rm[2][5][TR][TX];
+    const uint32_t blk = block_index(blockIdx.x, gridDim.x, g.remap);
+    const uint32_t per_z = tiles_x * tiles_y;
+    const uint32_t tz = blk / per_z, rem = blk - tz * per_z;
+    const uint32_t tyi = rem / tiles_x, txi = rem - tyi * tiles_x;
+    const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz;
+    const int x0 = (int)(txi * (TX - 2)), y0 = (int)(tyi * TY), z0 = (int)(tz * zc);
+    const int zend = min(z0 + (int)zc, nz);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int xg = wrap_coord(x0 - 1 + lane, nx);
+    // byte offsets of the source columns x - c_x for c_x = 1, 0, -1
+    uint32_t cb[3] = {(uint32_t)(xg == 0 ? nx - 1 : xg - 1) * (uint32_t)sizeof(TS),
+                      (uint32_t)xg * (uint32_t)sizeof(TS),
+                      (uint32_t)(xg == nx - 1 ? 0 : xg + 1) * (uint32_t)sizeof(TS)};
+    const uint32_t row_bytes = g.nx * (uint32_t)sizeof(TS);
+    bool bad = false;
+    const int nplanes = zend - z0 + 2;
+    // raw values of the phase-1 gathers of logical plane i (this wave's rows):
+    // population k from the source node, or at a wall the own node's opposite
+    auto load = [&](int i, TS (&dst)[PR][19]) {
+        const int zl = z0 - 1 + i;
+        if (WALL && (zl < 0 || zl >= nz)) return;
+        const int zg = WALL ? zl : wrap_coord(zl, nz);
+        const int zs[3] = {zg == nz - 1 ? 0 : zg + 1, zg, zg == 0 ? nz - 1 : zg - 1};   // z - c_z, c_z = -1, 0, 1
+#pragma unroll
+        for (int j = 0; j < PR; ++j) {
+            const int r = wv + j * NW;
+            if (r < TR) {
+                const int yg = wrap_coord(y0 - 1 + r, ny);
+                const int ys[3] = {yg == ny - 1 ? 0 : yg + 1, yg, yg == 0 ? ny - 1 : yg - 1};   // y - c_y
+#pragma unroll
+                for (int k = 0; k < 19; ++k) {
+                    const int cx = L::cx(k), cy = L::cy(k), cz = L::cz(k);
+                    const bool wl = WALL && ((cz == 1 && zg == 0) || (cz == -1 && zg == nz - 1));
+                    const uint32_t rb = wl ? ((uint32_t)zg * g.ny + (uint32_t)yg) * row_bytes
+                                           : ((uint32_t)zs[1 + cz] * g.ny + (uint32_t)ys[1 + cy]) * row_bytes;
+                    dst[j][k] = wl ? *row_elem(fin + (uint64_t)L::opp(k) * g.plane, rb, cb[1])
+                                   : *row_elem(fin + (uint64_t)k * g.plane, rb, cb[1 - cx]);
+                }
+            }
+        }
+    };
+    TS hn[PR][19];
+    load(0, hn);
+    for (int i = 0; i < nplanes; ++i) {
+        const int zl = z0 - 1 + i;
+        const int s1 = i & 1, s0 = s1 ^ 1;          // slots of plane i and of plane i - 1
+        const bool p1 = WALL ? (zl >= 0 && zl < nz) : true;
+        const int zg = WALL ? zl : wrap_coord(zl, nz);
+        TS hc[PR][19];
+#pragma unroll
+        for (int j = 0; j < PR; ++j)
+#pragma unroll
+            for (int k = 0; k < 19; ++k) hc[j][k] = hn[j][k];
+        if (i + 1 < nplanes) load(i + 1, hn);
+        // phase 1: plane zl (skipped beyond a wall)
+        TS keep[PR][5];
+        if (p1) {
+#pragma unroll
+            for (int j = 0; j < PR; ++j) {
+                const int r = wv + j * NW;
+                if (r < TR) {
+                    TC h[19];
+#pragma unroll
+                    for (int k = 0; k < 19; ++k) {
+                        const int cz = L::cz(k);
+                        const bool wl = WALL && ((cz == 1 && zg == 0) || (cz == -1 && zg == nz - 1));
+                        h[k] = wl ? -(TC)hc[j][k] + cf->ew[cz == 1 ? 0 : 1][k] : (TC)hc[j][k];
+                    }
+                    TC out[19];
+                    const TC phio = collide_node<19, TC, true, false, KVAR, NP>(cf, h, TC(0), 0u, nullptr, nullptr,
+                                                                               false, out);
+                    bad |= !__builtin_isfinite(phio);
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) r0[s1][c][r][lane] = (TS)out[Zc3::z[c]];
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) {
+                        rm[s1][c][r][lane] = (TS)out[Zc3::m[c]];
+                        keep[j][c] = (TS)out[Zc3::p[c]];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // phase 2: plane zl - 1 of the column's own nodes
+        if (i >= 2 && lane >= 1 && lane <= TX - 2) {
+            const int zc2 = zl - 1;
+            const bool lo = WALL && zc2 == 0, hi = WALL && zc2 == nz - 1;
+            const int x = x0 + lane - 1;
+            for (int r = 1 + wv; r <= TY; r += NW) {
+                const int y = y0 + r - 1;
+                TC h[19];
+#pragma unroll
+                for (int k = 0; k < 19; ++k) {
+                    const int cx = L::cx(k), cy = L::cy(k), cz = L::cz(k);
+                    if (WALL && cz == 1 && lo) {
+                        h[k] = -(TC)rm[s0][Zc3::pos(L::opp(k))][r][lane] + cf->ew[0][k];
+                    } else if (WALL && cz == -1 && hi) {
+                        h[k] = -(TC)rp[s0][Zc3::pos(L::opp(k))][r][lane] + cf->ew[1][k];
+                    } else if (cz == 1) {
+                        h[k] = (TC)rp[s1][Zc3::pos(k)][r - cy][lane - cx];
+                    } else if (cz == -1) {
+                        h[k] = (TC)rm[s1][Zc3::pos(k)][r - cy][lane - cx];
+                    } else {
+                        h[k] = (TC)r0[s0][Zc3::pos(k)][r - cy][lane - cx];
+                    }
+                }
+                TC out[19];
+                const TC phio = collide_node<19, TC, true, false, KVAR, NP>(cf, h, TC(0), 0u, nullptr, nullptr,
+                                                                           false, out);
+                bad |= !__builtin_isfinite(phio);
+                if (x < nx && y < ny) {
+                    const uint32_t m = ((uint32_t)zc2 * g.ny + (uint32_t)y) * g.nx + (uint32_t)x;
+                    store_planes<19, false>(fout, g.plane, m, out);
+                }
+            }
+        }
+        __syncthreads();
+        // the c_z = +1 populations of plane i, now that plane i - 2's are read
+        if (p1) {
+#pragma unroll
+            for (int j = 0; j < PR; ++j) {
+                const int r = wv + j * NW;
+                if (r < TR) {
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) rp[s1][c][r][lane] = keep[j][c];
+                }
+            }
+        }
+    }
+    if (bad) *flag = 1;
+}
+
 template <int Q, typename TS, typename TC, bool EQR, bool WALL, bool SB>
 __global__ void __launch_bounds__(kBlock)
 k_sweep_gen(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin,

@@ -57,4 +57,16 @@ hipError_t launch_set_wall_q19(const Dims &dm, void *coefs, const double *ewp, h
     LBM_BY_PREC(set_wall_typed, dm, coefs, ewp, st)
 }
 
+hipError_t launch_sweep2_q19(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                             int *flag, int shape, uint32_t zc, hipStream_t st) {
+    LBM_BY_PREC(sweep2_3d_typed, dm, g, coefs, fin, fout, flag, shape, zc, st)
+}
+
+bool two_step3_shape_of(int prec, int shape, int *rows, int *waves) {
+    int r = 0, w = 0;
+    const bool ok = prec == 0 ? two_step3_shape<double>(shape, r, w) : two_step3_shape<float>(shape, r, w);
+    if (ok) { *rows = r; *waves = w; }
+    return ok;
+}
+
 }  // namespace lbm

@@ -430,14 +430,57 @@ def test_two_step_passes_scheme_b_bit_identical(nx, ny, prec, shape):
         assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
 
 
+@pytest.mark.parametrize("n,prec,wall,shape", [((20, 18, 22), "f32", True, 0), ((20, 18, 22), "f64", True, 0),
+                                                ((70, 13, 9), "f32", False, 1), ((33, 7, 11), "f64", False, 1),
+                                                ((65, 9, 17), "f32", True, 2), ((9, 5, 4), "f16", True, 0),
+                                                ((3, 2, 2), "f32", True, 1), ((1, 1, 3), "f64", False, 0),
+                                                ((64, 30, 40), "f64", True, 0), ((130, 37, 21), "f32", True, 0),
+                                                ((40, 20, 30), "f16", False, 2)])
+def test_two_step_passes_d3q19_bit_identical(n, prec, wall, shape):
+    """D3Q19 two steps per pass (columns of 62 x 14, 6 or 2 nodes marching up
+    chunks of z planes through an LDS ring) against single sweeps: phi and the
+    stored state agree bit for bit after even and odd step counts, with and
+    without walls on z, on grids narrower and lower than a tile; the FP64
+    result matches the oracle."""
+    lbm = _lbm()
+    spec, _, _ = W.d3q19_walls(n, precision=prec)
+    if not wall:
+        spec["bc"] = ["periodic"] * 3
+    spec["phi_wall"] = [[0, 0], [0, 0], [0.3, 0.6]] if wall else spec["phi_wall"]
+    phi0 = W.gaussians_3d(n, 21)
+    say(f"[gpu] two-step passes d3q19 {n} {prec} walls={wall} shape={shape}")
+    a = lbm.Lbm(spec).init(phi0)
+    a.set_two_step(False)
+    b = lbm.Lbm(spec).init(phi0)
+    b.set_two_step(True, shape)
+    t = 0
+    for s in (4, 8, 37, 70):
+        a.step(s - t)
+        b.step(s - t)
+        t = s
+        assert torch.equal(a.phi(), b.phi()), s
+        wa, _ = a.current()
+        wb, _ = b.current()
+        assert wa == wb
+        assert torch.equal(a.storage_view(a.f[wa]), b.storage_view(b.f[wb])), s
+    if prec == "f64":
+        ref = oracle_run(spec, phi0, (70,))[70]
+        got = b.phi().cpu().numpy()
+        assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
+
+
 def test_two_step_refused_where_it_does_not_apply():
     lbm = _lbm()
     walls = dict(W.spec_nonlinear_2d(70, 30), bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]])
-    for spec in (W.d3q19_walls((20, 18, 22))[0], walls):
+    d3_src = dict(W.d3q19_walls((20, 18, 22))[0], rpoly=[0.0, 0.01, -0.01])
+    d3_rates = dict(W.d3q19_walls((20, 18, 22))[0], s=[0.0] + [1.0 + 0.01 * i for i in range(18)])
+    for spec in (d3_src, d3_rates, walls):
         s = lbm.Lbm(spec)
         with pytest.raises(lbm.LbmError) as ei:
             s.set_two_step(True)
         assert ei.value.code == lbm.LBM_E_UNSUPPORTED
+    assert lbm.Lbm(W.d3q19_walls((20, 18, 22))[0]).two_step_shapes() == [(6, 8), (2, 4)]
+    assert lbm.Lbm(W.d3q19_walls((20, 18, 22), precision="f32")[0]).two_step_shapes() == [(14, 16), (6, 8), (2, 4)]
     # tile shapes: 4 for 4- and 2-byte storage, 2 for FP64; the non-default
     # ones need 3-term polynomials
     assert lbm.Lbm(W.spec_nonlinear_2d(100, 37, precision="f32")).two_step_shapes() == \
