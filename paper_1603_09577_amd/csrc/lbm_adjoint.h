@@ -425,12 +425,12 @@ __device__ __forceinline__ TC adjoint_node(const Coefs<TC> *__restrict__ cf, con
 // waves in FP64 with (3/d) applied; the workgroup owns `slot` and adds to it
 // over the reversed sweeps (folded once when the gradient is read).  In 2-D
 // only xx, yy and xy (slots 0, 1, 3) can be non-zero.  Called by every thread
-// of the workgroup; sh is workgroup memory for 6 x (kBlock / 64) doubles that
-// no thread still reads.
-template <int D, typename TC>
+// of the workgroup; sh is workgroup memory for 6 x NW doubles (NW waves per
+// workgroup) that no thread still reads.
+template <int D, int NW = kBlock / 64, typename TC>
 __device__ __forceinline__ void k0_partials(const Coefs<TC> *__restrict__ cf, const TC *gk,
                                             double *__restrict__ gk_part, uint32_t slot,
-                                            double (*sh)[kBlock / 64]) {
+                                            double (*sh)[NW]) {
     constexpr int NK = D == 2 ? 3 : 6;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -445,7 +445,7 @@ __device__ __forceinline__ void k0_partials(const Coefs<TC> *__restrict__ cf, co
         const int i = (D == 2 && j == 2) ? 3 : j;
         double v = 0.0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) v += sh[j][w];
+        for (int w = 0; w < NW; ++w) v += sh[j][w];
         // An atomic add without return instead of a load, an add and a
         // store: the workgroup's last wave no longer waits for a global load
         // before it can finish.  The slot belongs to this workgroup and the
@@ -505,6 +505,18 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
     k0_partials<D>(cf, gk, gk_part, blockIdx.x, sh);
 }
 
+// Row (halo included) that row slot j of a tile of TR rows takes when NW
+// waves split the rows, slot j = wave + pass * NW.  With several rows per
+// wave, the first pass takes the four rows the tile shares with the tiles
+// above and below (0, 1, TR - 2, TR - 1), so that both tiles read them at
+// about the same time and the second read finds them in L2 (FP64 512^2:
+// fetched bytes 1.10 -> 1.03 x the algorithmic reads); the inner rows
+// follow.  A permutation of 0 .. TR - 1 for every TR >= 4.
+template <int TR, int NW>
+__device__ __forceinline__ constexpr int shared_rows_first(int j) {
+    return (TR / NW == 1 || j < 2) ? j : (j < 4 ? TR - 4 + j : j - 2);
+}
+
 // Two reversed sweeps in one pass (D2Q9, periodic, equal rates): sweep s,
 // then sweep s - 1, on a tile of 62 x TH nodes.  Phase 1 runs the reversed
 // map of sweep s on the tile and a one-node halo around it (64 x (TH + 2)
@@ -517,11 +529,13 @@ k_adjoint(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__
 // count only the tile's own nodes (the halo belongs to the neighbours).
 // pi_out must differ from pi_next: neighbouring tiles still read pi_{s+1} at
 // their halo.
+// A workgroup has NW waves; the TH + 2 rows of phase 1 split evenly over
+// them, and phase 2 gives the TH own rows to the waves in turn.
 // FP64 with short polynomials is held to 3 waves per SIMD (168 registers),
 // what the workgroup memory of its 6-row tiles allows anyway (3 workgroups of
 // 4 waves per CU); with 9-term polynomials that limit would spill.
-template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH>
-__global__ void __launch_bounds__(kBlock)
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW>
+__global__ void __launch_bounds__(NW * 64)
 __attribute__((amdgpu_waves_per_eu(sizeof(TC) == 8 && NP <= 4 ? 3 : 1, 8)))
 k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f1,
            const typename HistType<TS>::T *__restrict__ p1, const TS *__restrict__ f0,
@@ -530,8 +544,8 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
            double *__restrict__ gk_part, uint32_t tiles_x) {
     using L = Lattice<9>;
     constexpr int TX = 64, TR = TH + 2;
-    static_assert(TR % (kBlock / 64) == 0, "tile rows must split evenly over the waves");
-    static_assert(sizeof(TC) * 9 * TR * TX >= sizeof(double) * 6 * (kBlock / 64), "reduction scratch");
+    static_assert(TR % NW == 0, "tile rows must split evenly over the waves");
+    static_assert(sizeof(TC) * 9 * TR * TX >= sizeof(double) * 6 * NW, "reduction scratch");
     __shared__ alignas(16) TC lpsi[9][TR][TX];
     __shared__ TC lpi[TR][TX];
     const uint32_t tile = block_index(blockIdx.x, gridDim.x, g.remap);
@@ -559,10 +573,10 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
     const uint32_t rowb = g.nx * (uint32_t)sizeof(TS);
     // FP32 unrolls the rows (all loads in flight); FP64 takes them one by one
     // (about 165 registers per lane as it is: 3 waves per SIMD)
-    constexpr int kUnroll = sizeof(TC) == 4 ? TR / (kBlock / 64) : 1;
+    constexpr int kUnroll = sizeof(TC) == 4 ? TR / NW : 1;
 #pragma unroll kUnroll
-    for (int i = 0; i < TR / (kBlock / 64); ++i) {
-        const int r = wv + i * (kBlock / 64);
+    for (int i = 0; i < TR / NW; ++i) {
+        const int r = shared_rows_first<TR, NW>(wv + i * NW);
         const int yg = wrap_coord(y0 - 1 + r, ny);
         const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
         w.n = n;
@@ -588,7 +602,7 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
     // phase 2: the tile's own nodes, psi_s gathered from x + c_k in the tile
     if (xown) {
         const uint32_t x = (uint32_t)(x0 + lane - 1);
-        for (int r = 1 + wv; r <= TH && y0 + r - 1 < ny; r += kBlock / 64) {
+        for (int r = 1 + wv; r <= TH && y0 + r - 1 < ny; r += NW) {
             const int y = y0 + r - 1;
             const uint32_t n = (uint32_t)y * g.nx + x;
             w.n = n;
@@ -606,7 +620,7 @@ k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict_
         }
     }
     __syncthreads();   // the tile buffer becomes the reduction scratch
-    k0_partials<2>(cf, gk, gk_part, blockIdx.x, reinterpret_cast<double(*)[kBlock / 64]>(&lpsi[0][0][0]));
+    k0_partials<2, NW>(cf, gk, gk_part, blockIdx.x, reinterpret_cast<double(*)[NW]>(&lpsi[0][0][0]));
 }
 
 // zero the per-workgroup K0 slots (a kernel, so that the adjoint can be

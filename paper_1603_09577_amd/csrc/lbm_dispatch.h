@@ -412,14 +412,14 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
 
 // Two reversed sweeps per pass (D2Q9, periodic, equal rates): sweep s with
 // (f1, p1), then sweep s - 1 with (f0, p0); TH tile rows.
-template <typename TS, typename TC, int TH>
+template <typename TS, typename TC, int TH, int NW>
 hipError_t adjoint2_rows(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
                          const void *f0, const void *p0, const void *psi_next, const double *pi_next,
                          void *psi_out, double *pi_out, double *gk_part, hipStream_t st) {
     using TP = typename HistType<TS>::T;
     const auto *cf = (const Coefs<TC> *)coefs;
     const uint32_t tiles_x = (g.nx + 61) / 62, tiles_y = (g.ny + TH - 1) / TH;
-    const dim3 grid(tiles_x * tiles_y), block(kBlock);
+    const dim3 grid(tiles_x * tiles_y), block(NW * 64);
     const auto *a1 = (const TS *)f1, *a0 = (const TS *)f0;
     const auto *q1 = (const TP *)p1, *q0 = (const TP *)p0;
     const auto *pn = (const TC *)psi_next;
@@ -427,7 +427,7 @@ hipError_t adjoint2_rows(const Dims &dm, const Geom &g, const void *coefs, const
     const int code = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.deg3 ? 8 : (dm.lowdeg ? 1 : 0));
 #define LBM_ADJ2(S, K, NP, TAG)                                                                      \
     case (S * 4 + K * 2 + TAG):                                                                      \
-        hipLaunchKernelGGL((k_adjoint2<TS, TC, S, K, NP, TH>), grid, block, 0, st, g, cf, a1, q1, a0, q0, pn, \
+        hipLaunchKernelGGL((k_adjoint2<TS, TC, S, K, NP, TH, NW>), grid, block, 0, st, g, cf, a1, q1, a0, q0, pn, \
                            pi_next, po, pi_out, gk_part, tiles_x);                                   \
         break;
     switch (code) {
@@ -453,14 +453,14 @@ hipError_t adjoint2_typed(const Dims &dm, const Geom &g, const void *coefs, cons
                           void *psi_out, double *pi_out, double *gk_part, hipStream_t st) {
     static_assert(Q == 9, "two reversed sweeps per pass are D2Q9 only");
     if constexpr (sizeof(TC) == 8) {
-        return adjoint2_rows<TS, TC, 6>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out, gk_part,
-                                        st);
+        return adjoint2_rows<TS, TC, 6, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
+                                           gk_part, st);
     } else {
         if (adjoint_pair_rows_for(dm.prec, g.nx, g.ny) == 14)
-            return adjoint2_rows<TS, TC, 14>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
-                                             gk_part, st);
-        return adjoint2_rows<TS, TC, 6>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out, gk_part,
-                                        st);
+            return adjoint2_rows<TS, TC, 14, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
+                                                gk_part, st);
+        return adjoint2_rows<TS, TC, 6, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
+                                           gk_part, st);
     }
 }
 

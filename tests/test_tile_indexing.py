@@ -49,6 +49,23 @@ def row_form_index(x, y, nx, ny, k, sign):
     return rows[1 + sign * CY[k]] * nx + cols[1 + sign * CX[k]]
 
 
+def shared_rows_first(j, tr, nw):
+    """Row of slot j = wave + pass * nw of a two-sweep adjoint tile of tr rows:
+    with several rows per wave the four rows shared with the neighbouring
+    tiles come first."""
+    if tr // nw == 1 or j < 2:
+        return j
+    return tr - 4 + j if j < 4 else j - 2
+
+
+@pytest.mark.parametrize("tr,nw", [(8, 4), (8, 8), (16, 4), (16, 8), (16, 16), (12, 6), (4, 4), (8, 2)])
+def test_shared_rows_first_is_a_permutation(tr, nw):
+    rows = [shared_rows_first(wv + i * nw, tr, nw) for wv in range(nw) for i in range(tr // nw)]
+    assert sorted(rows) == list(range(tr))
+    if tr // nw > 1 and nw >= 4:
+        assert sorted(shared_rows_first(wv, tr, nw) for wv in range(4)) == [0, 1, tr - 2, tr - 1]
+
+
 SIZES = [(a, b) for a in (1, 2, 3, 61, 62, 63, 64, 65) for b in (1, 2, 3, 7, 14, 15, 17)] + [(130, 33)]
 
 
@@ -73,12 +90,12 @@ def test_two_step_phase1_rows(th, nw):
                                 assert 0 <= got < nx * ny
 
 
-@pytest.mark.parametrize("th", [6, 14])
-def test_two_sweep_adjoint_rows(th):
-    """Both phases of the two-sweep adjoint tile (4 waves): phase 1 gathers the
-    forward state (pull) and psi (transposed) on the tile and halo; phase 2
+@pytest.mark.parametrize("th,nw", [(6, 4), (14, 4)])
+def test_two_sweep_adjoint_rows(th, nw):
+    """Both phases of the two-sweep adjoint tile (nw waves): phase 1 gathers
+    the forward state (pull) and psi (transposed) on the tile and halo; phase 2
     gathers the forward state at the tile's own nodes."""
-    tr, nw = th + 2, 4
+    tr = th + 2
     for nx, ny in SIZES:
         for ty in range((ny + th - 1) // th):
             for tx in range((nx + TILE_W - 1) // TILE_W):
@@ -88,7 +105,7 @@ def test_two_sweep_adjoint_rows(th):
                     own = 1 <= lane <= TILE_W and x0 + lane - 1 < nx
                     for wv in range(nw):
                         for i in range(tr // nw):
-                            yg = wrap(y0 - 1 + wv + i * nw, ny)
+                            yg = wrap(y0 - 1 + shared_rows_first(wv + i * nw, tr, nw), ny)
                             n = yg * nx + xg
                             for k in range(9):
                                 for sign in (-1, 1):
