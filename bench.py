@@ -117,8 +117,9 @@ def time_steps(torch, sim, steps, warmup, samples=SAMPLES):
 # tile shape forced on D2Q9 two-step runs after tuning, with the XCD-aware
 # order (--two-step-shape; None: the tuner's choices)
 TWO_STEP_SHAPE = None
-# (rows, waves) of the two-step pass forced on D3Q19 runs (--two-step-3d;
-# None: the tuner's choice between single sweeps and each shape)
+# [(rows, waves), ...] two-step shapes forced on D3Q19 runs, the first the
+# precision has (--two-step-3d; None: the tuner's choice between single
+# sweeps and each shape)
 TWO_STEP_3D = None
 
 
@@ -133,9 +134,10 @@ def run_forward(torch, lbm, spec, phi0, steps, warmup, label, tune=True, two_ste
         rep += f"; two steps per pass forced {'on' if two_step else 'off'}"
     if TWO_STEP_3D is not None and sim.q == 19 and two_step is None:
         shapes = sim.two_step_shapes()
-        if TWO_STEP_3D in shapes:
-            sim.set_two_step(True, shapes.index(TWO_STEP_3D))
-            r, w = TWO_STEP_3D
+        pick = next((sh for sh in TWO_STEP_3D if sh in shapes), None)
+        if pick is not None:
+            sim.set_two_step(True, shapes.index(pick))
+            r, w = pick
             rep = re.sub(r" two \d rows \d+ waves \d+", f" two 1 rows {r} waves {w}", rep)
             rep += f"; two steps per pass with shape {r} x {w} forced"
     elif TWO_STEP_SHAPE is not None and (" two 1" in rep if two_step is None else two_step):
@@ -383,21 +385,21 @@ def cpu_baseline(spec, phi0, target_s=12.0, single_s=6.0):
 
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 1000 --warmup 50 --two-step-shape 1 --two-step-3d 6x8",
+             "python3 bench.py --no-cpu --steps 1000 --warmup 50 --two-step-shape 1 --two-step-3d 14x16,6x8",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 6x8",
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 14x16,6x8",
     "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 6x8",
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 14x16,6x8",
     "valu": "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVES -d gpurun_out/pmc_valu -o valu "
             "--output-format csv -- python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19 "
-            "--two-step-shape 1 --two-step-3d 6x8",
+            "--two-step-shape 1 --two-step-3d 14x16,6x8",
     "stall": "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
              "SQ_WAIT_INST_LDS -d gpurun_out/pmc_stall -o stall --output-format csv -- "
              "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19 --two-step-shape 1 "
-             "--two-step-3d 6x8",
+             "--two-step-3d 14x16,6x8",
     "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -d gpurun_out/pmc_l2 -o l2 --output-format csv -- "
           "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19 --two-step-shape 1 "
-          "--two-step-3d 6x8",
+          "--two-step-3d 14x16,6x8",
 }
 # vector-ALU issue peak without packed FP32: each SIMD issues one 64-lane
 # instruction every 4 clocks (16 lanes per clock), 4 SIMDs per CU, so one
@@ -694,9 +696,10 @@ def main():
                     help="after tuning, run two-step passes with this tile shape (lbm_two_step_shape index) "
                          "and the XCD-aware order; the profiles pin 1 with that order, the tuner's usual choice, "
                          "so that every profiled run times the same kernel")
-    ap.add_argument("--two-step-3d", metavar="ROWSxWAVES", default=None,
-                    help="run the D3Q19 legs with two steps per pass in this tile shape (6x8 exists in every "
-                         "precision), so that the profiled runs time one kernel whatever the tuner picks")
+    ap.add_argument("--two-step-3d", metavar="ROWSxWAVES[,...]", default=None,
+                    help="run the D3Q19 legs with two steps per pass in the first of these tile shapes that the "
+                         "precision has (14x16 FP32/FP16 only, 6x8 all), so that the profiled runs time one kernel "
+                         "whatever the tuner picks")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write the profiles/ summaries from rocprofv3 output under DIR and exit (no GPU)")
     args = ap.parse_args()
@@ -708,7 +711,7 @@ def main():
     global TWO_STEP_SHAPE, TWO_STEP_3D
     TWO_STEP_SHAPE = args.two_step_shape
     if args.two_step_3d:
-        TWO_STEP_3D = tuple(int(v) for v in args.two_step_3d.lower().split("x"))
+        TWO_STEP_3D = [tuple(int(v) for v in sh.split("x")) for sh in args.two_step_3d.lower().split(",")]
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
