@@ -435,7 +435,8 @@ def test_two_step_passes_scheme_b_bit_identical(nx, ny, prec, shape):
                                                 ((65, 9, 17), "f32", True, 2), ((9, 5, 4), "f16", True, 0),
                                                 ((3, 2, 2), "f32", True, 1), ((1, 1, 3), "f64", False, 0),
                                                 ((64, 30, 40), "f64", True, 0), ((130, 37, 21), "f32", True, 0),
-                                                ((40, 20, 30), "f16", False, 2)])
+                                                ((40, 20, 30), "f16", False, 2), ((5, 4, 1), "f64", True, 0),
+                                                ((7, 3, 2), "f32", True, 1), ((66, 15, 1), "f32", False, 0)])
 def test_two_step_passes_d3q19_bit_identical(n, prec, wall, shape):
     """D3Q19 two steps per pass (columns of 62 x 14, 6 or 2 nodes marching up
     chunks of z planes through an LDS ring) against single sweeps: phi and the
