@@ -761,6 +761,15 @@ def main():
         spec5f, _, _, _ = W.adjoint_2d(precision="f32")
         extra["adjoint_f32"] = run_adjoint(torch, lbm, spec5f, p5, 200, 20, "adjoint2d-512 f32")
         print(f"# adjoint f64 {extra['adjoint_f64']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        # the same physics on 1024^2: four rounds of workgroups instead of one,
+        # where the two-sweep launches are no longer held to one round's phases
+        big = {}
+        for prec in ("f64", "f32"):
+            specb, pb, _, _ = W.adjoint_2d(1024, precision=prec)
+            big[prec] = run_adjoint(torch, lbm, specb, pb, 100, 10, f"adjoint2d-1024 {prec}")
+        extra["adjoint_1024"] = dict(big, note="not the 512^2 adjoint workload: the same physics on 1024^2, "
+                                               "reported beside it")
+        torch.cuda.empty_cache()
     if "d3q19" in only:
         spec3, p3, _ = W.d3q19_walls(precision="f32")
         d3, s3, _ = run_forward(torch, lbm, spec3, p3, 200, 20, "d3q19-256 f32")
