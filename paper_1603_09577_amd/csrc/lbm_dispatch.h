@@ -217,14 +217,15 @@ hipError_t sweep2_3d_shape(const Dims &dm, const Geom &g, const void *coefs, con
     const dim3 grid(tiles_x * tiles_y * tiles_z), block(64 * NW);
     const TS *fi = (const TS *)fin;
     TS *fo = (TS *)fout;
-    const int code = (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
-#define LBM_SW3(K, W)                                                                                \
-    case (K * 2 + W):                                                                                \
-        hipLaunchKernelGGL((k_sweep2_3d<TS, TC, K, W, 3, TY, NW>), grid, block, 0, st, g, cf, fi, fo, tiles_x, \
+    const int code = (dm.sb ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
+#define LBM_SW3(B, K, W)                                                                             \
+    case (B * 4 + K * 2 + W):                                                                        \
+        hipLaunchKernelGGL((k_sweep2_3d<TS, TC, K, W, 3, TY, NW, B>), grid, block, 0, st, g, cf, fi, fo, tiles_x, \
                            tiles_y, zc, flag);                                                       \
         break;
     switch (code) {
-        LBM_SW3(0, 0) LBM_SW3(0, 1) LBM_SW3(1, 0) LBM_SW3(1, 1)
+        LBM_SW3(0, 0, 0) LBM_SW3(0, 0, 1) LBM_SW3(0, 1, 0) LBM_SW3(0, 1, 1)
+        LBM_SW3(1, 0, 0) LBM_SW3(1, 0, 1) LBM_SW3(1, 1, 0) LBM_SW3(1, 1, 1)
         default: return hipErrorInvalidValue;
     }
 #undef LBM_SW3
@@ -237,7 +238,8 @@ template <int Q, typename TS, typename TC>
 hipError_t sweep2_3d_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout, int *flag,
                            int shape, uint32_t zc, hipStream_t st) {
     if constexpr (Q == 19) {
-        if (!dm.eqr || !dm.deg3 || !dm.o32 || dm.src || dm.sb || zc < 1) return hipErrorNotSupported;
+        // no phi history (a Scheme-A source would need it at the halo nodes)
+        if (!dm.eqr || !dm.deg3 || !dm.o32 || (dm.src && !dm.sb) || zc < 1) return hipErrorNotSupported;
         if constexpr (sizeof(TS) == 8) {
             if (shape == 0) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, flag, zc, st);
             if (shape == 1) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, flag, zc, st);

@@ -914,8 +914,8 @@ k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ 
 // The general sweep: Scheme B and/or per-node fields.  Polynomials of any
 // length, K(phi) evaluated per node, Scheme-A history kept when SB is off.
 // ---------------------------------------------------------------------------
-// Two time steps per pass for D3Q19 (equal non-flux rates, no source, any
-// walls on z).  A workgroup owns a column of 62 x TY nodes in x and y and a
+// Two time steps per pass for D3Q19 (equal non-flux rates, no phi history:
+// no source, or a Scheme B source (SB); any walls on z).  A workgroup owns a column of 62 x TY nodes in x and y and a
 // chunk of zc planes in z, and marches up the chunk.  At logical plane i
 // (z = z0 - 1 + i) phase 1 runs step t on the column plus a one-node halo in
 // x and y and keeps the post-collision populations in LDS, rounded to the
@@ -949,7 +949,7 @@ struct Zc3 {
 // per-lane column offsets (x - c_x, periodic), and the loads of the next
 // plane are issued before the current plane's arithmetic, so that their
 // latency overlaps phase 1, phase 2 and both barriers.
-template <typename TS, typename TC, bool KVAR, bool WALL, int NP, int TY, int NW>
+template <typename TS, typename TC, bool KVAR, bool WALL, int NP, int TY, int NW, bool SB = false>
 __global__ void __launch_bounds__(64 * NW)
 k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
             uint32_t tiles_x, uint32_t tiles_y, uint32_t zc, int *flag) {
@@ -1029,7 +1029,7 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                         h[k] = wl ? -(TC)hc[j][k] + cf->ew[cz == 1 ? 0 : 1][k] : (TC)hc[j][k];
                     }
                     TC out[19];
-                    const TC phio = collide_node<19, TC, true, false, KVAR, NP>(cf, h, TC(0), 0u, nullptr, nullptr,
+                    const TC phio = collide_node<19, TC, true, false, KVAR, NP, SB>(cf, h, TC(0), 0u, nullptr, nullptr,
                                                                                false, out);
                     bad |= !__builtin_isfinite(phio);
 #pragma unroll
@@ -1067,7 +1067,7 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                     }
                 }
                 TC out[19];
-                const TC phio = collide_node<19, TC, true, false, KVAR, NP>(cf, h, TC(0), 0u, nullptr, nullptr,
+                const TC phio = collide_node<19, TC, true, false, KVAR, NP, SB>(cf, h, TC(0), 0u, nullptr, nullptr,
                                                                            false, out);
                 bad |= !__builtin_isfinite(phio);
                 if (x < nx && y < ny) {

@@ -470,6 +470,42 @@ def test_two_step_passes_d3q19_bit_identical(n, prec, wall, shape):
         assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
 
 
+@pytest.mark.parametrize("n,prec,wall,shape", [((20, 18, 22), "f64", True, 0), ((33, 7, 11), "f32", False, 1),
+                                                ((70, 16, 9), "f32", True, 0), ((9, 5, 4), "f16", True, 0),
+                                                ((5, 4, 1), "f64", True, 1)])
+def test_two_step_passes_d3q19_scheme_b_bit_identical(n, prec, wall, shape):
+    """D3Q19 in Scheme B with R(phi) of degree 2 (Eq. 35 solved per node):
+    Scheme B keeps no phi history, so the two-step pass applies, and it
+    matches single sweeps bit for bit; FP64 against the oracle."""
+    lbm = _lbm()
+    spec, _, _ = W.d3q19_walls(n, precision=prec)
+    spec = dict(spec, scheme="B", rpoly=[0.002, 0.01, -0.01])
+    if not wall:
+        spec["bc"] = ["periodic"] * 3
+    spec["phi_wall"] = [[0, 0], [0, 0], [0.3, 0.6]] if wall else spec["phi_wall"]
+    phi0 = W.gaussians_3d(n, 23)
+    say(f"[gpu] two-step passes d3q19 scheme B {n} {prec} walls={wall} shape={shape}")
+    a = lbm.Lbm(spec).init(phi0)
+    a.set_two_step(False)
+    b = lbm.Lbm(spec).init(phi0)
+    b.set_two_step(True, shape)
+    t = 0
+    for s in (4, 9, 40):
+        a.step(s - t)
+        b.step(s - t)
+        t = s
+        assert torch.equal(a.phi(), b.phi()), s
+        wa, _ = a.current()
+        wb, _ = b.current()
+        assert wa == wb
+        assert torch.equal(a.storage_view(a.f[wa]), b.storage_view(b.f[wb])), s
+    if prec == "f64":
+        ref = oracle_run(spec, phi0, (40,))[40]
+        got = b.phi().cpu().numpy()
+        say(f"    vs oracle: rel L2 {rel_l2(got, ref):.2e}, max {max_rel(got, ref)}")
+        assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
+
+
 def test_two_step_refused_where_it_does_not_apply():
     lbm = _lbm()
     walls = dict(W.spec_nonlinear_2d(70, 30), bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]])
