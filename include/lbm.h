@@ -147,9 +147,9 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out);
  *  p_bytes  the phi-history buffer (phi of the last step: Scheme A's
  *           R_k(t - 1), Remark II);
  *  p2_bytes a second history buffer, used only by two time steps per pass on
- *           runs that keep a history (D2Q9, periodic, equal non-flux rates,
- *           with a source); 0 when no pass would read it.  Without it such a
- *           run uses one sweep per step. */
+ *           runs that keep a history (a Scheme-A source, on runs where the
+ *           passes apply: lbm_set_two_step); 0 when no pass would read it.
+ *           Without it such a run uses one sweep per step. */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *f_bytes, size_t *p_bytes, size_t *p2_bytes);
 
 /* Bytes of one adjoint-variable buffer psi (same plane layout as the
@@ -231,11 +231,12 @@ int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_l
  *    steps); with a Scheme-A source they alternate the history between p and
  *    the caller's p2 (lbm_init).  Scheme-B sources need polynomials of
  *    degree <= 2.
- *  - D3Q19, equal non-flux rates, polynomials of degree <= 2, no source or a
- *    Scheme-B source (no phi history), walls on z or periodic: a workgroup owns a column of 62 x rows nodes and a
- *    chunk of z planes and marches up it, phase 1 (step t, with a one-node
- *    halo in x and y) feeding a ring of three planes in LDS that phase 2
- *    (step t + 1) reads one plane behind.
+ *  - D3Q19, equal non-flux rates, polynomials of degree <= 2, walls on z or
+ *    periodic: a workgroup owns a column of 62 x rows nodes and a chunk of z
+ *    planes and marches up it, phase 1 (step t, with a one-node halo in x
+ *    and y) feeding a ring of three planes in LDS that phase 2 (step t + 1)
+ *    reads one plane behind.  Passes run in pairs; with a Scheme-A source
+ *    they alternate the history between p and p2 as in 2-D.
  * Remaining steps use single sweeps.  On by default where it applies (with a
  * Scheme-A source: where p2 is bound); lbm_tune times it against single
  * sweeps.  Not used with a divergence check, per-node fields or Remark III.

@@ -416,17 +416,17 @@ uint32_t zchunk(const lbm_ctx *c) {
 
 // Without a source the kernels touch no history, and p stands in for p2.
 hipError_t sweep_pair(lbm_ctx *c, int start, hipStream_t st) {
+    void *p2 = keeps_history(c) ? c->p2 : c->p;
     if (c->dm.q == 19) {
         const uint32_t zc = zchunk(c);
         const Dims d = eff_dims(c);
-        hipError_t e = launch_sweep2_q19(d, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->d_flag,
+        hipError_t e = launch_sweep2_q19(d, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, p2, c->d_flag,
                                          c->two_shape, zc, st);
         if (e == hipSuccess)
-            e = launch_sweep2_q19(d, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], c->d_flag, c->two_shape, zc,
-                                  st);
+            e = launch_sweep2_q19(d, c->g, c->d_coefs, c->f[start ^ 1], c->f[start], p2, c->p, c->d_flag,
+                                  c->two_shape, zc, st);
         return e;
     }
-    void *p2 = keeps_history(c) ? c->p2 : c->p;
     const Dims d = eff_dims(c);
     hipError_t e = launch_sweep2_q9(d, c->g, c->d_coefs, c->f[start], c->f[start ^ 1], c->p, p2, c->d_flag,
                                     c->two_shape, st);
@@ -606,10 +606,9 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     // elements, at most `plane` of them) spans < 4 GiB: 32-bit byte offsets
     c->dm.o32 = (uint64_t)g.plane * 8u < (1ull << 32);
     // two steps per pass: D2Q9 periodic equal-rate runs; D3Q19 equal-rate runs
-    // with 3-term polynomials and no phi history (no source, or Scheme B;
-    // walls on z allowed)
+    // with 3-term polynomials (walls on z allowed)
     c->two_ok = (dm.q == 9 && !dm.wall && dm.eqr && c->dm.o32) ||
-                (dm.q == 19 && dm.eqr && dm.deg3 && (!dm.src || dm.sb) && c->dm.o32);
+                (dm.q == 19 && dm.eqr && dm.deg3 && c->dm.o32);
     c->two = c->two_ok;   // on by default where it applies (bit-identical; lbm_tune re-decides)
     {
         const uint32_t th = (uint32_t)adjoint_pair_rows(dm.prec, g.nx, g.ny);

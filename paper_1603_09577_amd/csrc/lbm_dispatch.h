@@ -211,21 +211,27 @@ constexpr bool two_step3_shape(int id, int &rows, int &waves) {
 
 template <typename TS, typename TC, int TY, int NW>
 hipError_t sweep2_3d_shape(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                           int *flag, uint32_t zc, hipStream_t st) {
+                           const void *pin, void *pout, int *flag, uint32_t zc, hipStream_t st) {
+    using TP = typename HistType<TS>::T;
     const auto *cf = (const Coefs<TC> *)coefs;
     const uint32_t tiles_x = (g.nx + 61) / 62, tiles_y = (g.ny + TY - 1) / TY, tiles_z = (g.nz + zc - 1) / zc;
     const dim3 grid(tiles_x * tiles_y * tiles_z), block(64 * NW);
     const TS *fi = (const TS *)fin;
     TS *fo = (TS *)fout;
-    const int code = (dm.sb ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
-#define LBM_SW3(B, K, W)                                                                             \
-    case (B * 4 + K * 2 + W):                                                                        \
-        hipLaunchKernelGGL((k_sweep2_3d<TS, TC, K, W, 3, TY, NW, B>), grid, block, 0, st, g, cf, fi, fo, tiles_x, \
-                           tiles_y, zc, flag);                                                       \
+    const TP *pi = (const TP *)pin;
+    TP *po = (TP *)pout;
+    // source: none, Scheme B (no history) or Scheme A (history pin -> pout)
+    const int sc = dm.sb ? 1 : (dm.src ? 2 : 0);
+    const int code = sc * 4 + (dm.kvar ? 2 : 0) + (dm.wall ? 1 : 0);
+#define LBM_SW3(S, K, W)                                                                             \
+    case (S * 4 + K * 2 + W):                                                                        \
+        hipLaunchKernelGGL((k_sweep2_3d<TS, TC, K, W, 3, TY, NW, S == 1, S == 2>), grid, block, 0, st, g, cf, fi, \
+                           fo, pi, po, tiles_x, tiles_y, zc, flag);                                  \
         break;
     switch (code) {
         LBM_SW3(0, 0, 0) LBM_SW3(0, 0, 1) LBM_SW3(0, 1, 0) LBM_SW3(0, 1, 1)
         LBM_SW3(1, 0, 0) LBM_SW3(1, 0, 1) LBM_SW3(1, 1, 0) LBM_SW3(1, 1, 1)
+        LBM_SW3(2, 0, 0) LBM_SW3(2, 0, 1) LBM_SW3(2, 1, 0) LBM_SW3(2, 1, 1)
         default: return hipErrorInvalidValue;
     }
 #undef LBM_SW3
@@ -235,18 +241,19 @@ hipError_t sweep2_3d_shape(const Dims &dm, const Geom &g, const void *coefs, con
 // D3Q19 two steps per pass: equal non-flux rates, 3-term polynomials, no source
 // (no phi history), walls on z or periodic; chunks of zc planes.
 template <int Q, typename TS, typename TC>
-hipError_t sweep2_3d_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout, int *flag,
-                           int shape, uint32_t zc, hipStream_t st) {
+hipError_t sweep2_3d_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
+                           const void *pin, void *pout, int *flag, int shape, uint32_t zc, hipStream_t st) {
     if constexpr (Q == 19) {
-        // no phi history (a Scheme-A source would need it at the halo nodes)
-        if (!dm.eqr || !dm.deg3 || !dm.o32 || (dm.src && !dm.sb) || zc < 1) return hipErrorNotSupported;
+        if (!dm.eqr || !dm.deg3 || !dm.o32 || zc < 1) return hipErrorNotSupported;
+        // a Scheme-A source reads the history pin and writes pout (distinct)
+        if (dm.src && !dm.sb && (!pin || !pout || pin == pout)) return hipErrorInvalidValue;
         if constexpr (sizeof(TS) == 8) {
-            if (shape == 0) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, flag, zc, st);
-            if (shape == 1) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, flag, zc, st);
+            if (shape == 0) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
+            if (shape == 1) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
         } else {
-            if (shape == 0) return sweep2_3d_shape<TS, TC, 14, 16>(dm, g, coefs, fin, fout, flag, zc, st);
-            if (shape == 1) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, flag, zc, st);
-            if (shape == 2) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, flag, zc, st);
+            if (shape == 0) return sweep2_3d_shape<TS, TC, 14, 16>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
+            if (shape == 1) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
+            if (shape == 2) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
         }
         return hipErrorInvalidValue;
     } else {

@@ -143,7 +143,7 @@ bool two_step_shape_of(int prec, int shape, int *rows, int *waves);
 // Two time steps per pass, D3Q19 (sweep_d3q19.hip): columns of 62 x rows nodes,
 // chunks of zc planes; its tile shapes
 hipError_t launch_sweep2_q19(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                             int *flag, int shape, uint32_t zc, hipStream_t st);
+                             const void *pin, void *pout, int *flag, int shape, uint32_t zc, hipStream_t st);
 bool two_step3_shape_of(int prec, int shape, int *rows, int *waves);
 int adjoint_pair_rows(int prec, uint32_t nx, uint32_t ny);
 // Two reversed sweeps per pass (sweep s, then s - 1), D2Q9 only; tile rows

@@ -949,16 +949,24 @@ struct Zc3 {
 // per-lane column offsets (x - c_x, periodic), and the loads of the next
 // plane are issued before the current plane's arithmetic, so that their
 // latency overlaps phase 1, phase 2 and both barriers.
-template <typename TS, typename TC, bool KVAR, bool WALL, int NP, int TY, int NW, bool SB = false>
+// SRC: a Scheme-A source.  Phase 1 reads the phi history of its nodes from
+// pin (phi(t - 1), the node itself) and keeps phi(t) in a two-slot ring of
+// its own, rounded to the history type as a store would round it; phase 2
+// takes that as its history and writes phi(t + 1) to pout, which must not be
+// pin (neighbouring columns still read pin at their halo).
+template <typename TS, typename TC, bool KVAR, bool WALL, int NP, int TY, int NW, bool SB = false, bool SRC = false>
 __global__ void __launch_bounds__(64 * NW)
 k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
+            const typename HistType<TS>::T *__restrict__ pin, typename HistType<TS>::T *__restrict__ pout,
             uint32_t tiles_x, uint32_t tiles_y, uint32_t zc, int *flag) {
     using L = Lattice<19>;
+    using TP = typename HistType<TS>::T;
     constexpr int TX = 64, TR = TY + 2;
     constexpr int PR = (TR + NW - 1) / NW;          // phase-1 rows per wave
     __shared__ TS rp[2][5][TR][TX];
     __shared__ TS r0[2][9][TR][TX];
     __shared__ TS rm[2][5][TR][TX];
+    __shared__ TP lp[SRC ? 2 : 1][SRC ? TR : 1][TX];
     const uint32_t blk = block_index(blockIdx.x, gridDim.x, g.remap);
     const uint32_t per_z = tiles_x * tiles_y;
     const uint32_t tz = blk / per_z, rem = blk - tz * per_z;
@@ -974,11 +982,12 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                       (uint32_t)xg * (uint32_t)sizeof(TS),
                       (uint32_t)(xg == nx - 1 ? 0 : xg + 1) * (uint32_t)sizeof(TS)};
     const uint32_t row_bytes = g.nx * (uint32_t)sizeof(TS);
+    uint32_t pcb = (uint32_t)xg * (uint32_t)sizeof(TP);   // the history of the node itself
     bool bad = false;
     const int nplanes = zend - z0 + 2;
     // raw values of the phase-1 gathers of logical plane i (this wave's rows):
     // population k from the source node, or at a wall the own node's opposite
-    auto load = [&](int i, TS (&dst)[PR][19]) {
+    auto load = [&](int i, TS (&dst)[PR][19], TP (&pdst)[PR]) {
         const int zl = z0 - 1 + i;
         if (WALL && (zl < 0 || zl >= nz)) return;
         const int zg = WALL ? zl : wrap_coord(zl, nz);
@@ -998,22 +1007,28 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                     dst[j][k] = wl ? *row_elem(fin + (uint64_t)L::opp(k) * g.plane, rb, cb[1])
                                    : *row_elem(fin + (uint64_t)k * g.plane, rb, cb[1 - cx]);
                 }
+                if (SRC) pdst[j] = *row_elem(pin, ((uint32_t)zg * g.ny + (uint32_t)yg) * g.nx * (uint32_t)sizeof(TP),
+                                             pcb);
             }
         }
     };
     TS hn[PR][19];
-    load(0, hn);
+    TP pn[PR];
+    load(0, hn, pn);
     for (int i = 0; i < nplanes; ++i) {
         const int zl = z0 - 1 + i;
         const int s1 = i & 1, s0 = s1 ^ 1;          // slots of plane i and of plane i - 1
         const bool p1 = WALL ? (zl >= 0 && zl < nz) : true;
         const int zg = WALL ? zl : wrap_coord(zl, nz);
         TS hc[PR][19];
+        TP pc[PR];
 #pragma unroll
-        for (int j = 0; j < PR; ++j)
+        for (int j = 0; j < PR; ++j) {
+            pc[j] = pn[j];
 #pragma unroll
             for (int k = 0; k < 19; ++k) hc[j][k] = hn[j][k];
-        if (i + 1 < nplanes) load(i + 1, hn);
+        }
+        if (i + 1 < nplanes) load(i + 1, hn, pn);
         // phase 1: plane zl (skipped beyond a wall)
         TS keep[PR][5];
         if (p1) {
@@ -1029,9 +1044,10 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                         h[k] = wl ? -(TC)hc[j][k] + cf->ew[cz == 1 ? 0 : 1][k] : (TC)hc[j][k];
                     }
                     TC out[19];
-                    const TC phio = collide_node<19, TC, true, false, KVAR, NP, SB>(cf, h, TC(0), 0u, nullptr, nullptr,
-                                                                               false, out);
+                    const TC phio = collide_node<19, TC, true, SRC, KVAR, NP, SB>(
+                        cf, h, SRC ? (TC)pc[j] : TC(0), 0u, nullptr, nullptr, false, out);
                     bad |= !__builtin_isfinite(phio);
+                    if (SRC) lp[s1 & (SRC ? 1 : 0)][SRC ? r : 0][lane] = (TP)phio;
 #pragma unroll
                     for (int c = 0; c < 9; ++c) r0[s1][c][r][lane] = (TS)out[Zc3::z[c]];
 #pragma unroll
@@ -1067,12 +1083,14 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                     }
                 }
                 TC out[19];
-                const TC phio = collide_node<19, TC, true, false, KVAR, NP, SB>(cf, h, TC(0), 0u, nullptr, nullptr,
-                                                                           false, out);
+                const TC pp_off = SRC ? (TC)lp[s0 & (SRC ? 1 : 0)][SRC ? r : 0][lane] : TC(0);
+                const TC phio = collide_node<19, TC, true, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr,
+                                                                             false, out);
                 bad |= !__builtin_isfinite(phio);
                 if (x < nx && y < ny) {
                     const uint32_t m = ((uint32_t)zc2 * g.ny + (uint32_t)y) * g.nx + (uint32_t)x;
                     store_planes<19, false>(fout, g.plane, m, out);
+                    if (SRC) *at<true>(pout, m) = (TP)phio;
                 }
             }
         }

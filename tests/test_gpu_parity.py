@@ -506,12 +506,53 @@ def test_two_step_passes_d3q19_scheme_b_bit_identical(n, prec, wall, shape):
         assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
 
 
+@pytest.mark.parametrize("n,prec,wall,shape", [((20, 18, 22), "f64", True, 0), ((33, 7, 11), "f32", False, 1),
+                                                ((70, 16, 9), "f32", True, 0), ((9, 5, 4), "f16", True, 0),
+                                                ((5, 4, 1), "f64", True, 1), ((65, 9, 17), "f32", True, 2)])
+def test_two_step_passes_d3q19_scheme_a_source_bit_identical(n, prec, wall, shape):
+    """D3Q19 with a Scheme-A source R(phi) (Eq. 9 with the phi history): the
+    pass reads the history of its nodes from one buffer, keeps phi(t) in LDS
+    for the second step and writes phi(t + 1) to the caller's second history
+    buffer; state, history and phi match single sweeps bit for bit; FP64
+    against the oracle."""
+    lbm = _lbm()
+    spec, _, _ = W.d3q19_walls(n, precision=prec)
+    spec = dict(spec, rpoly=[0.002, 0.01, -0.01], kpoly=[1.0, 0.0, 0.5])
+    if not wall:
+        spec["bc"] = ["periodic"] * 3
+    spec["phi_wall"] = [[0, 0], [0, 0], [0.3, 0.6]] if wall else spec["phi_wall"]
+    phi0 = W.gaussians_3d(n, 24)
+    say(f"[gpu] two-step passes d3q19 scheme A source {n} {prec} walls={wall} shape={shape}")
+    a = lbm.Lbm(spec).init(phi0)
+    a.set_two_step(False)
+    b = lbm.Lbm(spec).init(phi0)
+    assert b.p2 is not None
+    b.set_two_step(True, shape)
+    t = 0
+    for s in (4, 9, 40):
+        a.step(s - t)
+        b.step(s - t)
+        t = s
+        assert torch.equal(a.phi(), b.phi()), s
+        wa, _ = a.current()
+        wb, _ = b.current()
+        assert wa == wb
+        assert torch.equal(a.storage_view(a.f[wa]), b.storage_view(b.f[wb])), s
+        nb = a.N * (8 if prec == "f64" else 4)   # the history proper, not the buffer's padding
+        assert torch.equal(a.p[:nb], b.p[:nb]), s
+    if prec == "f64":
+        ref = oracle_run(spec, phi0, (40,))[40]
+        got = b.phi().cpu().numpy()
+        say(f"    vs oracle: rel L2 {rel_l2(got, ref):.2e}, max {max_rel(got, ref)}")
+        assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
+
+
 def test_two_step_refused_where_it_does_not_apply():
     lbm = _lbm()
     walls = dict(W.spec_nonlinear_2d(70, 30), bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]])
-    d3_src = dict(W.d3q19_walls((20, 18, 22))[0], rpoly=[0.0, 0.01, -0.01])
     d3_rates = dict(W.d3q19_walls((20, 18, 22))[0], s=[0.0] + [1.0 + 0.01 * i for i in range(18)])
-    for spec in (d3_src, d3_rates, walls):
+    d3_cubic = dict(W.d3q19_walls((20, 18, 22))[0], kpoly=[1.0, 0.0, 0.0, 0.5])
+    for spec in (d3_rates, d3_cubic, walls):
         s = lbm.Lbm(spec)
         with pytest.raises(lbm.LbmError) as ei:
             s.set_two_step(True)
