@@ -225,9 +225,10 @@ int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_l
  * LDS are rounded to the storage type as a store would round them), so
  * results equal single sweeps bit for bit, while the state crosses HBM once
  * per two steps.
- *  - D2Q9, periodic axes, equal non-flux rates (any grid size: tiles wrap
- *    periodically): a workgroup runs step t on a 62 x rows tile with a
- *    one-node halo and step t + 1 on the tile.  Passes run in pairs (four
+ *  - D2Q9, equal non-flux rates, periodic axes (any grid size: tiles wrap
+ *    periodically) or walls on y with polynomials of degree <= 2: a
+ *    workgroup runs step t on a 62 x rows tile with a one-node halo and step
+ *    t + 1 on the tile.  Passes run in pairs (four
  *    steps); with a Scheme-A source they alternate the history between p and
  *    the caller's p2 (lbm_init).  Scheme-B sources need polynomials of
  *    degree <= 2.

@@ -788,8 +788,12 @@ __device__ __forceinline__ int wrap_coord(int v, int n) {
 // NW waves of the workgroup).  Grids narrower or lower than a tile are fine:
 // halo lanes and rows then repeat nodes (computed identically) and only the
 // tile's own nodes inside the grid are stored.  SB: Scheme B with R(phi) (no
-// history; phi from Eq. 35 at every node of both phases).
-template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW, bool SB = false>
+// history; phi from Eq. 35 at every node of both phases).  WALL:
+// anti-bounce-back walls at both ends of y (x periodic).  Rows beyond a wall
+// are not computed; a population that comes from beyond the wall is the
+// node's own post-collision opposite, negated, plus the wall term, read from
+// the state in phase 1 and from LDS in phase 2 (the one-sweep gather's form).
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW, bool SB = false, bool WALL = false>
 __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__restrict__ cf,
                                             const TS *__restrict__ fin, TS *__restrict__ fout,
                                             const typename HistType<TS>::T *__restrict__ pin,
@@ -829,14 +833,18 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
         TS ps[NR];
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            const int yg = wrap_coord(y0 - 1 + wv + i * NW, ny);
+            const int yl = y0 - 1 + wv + i * NW;
+            if (WALL && (yl < 0 || yl >= ny)) continue;   // beyond a wall
+            const int yg = WALL ? yl : wrap_coord(yl, ny);
             const int ym = yg == 0 ? ny - 1 : yg - 1, yp = yg == ny - 1 ? 0 : yg + 1;
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 const int cy = L::cy(k);
-                const uint32_t row = (uint32_t)(cy == 1 ? ym : (cy == -1 ? yp : yg));
-                const char *rb = reinterpret_cast<const char *>(fin + (uint64_t)k * g.plane) + row * row_bytes;
-                uint32_t &c = cb[1 - L::cx(k)];
+                const bool wl = WALL && ((cy == 1 && yg == 0) || (cy == -1 && yg == ny - 1));
+                const uint32_t row = (uint32_t)(wl ? yg : (cy == 1 ? ym : (cy == -1 ? yp : yg)));
+                const char *rb = reinterpret_cast<const char *>(fin + (uint64_t)(wl ? L::opp(k) : k) * g.plane) +
+                                 row * row_bytes;
+                uint32_t &c = cb[wl ? 1 : 1 - L::cx(k)];
                 asm("" : "+v"(c));
                 hs[i][k] = *reinterpret_cast<const TS *>(rb + c);
             }
@@ -845,8 +853,17 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
             const int r = wv + i * NW;
+            const int yl = y0 - 1 + r;
+            if (WALL && (yl < 0 || yl >= ny)) continue;
+            TC h[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int cy = L::cy(k);
+                const bool wl = WALL && ((cy == 1 && yl == 0) || (cy == -1 && yl == ny - 1));
+                h[k] = wl ? -(TC)hs[i][k] + cf->ew[cy == 1 ? 0 : 1][k] : (TC)hs[i][k];
+            }
             TC out[9];
-            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP, SB>(cf, hs[i], ps[i], 0u, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP, SB>(cf, h, ps[i], 0u, nullptr, nullptr, false, out);
 #pragma unroll
             for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
             lp[r][lane] = (TP)phio;
@@ -856,18 +873,23 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
 #pragma unroll
         for (int i = 0; i < TR / NW; ++i) {
             const int r = wv + i * NW;
-            const int yg = wrap_coord(y0 - 1 + r, ny);
+            const int yl = y0 - 1 + r;
+            if (WALL && (yl < 0 || yl >= ny)) continue;   // beyond a wall
+            const int yg = WALL ? yl : wrap_coord(yl, ny);
             const int ym = yg == 0 ? ny - 1 : yg - 1, yp = yg == ny - 1 ? 0 : yg + 1;
             const uint32_t n = (uint32_t)yg * g.nx + (uint32_t)xg;
             TC h[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 const int cy = L::cy(k);
-                const uint32_t row = (uint32_t)(cy == 1 ? ym : (cy == -1 ? yp : yg));
-                const char *rb = reinterpret_cast<const char *>(fin + (uint64_t)k * g.plane) + row * row_bytes;
-                uint32_t &c = cb[1 - L::cx(k)];
+                const bool wl = WALL && ((cy == 1 && yg == 0) || (cy == -1 && yg == ny - 1));
+                const uint32_t row = (uint32_t)(wl ? yg : (cy == 1 ? ym : (cy == -1 ? yp : yg)));
+                const char *rb = reinterpret_cast<const char *>(fin + (uint64_t)(wl ? L::opp(k) : k) * g.plane) +
+                                 row * row_bytes;
+                uint32_t &c = cb[wl ? 1 : 1 - L::cx(k)];
                 asm("" : "+v"(c));
-                h[k] = (TC)*reinterpret_cast<const TS *>(rb + c);
+                const TC v = (TC)*reinterpret_cast<const TS *>(rb + c);
+                h[k] = wl ? -v + cf->ew[cy == 1 ? 0 : 1][k] : v;
             }
             const TC pp_off = SRC ? (TC)*at<true>(pin, n) : TC(0);
             TC out[9];
@@ -884,9 +906,15 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
         const int x = x0 + lane - 1;
         for (int r = 1 + wv; r <= TH; r += NW) {
             const int y = y0 + r - 1;
+            if (WALL && y >= ny) break;   // no rows beyond the wall
             TC h[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) h[k] = (TC)lf[k][r - L::cy(k)][lane - L::cx(k)];
+            for (int k = 0; k < 9; ++k) {
+                const int cy = L::cy(k);
+                const bool wl = WALL && ((cy == 1 && y == 0) || (cy == -1 && y == ny - 1));
+                h[k] = wl ? -(TC)lf[L::opp(k)][r][lane] + cf->ew[cy == 1 ? 0 : 1][k]
+                          : (TC)lf[k][r - cy][lane - L::cx(k)];
+            }
             const TC pp_off = SRC ? (TC)lp[r][lane] : TC(0);
             TC out[9];
             const TC phio = collide_node<9, TC, true, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr, false, out);
@@ -901,14 +929,15 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
     if (bad) *flag = 1;
 }
 
-template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW = kBlock / 64, bool SB = false>
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW = kBlock / 64, bool SB = false,
+          bool WALL = false>
 __global__ void __launch_bounds__(64 * NW)
 k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
          const typename HistType<TS>::T *__restrict__ pin, typename HistType<TS>::T *__restrict__ pout,
          uint32_t tiles_x, int *flag) {
     const uint32_t tile = block_index(blockIdx.x, gridDim.x, g.remap);
     const uint32_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    sweep2_tile<TS, TC, SRC, KVAR, NP, TH, NW, SB>(g, cf, fin, fout, pin, pout, tx, ty, flag);
+    sweep2_tile<TS, TC, SRC, KVAR, NP, TH, NW, SB, WALL>(g, cf, fin, fout, pin, pout, tx, ty, flag);
 }
 
 // The general sweep: Scheme B and/or per-node fields.  Polynomials of any

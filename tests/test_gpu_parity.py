@@ -547,9 +547,53 @@ def test_two_step_passes_d3q19_scheme_a_source_bit_identical(n, prec, wall, shap
         assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
 
 
+@pytest.mark.parametrize("nx,ny,prec,source,shape", [(100, 37, "f64", "A", 0), (100, 37, "f32", "A", 1),
+                                                      (130, 50, "f16", "none", 0), (61, 13, "f64", "B", 1),
+                                                      (131, 29, "f32", "B", 2), (64, 64, "f32", "none", 3),
+                                                      (3, 2, "f32", "A", 1), (70, 1, "f64", "A", 0),
+                                                      (190, 23, "f64", "none", 2)])
+def test_two_step_passes_walls_bit_identical(nx, ny, prec, source, shape):
+    """D2Q9 with anti-bounce-back walls on y (fixed wall values) in two steps
+    per pass: phase 1 skips the rows beyond the walls and both phases take the
+    one-sweep wall form, so phi, the state and the history match single
+    sweeps bit for bit (Scheme A with its history, Scheme B, no source; tile
+    shapes; grids lower than a tile and a single row); FP64 against the
+    oracle."""
+    lbm = _lbm()
+    spec = W.spec_nonlinear_2d(nx, ny, precision=prec, source=(source != "none"))
+    spec = dict(spec, bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]])
+    if source == "B":
+        spec["scheme"] = "B"
+    phi0 = W.noise_field((ny, nx), 31)
+    say(f"[gpu] two-step passes with walls {nx}x{ny} {prec} source={source} shape={shape}")
+    a = lbm.Lbm(spec).init(phi0)
+    a.set_two_step(False)
+    b = lbm.Lbm(spec).init(phi0)
+    b.set_two_step(True, shape)
+    t = 0
+    for s in (4, 9, 40):
+        a.step(s - t)
+        b.step(s - t)
+        t = s
+        assert torch.equal(a.phi(), b.phi()), s
+        wa, _ = a.current()
+        wb, _ = b.current()
+        assert wa == wb
+        assert torch.equal(a.storage_view(a.f[wa]), b.storage_view(b.f[wb])), s
+        if source == "A":
+            nb = a.N * (8 if prec == "f64" else 4)
+            assert torch.equal(a.p[:nb], b.p[:nb]), s
+    if prec == "f64":
+        ref = oracle_run(spec, phi0, (40,))[40]
+        got = b.phi().cpu().numpy()
+        say(f"    vs oracle: rel L2 {rel_l2(got, ref):.2e}, max {max_rel(got, ref)}")
+        assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
+
+
 def test_two_step_refused_where_it_does_not_apply():
     lbm = _lbm()
-    walls = dict(W.spec_nonlinear_2d(70, 30), bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]])
+    walls = dict(W.spec_nonlinear_2d(70, 30), bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]],
+                 kpoly=[1.0, 0.0, 0.0, 0.2])   # walls need 3-term polynomials
     d3_rates = dict(W.d3q19_walls((20, 18, 22))[0], s=[0.0] + [1.0 + 0.01 * i for i in range(18)])
     d3_cubic = dict(W.d3q19_walls((20, 18, 22))[0], kpoly=[1.0, 0.0, 0.0, 0.5])
     for spec in (d3_rates, d3_cubic, walls):

@@ -140,3 +140,63 @@ def test_adjoint_row_waves(nx):
                     got = row_form_index(x, y, nx, ny, k, sign)
                     assert got == general_index(n, nx, ny, k, sign)
                     assert 0 <= got < nx * ny
+
+
+OPP9 = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+
+
+@pytest.mark.parametrize("th,nw", [(14, 8), (14, 4), (10, 6), (6, 4), (6, 8), (14, 16)])
+def test_two_step_walls_schedule(th, nw):
+    """The D2Q9 two-step tile with anti-bounce-back walls at both ends of y
+    (x periodic): phase 1 computes only the rows inside the walls and loads,
+    for a population that would come from beyond a wall, the node's own
+    opposite population; phase 2 gathers every population from the LDS cell
+    of the node it comes from, or from the node's own cell for the wall form.
+    Every such source must be what the one-sweep gather reads, every LDS cell
+    read must have been written, and every node is stored once."""
+    for nx, ny in SIZES:
+        stored = set()
+        tiles_x, tiles_y = (nx + TILE_W - 1) // TILE_W, (ny + th - 1) // th
+        for ty in range(tiles_y):
+            for tx in range(tiles_x):
+                x0, y0 = tx * TILE_W, ty * th
+                lds = {}
+                # phase 1
+                for wv in range(nw):
+                    for i in range((th + 2) // nw):
+                        r = wv + i * nw
+                        yl = y0 - 1 + r
+                        if yl < 0 or yl >= ny:
+                            continue
+                        for lane in range(64):
+                            xg = wrap(x0 - 1 + lane, nx)
+                            for k in range(9):
+                                wl = (CY[k] == 1 and yl == 0) or (CY[k] == -1 and yl == ny - 1)
+                                src = (xg, yl) if wl else (wrap(xg - CX[k], nx), yl - CY[k])
+                                assert 0 <= src[0] < nx and 0 <= src[1] < ny
+                            lds[(r, lane)] = (xg, yl)
+                # phase 2
+                for wv in range(nw):
+                    r = 1 + wv
+                    while r <= th:
+                        y = y0 + r - 1
+                        if y >= ny:
+                            break
+                        for lane in range(1, TILE_W + 1):
+                            x = x0 + lane - 1
+                            for k in range(9):
+                                wl = (CY[k] == 1 and y == 0) or (CY[k] == -1 and y == ny - 1)
+                                if wl:
+                                    got = ("wall", OPP9[k], lds[(r, lane)])
+                                    want = ("wall", OPP9[k], (wrap(x, nx), y))
+                                else:
+                                    cell = lds.get((r - CY[k], lane - CX[k]))
+                                    assert cell is not None, (nx, ny, tx, ty, r, lane, k)
+                                    got = ("f*", k, cell)
+                                    want = ("f*", k, (wrap(wrap(x, nx) - CX[k], nx), y - CY[k]))
+                                assert got == want, (nx, ny, th, nw, x, y, k, got, want)
+                            if x < nx:
+                                assert (x, y) not in stored
+                                stored.add((x, y))
+                        r += nw
+        assert len(stored) == nx * ny
