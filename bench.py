@@ -827,7 +827,7 @@ def main():
     if head["two_step"]:
         m = re.match(r"(\d+) rows x (\d+) waves", head["tile_rows"] or "")
         prof = profile_entry("nonlinear2d-1024 f32 two-step",
-                             f"k_sweep2<float, float, true, true, 3, {m.group(1)}, {m.group(2)}>" if m else "?")
+                             f"k_sweep2<float, float, true, true, 3, {m.group(1)}, {m.group(2)}," if m else "?")
     else:
         prof = profile_entry("nonlinear2d-1024 f32")
     traffic = prof.get("traffic_bytes_per_launch") if prof else None
