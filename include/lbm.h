@@ -225,8 +225,9 @@ int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_l
  * LDS are rounded to the storage type as a store would round them), so
  * results equal single sweeps bit for bit, while the state crosses HBM once
  * per two steps.
- *  - D2Q9, equal non-flux rates, periodic axes (any grid size: tiles wrap
- *    periodically) or walls on y with polynomials of degree <= 2: a
+ *  - D2Q9, periodic axes (any grid size: tiles wrap periodically) with equal
+ *    non-flux rates, or, with polynomials of degree <= 2, also walls on y
+ *    and unequal rates (the latter in the default tile shape only): a
  *    workgroup runs step t on a 62 x rows tile with a one-node halo and step
  *    t + 1 on the tile.  Passes run in pairs (four
  *    steps); with a Scheme-A source they alternate the history between p and

@@ -605,17 +605,17 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     // every array a kernel indexes (planes of f and psi, p, pi: at most 8-byte
     // elements, at most `plane` of them) spans < 4 GiB: 32-bit byte offsets
     c->dm.o32 = (uint64_t)g.plane * 8u < (1ull << 32);
-    // two steps per pass: D2Q9 equal-rate runs (with walls on y: 3-term
-    // polynomials); D3Q19 equal-rate runs with 3-term polynomials (walls on z
-    // allowed)
-    c->two_ok = (dm.q == 9 && dm.eqr && (!dm.wall || dm.deg3) && c->dm.o32) ||
+    // two steps per pass: D2Q9 runs (with walls on y or unequal non-flux
+    // rates: 3-term polynomials); D3Q19 equal-rate runs with 3-term
+    // polynomials (walls on z allowed)
+    c->two_ok = (dm.q == 9 && ((dm.eqr && !dm.wall) || dm.deg3) && c->dm.o32) ||
                 (dm.q == 19 && dm.eqr && dm.deg3 && c->dm.o32);
     c->two = c->two_ok;   // on by default where it applies (bit-identical; lbm_tune re-decides)
     {
         const uint32_t th = (uint32_t)adjoint_pair_rows(dm.prec, g.nx, g.ny);
         const uint32_t tiles = ((g.nx + 61) / 62) * ((g.ny + th - 1) / th);
         // the two-sweep adjoint: periodic D2Q9 only
-        c->adj_slots = dm.q == 9 && !dm.wall && c->two_ok && tiles > g.nblocks ? tiles : g.nblocks;
+        c->adj_slots = dm.q == 9 && !dm.wall && dm.eqr && c->two_ok && tiles > g.nblocks ? tiles : g.nblocks;
     }
     hipError_t e = hipMalloc(&c->d_coefs, sizeof(Coefs<double>));
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipMalloc(coefficients)"); }
@@ -732,7 +732,8 @@ static bool shape_of(const lbm_ctx *c, int shape, int *rows, int *waves) {
 static bool two_shape_usable(const lbm_ctx *c, int shape) {
     int rows = 0, waves = 0;
     if (!shape_of(c, shape, &rows, &waves)) return false;
-    return shape == 0 || c->dm.deg3;
+    // the moment-space collision (unequal rates) has the default shape only
+    return shape == 0 || (c->dm.deg3 && c->dm.eqr);
 }
 
 int lbm_two_step_shape(const lbm_ctx *c, int shape, int *rows, int *waves) {
@@ -931,7 +932,8 @@ int lbm_adjoint_step(lbm_ctx *c, const void *f_s, const void *p_s, const void *p
 
 // Two reversed sweeps per launch: the forward pass's tile conditions.
 static bool adjoint_pair_applies(const lbm_ctx *c) {
-    return c->dm.q == 9 && !c->dm.wall && c->two_ok && c->dm.prec != 2 && c->adj_slots <= (uint32_t)kMaxAdjParts;
+    return c->dm.q == 9 && !c->dm.wall && c->dm.eqr && c->two_ok && c->dm.prec != 2 &&
+           c->adj_slots <= (uint32_t)kMaxAdjParts;
 }
 
 int lbm_adjoint_pair_ok(const lbm_ctx *c, int *ok) {

@@ -122,6 +122,32 @@ hipError_t sweep2_shape(const Dims &dm, const Geom &g, const void *coefs, const 
     TS *fo = (TS *)fout;
     const TP *pi = (const TP *)pin;
     TP *po = (TP *)pout;
+    if (!dm.eqr) {
+        // unequal non-flux rates (moment-space collision): 3-term polynomials,
+        // the default tile shape; any source, periodic or walls on y
+        if constexpr (TH == two_step_rows<TS>() && NW == kBlock / 64) {
+            if (!dm.deg3) return hipErrorInvalidValue;
+            const int cm = (dm.sb ? 8 : (dm.src ? 4 : 0)) | (dm.kvar ? 2 : 0) | (dm.wall ? 1 : 0);
+#define LBM_SW2M(S, B, K, W)                                                                         \
+    case ((B ? 8 : S * 4) + K * 2 + W):                                                              \
+        hipLaunchKernelGGL((k_sweep2<TS, TC, S, K, 3, TH, NW, B, W, false>), grid, block, 0, st, g, cf, fi, fo, pi, \
+                           po, tiles_x, flag);                                                       \
+        break;
+            switch (cm) {
+                LBM_SW2M(false, false, false, false) LBM_SW2M(false, false, false, true)
+                LBM_SW2M(false, false, true, false) LBM_SW2M(false, false, true, true)
+                LBM_SW2M(true, false, false, false) LBM_SW2M(true, false, false, true)
+                LBM_SW2M(true, false, true, false) LBM_SW2M(true, false, true, true)
+                LBM_SW2M(false, true, false, false) LBM_SW2M(false, true, false, true)
+                LBM_SW2M(false, true, true, false) LBM_SW2M(false, true, true, true)
+                default: return hipErrorInvalidValue;
+            }
+#undef LBM_SW2M
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     if (dm.wall) {
         // anti-bounce-back walls on y: 3-term kernels; no source, Scheme A
         // (history) or Scheme B
@@ -195,7 +221,8 @@ constexpr bool two_step_shape(int id, int &rows, int &waves) {
 template <int Q, typename TS, typename TC>
 hipError_t sweep2_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
                         const void *pin, void *pout, int *flag, int shape, hipStream_t st) {
-    if (Q != 9 || !dm.eqr || (dm.wall && !dm.deg3)) return hipErrorNotSupported;
+    if (Q != 9 || ((dm.wall || !dm.eqr) && !dm.deg3)) return hipErrorNotSupported;
+    if (!dm.eqr && shape != 0) return hipErrorInvalidValue;   // moment-space collision: the default shape
     if (shape < 0 || shape >= two_step_shape_count<TS>() || (shape > 0 && !dm.deg3)) return hipErrorInvalidValue;
     if constexpr (sizeof(TS) == 8) {
         if (shape == 1) return sweep2_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, pin, pout, flag, st);
@@ -479,7 +506,7 @@ hipError_t adjoint2_typed(const Dims &dm, const Geom &g, const void *coefs, cons
                           const void *f0, const void *p0, const void *psi_next, const double *pi_next,
                           void *psi_out, double *pi_out, double *gk_part, hipStream_t st) {
     static_assert(Q == 9, "two reversed sweeps per pass are D2Q9 only");
-    if (dm.wall) return hipErrorNotSupported;   // periodic tiles only
+    if (dm.wall || !dm.eqr) return hipErrorNotSupported;   // periodic, equal-rate tiles only
     if constexpr (sizeof(TC) == 8) {
         return adjoint2_rows<TS, TC, 6, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
                                            gk_part, st);

@@ -793,7 +793,10 @@ __device__ __forceinline__ int wrap_coord(int v, int n) {
 // are not computed; a population that comes from beyond the wall is the
 // node's own post-collision opposite, negated, plus the wall term, read from
 // the state in phase 1 and from LDS in phase 2 (the one-sweep gather's form).
-template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW, bool SB = false, bool WALL = false>
+// EQ: the equal-rate collision; otherwise the moment-space one (unequal
+// non-flux rates, Eq. 2 with S of Eq. 17).
+template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW, bool SB = false, bool WALL = false,
+          bool EQ = true>
 __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__restrict__ cf,
                                             const TS *__restrict__ fin, TS *__restrict__ fout,
                                             const typename HistType<TS>::T *__restrict__ pin,
@@ -863,7 +866,7 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
                 h[k] = wl ? -(TC)hs[i][k] + cf->ew[cy == 1 ? 0 : 1][k] : (TC)hs[i][k];
             }
             TC out[9];
-            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP, SB>(cf, h, ps[i], 0u, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, EQ, SRC, KVAR, NP, SB>(cf, h, ps[i], 0u, nullptr, nullptr, false, out);
 #pragma unroll
             for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
             lp[r][lane] = (TP)phio;
@@ -893,7 +896,7 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
             }
             const TC pp_off = SRC ? (TC)*at<true>(pin, n) : TC(0);
             TC out[9];
-            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP, SB>(cf, h, pp_off, n, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, EQ, SRC, KVAR, NP, SB>(cf, h, pp_off, n, nullptr, nullptr, false, out);
 #pragma unroll
             for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
             lp[r][lane] = (TP)phio;
@@ -917,7 +920,7 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
             }
             const TC pp_off = SRC ? (TC)lp[r][lane] : TC(0);
             TC out[9];
-            const TC phio = collide_node<9, TC, true, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, EQ, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr, false, out);
             bad |= !__builtin_isfinite(phio);
             if (x < nx && y < ny) {
                 const uint32_t m = (uint32_t)y * g.nx + (uint32_t)x;
@@ -930,14 +933,14 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
 }
 
 template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW = kBlock / 64, bool SB = false,
-          bool WALL = false>
+          bool WALL = false, bool EQ = true>
 __global__ void __launch_bounds__(64 * NW)
 k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
          const typename HistType<TS>::T *__restrict__ pin, typename HistType<TS>::T *__restrict__ pout,
          uint32_t tiles_x, int *flag) {
     const uint32_t tile = block_index(blockIdx.x, gridDim.x, g.remap);
     const uint32_t ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    sweep2_tile<TS, TC, SRC, KVAR, NP, TH, NW, SB, WALL>(g, cf, fin, fout, pin, pout, tx, ty, flag);
+    sweep2_tile<TS, TC, SRC, KVAR, NP, TH, NW, SB, WALL, EQ>(g, cf, fin, fout, pin, pout, tx, ty, flag);
 }
 
 // The general sweep: Scheme B and/or per-node fields.  Polynomials of any

@@ -590,6 +590,52 @@ def test_two_step_passes_walls_bit_identical(nx, ny, prec, source, shape):
         assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
 
 
+@pytest.mark.parametrize("nx,ny,prec,source,walls", [(100, 37, "f64", "A", False), (100, 37, "f32", "A", True),
+                                                      (130, 50, "f16", "none", False), (61, 13, "f64", "B", True),
+                                                      (131, 29, "f32", "B", False), (3, 2, "f64", "A", False),
+                                                      (70, 1, "f32", "none", True)])
+def test_two_step_passes_unequal_rates_bit_identical(nx, ny, prec, source, walls):
+    """Unequal non-flux rates, d != 1 and a nonlinear D (the moment-space
+    collision of Eq. 2 with S of Eq. 17) in two steps per pass: bit-identical
+    to single sweeps (state, history, phi), periodic or with walls on y, with
+    no source, Scheme A or Scheme B; FP64 against the oracle."""
+    lbm = _lbm()
+    spec = W.spec_nonlinear_2d(nx, ny, precision=prec, source=(source != "none"))
+    spec["s"] = [0.0, 1.3, 1.1, 1.0, 1.4, 1.0, 0.9, 1.2, 1.05]
+    spec["d"] = 0.8
+    spec["dpoly"] = [0.05, 0.9, 0.1]
+    if walls:
+        spec = dict(spec, bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]])
+    if source == "B":
+        spec["scheme"] = "B"
+    phi0 = W.noise_field((ny, nx), 33)
+    say(f"[gpu] two-step passes, unequal rates {nx}x{ny} {prec} source={source} walls={walls}")
+    a = lbm.Lbm(spec).init(phi0)
+    a.set_two_step(False)
+    b = lbm.Lbm(spec).init(phi0)
+    b.set_two_step(True)
+    t = 0
+    for s in (4, 9, 40):
+        a.step(s - t)
+        b.step(s - t)
+        t = s
+        assert torch.equal(a.phi(), b.phi()), s
+        wa, _ = a.current()
+        wb, _ = b.current()
+        assert wa == wb
+        assert torch.equal(a.storage_view(a.f[wa]), b.storage_view(b.f[wb])), s
+        if source == "A":
+            nb = a.N * (8 if prec == "f64" else 4)
+            assert torch.equal(a.p[:nb], b.p[:nb]), s
+    with pytest.raises(lbm.LbmError):
+        b.set_two_step(True, 1)   # the moment-space collision has the default tile shape only
+    if prec == "f64":
+        ref = oracle_run(spec, phi0, (40,))[40]
+        got = b.phi().cpu().numpy()
+        say(f"    vs oracle: rel L2 {rel_l2(got, ref):.2e}, max {max_rel(got, ref)}")
+        assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
+
+
 def test_two_step_refused_where_it_does_not_apply():
     lbm = _lbm()
     walls = dict(W.spec_nonlinear_2d(70, 30), bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]],
