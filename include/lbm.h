@@ -233,8 +233,8 @@ int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_l
  *    steps); with a Scheme-A source they alternate the history between p and
  *    the caller's p2 (lbm_init).  Scheme-B sources need polynomials of
  *    degree <= 2.
- *  - D3Q19, equal non-flux rates, polynomials of degree <= 2, walls on z or
- *    periodic: a workgroup owns a column of 62 x rows nodes and a chunk of z
+ *  - D3Q19, polynomials of degree <= 2 (unequal non-flux rates in the
+ *    default tile shape only), walls on z or periodic: a workgroup owns a column of 62 x rows nodes and a chunk of z
  *    planes and marches up it, phase 1 (step t, with a one-node halo in x
  *    and y) feeding a ring of three planes in LDS that phase 2 (step t + 1)
  *    reads one plane behind.  Passes run in pairs; with a Scheme-A source

@@ -606,10 +606,10 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
     // elements, at most `plane` of them) spans < 4 GiB: 32-bit byte offsets
     c->dm.o32 = (uint64_t)g.plane * 8u < (1ull << 32);
     // two steps per pass: D2Q9 runs (with walls on y or unequal non-flux
-    // rates: 3-term polynomials); D3Q19 equal-rate runs with 3-term
-    // polynomials (walls on z allowed)
+    // rates: 3-term polynomials); D3Q19 runs with 3-term polynomials (walls
+    // on z allowed)
     c->two_ok = (dm.q == 9 && ((dm.eqr && !dm.wall) || dm.deg3) && c->dm.o32) ||
-                (dm.q == 19 && dm.eqr && dm.deg3 && c->dm.o32);
+                (dm.q == 19 && dm.deg3 && c->dm.o32);
     c->two = c->two_ok;   // on by default where it applies (bit-identical; lbm_tune re-decides)
     {
         const uint32_t th = (uint32_t)adjoint_pair_rows(dm.prec, g.nx, g.ny);

@@ -268,6 +268,26 @@ hipError_t sweep2_3d_shape(const Dims &dm, const Geom &g, const void *coefs, con
     // source: none, Scheme B (no history) or Scheme A (history pin -> pout)
     const int sc = dm.sb ? 1 : (dm.src ? 2 : 0);
     const int code = sc * 4 + (dm.kvar ? 2 : 0) + (dm.wall ? 1 : 0);
+    if (!dm.eqr) {
+        // unequal non-flux rates (moment-space collision): the default shape
+        if constexpr ((sizeof(TS) == 8 && TY == 6 && NW == 8) || (sizeof(TS) != 8 && TY == 14 && NW == 16)) {
+#define LBM_SW3M(S, K, W)                                                                            \
+    case (S * 4 + K * 2 + W):                                                                        \
+        hipLaunchKernelGGL((k_sweep2_3d<TS, TC, K, W, 3, TY, NW, S == 1, S == 2, false>), grid, block, 0, st, g, cf, \
+                           fi, fo, pi, po, tiles_x, tiles_y, zc, flag);                              \
+        break;
+            switch (code) {
+                LBM_SW3M(0, 0, 0) LBM_SW3M(0, 0, 1) LBM_SW3M(0, 1, 0) LBM_SW3M(0, 1, 1)
+                LBM_SW3M(1, 0, 0) LBM_SW3M(1, 0, 1) LBM_SW3M(1, 1, 0) LBM_SW3M(1, 1, 1)
+                LBM_SW3M(2, 0, 0) LBM_SW3M(2, 0, 1) LBM_SW3M(2, 1, 0) LBM_SW3M(2, 1, 1)
+                default: return hipErrorInvalidValue;
+            }
+#undef LBM_SW3M
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
 #define LBM_SW3(S, K, W)                                                                             \
     case (S * 4 + K * 2 + W):                                                                        \
         hipLaunchKernelGGL((k_sweep2_3d<TS, TC, K, W, 3, TY, NW, S == 1, S == 2>), grid, block, 0, st, g, cf, fi, \
@@ -289,7 +309,8 @@ template <int Q, typename TS, typename TC>
 hipError_t sweep2_3d_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
                            const void *pin, void *pout, int *flag, int shape, uint32_t zc, hipStream_t st) {
     if constexpr (Q == 19) {
-        if (!dm.eqr || !dm.deg3 || !dm.o32 || zc < 1) return hipErrorNotSupported;
+        if (!dm.deg3 || !dm.o32 || zc < 1) return hipErrorNotSupported;
+        if (!dm.eqr && shape != 0) return hipErrorInvalidValue;   // moment-space collision: the default shape
         // a Scheme-A source reads the history pin and writes pout (distinct)
         if (dm.src && !dm.sb && (!pin || !pout || pin == pout)) return hipErrorInvalidValue;
         if constexpr (sizeof(TS) == 8) {

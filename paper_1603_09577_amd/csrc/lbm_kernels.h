@@ -946,8 +946,8 @@ k_sweep2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ 
 // The general sweep: Scheme B and/or per-node fields.  Polynomials of any
 // length, K(phi) evaluated per node, Scheme-A history kept when SB is off.
 // ---------------------------------------------------------------------------
-// Two time steps per pass for D3Q19 (equal non-flux rates, no phi history:
-// no source, or a Scheme B source (SB); any walls on z).  A workgroup owns a column of 62 x TY nodes in x and y and a
+// Two time steps per pass for D3Q19 (3-term polynomials; walls on z or
+// periodic).  A workgroup owns a column of 62 x TY nodes in x and y and a
 // chunk of zc planes in z, and marches up the chunk.  At logical plane i
 // (z = z0 - 1 + i) phase 1 runs step t on the column plus a one-node halo in
 // x and y and keeps the post-collision populations in LDS, rounded to the
@@ -986,7 +986,10 @@ struct Zc3 {
 // its own, rounded to the history type as a store would round it; phase 2
 // takes that as its history and writes phi(t + 1) to pout, which must not be
 // pin (neighbouring columns still read pin at their halo).
-template <typename TS, typename TC, bool KVAR, bool WALL, int NP, int TY, int NW, bool SB = false, bool SRC = false>
+// EQ: the equal-rate collision; otherwise the moment-space one (unequal
+// non-flux rates).
+template <typename TS, typename TC, bool KVAR, bool WALL, int NP, int TY, int NW, bool SB = false, bool SRC = false,
+          bool EQ = true>
 __global__ void __launch_bounds__(64 * NW)
 k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ fin, TS *__restrict__ fout,
             const typename HistType<TS>::T *__restrict__ pin, typename HistType<TS>::T *__restrict__ pout,
@@ -1076,7 +1079,7 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                         h[k] = wl ? -(TC)hc[j][k] + cf->ew[cz == 1 ? 0 : 1][k] : (TC)hc[j][k];
                     }
                     TC out[19];
-                    const TC phio = collide_node<19, TC, true, SRC, KVAR, NP, SB>(
+                    const TC phio = collide_node<19, TC, EQ, SRC, KVAR, NP, SB>(
                         cf, h, SRC ? (TC)pc[j] : TC(0), 0u, nullptr, nullptr, false, out);
                     bad |= !__builtin_isfinite(phio);
                     if (SRC) lp[s1 & (SRC ? 1 : 0)][SRC ? r : 0][lane] = (TP)phio;
@@ -1116,7 +1119,7 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                 }
                 TC out[19];
                 const TC pp_off = SRC ? (TC)lp[s0 & (SRC ? 1 : 0)][SRC ? r : 0][lane] : TC(0);
-                const TC phio = collide_node<19, TC, true, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr,
+                const TC phio = collide_node<19, TC, EQ, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr,
                                                                              false, out);
                 bad |= !__builtin_isfinite(phio);
                 if (x < nx && y < ny) {

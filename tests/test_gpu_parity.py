@@ -636,13 +636,56 @@ def test_two_step_passes_unequal_rates_bit_identical(nx, ny, prec, source, walls
         assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
 
 
+@pytest.mark.parametrize("n,prec,wall,source", [((20, 18, 22), "f64", True, "A"), ((33, 7, 11), "f32", False, "none"),
+                                                 ((70, 16, 9), "f32", True, "B"), ((9, 5, 4), "f16", True, "none"),
+                                                 ((5, 4, 1), "f64", True, "B"), ((65, 9, 17), "f32", True, "A")])
+def test_two_step_passes_d3q19_unequal_rates_bit_identical(n, prec, wall, source):
+    """D3Q19 with unequal non-flux rates (the moment-space collision in the
+    d'Humieres basis, reading R14) in two steps per pass, default tile shape:
+    bit-identical to single sweeps (state, history, phi), with no source,
+    Scheme A or Scheme B; FP64 against the oracle."""
+    lbm = _lbm()
+    spec, _, _ = W.d3q19_walls(n, precision=prec)
+    spec = dict(spec, s=[0.0] + [1.0 + 0.03 * ((7 * i) % 11) for i in range(1, 19)])
+    if source != "none":
+        spec = dict(spec, rpoly=[0.002, 0.01, -0.01], kpoly=[1.0, 0.0, 0.5], scheme=source)
+    if not wall:
+        spec["bc"] = ["periodic"] * 3
+    spec["phi_wall"] = [[0, 0], [0, 0], [0.3, 0.6]] if wall else spec["phi_wall"]
+    phi0 = W.gaussians_3d(n, 25)
+    say(f"[gpu] two-step passes d3q19 unequal rates {n} {prec} walls={wall} source={source}")
+    a = lbm.Lbm(spec).init(phi0)
+    a.set_two_step(False)
+    b = lbm.Lbm(spec).init(phi0)
+    b.set_two_step(True)
+    t = 0
+    for s in (4, 9, 30):
+        a.step(s - t)
+        b.step(s - t)
+        t = s
+        assert torch.equal(a.phi(), b.phi()), s
+        wa, _ = a.current()
+        wb, _ = b.current()
+        assert wa == wb
+        assert torch.equal(a.storage_view(a.f[wa]), b.storage_view(b.f[wb])), s
+        if source == "A":
+            nb = a.N * (8 if prec == "f64" else 4)
+            assert torch.equal(a.p[:nb], b.p[:nb]), s
+    with pytest.raises(lbm.LbmError):
+        b.set_two_step(True, 1)   # the moment-space collision has the default tile shape only
+    if prec == "f64":
+        ref = oracle_run(spec, phi0, (30,))[30]
+        got = b.phi().cpu().numpy()
+        say(f"    vs oracle: rel L2 {rel_l2(got, ref):.2e}, max {max_rel(got, ref)}")
+        assert rel_l2(got, ref) <= 1e-12 and max_rel(got, ref)[0] <= 1e-12
+
+
 def test_two_step_refused_where_it_does_not_apply():
     lbm = _lbm()
     walls = dict(W.spec_nonlinear_2d(70, 30), bc=["periodic", "abb", "periodic"], phi_wall=[[0, 0], [0.3, 0.7], [0, 0]],
                  kpoly=[1.0, 0.0, 0.0, 0.2])   # walls need 3-term polynomials
-    d3_rates = dict(W.d3q19_walls((20, 18, 22))[0], s=[0.0] + [1.0 + 0.01 * i for i in range(18)])
     d3_cubic = dict(W.d3q19_walls((20, 18, 22))[0], kpoly=[1.0, 0.0, 0.0, 0.5])
-    for spec in (d3_rates, d3_cubic, walls):
+    for spec in (d3_cubic, walls):
         s = lbm.Lbm(spec)
         with pytest.raises(lbm.LbmError) as ei:
             s.set_two_step(True)
