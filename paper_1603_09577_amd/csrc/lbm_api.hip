@@ -59,9 +59,8 @@ struct lbm_ctx {
     bool recentered = false;  // phi_ref on the device differs from the description's
     // per-node fields (caller-owned, FP64): K0(x) and the external source R(x, t)
     const double *kfield = nullptr, *rfield = nullptr;
-    // two time steps per pass (D2Q9 periodic equal-rate runs): the caller's
-    // second phi history buffer (needed only when the run keeps a history),
-    // and whether the path is on
+    // two time steps per pass: the caller's second phi history buffer (needed
+    // only when the run keeps a history), and whether the path is on
     void *p2 = nullptr;
     bool two_ok = false, two = false;
     int two_shape = 0;        // tile shape of two-step passes (two_step_shape_of; 0: the default)

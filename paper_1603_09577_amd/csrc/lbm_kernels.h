@@ -762,8 +762,9 @@ k_sweep(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f
 }
 
 // ---------------------------------------------------------------------------
-// Two time steps per pass (D2Q9, periodic, equal non-flux rates).  A
-// workgroup owns a tile of 62 x TH nodes.  Phase 1 runs step t on the tile
+// Two time steps per pass (D2Q9; periodic or walls on y, equal or unequal
+// non-flux rates: the template parameters below).  A workgroup owns a tile of
+// 62 x TH nodes.  Phase 1 runs step t on the tile
 // plus a one-node halo (64 x (TH + 2) nodes) from the stored state, and keeps
 // the post-collision populations and the new phi history in LDS, rounded to
 // the storage and history types exactly as a store would round them.  Phase 2

@@ -305,8 +305,8 @@ class Lbm:
         return buf.value.decode()
 
     def set_two_step(self, on, shape=0):
-        """Two time steps per pass inside step() (D2Q9 periodic equal-rate
-        runs), with tile shape `shape` (lbm_set_two_step, two_step_shapes)."""
+        """Two time steps per pass inside step() (where lbm_set_two_step
+        applies), with tile shape `shape` (lbm_set_two_step, two_step_shapes)."""
         _check(self.lib.lbm_set_two_step(self.ctx, 1 + int(shape) if on else 0))
 
     def two_step_shapes(self):
