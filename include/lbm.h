@@ -241,7 +241,7 @@ int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_l
  *    they alternate the history between p and p2 as in 2-D.
  * Remaining steps use single sweeps.  On by default where it applies (with a
  * Scheme-A source: where p2 is bound); lbm_tune times it against single
- * sweeps.  Not used with a divergence check, per-node fields or Remark III.
+ * sweeps.  Not used with per-node fields or Remark III.
  * mode: 0 off; k >= 1 on with tile shape k - 1 (lbm_two_step_shape; shape 0
  * is the default).  The non-default D2Q9 shapes need every polynomial of
  * degree <= 2.
@@ -260,7 +260,11 @@ int lbm_set_two_step(lbm_ctx *ctx, int mode);
  * shape. */
 int lbm_two_step_shape(const lbm_ctx *ctx, int shape, int *rows, int *waves);
 
-/* Divergence check every `every` steps inside lbm_step (0 = off). */
+/* Divergence check every `every` steps inside lbm_step (0 = off): lbm_step
+ * then waits on the host at every multiple of `every` (counted from lbm_init)
+ * and returns LBM_E_DIVERGED once a sweep has met a non-finite phi.  Steps
+ * between two checks still run as two-step passes where those apply; the
+ * per-step graphs are not used. */
 int lbm_set_check(lbm_ctx *ctx, int every);
 
 /* Re-centre the stored offsets of the current state (asynchronous, on the

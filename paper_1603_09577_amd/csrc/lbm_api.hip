@@ -390,7 +390,7 @@ bool two_ready(const lbm_ctx *c) {
     return c->two_ok && (!eff_dims(c).sb || c->dm.deg3) && (!keeps_history(c) || c->p2 != nullptr);
 }
 
-bool two_active(const lbm_ctx *c) { return c->two && two_ready(c) && !general_path(c) && c->check_every == 0; }
+bool two_active(const lbm_ctx *c) { return c->two && two_ready(c) && !general_path(c); }
 
 // Bytes of the second history buffer (0 when two-step passes never read one).
 size_t hist2_bytes(const lbm_ctx *c) {
@@ -492,10 +492,52 @@ hipError_t recenter(lbm_ctx *c, hipStream_t st) {
     return e;
 }
 
+// Reads the divergence flag (a host wait): LBM_E_DIVERGED once any sweep has
+// met a non-finite phi.
+int check_flag(lbm_ctx *c, hipStream_t st) {
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "divergence check");
+    if (flag) {
+        char buf[96];
+        std::snprintf(buf, sizeof(buf), "non-finite phi by step %lld", c->t);
+        return fail(LBM_E_DIVERGED, buf);
+    }
+    return LBM_OK;
+}
+
 // n sweeps from the current buffer: whole graphs of kGraphSteps sweeps, then
-// single launches (with the optional divergence check).
+// pairs of two-step passes where they apply, then single launches.  With the
+// divergence check (every k steps) the steps run in chunks that end on the
+// multiples of k, passes and single sweeps within a chunk, and the flag is
+// read at the end of each chunk that reaches a multiple.
 int advance(lbm_ctx *c, int nsteps, hipStream_t st) {
-    const bool graphs = c->check_every == 0 && !(c->desc.flags & LBM_FLAG_NO_GRAPH);
+    if (c->check_every > 0) {
+        while (nsteps > 0) {
+            int chunk = c->check_every - (int)(c->t % c->check_every);
+            if (chunk > nsteps) chunk = nsteps;
+            nsteps -= chunk;
+            while (two_active(c) && chunk >= 4) {
+                hipError_t e = sweep_pair(c, c->cur, st);
+                if (e != hipSuccess) return hip_fail(e, "two-step sweep kernel");
+                c->t += 4;
+                chunk -= 4;
+            }
+            for (; chunk > 0; --chunk) {
+                hipError_t e = sweep(c, c->f[c->cur], c->f[c->cur ^ 1], c->p, st);
+                if (e != hipSuccess) return hip_fail(e, "sweep kernel");
+                c->cur ^= 1;
+                ++c->t;
+            }
+            if (c->t % c->check_every == 0) {
+                const int rc = check_flag(c, st);
+                if (rc != LBM_OK) return rc;
+            }
+        }
+        return LBM_OK;
+    }
+    const bool graphs = !(c->desc.flags & LBM_FLAG_NO_GRAPH);
     while (graphs && nsteps >= kGraphSteps) {
         if (!c->gexec[c->cur]) {
             hipError_t e = make_graph(c, c->cur);
@@ -517,17 +559,6 @@ int advance(lbm_ctx *c, int nsteps, hipStream_t st) {
         if (e != hipSuccess) return hip_fail(e, "sweep kernel");
         c->cur ^= 1;
         ++c->t;
-        if (c->check_every > 0 && c->t % c->check_every == 0) {
-            int flag = 0;
-            e = hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return hip_fail(e, "divergence check");
-            if (flag) {
-                char buf[96];
-                std::snprintf(buf, sizeof(buf), "non-finite phi by step %lld", c->t);
-                return fail(LBM_E_DIVERGED, buf);
-            }
-        }
     }
     return LBM_OK;
 }

@@ -310,6 +310,28 @@ def test_divergence_detected():
     assert e.value.code == lbm.LBM_E_DIVERGED
 
 
+def test_divergence_check_keeps_two_step_passes():
+    """With the divergence check on, the steps between checks still run as
+    two-step passes: the result is the same bit for bit as without the check
+    (which runs graphs of passes), for check intervals that are and are not
+    multiples of 4, and an unstable run is still caught."""
+    lbm = _lbm()
+    spec = W.spec_nonlinear_2d(130, 50, precision="f32")
+    phi0 = W.noise_field((50, 130), 41)
+    say("[gpu] divergence check with two-step passes")
+    ref = lbm.Lbm(spec).init(phi0)
+    ref.step(103)
+    for every in (8, 10, 7):
+        sim = lbm.Lbm(spec).init(phi0)
+        sim.set_check(every)
+        sim.step(51)
+        sim.step(52)
+        assert torch.equal(sim.phi(), ref.phi()), every
+        wa, _ = sim.current()
+        wb, _ = ref.current()
+        assert wa == wb
+
+
 def test_graph_replay_identical_to_direct_launches():
     """lbm_step replays captured 32-sweep graphs; the result is bit-identical
     to launching every sweep directly."""
