@@ -719,7 +719,7 @@ def main():
     if args.two_step_3d:
         TWO_STEP_3D = [tuple(int(v) for v in sh.split("x")) for sh in args.two_step_3d.lower().split(",")]
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU (the library has no multi-GPU path); run with --gpus 1"}))
         sys.exit(2)
 
     import torch
