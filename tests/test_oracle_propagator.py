@@ -1,5 +1,5 @@
 """Exact discrete propagator for linear periodic runs: a pin of the oracle's
-relaxation with unequal rates (the survey's P6).
+relaxation with unequal rates.
 
 With B = phi u, D = phi Dten, a constant K and no source, one step of Eq. 2
 with the equilibrium of Eq. 3 is linear in the populations of a node:
