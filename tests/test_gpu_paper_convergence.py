@@ -1,14 +1,15 @@
 """The paper's convergence studies on the GPU at its printed resolutions
 (Sec. 3.1 Fig. 1-2, Sec. 3.4 Fig. 11, Sec. 3.5 Fig. 14), FP64.
 
-Reading R36: the figures report second order in space over the printed
+How the studies are read: the figures report second order in space over the printed
 lattice spacings, which holds only if the relaxation rates stay fixed while
 the grid is refined, i.e. under diffusive scaling (dt proportional to dx^2).
-The runs here take c = dx / dt = 1 on the coarsest printed grid (reading R23)
+The runs here take c = dx / dt = 1 on the coarsest printed grid
 and refine diffusively from there.  With c = 1 on every grid the error of
 the Pe = 100 problems stops falling (the lattice diffusivity grows with the
 resolution); `test_fixed_lattice_speed_stalls` records that.  Printed
-"N x N" periodic lattices have N - 1 distinct nodes (reading R23).
+"N x N" periodic lattices are read as N - 1 distinct nodes (the first and
+last grid lines are the same periodic line).
 
     Fig. 1 (Sec. 3.1, 201^2, T = 3, Pe = 100 and 1000): GRE reported, < 5e-4.
     Fig. 2 (Sec. 3.1, dx = L/100 ... L/500, T = 3): fitted order 2 +- 0.2.
@@ -163,7 +164,7 @@ def test_fig14_variable_k_order(kappa):
 
 
 def test_fixed_lattice_speed_stalls():
-    """Evidence for reading R36: with c = 1 on every grid the Pe = 100 sine
+    """Evidence for that reading: with c = 1 on every grid the Pe = 100 sine
     wave's GRE stops falling between dx = L/200 and L/500 (the lattice
     diffusivity rises from 0.2 to 0.5), far from second order."""
     kappa = 0.002

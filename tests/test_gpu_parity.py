@@ -663,7 +663,7 @@ def test_two_step_passes_unequal_rates_bit_identical(nx, ny, prec, source, walls
                                                  ((5, 4, 1), "f64", True, "B"), ((65, 9, 17), "f32", True, "A")])
 def test_two_step_passes_d3q19_unequal_rates_bit_identical(n, prec, wall, source):
     """D3Q19 with unequal non-flux rates (the moment-space collision in the
-    d'Humieres basis, reading R14) in two steps per pass, default tile shape:
+    d'Humieres basis, whose rate slots the paper does not fix) in two steps per pass, default tile shape:
     bit-identical to single sweeps (state, history, phi), with no source,
     Scheme A or Scheme B; FP64 against the oracle."""
     lbm = _lbm()

@@ -853,7 +853,7 @@ def test_scheme_b_explicit_case_unchanged():
 
 
 # ---------------------------------------------------------------------------
-# reading R32: the nonlinear 2-D workload read in lattice units diverges
+# grid units of the nonlinear workloads: read in lattice units they diverge
 # ---------------------------------------------------------------------------
 
 def _nonlinear_in_units(dx, dt, n=64):
