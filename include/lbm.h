@@ -132,7 +132,7 @@ typedef struct lbm_desc {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Validate a description and derive the model constants.  Rejects
- * (LBM_E_INVALID): unknown lattice, sizes < 1 or more than 2^31 nodes,
+ * (LBM_E_INVALID): unknown lattice, sizes < 1 or 2^31 nodes or more,
  * d <= 0, a used rate outside (0, 2), k0 not symmetric positive definite,
  * dten not symmetric.  LBM_E_UNSUPPORTED: walls on an axis other than the
  * last, Scheme B with rpoly of degree > 2, a rational B (bden) without
