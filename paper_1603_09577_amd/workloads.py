@@ -16,6 +16,7 @@ __all__ = [
     "spec_linear_gaussian", "spec_nonlinear_2d", "spec_d3q19_aniso",
     "gaussian_hill", "noise_field", "gaussians_3d", "random_spd3",
     "hill_linear_64", "nonlinear_2d", "d3q19_walls", "adjoint_2d", "adjoint_2d_sourcefree", "batch_specs",
+    "nonlinear_2d_walls_rates", "d3q19_walls_source",
     "burgers_fisher_wave", "spec_burgers_fisher",
 ]
 
@@ -223,6 +224,25 @@ def d3q19_walls(n=(256, 256, 256), precision="f64"):
     u = (0.03, 0, 0.01), sum of 8 Gaussians (seed 3), 2000 steps."""
     spec = spec_d3q19_aniso(n, K=random_spd3(3), precision=precision, phi_ref=0.0)
     return spec, gaussians_3d(n, 3), 2000
+
+
+def nonlinear_2d_walls_rates(n=1024, precision="f64"):
+    """The nonlinear 2-D physics between anti-bounce-back walls on y (phi_w =
+    0.3 below, 0.7 above) with unequal non-flux rates, seed 5, 5000 steps."""
+    spec = spec_nonlinear_2d(n, precision=precision)
+    spec = dict(spec, bc=["periodic", "abb", "periodic"], phi_wall=[[0.0, 0.0], [0.3, 0.7], [0.0, 0.0]],
+                s=[0.0, 1.3, 1.1, 1.0, 1.4, 1.0, 0.9, 1.2, 1.05])
+    return spec, noise_field((n, n), 5), 5000
+
+
+def d3q19_walls_source(n=(128, 128, 128), precision="f64"):
+    """The D3Q19 walls workload with a Scheme-A source R = 0.002 - 0.004 phi +
+    0.001 phi^2 (R' < 0 on the range phi takes, so perturbations decay rather
+    than grow; the root at phi = 2 - sqrt(2) attracts) and K = K0 (1 + phi^2 /
+    2), 1000 steps."""
+    spec, phi0, _ = d3q19_walls(n, precision=precision)
+    spec = dict(spec, rpoly=[0.002, -0.004, 0.001], kpoly=[1.0, 0.0, 0.5])
+    return spec, phi0, 1000
 
 
 def adjoint_2d(n=512, precision="f64"):

@@ -36,11 +36,15 @@ def cases():
     spec2, phi2, T2 = W.nonlinear_2d(1024)
     spec3, phi3, T3 = W.d3q19_walls((64, 64, 64))
     spec4, phi4, T4 = W.d3q19_walls((128, 128, 128))
+    spec5, phi5, T5 = W.nonlinear_2d_walls_rates(1024)
+    spec6, phi6, T6 = W.d3q19_walls_source((128, 128, 128))
     return {
         "nonlinear2d-1024": (spec2, phi2, (1, 10, 100, 1000, T2), 64),
         "d3q19-walls-64": (spec3, phi3, (1, 10, 100, 1000, T3), 16),
         "d3q19-walls-128": (spec4, phi4, (1, 10, 100, 1000, T4), 16),
         "nonlinear2d-1024-scheme-b": (dict(spec2, scheme="B"), phi2, (1, 10, 100, 1000, T2), 64),
+        "nonlinear2d-1024-walls-rates": (spec5, phi5, (1, 10, 100, 1000, T5), 64),
+        "d3q19-128-source": (spec6, phi6, (1, 10, 100, T6), 16),
     }
 
 
