@@ -63,6 +63,10 @@ struct lbm_ctx {
     // only when the run keeps a history), and whether the path is on
     void *p2 = nullptr;
     bool two_ok = false, two = false;
+    // D3Q19 passes: resident workgroups per CU of each tile shape's kernel
+    // (0: not asked yet) and the device's CU count, for the z-chunk choice
+    int occ3[4] = {0, 0, 0, 0};
+    int ncu = 0;
     int two_shape = 0;        // tile shape of two-step passes (two_step_shape_of; 0: the default)
     uint32_t adj_slots = 0;   // K0 partial slots: workgroups of the one- and two-sweep adjoints
     bool bound = false;
@@ -403,14 +407,54 @@ size_t hist2_bytes(const lbm_ctx *c) {
 // Planes per z chunk of the D3Q19 two-step pass: enough chunks that the
 // launch has at least 1024 workgroups (four per CU), each chunk computing two
 // planes beyond its own in phase 1.
+// Resident workgroups per CU of the D3Q19 pass in the current tile shape and
+// the CU count, asked of the runtime once per shape (outside graph capture:
+// lbm_init, lbm_set_two_step and lbm_tune call this before any pass).
+void prepare_zchunk(lbm_ctx *c) {
+    if (c->dm.q != 19 || !c->two_ok || c->two_shape < 0 || c->two_shape > 3) return;
+    if (!c->ncu) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            c->ncu = n;
+    }
+    if (!c->occ3[c->two_shape]) {
+        int occ = 0;
+        if (sweep2_q19_occupancy(eff_dims(c), c->g, c->two_shape, &occ) == hipSuccess && occ > 0)
+            c->occ3[c->two_shape] = occ;
+    }
+}
+
+// z planes per column of the D3Q19 pass.  Each workgroup lives for its chunk
+// of zc planes plus two, and one workgroup slot per CU (or a few) runs them
+// in rounds, so the pass takes about ceil(workgroups / slots) * (zc + 2)
+// plane-times: the chunk that minimises this fills the last round (256^3,
+// FP32 14 x 16, one slot per CU: zc = 32 gives 760 workgroups in 2.97
+// rounds, 52 GLUPS; zc = 24 gave 1045 in 4.08, i.e. five rounds, 44.5).
+// Without the occupancy figures: about 1024 workgroups.
 uint32_t zchunk(const lbm_ctx *c) {
     int rows = 0, waves = 0;
     if (!two_step3_shape_of(c->dm.prec, c->two_shape, &rows, &waves)) return c->g.nz;
-    const uint32_t tiles_xy = ((c->g.nx + 61) / 62) * ((c->g.ny + (uint32_t)rows - 1) / (uint32_t)rows);
-    uint32_t tiles_z = (1024 + tiles_xy - 1) / tiles_xy;
-    if (tiles_z > c->g.nz) tiles_z = c->g.nz;
+    const uint64_t tiles_xy = (uint64_t)((c->g.nx + 61) / 62) * ((c->g.ny + (uint32_t)rows - 1) / (uint32_t)rows);
+    const uint32_t nz = c->g.nz;
+    const int occ = (c->two_shape >= 0 && c->two_shape < 4) ? c->occ3[c->two_shape] : 0;
+    if (occ > 0 && c->ncu > 0) {
+        const uint64_t slots = (uint64_t)occ * (uint64_t)c->ncu;
+        uint32_t best_zc = nz;
+        uint64_t best = ~0ull;
+        for (uint32_t zc = 1; zc <= nz; ++zc) {
+            const uint64_t tz = (nz + zc - 1) / zc;
+            if (zc > 1 && (nz + zc - 2) / (zc - 1) == tz) continue;   // same chunk count as zc - 1
+            const uint64_t rounds = (tiles_xy * tz + slots - 1) / slots;
+            const uint64_t cost = rounds * (zc + 2);
+            if (cost < best) { best = cost; best_zc = zc; }
+        }
+        return best_zc;
+    }
+    uint64_t tiles_z = (1024 + tiles_xy - 1) / tiles_xy;
+    if (tiles_z > nz) tiles_z = nz;
     if (tiles_z < 1) tiles_z = 1;
-    return (c->g.nz + tiles_z - 1) / tiles_z;
+    return (uint32_t)((nz + tiles_z - 1) / tiles_z);
 }
 
 // Without a source the kernels touch no history, and p stands in for p2.
@@ -718,6 +762,7 @@ int lbm_init(lbm_ctx *c, const double *phi0, void *f_a, void *f_b, void *p, void
     // a fill kernel, not a memset node, in case the caller captures this call
     e = launch_zero((double *)c->d_flag, 1, st);
     if (e != hipSuccess) return hip_fail(e, "flag reset");
+    prepare_zchunk(c);
     return LBM_OK;
 }
 
@@ -777,8 +822,8 @@ int lbm_set_two_step(lbm_ctx *c, int mode) {
     if (mode < 0) return fail(LBM_E_INVALID, "mode must be 0 (off) or 1 + a tile shape");
     if (mode && !c->two_ok)
         return fail(LBM_E_UNSUPPORTED,
-                    "two steps per pass need equal non-flux rates and D2Q9 with periodic axes, or D3Q19 without a "
-                    "source and with polynomials of degree <= 2");
+                    "two steps per pass need 32-bit offsets and, on D3Q19 and with walls or unequal rates on "
+                    "D2Q9, polynomials of degree <= 2");
     if (mode && eff_dims(c).sb && !c->dm.deg3)
         return fail(LBM_E_UNSUPPORTED, "two steps per pass with a Scheme-B source need polynomials of degree <= 2");
     if (mode && c->bound && keeps_history(c) && !c->p2)
@@ -789,6 +834,7 @@ int lbm_set_two_step(lbm_ctx *c, int mode) {
     drop_graphs(c);
     c->two = mode != 0;
     c->two_shape = shape;
+    prepare_zchunk(c);
     return LBM_OK;
 }
 
@@ -1111,6 +1157,7 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
                 const int shape = order[ri / remaps];
                 if (!two_shape_usable(c, shape)) continue;
                 c->two_shape = shape;
+                prepare_zchunk(c);
                 c->g.remap = (remaps == 2 && ri % remaps == 0) ? 1u : 0u;
                 hipError_t e = sweep_pair(c, c->cur, st);
                 if (e == hipSuccess) e = hipEventRecord(e0, st);
@@ -1152,6 +1199,7 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
     c->g.remap = best_remap;
     c->two = best_two;
     c->two_shape = best_shape;
+    prepare_zchunk(c);
     drop_graphs(c);
     int brows = 0, bwaves = 0;
     if (best_two) shape_of(c, best_shape, &brows, &bwaves);

@@ -254,9 +254,11 @@ constexpr bool two_step3_shape(int id, int &rows, int &waves) {
     return true;
 }
 
+// occ != nullptr: launch nothing and report the kernel's resident workgroups
+// per CU instead (the z-chunk choice needs it).
 template <typename TS, typename TC, int TY, int NW>
 hipError_t sweep2_3d_shape(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                           const void *pin, void *pout, int *flag, uint32_t zc, hipStream_t st) {
+                           const void *pin, void *pout, int *flag, uint32_t zc, hipStream_t st, int *occ) {
     using TP = typename HistType<TS>::T;
     const auto *cf = (const Coefs<TC> *)coefs;
     const uint32_t tiles_x = (g.nx + 61) / 62, tiles_y = (g.ny + TY - 1) / TY, tiles_z = (g.nz + zc - 1) / zc;
@@ -273,6 +275,9 @@ hipError_t sweep2_3d_shape(const Dims &dm, const Geom &g, const void *coefs, con
         if constexpr ((sizeof(TS) == 8 && TY == 6 && NW == 8) || (sizeof(TS) != 8 && TY == 14 && NW == 16)) {
 #define LBM_SW3M(S, K, W)                                                                            \
     case (S * 4 + K * 2 + W):                                                                        \
+        if (occ)                                                                                     \
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                     \
+                occ, k_sweep2_3d<TS, TC, K, W, 3, TY, NW, S == 1, S == 2, false>, 64 * NW, 0);       \
         hipLaunchKernelGGL((k_sweep2_3d<TS, TC, K, W, 3, TY, NW, S == 1, S == 2, false>), grid, block, 0, st, g, cf, \
                            fi, fo, pi, po, tiles_x, tiles_y, zc, flag);                              \
         break;
@@ -290,6 +295,9 @@ hipError_t sweep2_3d_shape(const Dims &dm, const Geom &g, const void *coefs, con
     }
 #define LBM_SW3(S, K, W)                                                                             \
     case (S * 4 + K * 2 + W):                                                                        \
+        if (occ)                                                                                     \
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                     \
+                occ, k_sweep2_3d<TS, TC, K, W, 3, TY, NW, S == 1, S == 2>, 64 * NW, 0);              \
         hipLaunchKernelGGL((k_sweep2_3d<TS, TC, K, W, 3, TY, NW, S == 1, S == 2>), grid, block, 0, st, g, cf, fi, \
                            fo, pi, po, tiles_x, tiles_y, zc, flag);                                  \
         break;
@@ -307,19 +315,20 @@ hipError_t sweep2_3d_shape(const Dims &dm, const Geom &g, const void *coefs, con
 // (no phi history), walls on z or periodic; chunks of zc planes.
 template <int Q, typename TS, typename TC>
 hipError_t sweep2_3d_typed(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
-                           const void *pin, void *pout, int *flag, int shape, uint32_t zc, hipStream_t st) {
+                           const void *pin, void *pout, int *flag, int shape, uint32_t zc, hipStream_t st,
+                           int *occ) {
     if constexpr (Q == 19) {
         if (!dm.deg3 || !dm.o32 || zc < 1) return hipErrorNotSupported;
         if (!dm.eqr && shape != 0) return hipErrorInvalidValue;   // moment-space collision: the default shape
         // a Scheme-A source reads the history pin and writes pout (distinct)
-        if (dm.src && !dm.sb && (!pin || !pout || pin == pout)) return hipErrorInvalidValue;
+        if (!occ && dm.src && !dm.sb && (!pin || !pout || pin == pout)) return hipErrorInvalidValue;
         if constexpr (sizeof(TS) == 8) {
-            if (shape == 0) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
-            if (shape == 1) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
+            if (shape == 0) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st, occ);
+            if (shape == 1) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st, occ);
         } else {
-            if (shape == 0) return sweep2_3d_shape<TS, TC, 14, 16>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
-            if (shape == 1) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
-            if (shape == 2) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st);
+            if (shape == 0) return sweep2_3d_shape<TS, TC, 14, 16>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st, occ);
+            if (shape == 1) return sweep2_3d_shape<TS, TC, 6, 8>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st, occ);
+            if (shape == 2) return sweep2_3d_shape<TS, TC, 2, 4>(dm, g, coefs, fin, fout, pin, pout, flag, zc, st, occ);
         }
         return hipErrorInvalidValue;
     } else {

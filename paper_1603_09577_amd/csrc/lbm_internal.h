@@ -144,6 +144,8 @@ bool two_step_shape_of(int prec, int shape, int *rows, int *waves);
 // chunks of zc planes; its tile shapes
 hipError_t launch_sweep2_q19(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
                              const void *pin, void *pout, int *flag, int shape, uint32_t zc, hipStream_t st);
+// resident workgroups per CU of the D3Q19 two-step kernel this run would launch
+hipError_t sweep2_q19_occupancy(const Dims &dm, const Geom &g, int shape, int *blocks_per_cu);
 bool two_step3_shape_of(int prec, int shape, int *rows, int *waves);
 int adjoint_pair_rows(int prec, uint32_t nx, uint32_t ny);
 // Two reversed sweeps per pass (sweep s, then s - 1), D2Q9 only; tile rows

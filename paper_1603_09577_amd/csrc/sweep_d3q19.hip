@@ -59,7 +59,12 @@ hipError_t launch_set_wall_q19(const Dims &dm, void *coefs, const double *ewp, h
 
 hipError_t launch_sweep2_q19(const Dims &dm, const Geom &g, const void *coefs, const void *fin, void *fout,
                              const void *pin, void *pout, int *flag, int shape, uint32_t zc, hipStream_t st) {
-    LBM_BY_PREC(sweep2_3d_typed, dm, g, coefs, fin, fout, pin, pout, flag, shape, zc, st)
+    LBM_BY_PREC(sweep2_3d_typed, dm, g, coefs, fin, fout, pin, pout, flag, shape, zc, st, nullptr)
+}
+
+hipError_t sweep2_q19_occupancy(const Dims &dm, const Geom &g, int shape, int *blocks_per_cu) {
+    LBM_BY_PREC(sweep2_3d_typed, dm, g, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, shape, 1u, nullptr,
+                blocks_per_cu)
 }
 
 bool two_step3_shape_of(int prec, int shape, int *rows, int *waves) {
