@@ -421,6 +421,15 @@ int lbm_adjoint_step2(lbm_ctx *ctx, const void *f_s, const void *p_s, const void
 /* *ok = 1 if lbm_adjoint_step2 applies to this context, else 0. */
 int lbm_adjoint_pair_ok(const lbm_ctx *ctx, int *ok);
 
+/* Tile rows of lbm_adjoint_step2: 6 or 10 nodes per column (62 columns per
+ * tile).  lbm_create picks the tiling that runs the launch in fewer rounds of
+ * resident workgroups on the device (6 at equal rounds); rows = 6 or 10
+ * forces one, 0 restores that choice, anything else is LBM_E_INVALID.  Both
+ * give the same psi and pi bit for bit; the K0 sums differ in the order of
+ * FP64 additions.  lbm_adjoint_rows reports the rows in use. */
+int lbm_set_adjoint_rows(lbm_ctx *ctx, int rows);
+int lbm_adjoint_rows(const lbm_ctx *ctx, int *rows);
+
 /* Adjoint of the initialisation (Eq. 40): dL/dphi0 = sum_k psi_0,k dfeq_k/dphi
  * + pi_0, into gphi0_dev (FP64). */
 int lbm_adjoint_init(lbm_ctx *ctx, const double *phi0_dev, const void *psi0, const double *pi0,

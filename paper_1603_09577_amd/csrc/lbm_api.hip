@@ -68,6 +68,8 @@ struct lbm_ctx {
     int occ3[4] = {0, 0, 0, 0};
     int ncu = 0;
     int two_shape = 0;        // tile shape of two-step passes (two_step_shape_of; 0: the default)
+    int adj_rows = 6;         // tile rows of the two-sweep adjoint (6 or 10)
+    int adj_rows_auto = 6;    // the rows pick_adj_rows chose
     uint32_t adj_slots = 0;   // K0 partial slots: workgroups of the one- and two-sweep adjoints
     bool bound = false;
     // graphs of kGraphSteps sweeps starting from buffer 0 / 1, captured on an
@@ -404,25 +406,47 @@ size_t hist2_bytes(const lbm_ctx *c) {
 // Four steps as two passes of two steps each: f[start] -> f[start ^ 1] with the
 // history p -> p2, then back; state and history end where four single sweeps
 // would leave them.
-// Planes per z chunk of the D3Q19 two-step pass: enough chunks that the
-// launch has at least 1024 workgroups (four per CU), each chunk computing two
-// planes beyond its own in phase 1.
+void query_cus(lbm_ctx *c) {
+    if (c->ncu) return;
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+        c->ncu = n;
+}
+
 // Resident workgroups per CU of the D3Q19 pass in the current tile shape and
 // the CU count, asked of the runtime once per shape (outside graph capture:
 // lbm_init, lbm_set_two_step and lbm_tune call this before any pass).
 void prepare_zchunk(lbm_ctx *c) {
     if (c->dm.q != 19 || !c->two_ok || c->two_shape < 0 || c->two_shape > 3) return;
-    if (!c->ncu) {
-        int dev = 0, n = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-            c->ncu = n;
-    }
+    query_cus(c);
     if (!c->occ3[c->two_shape]) {
         int occ = 0;
         if (sweep2_q19_occupancy(eff_dims(c), c->g, c->two_shape, &occ) == hipSuccess && occ > 0)
             c->occ3[c->two_shape] = occ;
     }
+}
+
+// Tile rows of the two-sweep adjoint.  Its workgroups run in rounds of
+// (resident workgroups per CU) x CUs, and a partial last round costs a whole
+// one.  10-row tiles recompute fewer halo rows but fit fewer workgroups per
+// CU; they win where they need fewer rounds than 6-row tiles (512^2 FP64:
+// 9.8 against 11.0 us per pair; 768^2 FP32: 9.5 against 10.0), and 6-row
+// tiles win at equal rounds (1024^2 FP64: 34.3 against 36.6).
+void pick_adj_rows(lbm_ctx *c) {
+    query_cus(c);
+    c->adj_rows = 6;
+    int occ6 = 0, occ10 = 0;
+    if (c->ncu <= 0 || adjoint2_q9_occupancy(c->dm, c->g, 6, &occ6) != hipSuccess ||
+        adjoint2_q9_occupancy(c->dm, c->g, 10, &occ10) != hipSuccess || occ6 <= 0 || occ10 <= 0)
+        return;
+    auto rounds = [&](uint32_t th, int occ) {
+        const uint64_t tiles = (uint64_t)((c->g.nx + 61) / 62) * ((c->g.ny + th - 1) / th);
+        const uint64_t slots = (uint64_t)occ * (uint64_t)c->ncu;
+        return (tiles + slots - 1) / slots;
+    };
+    if (rounds(10, occ10) < rounds(6, occ6)) c->adj_rows = 10;
+    c->adj_rows_auto = c->adj_rows;
 }
 
 // z planes per column of the D3Q19 pass.  Each workgroup lives for its chunk
@@ -686,10 +710,11 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
                 (dm.q == 19 && dm.deg3 && c->dm.o32);
     c->two = c->two_ok;   // on by default where it applies (bit-identical; lbm_tune re-decides)
     {
-        const uint32_t th = (uint32_t)adjoint_pair_rows(dm.prec, g.nx, g.ny);
-        const uint32_t tiles = ((g.nx + 61) / 62) * ((g.ny + th - 1) / th);
-        // the two-sweep adjoint: periodic D2Q9 only
+        // the two-sweep adjoint: periodic D2Q9 only; its partial slots cover
+        // the 6-row tiling, the finer of the two
+        const uint32_t tiles = ((g.nx + 61) / 62) * ((g.ny + 5) / 6);
         c->adj_slots = dm.q == 9 && !dm.wall && dm.eqr && c->two_ok && tiles > g.nblocks ? tiles : g.nblocks;
+        if (dm.q == 9 && !dm.wall && dm.eqr && c->two_ok && dm.prec != 2) pick_adj_rows(c);
     }
     hipError_t e = hipMalloc(&c->d_coefs, sizeof(Coefs<double>));
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipMalloc(coefficients)"); }
@@ -1018,6 +1043,19 @@ int lbm_adjoint_pair_ok(const lbm_ctx *c, int *ok) {
     return LBM_OK;
 }
 
+int lbm_set_adjoint_rows(lbm_ctx *c, int rows) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    if (rows != 0 && rows != 6 && rows != 10) return fail(LBM_E_INVALID, "adjoint tile rows must be 0, 6 or 10");
+    c->adj_rows = rows == 0 ? c->adj_rows_auto : rows;
+    return LBM_OK;
+}
+
+int lbm_adjoint_rows(const lbm_ctx *c, int *rows) {
+    if (!c || !rows) return fail(LBM_E_INVALID, "null argument");
+    *rows = c->adj_rows;
+    return LBM_OK;
+}
+
 int lbm_adjoint_step2(lbm_ctx *c, const void *f_s, const void *p_s, const void *f_sm1, const void *p_sm1,
                       const void *psi_next, const double *pi_next, void *psi_out, double *pi_out, void *stream) {
     if (!c || !f_s || !p_s || !f_sm1 || !p_sm1 || !psi_next || !pi_next || !psi_out || !pi_out)
@@ -1033,7 +1071,7 @@ int lbm_adjoint_step2(lbm_ctx *c, const void *f_s, const void *p_s, const void *
         return fail(LBM_E_UNSUPPORTED,
                     "two reversed sweeps per launch need D2Q9, periodic axes and equal rates");
     hipError_t e = launch_adjoint2_q9(c->dm, c->g, c->d_coefs, f_s, p_s, f_sm1, p_sm1, psi_next, pi_next, psi_out,
-                                      pi_out, c->d_adj_part, (hipStream_t)stream);
+                                      pi_out, c->d_adj_part, c->adj_rows, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint pair kernel");
     return LBM_OK;
 }

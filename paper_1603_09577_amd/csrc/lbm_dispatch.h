@@ -496,10 +496,12 @@ hipError_t adjoint_typed(const Dims &dm, const Geom &g, const void *coefs, const
 
 // Two reversed sweeps per pass (D2Q9, periodic, equal rates): sweep s with
 // (f1, p1), then sweep s - 1 with (f0, p0); TH tile rows.
+// occ != nullptr: launch nothing and report the kernel's resident workgroups
+// per CU instead.
 template <typename TS, typename TC, int TH, int NW>
 hipError_t adjoint2_rows(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
                          const void *f0, const void *p0, const void *psi_next, const double *pi_next,
-                         void *psi_out, double *pi_out, double *gk_part, hipStream_t st) {
+                         void *psi_out, double *pi_out, double *gk_part, hipStream_t st, int *occ) {
     using TP = typename HistType<TS>::T;
     const auto *cf = (const Coefs<TC> *)coefs;
     const uint32_t tiles_x = (g.nx + 61) / 62, tiles_y = (g.ny + TH - 1) / TH;
@@ -511,6 +513,9 @@ hipError_t adjoint2_rows(const Dims &dm, const Geom &g, const void *coefs, const
     const int code = (dm.src ? 4 : 0) | (dm.kvar ? 2 : 0) | (dm.deg3 ? 8 : (dm.lowdeg ? 1 : 0));
 #define LBM_ADJ2(S, K, NP, TAG)                                                                      \
     case (S * 4 + K * 2 + TAG):                                                                      \
+        if (occ)                                                                                     \
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_adjoint2<TS, TC, S, K, NP, TH, NW>, \
+                                                                NW * 64, 0);                         \
         hipLaunchKernelGGL((k_adjoint2<TS, TC, S, K, NP, TH, NW>), grid, block, 0, st, g, cf, a1, q1, a0, q0, pn, \
                            pi_next, po, pi_out, gk_part, tiles_x);                                   \
         break;
@@ -524,29 +529,21 @@ hipError_t adjoint2_rows(const Dims &dm, const Geom &g, const void *coefs, const
     return hipGetLastError();
 }
 
-// Tile rows of the two-sweep adjoint: 6 in FP64 (workgroup memory); in FP32
-// 14 when that still gives 1024 tiles (4 workgroups per CU), else 6.
-inline int adjoint_pair_rows_for(int prec, uint32_t nx, uint32_t ny) {
-    if (prec == 0) return 6;
-    return ((nx + 61) / 62) * ((ny + 13) / 14) >= 1024 ? 14 : 6;
-}
-
+// Tile rows of the two-sweep adjoint: 6 or 10 (the host picks one per
+// context, lbm_api.hip); 4 waves per workgroup.
 template <int Q, typename TS, typename TC>
 hipError_t adjoint2_typed(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
                           const void *f0, const void *p0, const void *psi_next, const double *pi_next,
-                          void *psi_out, double *pi_out, double *gk_part, hipStream_t st) {
+                          void *psi_out, double *pi_out, double *gk_part, hipStream_t st, int rows, int *occ) {
     static_assert(Q == 9, "two reversed sweeps per pass are D2Q9 only");
     if (dm.wall || !dm.eqr) return hipErrorNotSupported;   // periodic, equal-rate tiles only
-    if constexpr (sizeof(TC) == 8) {
-        return adjoint2_rows<TS, TC, 6, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
-                                           gk_part, st);
-    } else {
-        if (adjoint_pair_rows_for(dm.prec, g.nx, g.ny) == 14)
-            return adjoint2_rows<TS, TC, 14, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
-                                                gk_part, st);
-        return adjoint2_rows<TS, TC, 6, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
-                                           gk_part, st);
-    }
+    if (rows == 6)
+        return adjoint2_rows<TS, TC, 6, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out, gk_part,
+                                           st, occ);
+    if (rows == 10)
+        return adjoint2_rows<TS, TC, 10, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
+                                            gk_part, st, occ);
+    return hipErrorInvalidValue;
 }
 
 template <int Q, typename TS, typename TC>

@@ -1,8 +1,9 @@
 """Two reversed sweeps per launch (lbm_adjoint_step2).
 
 * psi and pi equal those of two one-sweep launches bit for bit (FP64 and
-  FP32, with and without the Scheme-A source, ragged tiles in x and y, and a
-  grid with more tiles than one-sweep workgroups); the K0 sums agree up to
+  FP32, with and without the Scheme-A source, ragged tiles in x and y, a
+  grid with more tiles than one-sweep workgroups, 6- and 10-row tiles); the
+  K0 sums agree up to
   the order of additions (FP64 <= 1e-12 relative; FP32 terms are summed over
   a wave in FP32, <= 1e-6),
 * the checkpointed rollout gives the same dL/dphi0 with and without pairs,
@@ -50,18 +51,21 @@ def consecutive_states(sim):
 CASES = [
     ("f64", 100, 37, True), ("f64", 128, 64, True), ("f64", 100, 37, False),
     ("f32", 100, 37, True), ("f32", 64, 16, True), ("f32", 190, 45, False),
-    ("f32", 1024, 848, True),    # 1037 tiles of 14 rows (smaller grids take 6-row tiles)
+    ("f32", 1024, 848, True),    # 2414 tiles of 6 rows, 1445 of 10: several rounds of workgroups
     ("f64", 40, 30, True), ("f32", 33, 5, True),     # grids narrower and lower than a tile
 ]
 
 
+@pytest.mark.parametrize("rows", [6, 10])
 @pytest.mark.parametrize("prec,nx,ny,source", CASES)
-def test_pair_equals_two_single_sweeps(prec, nx, ny, source):
+def test_pair_equals_two_single_sweeps(prec, nx, ny, source, rows):
     from paper_1603_09577_amd import lbm
-    say(f"[gpu adjoint pairs] {prec} {nx}x{ny} source={source}")
+    say(f"[gpu adjoint pairs] {prec} {nx}x{ny} source={source} rows={rows}")
     spec = W.spec_nonlinear_2d(nx, ny, precision=prec, source=source)
     sim = lbm.Lbm(spec).init(W.noise_field((ny, nx), 31))
     assert sim.adjoint_pair_ok
+    sim.set_adjoint_rows(rows)
+    assert sim.adjoint_rows == rows
     sim.step(6)
     (fa, pa), (fb, pb) = consecutive_states(sim)
     rng = np.random.default_rng(32)
@@ -142,6 +146,27 @@ def test_rollout_with_pairs_matches_oracle():
     e0, ek = rel(p0.grad.cpu().numpy(), go), rel(k0.grad.numpy(), ko)
     say(f"[gpu adjoint pairs] vs oracle 70x24 T={T}: dphi0 {e0:.2e} dK0 {ek:.2e}")
     assert e0 <= 1e-10 and ek <= 1e-10
+
+
+def test_adjoint_rows_choice_and_setter():
+    """The tiling picked at creation is 6 or 10 rows, a forced one holds until
+    0 restores the pick, and other values are refused."""
+    from paper_1603_09577_amd import lbm
+    for prec, n in (("f64", 512), ("f64", 1024), ("f32", 768), ("f32", 1024)):
+        sim = lbm.Lbm(W.spec_nonlinear_2d(n, n, precision=prec))
+        auto = sim.adjoint_rows
+        say(f"[gpu adjoint pairs] {prec} {n}^2 picks {auto}-row tiles")
+        assert auto in (6, 10)
+        other = 16 - auto
+        sim.set_adjoint_rows(other)
+        assert sim.adjoint_rows == other
+        sim.set_adjoint_rows(0)
+        assert sim.adjoint_rows == auto
+        for bad in (-1, 7, 14):
+            with pytest.raises(lbm.LbmError) as ei:
+                sim.set_adjoint_rows(bad)
+            assert ei.value.code == lbm.LBM_E_INVALID
+        assert sim.adjoint_rows == auto
 
 
 def test_pair_refused_where_it_does_not_apply():
