@@ -170,8 +170,8 @@ int lbm_init(lbm_ctx *ctx, const double *phi0_dev, void *f_a, void *f_b, void *p
 /* Advance nsteps time steps (Eq. 2 with the Scheme-A source, anti-bounce-back
  * walls), one fused stream-collide sweep per step.  Runs of 32 sweeps are
  * replayed from a HIP graph captured on first use (an internal stream; the
- * graph is launched on the caller's stream) unless LBM_FLAG_NO_GRAPH is set or
- * a divergence check is enabled.  Asynchronous unless a divergence check is
+ * graph is launched on the caller's stream) unless LBM_FLAG_NO_GRAPH is set,
+ * a divergence check is enabled or lbm_tune found direct launches faster.  Asynchronous unless a divergence check is
  * due (lbm_set_check), in which case it synchronises the stream and returns
  * LBM_E_DIVERGED when a non-finite phi appeared. */
 int lbm_step(lbm_ctx *ctx, int nsteps, void *stream);
@@ -215,7 +215,11 @@ int lbm_set_nontemporal(lbm_ctx *ctx, int on);
  * and with the XCD-aware block order (one contiguous slab per XCD) or the
  * hardware's round-robin order (unless LBM_FLAG_NO_XCD_REMAP pins the
  * latter), and, where allowed, two time steps per pass (lbm_set_two_step);
- * keeps the fastest, writes the timings into `report` (may be NULL) and
+ * keeps the fastest; then, unless LBM_FLAG_NO_GRAPH is set or a divergence
+ * check is enabled, times lbm_step's graph replays against direct launches of
+ * the same kernels and keeps graphs unless direct launches are at least 1%
+ * faster (results are identical either way); writes the timings into
+ * `report` (may be NULL) and
  * re-initialises the state from the phi0 given to lbm_init (step counter
  * back to 0; phi0 must still be valid). */
 int lbm_tune(lbm_ctx *ctx, int reps, void *stream, char *report, size_t report_len);

@@ -63,6 +63,9 @@ struct lbm_ctx {
     // only when the run keeps a history), and whether the path is on
     void *p2 = nullptr;
     bool two_ok = false, two = false;
+    // lbm_step replays captured graphs of kGraphSteps sweeps (lbm_tune may
+    // find direct launches faster)
+    bool use_graphs = true;
     // D3Q19 passes: resident workgroups per CU of each tile shape's kernel
     // (0: not asked yet) and the device's CU count, for the z-chunk choice
     int occ3[4] = {0, 0, 0, 0};
@@ -605,7 +608,7 @@ int advance(lbm_ctx *c, int nsteps, hipStream_t st) {
         }
         return LBM_OK;
     }
-    const bool graphs = !(c->desc.flags & LBM_FLAG_NO_GRAPH);
+    const bool graphs = !(c->desc.flags & LBM_FLAG_NO_GRAPH) && c->use_graphs;
     while (graphs && nsteps >= kGraphSteps) {
         if (!c->gexec[c->cur]) {
             hipError_t e = make_graph(c, c->cur);
@@ -1232,18 +1235,49 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     c->g.remap = best_remap;
     c->two = best_two;
     c->two_shape = best_shape;
     prepare_zchunk(c);
     drop_graphs(c);
+    // runs of kGraphSteps sweeps: graph replays against direct launches of the
+    // same kernels, alternately, twice each (on 1024^2 FP32 passes direct
+    // launches measured 1.5-3% faster; on small grids the host's launch rate
+    // can fall behind the kernels, which graphs avoid).  Graphs stay unless
+    // direct launches are at least 1% faster.
+    float graph_ms = -1.f, direct_ms = -1.f;
+    c->use_graphs = true;
+    if (!(c->desc.flags & LBM_FLAG_NO_GRAPH) && c->check_every == 0) {
+        for (int trial = 0; trial < 4; ++trial) {
+            c->use_graphs = (trial & 1) == 0;
+            int rc = advance(c, kGraphSteps, st);   // warm-up (and the graph capture)
+            hipError_t e = rc == LBM_OK ? hipEventRecord(e0, st) : hipErrorUnknown;
+            if (e == hipSuccess) rc = advance(c, 2 * kGraphSteps, st);
+            if (e == hipSuccess && rc == LBM_OK) e = hipEventRecord(e1, st);
+            if (e == hipSuccess && rc == LBM_OK) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess && rc == LBM_OK) e = hipEventElapsedTime(&ms, e0, e1);
+            if (rc != LBM_OK || e != hipSuccess) {
+                (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+                return rc != LBM_OK ? rc : hip_fail(e, "tuning graph launches");
+            }
+            ms /= 2 * kGraphSteps;
+            float &t = c->use_graphs ? graph_ms : direct_ms;
+            if (t < 0.f || ms < t) t = ms;
+        }
+        c->use_graphs = !(direct_ms < 0.99f * graph_ms);
+        char gl[112];
+        std::snprintf(gl, sizeof(gl), "graph replays: %.4f ms per step, direct launches: %.4f ms per step\n", graph_ms,
+                      direct_ms);
+        rep += gl;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     int brows = 0, bwaves = 0;
     if (best_two) shape_of(c, best_shape, &brows, &bwaves);
-    char line[160];
-    std::snprintf(line, sizeof(line), "chosen chunk %d nt %d remap %u two %d rows %d waves %d (%.4f ms)", best_chunk,
-                  (int)best_nt, best_remap, (int)best_two, brows, bwaves, best);
+    char line[176];
+    std::snprintf(line, sizeof(line), "chosen chunk %d nt %d remap %u two %d rows %d waves %d graphs %d (%.4f ms)",
+                  best_chunk, (int)best_nt, best_remap, (int)best_two, brows, bwaves, (int)c->use_graphs, best);
     rep += line;
     if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
     // the history buffer was overwritten by the trial sweeps: restart from phi0
