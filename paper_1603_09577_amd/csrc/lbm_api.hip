@@ -1228,7 +1228,11 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
             std::snprintf(line, sizeof(line), "two steps per pass rows %d waves %d remap %u: %.4f ms per step\n",
                           rows, waves, remap, ms);
             rep += line;
-            if (ms < 0.98f * best_two_ms || (shape == best_shape && ms < best_two_ms)) {
+            // any later candidate (another shape, or the other block order of
+            // the same shape) must be 2% faster: a short trial once took the
+            // round-robin order for FP64 1024^2 passes, 58 against 67 GLUPS
+            // over 1000 steps
+            if (ms < 0.98f * best_two_ms) {
                 best_two_ms = ms;
                 best_shape = shape;
                 if (ms < best) { best = ms; best_two = true; best_remap = remap; }

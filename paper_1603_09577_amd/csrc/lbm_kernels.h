@@ -409,6 +409,38 @@ __device__ __forceinline__ T phi_scheme_b(const Coefs<TC> *__restrict__ cf, T x0
     return x0 + T(0.5) * *R;
 }
 
+// The Scheme-A source terms of one time level at a node: R and Btilde of
+// Eq. 28 (gamma = 0), from which Eq. 9 builds R_k.
+template <typename TC>
+struct SrcLevel {
+    TC R;
+    TC Bt[3];
+};
+
+// Hands this level's terms (R, Bt) to cur and takes the previous level's
+// (Rp, Btp) from prev, or rebuilds them at phi(t - 1) = phi_ref + pp_off.
+template <int D, bool KVAR, int NP, typename TC>
+__device__ __forceinline__ void src_levels(const Coefs<TC> *__restrict__ cf, bool kfon, const TC *g0n, TC pp_off,
+                                           TC R, const TC *Bt, SrcLevel<TC> *cur, const SrcLevel<TC> *prev,
+                                           TC &Rp, TC *Btp) {
+    if (cur) {
+        cur->R = R;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) cur->Bt[a] = Bt[a];
+    }
+    if (prev) {
+        Rp = prev->R;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Btp[a] = prev->Bt[a];
+        return;
+    }
+    TC Ap[6];
+    const TC pp = cf->phi_ref + pp_off;
+    if (kfon) ablock_field<D, NP>(cf, g0n, pp, Ap);
+    else ablock<D, KVAR, NP>(cf, pp, Ap);
+    source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
+}
+
 // One node of the sweep (shared by the single-instance and batched kernels).
 //
 // SB: Scheme B (Eq. 33-35): the stored variable is fbar = f - R_k / 2, phi =
@@ -425,9 +457,15 @@ __device__ __forceinline__ T phi_scheme_b(const Coefs<TC> *__restrict__ cf, T x0
 // form), with the phi history pp_off = phi(t - 1) - phi_ref: writes the
 // post-collision populations to out and returns phio = phi - phi_ref, which
 // the caller stores as the history when SRC or rem3 (see sweep_node).
+// Scheme A only: cur (if given) receives this level's source terms; prev (if
+// given) supplies the previous level's instead of rebuilding them from
+// pp_off.  A caller that passes the terms of the same node one step later
+// gets the values the rebuild would give (the same function of the same phi)
+// without its arithmetic.
 template <int Q, typename TC, bool EQR, bool SRC, bool KVAR, int NP, bool SB = false, bool KF = false>
 __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, const TC *h, TC pp_off, uint32_t n,
-                                           const double *kfield, const double *rfield, bool rem3, TC *out) {
+                                           const double *kfield, const double *rfield, bool rem3, TC *out,
+                                           SrcLevel<TC> *cur = nullptr, const SrcLevel<TC> *prev = nullptr) {
     using L = Lattice<Q>;
     constexpr int D = L::dim;
     TC g0n[6];
@@ -476,12 +514,9 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
         TC Vo[3] = {TC(0), TC(0), TC(0)};
         TC jsh[3] = {TC(0), TC(0), TC(0)};   // Scheme B: R B' / 2, the part of j the shift removed
         if (SRC) {
-            TC Bt[3], R, Btp[3], Rp, Ap[6];
+            TC Bt[3], R, Btp[3], Rp;
             source_terms<D, NP>(cf, phi, A, Bt, R);
-            const TC pp = cf->phi_ref + pp_off;
-            if (kfon) ablock_field<D, NP>(cf, g0n, pp, Ap);
-            else ablock<D, KVAR, NP>(cf, pp, Ap);
-            source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
+            src_levels<D, KVAR, NP>(cf, kfon, g0n, pp_off, R, Bt, cur, prev, Rp, Btp);
             Se = TC(1.5) * R - TC(0.5) * Rp;
 #pragma unroll
             for (int a = 0; a < D; ++a) Vo[a] = TC(4.5) * R * Bt[a] - TC(1.5) * Rp * Btp[a];
@@ -651,12 +686,9 @@ __device__ __forceinline__ TC collide_node(const Coefs<TC> *__restrict__ cf, con
 
     if (SRC && !EQR) {
         // Scheme A: + 3/2 R_k(t) - 1/2 R_k(t - 1), R_k = w_k (1 + 3 c.Btilde) R (Eq. 9)
-        TC Bt[3], R, Btp[3], Rp, Ap[6];
+        TC Bt[3], R, Btp[3], Rp;
         source_terms<D, NP>(cf, phi, A, Bt, R);
-        const TC pp = cf->phi_ref + pp_off;
-        if (kfon) ablock_field<D, NP>(cf, g0n, pp, Ap);
-        else ablock<D, KVAR, NP>(cf, pp, Ap);
-        source_terms<D, NP>(cf, pp, Ap, Btp, Rp);
+        src_levels<D, KVAR, NP>(cf, kfon, g0n, pp_off, R, Bt, cur, prev, Rp, Btp);
         const TC r1 = TC(1.5) * R, r0 = TC(0.5) * Rp;
         Se = r1 - r0;
 #pragma unroll
@@ -805,10 +837,17 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
                                             int *flag) {
     using L = Lattice<9>;
     using TP = typename HistType<TS>::T;
-    constexpr int TX = 64, TR = TH + 2;
+    constexpr int TX = 64, TR = TH + 2, NR = TR / NW;
     static_assert(TR % NW == 0, "tile rows must split evenly over the waves");
+    // Scheme A: phase 2 takes each node's previous-level source terms from
+    // the registers of the wave that formed them in phase 1 (the same node,
+    // one step earlier) instead of rebuilding them from the phi history; the
+    // history type equals the compute type, so the rebuild would see the same
+    // phi and give the same values
+    constexpr bool HAND = SRC && !SB && std::is_same<TP, TC>::value;
     __shared__ TS lf[9][TR][TX];
-    __shared__ TP lp[TR][TX];
+    __shared__ TP lp[HAND ? 1 : TR][TX];
+    SrcLevel<TC> lev[HAND ? NR : 1];
     const int x0 = (int)(tx * (TX - 2)), y0 = (int)(ty * TH);
     const int lane = threadIdx.x & 63;
     // the wave index is the same in every lane; taken into a scalar register,
@@ -832,7 +871,6 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
         // collision, so the latency of its later rows overlaps the arithmetic
         // of the first (measured +1% with 6 x 8 tiles, +8% with 6 x 4; the
         // FP32 shapes gained nothing that way)
-        constexpr int NR = TR / NW;
         TS hs[NR][9];
         TS ps[NR];
 #pragma unroll
@@ -867,15 +905,16 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
                 h[k] = wl ? -(TC)hs[i][k] + cf->ew[cy == 1 ? 0 : 1][k] : (TC)hs[i][k];
             }
             TC out[9];
-            const TC phio = collide_node<9, TC, EQ, SRC, KVAR, NP, SB>(cf, h, ps[i], 0u, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, EQ, SRC, KVAR, NP, SB>(cf, h, ps[i], 0u, nullptr, nullptr, false, out,
+                                                                        HAND ? &lev[HAND ? i : 0] : nullptr);
 #pragma unroll
             for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
-            lp[r][lane] = (TP)phio;
+            if (!HAND) lp[HAND ? 0 : r][lane] = (TP)phio;
             bad |= !__builtin_isfinite(phio);
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < TR / NW; ++i) {
+        for (int i = 0; i < NR; ++i) {
             const int r = wv + i * NW;
             const int yl = y0 - 1 + r;
             if (WALL && (yl < 0 || yl >= ny)) continue;   // beyond a wall
@@ -897,20 +936,20 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
             }
             const TC pp_off = SRC ? (TC)*at<true>(pin, n) : TC(0);
             TC out[9];
-            const TC phio = collide_node<9, TC, EQ, SRC, KVAR, NP, SB>(cf, h, pp_off, n, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, EQ, SRC, KVAR, NP, SB>(cf, h, pp_off, n, nullptr, nullptr, false, out,
+                                                                        HAND ? &lev[HAND ? i : 0] : nullptr);
 #pragma unroll
             for (int k = 0; k < 9; ++k) lf[k][r][lane] = (TS)out[k];
-            lp[r][lane] = (TP)phio;
+            if (!HAND) lp[HAND ? 0 : r][lane] = (TP)phio;
             bad |= !__builtin_isfinite(phio);
         }
     }
     __syncthreads();
-    // phase 2: interior lanes 1..62, rows 1..TH
+    // phase 2: interior lanes 1..62, rows 1..TH (no rows beyond a wall)
     if (lane >= 1 && lane <= TX - 2) {
         const int x = x0 + lane - 1;
-        for (int r = 1 + wv; r <= TH; r += NW) {
+        auto row2 = [&](int r, const SrcLevel<TC> *prev) {
             const int y = y0 + r - 1;
-            if (WALL && y >= ny) break;   // no rows beyond the wall
             TC h[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
@@ -919,14 +958,29 @@ __device__ __forceinline__ void sweep2_tile(const Geom &g, const Coefs<TC> *__re
                 h[k] = wl ? -(TC)lf[L::opp(k)][r][lane] + cf->ew[cy == 1 ? 0 : 1][k]
                           : (TC)lf[k][r - cy][lane - L::cx(k)];
             }
-            const TC pp_off = SRC ? (TC)lp[r][lane] : TC(0);
+            const TC pp_off = (SRC && !HAND) ? (TC)lp[HAND ? 0 : r][lane] : TC(0);
             TC out[9];
-            const TC phio = collide_node<9, TC, EQ, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr, false, out);
+            const TC phio = collide_node<9, TC, EQ, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr, false, out,
+                                                                        nullptr, prev);
             bad |= !__builtin_isfinite(phio);
             if (x < nx && y < ny) {
                 const uint32_t m = (uint32_t)y * g.nx + (uint32_t)x;
                 store_planes<9, false>(fout, g.plane, m, out);
                 if (SRC) *at<true>(pout, m) = (TP)phio;
+            }
+        };
+        if constexpr (HAND) {
+            // the rows this wave ran in phase 1, halo rows excepted
+#pragma unroll
+            for (int i = 0; i < NR; ++i) {
+                const int r = wv + i * NW;
+                if (r < 1 || r > TH || (WALL && y0 + r - 1 >= ny)) continue;
+                row2(r, &lev[i]);
+            }
+        } else {
+            for (int r = 1 + wv; r <= TH; r += NW) {
+                if (WALL && y0 + r - 1 >= ny) break;
+                row2(r, nullptr);
             }
         }
     }
