@@ -531,12 +531,13 @@ __device__ __forceinline__ constexpr int shared_rows_first(int j) {
 // their halo.
 // A workgroup has NW waves; the TH + 2 rows of phase 1 split evenly over
 // them, and phase 2 gives the TH own rows to the waves in turn.
-// FP64 with short polynomials is held to 3 waves per SIMD (168 registers),
-// what the workgroup memory of its 6-row tiles allows anyway (3 workgroups of
-// 4 waves per CU); with 9-term polynomials that limit would spill.
+// FP64 6-row tiles with short polynomials are held to 3 waves per SIMD (168
+// registers), what their workgroup memory allows anyway (3 workgroups of 4
+// waves per CU); with 9-term polynomials that limit would spill.  10-row
+// tiles fit 2 workgroups per CU, and take no register limit.
 template <typename TS, typename TC, bool SRC, bool KVAR, int NP, int TH, int NW>
 __global__ void __launch_bounds__(NW * 64)
-__attribute__((amdgpu_waves_per_eu(sizeof(TC) == 8 && NP <= 4 ? 3 : 1, 8)))
+__attribute__((amdgpu_waves_per_eu(sizeof(TC) == 8 && NP <= 4 && TH == 6 ? 3 : 1, 8)))
 k_adjoint2(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict__ f1,
            const typename HistType<TS>::T *__restrict__ p1, const TS *__restrict__ f0,
            const typename HistType<TS>::T *__restrict__ p0, const TC *__restrict__ psi_next,
