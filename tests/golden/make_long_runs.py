@@ -38,6 +38,7 @@ def cases():
     spec4, phi4, T4 = W.d3q19_walls((128, 128, 128))
     spec5, phi5, T5 = W.nonlinear_2d_walls_rates(1024)
     spec6, phi6, T6 = W.d3q19_walls_source((128, 128, 128))
+    spec7, phi7, _ = W.d3q19_walls((256, 256, 256))
     return {
         "nonlinear2d-1024": (spec2, phi2, (1, 10, 100, 1000, T2), 64),
         "d3q19-walls-64": (spec3, phi3, (1, 10, 100, 1000, T3), 16),
@@ -45,6 +46,9 @@ def cases():
         "nonlinear2d-1024-scheme-b": (dict(spec2, scheme="B"), phi2, (1, 10, 100, 1000, T2), 64),
         "nonlinear2d-1024-walls-rates": (spec5, phi5, (1, 10, 100, 1000, T5), 64),
         "d3q19-128-source": (spec6, phi6, (1, 10, 100, T6), 16),
+        # the full 256^3 grid for the first 200 of its 2000 steps (the whole
+        # run would take the host oracle hours; 128^3 covers the full length)
+        "d3q19-walls-256": (spec7, phi7, (1, 10, 100, 200), 32),
     }
 
 
