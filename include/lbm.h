@@ -425,14 +425,19 @@ int lbm_adjoint_step2(lbm_ctx *ctx, const void *f_s, const void *p_s, const void
 /* *ok = 1 if lbm_adjoint_step2 applies to this context, else 0. */
 int lbm_adjoint_pair_ok(const lbm_ctx *ctx, int *ok);
 
-/* Tile rows of lbm_adjoint_step2: 6 or 10 nodes per column (62 columns per
- * tile).  lbm_create picks the tiling that runs the launch in fewer rounds of
- * resident workgroups on the device (6 at equal rounds); rows = 6 or 10
- * forces one, 0 restores that choice, anything else is LBM_E_INVALID.  Both
- * give the same psi and pi bit for bit; the K0 sums differ in the order of
- * FP64 additions.  lbm_adjoint_rows reports the rows in use. */
-int lbm_set_adjoint_rows(lbm_ctx *ctx, int rows);
-int lbm_adjoint_rows(const lbm_ctx *ctx, int *rows);
+/* Tile shapes of lbm_adjoint_step2, 62 columns wide: shape 0 = 6 rows x 4
+ * waves per workgroup, 1 = 10 x 4, 2 = 10 x 12 (one row per wave).
+ * lbm_adjoint_tile_shape reports a shape's rows and waves (LBM_E_INVALID past
+ * the last).  lbm_create picks one for the grid and device: the 6- or 10-row
+ * tiling that runs the launch in fewer rounds of resident workgroups (6 at
+ * equal rounds), and 10 x 12 for FP32 launches with at most 6 waves per SIMD
+ * in all.  lbm_set_adjoint_tile forces shape mode - 1, or restores the pick
+ * with mode 0 (LBM_E_INVALID otherwise); lbm_adjoint_tile reports the shape
+ * in use.  Every shape gives the same psi and pi bit for bit; the K0 sums
+ * differ in the order of FP64 additions. */
+int lbm_adjoint_tile_shape(const lbm_ctx *ctx, int shape, int *rows, int *waves);
+int lbm_set_adjoint_tile(lbm_ctx *ctx, int mode);
+int lbm_adjoint_tile(const lbm_ctx *ctx, int *shape);
 
 /* Adjoint of the initialisation (Eq. 40): dL/dphi0 = sum_k psi_0,k dfeq_k/dphi
  * + pi_0, into gphi0_dev (FP64). */

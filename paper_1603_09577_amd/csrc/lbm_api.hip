@@ -71,8 +71,8 @@ struct lbm_ctx {
     int occ3[4] = {0, 0, 0, 0};
     int ncu = 0;
     int two_shape = 0;        // tile shape of two-step passes (two_step_shape_of; 0: the default)
-    int adj_rows = 6;         // tile rows of the two-sweep adjoint (6 or 10)
-    int adj_rows_auto = 6;    // the rows pick_adj_rows chose
+    int adj_shape = 0;        // tile shape of the two-sweep adjoint (adjoint2_shape_of)
+    int adj_shape_auto = 0;   // the shape pick_adj_shape chose
     uint32_t adj_slots = 0;   // K0 partial slots: workgroups of the one- and two-sweep adjoints
     bool bound = false;
     // graphs of kGraphSteps sweeps starting from buffer 0 / 1, captured on an
@@ -430,26 +430,34 @@ void prepare_zchunk(lbm_ctx *c) {
     }
 }
 
-// Tile rows of the two-sweep adjoint.  Its workgroups run in rounds of
-// (resident workgroups per CU) x CUs, and a partial last round costs a whole
-// one.  10-row tiles recompute fewer halo rows but fit fewer workgroups per
-// CU; they win where they need fewer rounds than 6-row tiles (512^2 FP64:
-// 9.8 against 11.0 us per pair; 768^2 FP32: 9.5 against 10.0), and 6-row
-// tiles win at equal rounds (1024^2 FP64: 34.3 against 36.6).
-void pick_adj_rows(lbm_ctx *c) {
+// Tile shape of the two-sweep adjoint: 6 x 4, 10 x 4 or 10 x 12 (rows x
+// waves).  Its workgroups run in rounds of (resident workgroups per CU) x
+// CUs, and a partial last round costs a whole one.  10-row tiles recompute
+// fewer halo rows but fit fewer workgroups per CU; they win where they need
+// fewer rounds than 6-row tiles (512^2 FP64: 9.3 against 10.9 us per reversed
+// sweep; 768^2 FP32: 9.5 against 10.0), and 6-row tiles win at equal rounds
+// (1024^2 FP64: 34.7 against 36.8).  An FP32 launch too small to give every
+// SIMD several waves (at most 6 waves per SIMD with 12 per 10-row tile; 512^2
+// has 468 such tiles) runs 10-row tiles with one row per wave: 5.3 against
+// 6.1 us.  FP64, held to 2 or 3 waves per SIMD by its registers, gains
+// nothing from the extra waves (512^2: 10.3 against 9.3).
+void pick_adj_shape(lbm_ctx *c) {
     query_cus(c);
-    c->adj_rows = 6;
+    c->adj_shape = 0;
     int occ6 = 0, occ10 = 0;
-    if (c->ncu <= 0 || adjoint2_q9_occupancy(c->dm, c->g, 6, &occ6) != hipSuccess ||
-        adjoint2_q9_occupancy(c->dm, c->g, 10, &occ10) != hipSuccess || occ6 <= 0 || occ10 <= 0)
+    if (c->ncu <= 0 || adjoint2_q9_occupancy(c->dm, c->g, 0, &occ6) != hipSuccess ||
+        adjoint2_q9_occupancy(c->dm, c->g, 1, &occ10) != hipSuccess || occ6 <= 0 || occ10 <= 0) {
+        c->adj_shape_auto = c->adj_shape;
         return;
+    }
+    auto tiles = [&](uint32_t th) { return (uint64_t)((c->g.nx + 61) / 62) * ((c->g.ny + th - 1) / th); };
     auto rounds = [&](uint32_t th, int occ) {
-        const uint64_t tiles = (uint64_t)((c->g.nx + 61) / 62) * ((c->g.ny + th - 1) / th);
         const uint64_t slots = (uint64_t)occ * (uint64_t)c->ncu;
-        return (tiles + slots - 1) / slots;
+        return (tiles(th) + slots - 1) / slots;
     };
-    if (rounds(10, occ10) < rounds(6, occ6)) c->adj_rows = 10;
-    c->adj_rows_auto = c->adj_rows;
+    if (rounds(10, occ10) < rounds(6, occ6)) c->adj_shape = 1;
+    if (c->dm.prec == 1 && tiles(10) * 12 <= 6ull * 4 * (uint64_t)c->ncu) c->adj_shape = 2;
+    c->adj_shape_auto = c->adj_shape;
 }
 
 // z planes per column of the D3Q19 pass.  Each workgroup lives for its chunk
@@ -717,7 +725,7 @@ int lbm_create(const lbm_desc *desc, lbm_ctx **out) {
         // the 6-row tiling, the finer of the two
         const uint32_t tiles = ((g.nx + 61) / 62) * ((g.ny + 5) / 6);
         c->adj_slots = dm.q == 9 && !dm.wall && dm.eqr && c->two_ok && tiles > g.nblocks ? tiles : g.nblocks;
-        if (dm.q == 9 && !dm.wall && dm.eqr && c->two_ok && dm.prec != 2) pick_adj_rows(c);
+        if (dm.q == 9 && !dm.wall && dm.eqr && c->two_ok && dm.prec != 2) pick_adj_shape(c);
     }
     hipError_t e = hipMalloc(&c->d_coefs, sizeof(Coefs<double>));
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipMalloc(coefficients)"); }
@@ -1046,16 +1054,24 @@ int lbm_adjoint_pair_ok(const lbm_ctx *c, int *ok) {
     return LBM_OK;
 }
 
-int lbm_set_adjoint_rows(lbm_ctx *c, int rows) {
-    if (!c) return fail(LBM_E_INVALID, "null context");
-    if (rows != 0 && rows != 6 && rows != 10) return fail(LBM_E_INVALID, "adjoint tile rows must be 0, 6 or 10");
-    c->adj_rows = rows == 0 ? c->adj_rows_auto : rows;
+int lbm_adjoint_tile_shape(const lbm_ctx *c, int shape, int *rows, int *waves) {
+    if (!c || !rows || !waves) return fail(LBM_E_INVALID, "null argument");
+    if (!adjoint2_shape_of(shape, rows, waves)) return fail(LBM_E_INVALID, "no such adjoint tile shape");
     return LBM_OK;
 }
 
-int lbm_adjoint_rows(const lbm_ctx *c, int *rows) {
-    if (!c || !rows) return fail(LBM_E_INVALID, "null argument");
-    *rows = c->adj_rows;
+int lbm_set_adjoint_tile(lbm_ctx *c, int mode) {
+    if (!c) return fail(LBM_E_INVALID, "null context");
+    int rows = 0, waves = 0;
+    if (mode < 0 || (mode > 0 && !adjoint2_shape_of(mode - 1, &rows, &waves)))
+        return fail(LBM_E_INVALID, "mode must be 0 (the pick) or 1 + an adjoint tile shape");
+    c->adj_shape = mode == 0 ? c->adj_shape_auto : mode - 1;
+    return LBM_OK;
+}
+
+int lbm_adjoint_tile(const lbm_ctx *c, int *shape) {
+    if (!c || !shape) return fail(LBM_E_INVALID, "null argument");
+    *shape = c->adj_shape;
     return LBM_OK;
 }
 
@@ -1074,7 +1090,7 @@ int lbm_adjoint_step2(lbm_ctx *c, const void *f_s, const void *p_s, const void *
         return fail(LBM_E_UNSUPPORTED,
                     "two reversed sweeps per launch need D2Q9, periodic axes and equal rates");
     hipError_t e = launch_adjoint2_q9(c->dm, c->g, c->d_coefs, f_s, p_s, f_sm1, p_sm1, psi_next, pi_next, psi_out,
-                                      pi_out, c->d_adj_part, c->adj_rows, (hipStream_t)stream);
+                                      pi_out, c->d_adj_part, c->adj_shape, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "adjoint pair kernel");
     return LBM_OK;
 }

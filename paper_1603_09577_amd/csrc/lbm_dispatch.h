@@ -529,20 +529,23 @@ hipError_t adjoint2_rows(const Dims &dm, const Geom &g, const void *coefs, const
     return hipGetLastError();
 }
 
-// Tile rows of the two-sweep adjoint: 6 or 10 (the host picks one per
-// context, lbm_api.hip); 4 waves per workgroup.
+// Tile shapes of the two-sweep adjoint, (rows, waves per workgroup): 6 x 4,
+// 10 x 4 and 10 x 12 (the host picks one per context, lbm_api.hip).
+constexpr int kAdjShapes = 3;
+constexpr int kAdjShape[kAdjShapes][2] = {{6, 4}, {10, 4}, {10, 12}};
+
 template <int Q, typename TS, typename TC>
 hipError_t adjoint2_typed(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
                           const void *f0, const void *p0, const void *psi_next, const double *pi_next,
-                          void *psi_out, double *pi_out, double *gk_part, hipStream_t st, int rows, int *occ) {
+                          void *psi_out, double *pi_out, double *gk_part, hipStream_t st, int shape, int *occ) {
     static_assert(Q == 9, "two reversed sweeps per pass are D2Q9 only");
     if (dm.wall || !dm.eqr) return hipErrorNotSupported;   // periodic, equal-rate tiles only
-    if (rows == 6)
-        return adjoint2_rows<TS, TC, 6, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out, gk_part,
-                                           st, occ);
-    if (rows == 10)
-        return adjoint2_rows<TS, TC, 10, 4>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out,
-                                            gk_part, st, occ);
+#define LBM_ADJ2S(ID, TH, NW)                                                                        \
+    if (shape == ID)                                                                                 \
+        return adjoint2_rows<TS, TC, TH, NW>(dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out, \
+                                             gk_part, st, occ);
+    LBM_ADJ2S(0, 6, 4) LBM_ADJ2S(1, 10, 4) LBM_ADJ2S(2, 10, 12)
+#undef LBM_ADJ2S
     return hipErrorInvalidValue;
 }
 

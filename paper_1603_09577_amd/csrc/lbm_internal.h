@@ -147,12 +147,15 @@ hipError_t launch_sweep2_q19(const Dims &dm, const Geom &g, const void *coefs, c
 // resident workgroups per CU of the D3Q19 two-step kernel this run would launch
 hipError_t sweep2_q19_occupancy(const Dims &dm, const Geom &g, int shape, int *blocks_per_cu);
 bool two_step3_shape_of(int prec, int shape, int *rows, int *waves);
-// Two reversed sweeps per pass (sweep s, then s - 1), D2Q9 only, in tiles of
-// `rows` rows (6 or 10); and the resident workgroups per CU of that kernel.
+// Two reversed sweeps per pass (sweep s, then s - 1), D2Q9 only, in tile
+// shape `shape` (adjoint2_shape_of); and the resident workgroups per CU of
+// that kernel.
 hipError_t launch_adjoint2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
                               const void *f0, const void *p0, const void *psi_next, const double *pi_next,
-                              void *psi_out, double *pi_out, double *gk_part, int rows, hipStream_t st);
-hipError_t adjoint2_q9_occupancy(const Dims &dm, const Geom &g, int rows, int *blocks_per_cu);
+                              void *psi_out, double *pi_out, double *gk_part, int shape, hipStream_t st);
+hipError_t adjoint2_q9_occupancy(const Dims &dm, const Geom &g, int shape, int *blocks_per_cu);
+// rows and waves per workgroup of an adjoint tile shape; false past the last
+bool adjoint2_shape_of(int shape, int *rows, int *waves);
 
 // Generic FP64 reductions (lbm_reduce.hip).
 hipError_t launch_reduce(const double *phi, const double *ref, uint32_t n, double *part,

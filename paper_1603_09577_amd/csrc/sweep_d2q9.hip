@@ -77,16 +77,23 @@ bool two_step_shape_of(int prec, int shape, int *rows, int *waves) {
 
 hipError_t launch_adjoint2_q9(const Dims &dm, const Geom &g, const void *coefs, const void *f1, const void *p1,
                               const void *f0, const void *p0, const void *psi_next, const double *pi_next,
-                              void *psi_out, double *pi_out, double *gk_part, int rows, hipStream_t st) {
+                              void *psi_out, double *pi_out, double *gk_part, int shape, hipStream_t st) {
     if (!dm.eqr || dm.wall) return hipErrorInvalidValue;
     LBM_BY_PREC_ADJ(adjoint2_typed, dm, g, coefs, f1, p1, f0, p0, psi_next, pi_next, psi_out, pi_out, gk_part, st,
-                    rows, nullptr)
+                    shape, nullptr)
 }
 
-hipError_t adjoint2_q9_occupancy(const Dims &dm, const Geom &g, int rows, int *blocks_per_cu) {
+hipError_t adjoint2_q9_occupancy(const Dims &dm, const Geom &g, int shape, int *blocks_per_cu) {
     if (!dm.eqr || dm.wall) return hipErrorInvalidValue;
     LBM_BY_PREC_ADJ(adjoint2_typed, dm, g, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                    nullptr, nullptr, nullptr, rows, blocks_per_cu)
+                    nullptr, nullptr, nullptr, shape, blocks_per_cu)
+}
+
+bool adjoint2_shape_of(int shape, int *rows, int *waves) {
+    if (shape < 0 || shape >= kAdjShapes) return false;
+    *rows = kAdjShape[shape][0];
+    *waves = kAdjShape[shape][1];
+    return true;
 }
 
 

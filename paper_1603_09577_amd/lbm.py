@@ -34,7 +34,7 @@ EXPORTS = [
     "lbm_batch_get_shape", "lbm_batch_destroy", "lbm_probe_copy", "lbm_set_chunk", "lbm_tune",
     "lbm_set_nontemporal", "lbm_recenter", "lbm_set_recenter", "lbm_set_fields", "lbm_set_phi_wall",
     "lbm_set_two_step", "lbm_two_step_shape", "lbm_adjoint_step2", "lbm_adjoint_pair_ok", "lbm_set_remap",
-    "lbm_set_adjoint_rows", "lbm_adjoint_rows",
+    "lbm_adjoint_tile_shape", "lbm_set_adjoint_tile", "lbm_adjoint_tile",
     "lbm_reduce_async", "lbm_reduce_state", "lbm_reduce_noalloc",
 ]
 
@@ -135,8 +135,10 @@ def load():
                                ctypes.c_int),
         "lbm_adjoint_step2": ([_VP] * 10, ctypes.c_int),
         "lbm_adjoint_pair_ok": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
-        "lbm_set_adjoint_rows": ([_VP, ctypes.c_int], ctypes.c_int),
-        "lbm_adjoint_rows": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "lbm_adjoint_tile_shape": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                                   ctypes.c_int),
+        "lbm_set_adjoint_tile": ([_VP, ctypes.c_int], ctypes.c_int),
+        "lbm_adjoint_tile": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "lbm_reduce_async": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
         "lbm_reduce_state": ([_VP, _VP, _VP, _VP], ctypes.c_int),
         "lbm_reduce_noalloc": ([_VP, _VP, ctypes.c_size_t, _VP, _VP], ctypes.c_int),
@@ -406,17 +408,26 @@ class Lbm:
         _check(self.lib.lbm_adjoint_pair_ok(self.ctx, ctypes.byref(ok)))
         return bool(ok.value)
 
-    @property
-    def adjoint_rows(self):
-        """Tile rows of adjoint_step2 (6 or 10)."""
-        r = ctypes.c_int()
-        _check(self.lib.lbm_adjoint_rows(self.ctx, ctypes.byref(r)))
-        return r.value
+    def adjoint_tile_shapes(self):
+        """[(rows, waves per workgroup)] of the adjoint_step2 tile shapes."""
+        out, i = [], 0
+        r, w = ctypes.c_int(), ctypes.c_int()
+        while self.lib.lbm_adjoint_tile_shape(self.ctx, i, ctypes.byref(r), ctypes.byref(w)) == 0:
+            out.append((r.value, w.value))
+            i += 1
+        return out
 
-    def set_adjoint_rows(self, rows):
-        """Force 6- or 10-row tiles for adjoint_step2; 0 restores the choice
-        made at creation (fewer rounds of resident workgroups)."""
-        _check(self.lib.lbm_set_adjoint_rows(self.ctx, int(rows)))
+    @property
+    def adjoint_tile(self):
+        """Index of the adjoint_step2 tile shape in use (adjoint_tile_shapes)."""
+        s = ctypes.c_int()
+        _check(self.lib.lbm_adjoint_tile(self.ctx, ctypes.byref(s)))
+        return s.value
+
+    def set_adjoint_tile(self, shape=None):
+        """Force adjoint_step2 tile shape `shape`; None restores the pick made
+        at creation."""
+        _check(self.lib.lbm_set_adjoint_tile(self.ctx, 0 if shape is None else 1 + int(shape)))
 
     def adjoint_pairs_faster(self, reps=8, trials=3):
         """Whether two reversed sweeps per launch beat two one-sweep launches

@@ -111,8 +111,9 @@ def test_null_arguments(L):
     assert L.lbm_adjoint_step(None, None, None, None, None, None, None, None) == lbm.LBM_E_INVALID
     assert L.lbm_adjoint_step2(*([None] * 10)) == lbm.LBM_E_INVALID
     assert L.lbm_adjoint_pair_ok(None, None) == lbm.LBM_E_INVALID
-    assert L.lbm_set_adjoint_rows(None, 6) == lbm.LBM_E_INVALID
-    assert L.lbm_adjoint_rows(None, None) == lbm.LBM_E_INVALID
+    assert L.lbm_adjoint_tile_shape(None, 0, None, None) == lbm.LBM_E_INVALID
+    assert L.lbm_set_adjoint_tile(None, 1) == lbm.LBM_E_INVALID
+    assert L.lbm_adjoint_tile(None, None) == lbm.LBM_E_INVALID
     assert L.lbm_two_step_shape(None, 0, None, None) == lbm.LBM_E_INVALID
     assert L.lbm_set_remap(None, 1) == lbm.LBM_E_INVALID
     assert L.lbm_recenter(None, None) == lbm.LBM_E_INVALID

@@ -2,7 +2,7 @@
 
 * psi and pi equal those of two one-sweep launches bit for bit (FP64 and
   FP32, with and without the Scheme-A source, ragged tiles in x and y, a
-  grid with more tiles than one-sweep workgroups, 6- and 10-row tiles); the
+  grid with more tiles than one-sweep workgroups, every tile shape); the
   K0 sums agree up to
   the order of additions (FP64 <= 1e-12 relative; FP32 terms are summed over
   a wave in FP32, <= 1e-6),
@@ -56,16 +56,16 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("rows", [6, 10])
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("prec,nx,ny,source", CASES)
-def test_pair_equals_two_single_sweeps(prec, nx, ny, source, rows):
+def test_pair_equals_two_single_sweeps(prec, nx, ny, source, shape):
     from paper_1603_09577_amd import lbm
-    say(f"[gpu adjoint pairs] {prec} {nx}x{ny} source={source} rows={rows}")
     spec = W.spec_nonlinear_2d(nx, ny, precision=prec, source=source)
     sim = lbm.Lbm(spec).init(W.noise_field((ny, nx), 31))
+    say(f"[gpu adjoint pairs] {prec} {nx}x{ny} source={source} tile {sim.adjoint_tile_shapes()[shape]}")
     assert sim.adjoint_pair_ok
-    sim.set_adjoint_rows(rows)
-    assert sim.adjoint_rows == rows
+    sim.set_adjoint_tile(shape)
+    assert sim.adjoint_tile == shape
     sim.step(6)
     (fa, pa), (fb, pb) = consecutive_states(sim)
     rng = np.random.default_rng(32)
@@ -148,25 +148,32 @@ def test_rollout_with_pairs_matches_oracle():
     assert e0 <= 1e-10 and ek <= 1e-10
 
 
-def test_adjoint_rows_choice_and_setter():
-    """The tiling picked at creation is 6 or 10 rows, a forced one holds until
-    0 restores the pick, and other values are refused."""
+def test_adjoint_tile_choice_and_setter():
+    """The tile shapes are 6 x 4, 10 x 4 and 10 x 12; the pick made at
+    creation follows the rule of the header (checked where it is fixed by the
+    grid alone: the FP32 512^2 launch is small enough for 10 x 12, FP64 never
+    takes it, 1024^2 FP32 is not); a forced shape holds until None restores
+    the pick, and other modes are refused."""
     from paper_1603_09577_amd import lbm
-    for prec, n in (("f64", 512), ("f64", 1024), ("f32", 768), ("f32", 1024)):
+    for prec, n in (("f64", 512), ("f64", 1024), ("f32", 512), ("f32", 768), ("f32", 1024)):
         sim = lbm.Lbm(W.spec_nonlinear_2d(n, n, precision=prec))
-        auto = sim.adjoint_rows
-        say(f"[gpu adjoint pairs] {prec} {n}^2 picks {auto}-row tiles")
-        assert auto in (6, 10)
-        other = 16 - auto
-        sim.set_adjoint_rows(other)
-        assert sim.adjoint_rows == other
-        sim.set_adjoint_rows(0)
-        assert sim.adjoint_rows == auto
-        for bad in (-1, 7, 14):
+        assert sim.adjoint_tile_shapes() == [(6, 4), (10, 4), (10, 12)]
+        auto = sim.adjoint_tile
+        say(f"[gpu adjoint pairs] {prec} {n}^2 picks {sim.adjoint_tile_shapes()[auto]}")
+        if prec == "f64" or n >= 768:
+            assert auto in (0, 1)
+        else:
+            assert auto == 2
+        for shape in (0, 1, 2):
+            sim.set_adjoint_tile(shape)
+            assert sim.adjoint_tile == shape
+        sim.set_adjoint_tile(None)
+        assert sim.adjoint_tile == auto
+        for bad in (3, 6, -2):          # modes 4, 7 and -1
             with pytest.raises(lbm.LbmError) as ei:
-                sim.set_adjoint_rows(bad)
+                sim.set_adjoint_tile(bad)
             assert ei.value.code == lbm.LBM_E_INVALID
-        assert sim.adjoint_rows == auto
+        assert sim.adjoint_tile == auto
 
 
 def test_pair_refused_where_it_does_not_apply():

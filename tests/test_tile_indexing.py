@@ -90,7 +90,7 @@ def test_two_step_phase1_rows(th, nw):
                                 assert 0 <= got < nx * ny
 
 
-@pytest.mark.parametrize("th,nw", [(6, 4), (10, 4)])
+@pytest.mark.parametrize("th,nw", [(6, 4), (10, 4), (10, 12)])
 def test_two_sweep_adjoint_rows(th, nw):
     """Both phases of the two-sweep adjoint tile (nw waves): phase 1 gathers
     the forward state (pull) and psi (transposed) on the tile and halo; phase 2
