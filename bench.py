@@ -283,6 +283,8 @@ def run_adjoint(torch, lbm, spec, phi0, steps, warmup, label, pairs=True):
     out = {"label": label, "nodes": sim.N, "steps": steps, "ms_per_step": per * 1e3,
            "mlups": sim.N / per / 1e6, "pairs": use_pairs}
     if use_pairs:
+        r, w = sim.adjoint_tile_shapes()[sim.adjoint_tile]
+        out["tile"] = f"{r} rows x {w} waves"
         bpl = adjoint_pair_bytes_per_node(sim.q, prec, src)
         gbs = bpl * sim.N / (2 * per) / 1e9
         out.update({"bytes_per_node": bpl, "bytes_per_node_note": "per launch of two reversed sweeps",

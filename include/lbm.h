@@ -431,7 +431,7 @@ int lbm_adjoint_pair_ok(const lbm_ctx *ctx, int *ok);
  * the last).  lbm_create picks one for the grid and device: the 6- or 10-row
  * tiling that runs the launch in fewer rounds of resident workgroups (6 at
  * equal rounds), and 10 x 12 for FP32 launches with at most 6 waves per SIMD
- * in all.  lbm_set_adjoint_tile forces shape mode - 1, or restores the pick
+ * in all where it at least halves the tiles per CU.  lbm_set_adjoint_tile forces shape mode - 1, or restores the pick
  * with mode 0 (LBM_E_INVALID otherwise); lbm_adjoint_tile reports the shape
  * in use.  Every shape gives the same psi and pi bit for bit; the K0 sums
  * differ in the order of FP64 additions. */

@@ -437,10 +437,12 @@ void prepare_zchunk(lbm_ctx *c) {
 // fewer rounds than 6-row tiles (512^2 FP64: 9.3 against 10.9 us per reversed
 // sweep; 768^2 FP32: 9.5 against 10.0), and 6-row tiles win at equal rounds
 // (1024^2 FP64: 34.7 against 36.8).  An FP32 launch too small to give every
-// SIMD several waves (at most 6 waves per SIMD with 12 per 10-row tile; 512^2
-// has 468 such tiles) runs 10-row tiles with one row per wave: 5.3 against
-// 6.1 us.  FP64, held to 2 or 3 waves per SIMD by its registers, gains
-// nothing from the extra waves (512^2: 10.3 against 9.3).
+// SIMD several waves (at most 6 waves per SIMD with 12 per 10-row tile) runs
+// 10-row tiles with one row per wave when that at least halves the tiles
+// per CU (512^2: 2 against 4; 5.3 against 6.1 us); with as many tiles per CU
+// the 6-row tiles' smaller work per tile wins (384^2: 4.8 against 4.3 us).
+// FP64, held to 2 or 3 waves per SIMD by its registers, gains nothing from
+// the extra waves (512^2: 10.3 against 9.3).
 void pick_adj_shape(lbm_ctx *c) {
     query_cus(c);
     c->adj_shape = 0;
@@ -456,7 +458,9 @@ void pick_adj_shape(lbm_ctx *c) {
         return (tiles(th) + slots - 1) / slots;
     };
     if (rounds(10, occ10) < rounds(6, occ6)) c->adj_shape = 1;
-    if (c->dm.prec == 1 && tiles(10) * 12 <= 6ull * 4 * (uint64_t)c->ncu) c->adj_shape = 2;
+    const uint64_t ncu = (uint64_t)c->ncu;
+    const uint64_t per_cu6 = (tiles(6) + ncu - 1) / ncu, per_cu10 = (tiles(10) + ncu - 1) / ncu;
+    if (c->dm.prec == 1 && tiles(10) * 12 <= 6 * 4 * ncu && 2 * per_cu10 <= per_cu6) c->adj_shape = 2;
     c->adj_shape_auto = c->adj_shape;
 }
 

@@ -431,12 +431,15 @@ class Lbm:
 
     def adjoint_pairs_faster(self, reps=8, trials=3):
         """Whether two reversed sweeps per launch beat two one-sweep launches
-        here: both are timed `trials` times, alternately, on scratch buffers
-        (zero adjoint variables, the current forward state), and pairs are
-        taken only when their best time per sweep is at least 2% below the
-        one-sweep kernel's best, so that near-ties resolve the same way in
-        every run.  The answer is kept.  The trial adds to the K0 sums, so
-        call it before lbm_adjoint_seed, which clears them."""
+        here, and in which tile shape: the one-sweep kernel and the pair in
+        every tile shape are timed `trials` times, alternately, on scratch
+        buffers (zero adjoint variables, the current forward state).  The
+        pair keeps the shape picked at creation unless another is at least 2%
+        faster (set_adjoint_tile), and pairs are taken only when their best
+        time per sweep is at least 2% below the one-sweep kernel's best, so
+        that near-ties resolve the same way in every run.  The answer is
+        kept.  The trial adds to the K0 sums, so call it before
+        lbm_adjoint_seed, which clears them."""
         import torch
         if getattr(self, "_adj_pairs", None) is not None:
             return self._adj_pairs
@@ -448,27 +451,40 @@ class Lbm:
         a, pa = self.adjoint_buffers()
         b, pb = self.adjoint_buffers()
         a.zero_(); pa.zero_(); b.zero_(); pb.zero_()
+        picked = self.adjoint_tile
+        order = [picked] + [s for s in range(len(self.adjoint_tile_shapes())) if s != picked]
 
         def singles():
             for _ in range(reps):
                 self.adjoint_step(f, p, a, pa, b, pa)
                 self.adjoint_step(f, p, b, pa, a, pa)
 
-        def pairs():
+        def pairs(shape):
+            self.set_adjoint_tile(shape)
             for _ in range(reps):
                 self.adjoint_step2(f, p, f, p, a, pa, b, pb)
                 self.adjoint_step2(f, p, f, p, b, pb, a, pa)
 
-        singles(); pairs()
-        per_single, per_pair = float("inf"), float("inf")
+        singles()
+        for s in order:
+            pairs(s)
+        per_single = float("inf")
+        per_pair = {s: float("inf") for s in order}
         for _ in range(trials):
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 + 2 * len(order))]
             ev[0].record(); singles(); ev[1].record()
-            ev[2].record(); pairs(); ev[3].record()
+            for i, s in enumerate(order):
+                ev[2 + 2 * i].record(); pairs(s); ev[3 + 2 * i].record()
             torch.cuda.synchronize()
             per_single = min(per_single, ev[0].elapsed_time(ev[1]) / (2 * reps))
-            per_pair = min(per_pair, ev[2].elapsed_time(ev[3]) / (4 * reps))
-        self._adj_pairs = per_pair < 0.98 * per_single
+            for i, s in enumerate(order):
+                per_pair[s] = min(per_pair[s], ev[2 + 2 * i].elapsed_time(ev[3 + 2 * i]) / (4 * reps))
+        best = picked
+        for s in order[1:]:
+            if per_pair[s] < 0.98 * per_pair[best]:
+                best = s
+        self.set_adjoint_tile(best)
+        self._adj_pairs = per_pair[best] < 0.98 * per_single
         return self._adj_pairs
 
     def adjoint_step2(self, f_s, p_s, f_sm1, p_sm1, psi_next, pi_next, psi_out, pi_out, stream=None):
