@@ -123,6 +123,8 @@ def time_steps(torch, sim, steps, warmup, samples=SAMPLES):
 # tile shape forced on D2Q9 two-step runs after tuning, with the XCD-aware
 # order (--two-step-shape; None: the tuner's choices)
 TWO_STEP_SHAPE = None
+# whether the adjoint pair's trial also times every tile shape (--adjoint-tile-pick: no)
+ADJ_TILE_TRIAL = True
 # [(rows, waves), ...] two-step shapes forced on D3Q19 runs, the first the
 # precision has (--two-step-3d; None: the tuner's choice between single
 # sweeps and each shape)
@@ -247,7 +249,7 @@ def run_adjoint(torch, lbm, spec, phi0, steps, warmup, label, pairs=True):
     psi_a, pi = sim.adjoint_buffers()
     psi_b, pi_b = sim.adjoint_buffers()
     g = torch.full(sim.shape, 1e-3, dtype=torch.float64, device=sim.device)
-    use_pairs = pairs and steps % 2 == 0 and sim.adjoint_pairs_faster()
+    use_pairs = pairs and steps % 2 == 0 and sim.adjoint_pairs_faster(shapes=ADJ_TILE_TRIAL)
     sim.adjoint_seed(g, psi_a, pi)
 
     def launches(n):
@@ -393,21 +395,24 @@ def cpu_baseline(spec, phi0, target_s=12.0, single_s=6.0):
 
 PROFILE_COMMANDS = {
     "trace": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 1000 --warmup 50 --two-step-shape 1 --two-step-3d 14x16,6x8",
+             "python3 bench.py --no-cpu --steps 1000 --warmup 50 --two-step-shape 1 --two-step-3d 14x16,6x8 "
+             "--adjoint-tile-pick",
     "fetch": "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 14x16,6x8",
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 14x16,6x8 "
+             "--adjoint-tile-pick",
     "write": "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write --output-format csv -- "
-             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 14x16,6x8",
+             "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19,batch --two-step-shape 1 --two-step-3d 14x16,6x8 "
+             "--adjoint-tile-pick",
     "valu": "rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVES -d gpurun_out/pmc_valu -o valu "
             "--output-format csv -- python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19 "
-            "--two-step-shape 1 --two-step-3d 14x16,6x8",
+            "--two-step-shape 1 --two-step-3d 14x16,6x8 --adjoint-tile-pick",
     "stall": "rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
              "SQ_WAIT_INST_LDS -d gpurun_out/pmc_stall -o stall --output-format csv -- "
              "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19 --two-step-shape 1 "
-             "--two-step-3d 14x16,6x8",
+             "--two-step-3d 14x16,6x8 --adjoint-tile-pick",
     "l2": "rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum -d gpurun_out/pmc_l2 -o l2 --output-format csv -- "
           "python3 bench.py --no-cpu --steps 20 --warmup 0 --only adjoint,d3q19 --two-step-shape 1 "
-          "--two-step-3d 14x16,6x8",
+          "--two-step-3d 14x16,6x8 --adjoint-tile-pick",
 }
 # vector-ALU issue peak without packed FP32: each SIMD issues one 64-lane
 # instruction every 4 clocks (16 lanes per clock), 4 SIMDs per CU, so one
@@ -708,6 +713,9 @@ def main():
                     help="run the D3Q19 legs with two steps per pass in the first of these tile shapes that the "
                          "precision has (14x16 FP32/FP16 only, 6x8 all), so that the profiled runs time one kernel "
                          "whatever the tuner picks")
+    ap.add_argument("--adjoint-tile-pick", action="store_true",
+                    help="keep the adjoint pair's tile shape picked at creation instead of timing every shape, so "
+                         "that the profiled runs, whose timings the counters disturb, time the same kernel")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write the profiles/ summaries from rocprofv3 output under DIR and exit (no GPU)")
     args = ap.parse_args()
@@ -716,8 +724,9 @@ def main():
         print(json.dumps({k: v["traffic_bytes_per_launch"] / v["algorithmic_bytes_per_launch"]
                           for k, v in out["workloads"].items()}))
         return
-    global TWO_STEP_SHAPE, TWO_STEP_3D
+    global TWO_STEP_SHAPE, TWO_STEP_3D, ADJ_TILE_TRIAL
     TWO_STEP_SHAPE = args.two_step_shape
+    ADJ_TILE_TRIAL = not args.adjoint_tile_pick
     if args.two_step_3d:
         TWO_STEP_3D = [tuple(int(v) for v in sh.split("x")) for sh in args.two_step_3d.lower().split(",")]
     if args.gpus != 1:

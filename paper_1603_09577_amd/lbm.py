@@ -429,7 +429,7 @@ class Lbm:
         at creation."""
         _check(self.lib.lbm_set_adjoint_tile(self.ctx, 0 if shape is None else 1 + int(shape)))
 
-    def adjoint_pairs_faster(self, reps=8, trials=3):
+    def adjoint_pairs_faster(self, reps=8, trials=3, shapes=True):
         """Whether two reversed sweeps per launch beat two one-sweep launches
         here, and in which tile shape: the one-sweep kernel and the pair in
         every tile shape are timed `trials` times, alternately, on scratch
@@ -437,9 +437,9 @@ class Lbm:
         pair keeps the shape picked at creation unless another is at least 2%
         faster (set_adjoint_tile), and pairs are taken only when their best
         time per sweep is at least 2% below the one-sweep kernel's best, so
-        that near-ties resolve the same way in every run.  The answer is
-        kept.  The trial adds to the K0 sums, so call it before
-        lbm_adjoint_seed, which clears them."""
+        that near-ties resolve the same way in every run (shapes=False: only
+        the picked shape is timed).  The answer is kept.  The trial adds to
+        the K0 sums, so call it before lbm_adjoint_seed, which clears them."""
         import torch
         if getattr(self, "_adj_pairs", None) is not None:
             return self._adj_pairs
@@ -452,7 +452,7 @@ class Lbm:
         b, pb = self.adjoint_buffers()
         a.zero_(); pa.zero_(); b.zero_(); pb.zero_()
         picked = self.adjoint_tile
-        order = [picked] + [s for s in range(len(self.adjoint_tile_shapes())) if s != picked]
+        order = [picked] + ([s for s in range(len(self.adjoint_tile_shapes())) if s != picked] if shapes else [])
 
         def singles():
             for _ in range(reps):
