@@ -1037,10 +1037,11 @@ struct Zc3 {
 // plane are issued before the current plane's arithmetic, so that their
 // latency overlaps phase 1, phase 2 and both barriers.
 // SRC: a Scheme-A source.  Phase 1 reads the phi history of its nodes from
-// pin (phi(t - 1), the node itself) and keeps phi(t) in a two-slot ring of
-// its own, rounded to the history type as a store would round it; phase 2
-// takes that as its history and writes phi(t + 1) to pout, which must not be
-// pin (neighbouring columns still read pin at their halo).
+// pin (phi(t - 1), the node itself) and keeps phi(t), rounded to the history
+// type as a store would round it, and the source terms of phi(t) for phase 2
+// of the next plane (in registers when the history type is the compute type,
+// else phi(t) in a two-slot ring); phase 2 writes phi(t + 1) to pout, which
+// must not be pin (neighbouring columns still read pin at their halo).
 // EQ: the equal-rate collision; otherwise the moment-space one (unequal
 // non-flux rates).
 template <typename TS, typename TC, bool KVAR, bool WALL, int NP, int TY, int NW, bool SB = false, bool SRC = false,
@@ -1056,7 +1057,14 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
     __shared__ TS rp[2][5][TR][TX];
     __shared__ TS r0[2][9][TR][TX];
     __shared__ TS rm[2][5][TR][TX];
-    __shared__ TP lp[SRC ? 2 : 1][SRC ? TR : 1][TX];
+    // Scheme A: phase 2 runs the rows the wave ran in phase 1 one plane
+    // earlier, so that phi(t) and the source terms of phi(t) of its nodes come
+    // from the wave's registers (the history type equals the compute type:
+    // they are the values the rebuild from the history would give)
+    constexpr bool HAND = SRC && !SB && std::is_same<TP, TC>::value;
+    __shared__ TP lp[(SRC && !HAND) ? 2 : 1][(SRC && !HAND) ? TR : 1][TX];
+    SrcLevel<TC> lev1[HAND ? PR : 1], lev0[HAND ? PR : 1];   // planes i - 1 and i
+    TP ph1[HAND ? PR : 1];                                    // phi - phi_ref of plane i - 1
     const uint32_t blk = block_index(blockIdx.x, gridDim.x, g.remap);
     const uint32_t per_z = tiles_x * tiles_y;
     const uint32_t tz = blk / per_z, rem = blk - tz * per_z;
@@ -1121,6 +1129,7 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
         if (i + 1 < nplanes) load(i + 1, hn, pn);
         // phase 1: plane zl (skipped beyond a wall)
         TS keep[PR][5];
+        TP ph0[HAND ? PR : 1];
         if (p1) {
 #pragma unroll
             for (int j = 0; j < PR; ++j) {
@@ -1135,9 +1144,11 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                     }
                     TC out[19];
                     const TC phio = collide_node<19, TC, EQ, SRC, KVAR, NP, SB>(
-                        cf, h, SRC ? (TC)pc[j] : TC(0), 0u, nullptr, nullptr, false, out);
+                        cf, h, SRC ? (TC)pc[j] : TC(0), 0u, nullptr, nullptr, false, out,
+                        HAND ? &lev0[HAND ? j : 0] : nullptr);
                     bad |= !__builtin_isfinite(phio);
-                    if (SRC) lp[s1 & (SRC ? 1 : 0)][SRC ? r : 0][lane] = (TP)phio;
+                    if (SRC && !HAND) lp[s1 & 1][(SRC && !HAND) ? r : 0][lane] = (TP)phio;
+                    if (HAND) ph0[HAND ? j : 0] = (TP)phio;
 #pragma unroll
                     for (int c = 0; c < 9; ++c) r0[s1][c][r][lane] = (TS)out[Zc3::z[c]];
 #pragma unroll
@@ -1154,7 +1165,7 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
             const int zc2 = zl - 1;
             const bool lo = WALL && zc2 == 0, hi = WALL && zc2 == nz - 1;
             const int x = x0 + lane - 1;
-            for (int r = 1 + wv; r <= TY; r += NW) {
+            auto row2 = [&](int r, TC pp_off, const SrcLevel<TC> *prev) {
                 const int y = y0 + r - 1;
                 TC h[19];
 #pragma unroll
@@ -1173,15 +1184,31 @@ k_sweep2_3d(const Geom g, const Coefs<TC> *__restrict__ cf, const TS *__restrict
                     }
                 }
                 TC out[19];
-                const TC pp_off = SRC ? (TC)lp[s0 & (SRC ? 1 : 0)][SRC ? r : 0][lane] : TC(0);
                 const TC phio = collide_node<19, TC, EQ, SRC, KVAR, NP, SB>(cf, h, pp_off, 0u, nullptr, nullptr,
-                                                                             false, out);
+                                                                             false, out, nullptr, prev);
                 bad |= !__builtin_isfinite(phio);
                 if (x < nx && y < ny) {
                     const uint32_t m = ((uint32_t)zc2 * g.ny + (uint32_t)y) * g.nx + (uint32_t)x;
                     store_planes<19, false>(fout, g.plane, m, out);
                     if (SRC) *at<true>(pout, m) = (TP)phio;
                 }
+            };
+            if constexpr (HAND) {
+#pragma unroll
+                for (int j = 0; j < PR; ++j) {
+                    const int r = wv + j * NW;
+                    if (r >= 1 && r <= TY) row2(r, (TC)ph1[j], &lev1[j]);
+                }
+            } else {
+                for (int r = 1 + wv; r <= TY; r += NW)
+                    row2(r, SRC ? (TC)lp[s0 & 1][(SRC && !HAND) ? r : 0][lane] : TC(0), nullptr);
+            }
+        }
+        if constexpr (HAND) {
+#pragma unroll
+            for (int j = 0; j < PR; ++j) {
+                lev1[j] = lev0[j];
+                ph1[j] = ph0[j];
             }
         }
         __syncthreads();
