@@ -217,7 +217,7 @@ int lbm_set_nontemporal(lbm_ctx *ctx, int on);
  * latter), and, where allowed, two time steps per pass (lbm_set_two_step);
  * keeps the fastest; then, unless LBM_FLAG_NO_GRAPH is set or a divergence
  * check is enabled, times lbm_step's graph replays against direct launches of
- * the same kernels and keeps graphs unless direct launches are at least 1%
+ * the same kernels and keeps direct launches unless graphs are at least 1%
  * faster (results are identical either way); writes the timings into
  * `report` (may be NULL) and
  * re-initialises the state from the phi0 given to lbm_init (step counter

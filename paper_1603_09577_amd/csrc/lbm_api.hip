@@ -1265,18 +1265,19 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
     prepare_zchunk(c);
     drop_graphs(c);
     // runs of kGraphSteps sweeps: graph replays against direct launches of the
-    // same kernels, alternately, twice each (on 1024^2 FP32 passes direct
-    // launches measured 1.5-3% faster; on small grids the host's launch rate
-    // can fall behind the kernels, which graphs avoid).  Graphs stay unless
-    // direct launches are at least 1% faster.
+    // same kernels, alternately, three times each (direct launches measured
+    // 0.5-3% faster from 128^2 to 1024^2 and level on 256^3, where a launch
+    // takes 0.3 ms; the trial is there for grids so small that the host's
+    // launch rate would fall behind the kernels, which graphs avoid).  Direct
+    // launches are kept unless graphs are at least 1% faster.
     float graph_ms = -1.f, direct_ms = -1.f;
     c->use_graphs = true;
     if (!(c->desc.flags & LBM_FLAG_NO_GRAPH) && c->check_every == 0) {
-        for (int trial = 0; trial < 4; ++trial) {
+        for (int trial = 0; trial < 6; ++trial) {
             c->use_graphs = (trial & 1) == 0;
             int rc = advance(c, kGraphSteps, st);   // warm-up (and the graph capture)
             hipError_t e = rc == LBM_OK ? hipEventRecord(e0, st) : hipErrorUnknown;
-            if (e == hipSuccess) rc = advance(c, 2 * kGraphSteps, st);
+            if (e == hipSuccess) rc = advance(c, 4 * kGraphSteps, st);
             if (e == hipSuccess && rc == LBM_OK) e = hipEventRecord(e1, st);
             if (e == hipSuccess && rc == LBM_OK) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -1285,11 +1286,11 @@ int lbm_tune(lbm_ctx *c, int reps, void *stream, char *report, size_t report_len
                 (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
                 return rc != LBM_OK ? rc : hip_fail(e, "tuning graph launches");
             }
-            ms /= 2 * kGraphSteps;
+            ms /= 4 * kGraphSteps;
             float &t = c->use_graphs ? graph_ms : direct_ms;
             if (t < 0.f || ms < t) t = ms;
         }
-        c->use_graphs = !(direct_ms < 0.99f * graph_ms);
+        c->use_graphs = graph_ms < 0.99f * direct_ms;
         char gl[112];
         std::snprintf(gl, sizeof(gl), "graph replays: %.4f ms per step, direct launches: %.4f ms per step\n", graph_ms,
                       direct_ms);
